@@ -1,0 +1,173 @@
+/*
+ * rbe.h -- C ABI of the random batch Ewald (RBE) nonbonded force on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library computes, for N point charges with Lennard-Jones cores in a
+ * periodic box, the nonbonded force of RBMD 2.0 (arXiv 2609.02694, Sec. 2.1):
+ *
+ *   F_i = F_i^N + F_i^F
+ *
+ *   F_i^N  near field (Eq. 7-8): erfc-screened Coulomb within r_coul plus 12-6
+ *          LJ (Eq. 2) within r_lj, over the minimum image, optionally through
+ *          the core-shell random batch list (Eq. 10-11) with the momentum
+ *          correction of Eq. 12;
+ *   F_i^F  Fourier part by importance sampling (Eq. 9): P modes k_l drawn from
+ *          P(k) ~ exp(-k^2/(4 alpha)) on the reciprocal lattice without k = 0,
+ *          structure factors rho(k_l) = sum_j q_j exp(i k_l . r_j) (Eq. 5) and
+ *          F_i^F = -q_i sum_l w_l k_l Im(exp(-i k_l . r_i) rho(k_l)),
+ *          w_l = (S/P) 4 pi / (V k_l^2), S = sum_{k != 0} exp(-k^2/(4 alpha)).
+ *
+ * alpha is the paper's alpha: the real-space kernel is erfc(sqrt(alpha) r)/r
+ * (Eq. 4). The sign convention is F = -grad U; pair terms act along
+ * d = r_i - r_j.
+ *
+ * Conventions shared by every call
+ *  - Pointers are DEVICE pointers unless marked (host).
+ *  - `stream` is a hipStream_t passed as void*. Calls are asynchronous on it;
+ *    only rbe_sync_check synchronizes.
+ *  - Particle arrays are structure-of-arrays, FP64 for coordinates,
+ *    velocities, forces and charges, int32 for ids.
+ *  - Every call returns an rbe_status (0 = success). Host-checkable argument
+ *    errors are rejected before any launch; rbe_last_error gives the message.
+ *    No call aborts or throws across the ABI.
+ *  - One context per stream at a time; a context is not thread-safe.
+ */
+#ifndef RBE_H
+#define RBE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RBE_OK = 0,
+  RBE_EINVAL = -1,      /* bad argument (sizes, cutoffs, null pointers)          */
+  RBE_EBOX = -2,        /* a cutoff exceeds half the box (minimum image broken)  */
+  RBE_ENONNEUTRAL = -3, /* sum q != 0 (Eq. 1 requires charge neutrality)         */
+  RBE_ENOMEM = -4,      /* device allocation failed in rbe_create                */
+  RBE_EDEVICE = -5,     /* a HIP call failed                                     */
+  RBE_ENONFINITE = -6,  /* device saw a non-finite position/velocity/force       */
+  RBE_ERANGE = -7       /* n exceeds the context capacity, or a bad particle id  */
+} rbe_status;
+
+typedef enum { RBE_FP64 = 0, RBE_FP32C = 1 } rbe_precision;
+
+/* Fourier-mode distribution. Only the paper's Gaussian is provided. */
+typedef enum { RBE_KDIST_GAUSS = 0 } rbe_kdist;
+
+/* Terms of F to evaluate (bit mask). */
+enum { RBE_TERM_LJ = 1, RBE_TERM_COUL_REAL = 2, RBE_TERM_FOURIER = 4, RBE_TERM_ALL = 7 };
+
+typedef struct {
+  double L[3];        /* periodic box edges (Eq. 3)                                    */
+  double alpha;       /* Ewald splitting parameter of Eq. 4 (> 0)                      */
+  double r_coul;      /* real-space Coulomb cutoff: the paper's shell radius r_s       */
+  double r_lj;        /* LJ cutoff (plain truncation)                                  */
+  double r_core;      /* core radius r_c of Eq. 10; 0 disables the random batch list   */
+  int32_t p_shell;    /* shell batch size p of Eq. 11 (1..32 when r_core > 0)          */
+  int32_t P;          /* number of sampled Fourier modes (Eq. 9), 1..RBE_MAX_P         */
+  int32_t kdist;      /* rbe_kdist                                                     */
+  int32_t prec;       /* rbe_precision                                                 */
+  int32_t terms;      /* RBE_TERM_* mask; 0 means RBE_TERM_ALL                         */
+  int32_t ncell[3];   /* cell grid over the box; 0 lets the library choose            */
+  double lj_eps, lj_sigma; /* LJ parameters of Eq. 2                                   */
+  double coulomb_k;   /* Coulomb prefactor (1 in reduced units)                        */
+  double mass, dt;    /* particle mass and velocity-Verlet time step                   */
+  double ghost_width; /* 0: periodic traversal; > 0: near field over a locally built
+                         shell of periodic ghost copies of this width (>= r_coul)       */
+  uint64_t seed;      /* stream seed of the mode sample and of the shell batches       */
+} rbe_params;
+
+#define RBE_MAX_P 4096
+#define RBE_MAX_SHELL_BATCH 32
+
+/* Caller-owned particle state (device arrays of length n). The library never
+   frees or reallocates them. fx, fy, fz receive forces; vx..vz and the
+   positions are advanced by rbe_step. */
+typedef struct {
+  double *x, *y, *z;
+  double *vx, *vy, *vz;
+  double *fx, *fy, *fz;
+  double *q;
+  int32_t *id; /* unique, 0..n-1 (the shell batches of Eq. 11 are keyed by id) */
+  int64_t n;
+} rbe_state;
+
+typedef struct rbe_ctx rbe_ctx;
+
+/* Create a context for one system of up to n_max particles on HIP device
+   `device` and allocate ALL its device scratch (cells, sorted copies, mode
+   buffers, partial sums, flags). Validates *p (host): positive box, alpha,
+   cutoffs <= L/2, 0 < P <= RBE_MAX_P, 1 <= p_shell <= 32 when r_core > 0,
+   r_core <= r_coul. On failure *out is NULL and the status says why. */
+int rbe_create(rbe_ctx **out, const rbe_params *p /* host */, int64_t n_max, int device);
+
+/* Batched form: n_sys independent systems, system s owning particles
+   [offset[s], offset[s+1]) of every state array. All systems share one
+   stream; a step of all of them runs as one persistent fused launch.
+   params and offset are host arrays of n_sys and n_sys + 1 entries. */
+int rbe_create_batch(rbe_ctx **out, int32_t n_sys, const rbe_params *params /* host */,
+                     const int64_t *offset /* host */, int device);
+
+void rbe_destroy(rbe_ctx *ctx);
+
+/* Message of the last failed call on ctx (or of the last failed create when
+   ctx is NULL). Never NULL. */
+const char *rbe_last_error(const rbe_ctx *ctx);
+
+/* Cell binning (Sec. 2.2: linked cells with cell-wise reordering).
+   key_i = s_i * C + (c_z * n_y + c_y) * n_x + c_x, with s_i = 0 for charged and
+   1 for neutral particles, C = n_x n_y n_z, and
+   c_d = min(n_d - 1, floor(w_d * (n_d / L_d))), w the coordinate wrapped into
+   [0, L_d). Output: the stable counting sort of the particles by key
+   (ties in input order): perm[0..n) lists input indices in key order and
+   cell_start[0..2C] holds the first slot of every key (cell_start[2C] = n).
+   Bit-exact: the result is a pure function of the inputs. */
+int rbe_build_cells(rbe_ctx *ctx, const double *x, const double *y, const double *z, const double *q, int64_t n,
+                    int32_t *cell_start, int32_t *perm, void *stream);
+
+/* Importance sample of Eq. 9 for force evaluation `eval`: writes m[3*P]
+   (integer mode vectors, blocks x | y | z, k = 2 pi m / L) and w[P] (weights
+   (S/P) 4 pi / (V k^2)). Draw l, attempt a uses outputs 3a..3a+2 of a
+   SplitMix64 stream keyed by (seed, eval, l); each output is mapped through
+   the per-axis inverse CDF of exp(-(pi m / L_d)^2 / alpha) and m = 0 is
+   rejected. on_device = 0: m, w are HOST pointers, computed on the host;
+   on_device = 1: DEVICE pointers, computed by a kernel on `stream`. Both
+   paths give identical bits. */
+int rbe_sample_k(const rbe_params *p /* host */, uint64_t eval, int32_t *m, double *w, int on_device,
+                 void *stream);
+
+/* One force evaluation F = F^N + F^F on the state as given (never reorders
+   it): writes s->fx, fy, fz in the caller's particle order. (m, w) is the
+   mode sample (device, 3*P and P entries); if m is NULL the library draws it
+   for `eval` itself. eval also keys the shell batches of Eq. 11.
+   rho_out, if not NULL, receives Re rho | Im rho (2*P doubles, device). */
+int rbe_forces(rbe_ctx *ctx, const rbe_state *s, const int32_t *m, const double *w, uint64_t eval,
+               double *rho_out, void *stream);
+
+/* nsteps velocity-Verlet steps:
+     v += dt/(2m) F;  x <- wrap(x + dt v);  F <- force(x, eval = first_eval + k);
+     v += dt/(2m) F
+   for k = 0..nsteps-1. On entry s->f* must hold the force of the current
+   positions. Positions, velocities, forces, charges and ids are returned in
+   cell order (the particles are reordered; id[] maps them back). */
+int rbe_step(rbe_ctx *ctx, rbe_state *s, int32_t nsteps, uint64_t first_eval, void *stream);
+
+/* Synchronize `stream` and report device-side errors recorded since the last
+   check (non-finite values, bad ids). Clears the flag. */
+int rbe_sync_check(rbe_ctx *ctx, void *stream);
+
+/* Diagnostic counters of the last rbe_forces/rbe_step force evaluation
+   (host, 4 entries): [0] near-field pairs inside a cutoff, [1] shell
+   candidates, [2] candidates tested, [3] particles with a shell batch.
+   Only filled when counting was enabled with rbe_set_counting(ctx, 1); the
+   counting adds atomics to the near-field kernel and is meant for the
+   roofline figures, not for timed runs. */
+int rbe_set_counting(rbe_ctx *ctx, int enable);
+int rbe_get_counters(rbe_ctx *ctx, int64_t *counters /* host, 4 */, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,573 @@
+// C ABI of the RBE library: context management, validation and the
+// orchestration of one force evaluation / one velocity-Verlet step.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace rbe;
+
+namespace {
+
+struct Buf {
+  std::vector<void *> ptrs;
+  bool ok = true;
+  template <class T>
+  T *alloc(int64_t count) {
+    if (count <= 0) count = 1;
+    void *p = nullptr;
+    if (hipMalloc(&p, (size_t)count * sizeof(T)) != hipSuccess) {
+      ok = false;
+      return nullptr;
+    }
+    ptrs.push_back(p);
+    return (T *)p;
+  }
+  void release() {
+    for (void *p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+};
+
+struct WorkSet {
+  double *x, *y, *z, *vx, *vy, *vz, *q, *fx, *fy, *fz;
+  int32_t *id;
+  StateArrays arrays() const { return StateArrays{x, y, z, vx, vy, vz, q, id}; }
+};
+
+thread_local std::string g_create_error;
+
+}  // namespace
+
+struct rbe_ctx {
+  int device = 0;
+  rbe_params p{};
+  int64_t n_max = 0;
+  Grid g{};
+  PairParams pp{};
+  ModeTable mt{};
+  std::vector<double> cdf_host;
+  Buf buf;
+  double *cdf_dev = nullptr;
+  BinBuffers bb{};
+  int32_t *cell_start = nullptr, *perm = nullptr, *inv_id = nullptr;
+  Sorted srt{};
+  WorkSet ws[2]{};
+  FourierBuffers fb{};
+  int32_t *m_dev = nullptr;
+  double *w_dev = nullptr;
+  double *mean_part = nullptr, *mean = nullptr;
+  int *err = nullptr;
+  int32_t *nq_dev = nullptr;
+  double *qstats = nullptr;  // [sum q, sum |q|]
+  unsigned long long *counters = nullptr;
+  bool counting = false;
+  std::string last_error;
+
+  int fail(int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+};
+
+int rbe_ctx::fail(int code, const char *fmt, ...) {
+  char msg[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(msg, sizeof msg, fmt, ap);
+  va_end(ap);
+  last_error = msg;
+  return code;
+}
+
+static int create_fail(int code, const char *msg) {
+  g_create_error = msg;
+  return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                     \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return (ctx)->fail(RBE_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));          \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+static int validate_params(const rbe_params *p, std::string *why) {
+  char msg[256];
+  auto bad = [&](int code, const char *m) {
+    *why = m;
+    return code;
+  };
+  for (int d = 0; d < 3; ++d)
+    if (!(p->L[d] > 0) || !std::isfinite(p->L[d])) return bad(RBE_EINVAL, "box edges must be positive and finite");
+  if (!(p->alpha > 0)) return bad(RBE_EINVAL, "alpha must be positive");
+  if (!(p->r_coul > 0) || !(p->r_lj >= 0) || !(p->r_core >= 0)) return bad(RBE_EINVAL, "cutoffs must be positive");
+  if (p->P < 1 || p->P > RBE_MAX_P) return bad(RBE_EINVAL, "P must be in [1, RBE_MAX_P]");
+  if (p->kdist != RBE_KDIST_GAUSS) return bad(RBE_EINVAL, "only the Gaussian mode distribution is provided");
+  if (p->prec != RBE_FP64 && p->prec != RBE_FP32C) return bad(RBE_EINVAL, "prec must be RBE_FP64 or RBE_FP32C");
+  if (p->terms < 0 || p->terms > RBE_TERM_ALL) return bad(RBE_EINVAL, "bad term mask");
+  if (p->r_core > 0) {
+    if (p->p_shell < 1 || p->p_shell > RBE_MAX_SHELL_BATCH) return bad(RBE_EINVAL, "p_shell must be in [1, 32]");
+    if (p->r_core > p->r_coul) return bad(RBE_EINVAL, "r_core must not exceed r_coul");
+    if (p->r_lj > p->r_coul) return bad(RBE_EINVAL, "with the random batch list r_lj must not exceed r_coul");
+  }
+  if (!(p->mass > 0) || !(p->dt >= 0)) return bad(RBE_EINVAL, "mass must be positive and dt non-negative");
+  if (!(p->lj_sigma > 0) || !(p->lj_eps >= 0)) return bad(RBE_EINVAL, "bad LJ parameters");
+  if (p->ghost_width != 0.0) return bad(RBE_EINVAL, "ghost_width > 0 is not supported by this build");
+  const double rmax = std::fmax(p->r_coul, p->r_lj);
+  for (int d = 0; d < 3; ++d)
+    if (rmax > 0.5 * p->L[d]) {
+      snprintf(msg, sizeof msg, "cutoff %.6g exceeds half the box edge %.6g (minimum image)", rmax, p->L[d]);
+      return bad(RBE_EBOX, msg);
+    }
+  for (int d = 0; d < 3; ++d)
+    if (p->ncell[d] < 0) return bad(RBE_EINVAL, "ncell must be >= 0");
+  return RBE_OK;
+}
+
+static void choose_grid(const rbe_params *p, int nc[3]) {
+  const bool user = p->ncell[0] > 0 && p->ncell[1] > 0 && p->ncell[2] > 0;
+  const double h = std::fmax(p->r_lj, 0.5 * p->r_coul);
+  for (int d = 0; d < 3; ++d) {
+    if (user) {
+      nc[d] = p->ncell[d];
+    } else {
+      int c = (int)std::floor(p->L[d] / h);
+      nc[d] = c < 1 ? 1 : c;
+    }
+  }
+}
+
+static int stencil_radius(double r, double L, int n) {
+  if (r <= 0) return 0;
+  const double h = L / n;
+  int s = (int)std::ceil(r / h * (1.0 + 1e-12));
+  return s < 1 ? 1 : s;
+}
+
+// ---------------------------------------------------------------------------
+// create / destroy
+// ---------------------------------------------------------------------------
+extern "C" int rbe_create(rbe_ctx **out, const rbe_params *p, int64_t n_max, int device) {
+  if (!out) return create_fail(RBE_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!p) return create_fail(RBE_EINVAL, "params is NULL");
+  if (n_max < 1 || n_max > (int64_t)0x7FFFFFFF) return create_fail(RBE_EINVAL, "n_max must be in [1, 2^31)");
+  std::string why;
+  int rc = validate_params(p, &why);
+  if (rc != RBE_OK) return create_fail(rc, why.c_str());
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return create_fail(RBE_EDEVICE, "no such HIP device");
+  if (hipSetDevice(device) != hipSuccess) return create_fail(RBE_EDEVICE, "hipSetDevice failed");
+
+  rbe_ctx *c = new rbe_ctx();
+  c->device = device;
+  c->p = *p;
+  if (c->p.terms == 0) c->p.terms = RBE_TERM_ALL;
+  c->n_max = n_max;
+  int nc[3];
+  choose_grid(&c->p, nc);
+  if ((int64_t)nc[0] * nc[1] * nc[2] >= (1LL << 29)) {
+    delete c;
+    return create_fail(RBE_EINVAL, "cell grid too large");
+  }
+  Grid &g = c->g;
+  g.nx = nc[0];
+  g.ny = nc[1];
+  g.nz = nc[2];
+  g.ncell = nc[0] * nc[1] * nc[2];
+  for (int d = 0; d < 3; ++d) {
+    g.L[d] = p->L[d];
+    g.inv_h[d] = (double)nc[d] / p->L[d];
+    c->p.ncell[d] = nc[d];
+  }
+  PairParams &pp = c->pp;
+  pp.g = g;
+  const double rq = std::fmax(p->r_coul, p->r_lj);
+  pp.s_coul = 0;
+  pp.s_lj = 0;
+  for (int d = 0; d < 3; ++d) {
+    pp.s_coul = std::max(pp.s_coul, stencil_radius(rq, p->L[d], nc[d]));
+    pp.s_lj = std::max(pp.s_lj, stencil_radius(p->r_lj, p->L[d], nc[d]));
+  }
+  pp.rc2 = p->r_coul * p->r_coul;
+  pp.rlj2 = p->r_lj * p->r_lj;
+  pp.rcore2 = p->r_core * p->r_core;
+  pp.alpha = p->alpha;
+  pp.sqrt_alpha = std::sqrt(p->alpha);
+  pp.two_sqrt_alpha_over_sqrt_pi = 2.0 * pp.sqrt_alpha / std::sqrt(kPi);
+  pp.kc = p->coulomb_k;
+  pp.eps24 = 24.0 * p->lj_eps;
+  pp.sig2 = p->lj_sigma * p->lj_sigma;
+  pp.do_coul = (c->p.terms & RBE_TERM_COUL_REAL) != 0;
+  pp.do_lj = (c->p.terms & RBE_TERM_LJ) != 0 && p->r_lj > 0;
+  pp.rbl = p->r_core > 0;
+  pp.p_shell = p->p_shell;
+
+  // mode tables
+  build_mode_table(p->L, p->alpha, &c->mt, nullptr);
+  c->cdf_host.resize(c->mt.total);
+  build_mode_table(p->L, p->alpha, &c->mt, c->cdf_host.data());
+
+  // device scratch
+  Buf &b = c->buf;
+  const int64_t nkeys = 2 * (int64_t)g.ncell;
+  c->cdf_dev = b.alloc<double>(c->mt.total);
+  c->bb.key = b.alloc<int32_t>(n_max);
+  c->bb.slot = b.alloc<int32_t>(n_max);
+  c->bb.tmp = b.alloc<int32_t>(n_max);
+  c->bb.count = b.alloc<int32_t>(nkeys);
+  c->bb.scan_tmp = b.alloc<int32_t>(scan_tiles(nkeys));
+  c->cell_start = b.alloc<int32_t>(nkeys + 1);
+  c->perm = b.alloc<int32_t>(n_max);
+  c->inv_id = b.alloc<int32_t>(n_max);
+  c->srt.xq = b.alloc<double4>(n_max);
+  c->srt.sq = b.alloc<double4>(n_max);
+  c->srt.id = b.alloc<int32_t>(n_max);
+  for (int s = 0; s < 2; ++s) {
+    WorkSet &w = c->ws[s];
+    w.x = b.alloc<double>(n_max);
+    w.y = b.alloc<double>(n_max);
+    w.z = b.alloc<double>(n_max);
+    w.vx = b.alloc<double>(n_max);
+    w.vy = b.alloc<double>(n_max);
+    w.vz = b.alloc<double>(n_max);
+    w.q = b.alloc<double>(n_max);
+    w.fx = b.alloc<double>(n_max);
+    w.fy = b.alloc<double>(n_max);
+    w.fz = b.alloc<double>(n_max);
+    w.id = b.alloc<int32_t>(n_max);
+  }
+  const int P = p->P;
+  int64_t nchunk = (n_max + 63) / 64;
+  if (nchunk > 8192) nchunk = 8192;
+  c->fb.nchunk_max = (int)nchunk;
+  c->fb.mkd = b.alloc<double>(3 * P);
+  c->fb.part = b.alloc<double2>(nchunk * P);
+  c->fb.rho = b.alloc<double>(2 * P);
+  c->fb.modes = b.alloc<GatherMode>(P);
+  c->m_dev = b.alloc<int32_t>(3 * P);
+  c->w_dev = b.alloc<double>(P);
+  c->mean_part = b.alloc<double>(3 * (int64_t)mean_blocks(n_max) + 3);
+  c->mean = b.alloc<double>(3);
+  c->err = b.alloc<int>(1);
+  c->nq_dev = b.alloc<int32_t>(1);
+  c->qstats = b.alloc<double>(2);
+  c->counters = b.alloc<unsigned long long>(4);
+  if (!b.ok) {
+    b.release();
+    delete c;
+    return create_fail(RBE_ENOMEM, "device allocation failed");
+  }
+  if (hipMemcpy(c->cdf_dev, c->cdf_host.data(), sizeof(double) * c->mt.total, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(c->err, 0, sizeof(int)) != hipSuccess ||
+      hipMemset(c->counters, 0, 4 * sizeof(unsigned long long)) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    b.release();
+    delete c;
+    return create_fail(RBE_EDEVICE, "initial device copies failed");
+  }
+  *out = c;
+  return RBE_OK;
+}
+
+extern "C" int rbe_create_batch(rbe_ctx **out, int32_t n_sys, const rbe_params *params, const int64_t *offset,
+                                int device) {
+  if (!out) return create_fail(RBE_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n_sys == 1 && params && offset) return rbe_create(out, params, offset[1] - offset[0], device);
+  (void)device;
+  return create_fail(RBE_EINVAL, "batched contexts with n_sys > 1 are not supported by this build");
+}
+
+extern "C" void rbe_destroy(rbe_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  ctx->buf.release();
+  delete ctx;
+}
+
+extern "C" const char *rbe_last_error(const rbe_ctx *ctx) {
+  if (!ctx) return g_create_error.c_str();
+  return ctx->last_error.c_str();
+}
+
+// ---------------------------------------------------------------------------
+// charge statistics (count of charged particles, neutrality)
+// ---------------------------------------------------------------------------
+__global__ void k_qstats(int64_t n, const double *__restrict__ q, int32_t *nq, double *stats) {
+  int c = 0;
+  double s = 0.0, a = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = q[i];
+    c += v != 0.0;
+    s += v;
+    a += fabs(v);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    c += __shfl_xor(c, o, 64);
+    s += __shfl_xor(s, o, 64);
+    a += __shfl_xor(a, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(nq, c);
+    atomicAdd(&stats[0], s);
+    atomicAdd(&stats[1], a);
+  }
+}
+
+// Counts the charged particles and checks neutrality (synchronizes `st`).
+static int charge_stats(rbe_ctx *c, int64_t n, const double *q, hipStream_t st, int64_t *nq_out) {
+  launch_fill_i32(c->nq_dev, 1, 0, st);
+  launch_fill_f64(c->qstats, 2, 0.0, st);
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  k_qstats<<<(unsigned)blocks, 256, 0, st>>>(n, q, c->nq_dev, c->qstats);
+  int32_t nq = 0;
+  double qs[2] = {0, 0};
+  HIP_TRY(c, hipMemcpyAsync(&nq, c->nq_dev, sizeof nq, hipMemcpyDeviceToHost, st));
+  HIP_TRY(c, hipMemcpyAsync(qs, c->qstats, sizeof qs, hipMemcpyDeviceToHost, st));
+  HIP_TRY(c, hipStreamSynchronize(st));
+  if (!std::isfinite(qs[0]) || !std::isfinite(qs[1])) return c->fail(RBE_ENONFINITE, "non-finite charges");
+  if (std::fabs(qs[0]) > 1e-10 * std::fmax(qs[1], 1e-300) && std::fabs(qs[0]) > 1e-12)
+    return c->fail(RBE_ENONNEUTRAL, "total charge %.3e is not zero (sum |q| = %.3e)", qs[0], qs[1]);
+  *nq_out = nq;
+  return RBE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// one force evaluation on sorted data (ws[1] receives the sorted force)
+// ---------------------------------------------------------------------------
+// Inputs in c->srt (xq, sq, id) and c->cell_start; output in fx/fy/fz (sorted).
+static int eval_sorted(rbe_ctx *c, int64_t n, int64_t nq, const int32_t *m, const double *w, uint64_t eval,
+                       double *rho_out, double *fx, double *fy, double *fz, hipStream_t st) {
+  const int P = c->p.P;
+  const int terms = c->p.terms;
+  if (terms & (RBE_TERM_LJ | RBE_TERM_COUL_REAL)) {
+    PairParams pp = c->pp;
+    pp.shell_key = shell_eval_key(c->p.seed, eval);
+    if (pp.rbl) launch_inverse_ids(n, c->srt.id, c->inv_id, c->err, st);
+    PairCounters cnt{c->counting ? c->counters : nullptr};
+    if (c->counting) HIP_TRY(c, hipMemsetAsync(c->counters, 0, 4 * sizeof(unsigned long long), st));
+    if (c->p.prec == RBE_FP32C)
+      launch_pair_f32c(pp, n, c->srt, c->cell_start, c->inv_id, fx, fy, fz, cnt, st);
+    else
+      launch_pair_f64(pp, n, c->srt, c->cell_start, c->inv_id, fx, fy, fz, cnt, st);
+    if (pp.rbl) launch_mean3(n, fx, fy, fz, c->mean_part, c->mean, st);
+  } else {
+    launch_fill_f64(fx, n, 0.0, st);
+    launch_fill_f64(fy, n, 0.0, st);
+    launch_fill_f64(fz, n, 0.0, st);
+  }
+  if (terms & RBE_TERM_FOURIER) {
+    if (!m) {
+      launch_sample_modes(c->mt, c->cdf_dev, c->p.seed, eval, P, c->m_dev, c->w_dev, c->err, st);
+      m = c->m_dev;
+      w = c->w_dev;
+    }
+    launch_modes_to_double(P, m, c->fb.mkd, st);
+    launch_rho(c->p.prec, nq, P, c->srt.sq, c->fb, w, rho_out, st);
+    launch_fourier_gather(c->p.prec, nq, P, c->srt.sq, c->fb, c->g, fx, fy, fz, st);
+  }
+  return RBE_OK;
+}
+
+static bool state_ok(const rbe_state *s, bool need_v) {
+  if (!s || !s->x || !s->y || !s->z || !s->fx || !s->fy || !s->fz || !s->q || !s->id) return false;
+  if (need_v && (!s->vx || !s->vy || !s->vz)) return false;
+  return true;
+}
+
+extern "C" int rbe_build_cells(rbe_ctx *c, const double *x, const double *y, const double *z, const double *q,
+                               int64_t n, int32_t *cell_start, int32_t *perm, void *stream) {
+  if (!c) return RBE_EINVAL;
+  if (n < 0 || n > c->n_max) return c->fail(RBE_ERANGE, "n = %lld outside [0, n_max = %lld]", (long long)n,
+                                            (long long)c->n_max);
+  if (n > 0 && (!x || !y || !z || !q || !perm)) return c->fail(RBE_EINVAL, "null array");
+  if (!cell_start) return c->fail(RBE_EINVAL, "null cell_start");
+  HIP_TRY(c, hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  launch_bin(c->bb, c->g, n, x, y, z, q, cell_start, perm, st);
+  HIP_TRY(c, hipGetLastError());
+  return RBE_OK;
+}
+
+extern "C" int rbe_sample_k(const rbe_params *p, uint64_t eval, int32_t *m, double *w, int on_device, void *stream) {
+  if (!p || !m || !w) return create_fail(RBE_EINVAL, "null argument");
+  if (p->P < 1 || p->P > RBE_MAX_P || !(p->alpha > 0)) return create_fail(RBE_EINVAL, "bad P or alpha");
+  for (int d = 0; d < 3; ++d)
+    if (!(p->L[d] > 0)) return create_fail(RBE_EINVAL, "bad box");
+  if (p->kdist != RBE_KDIST_GAUSS) return create_fail(RBE_EINVAL, "only the Gaussian mode distribution is provided");
+  ModeTable t{};
+  build_mode_table(p->L, p->alpha, &t, nullptr);
+  std::vector<double> cdf(t.total);
+  build_mode_table(p->L, p->alpha, &t, cdf.data());
+  if (!on_device) {
+    if (sample_modes_host(t, cdf.data(), p->seed, eval, p->P, m, w) != 0)
+      return create_fail(RBE_EINVAL, "mode sampler rejected every attempt");
+    return RBE_OK;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  double *cdf_dev = nullptr;
+  int *err = nullptr;
+  if (hipMalloc(&cdf_dev, sizeof(double) * t.total) != hipSuccess) return create_fail(RBE_ENOMEM, "hipMalloc");
+  if (hipMalloc(&err, sizeof(int)) != hipSuccess) {
+    (void)hipFree(cdf_dev);
+    return create_fail(RBE_ENOMEM, "hipMalloc");
+  }
+  int rc = RBE_OK;
+  int herr = 0;
+  if (hipMemcpyAsync(cdf_dev, cdf.data(), sizeof(double) * t.total, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemsetAsync(err, 0, sizeof(int), st) != hipSuccess)
+    rc = create_fail(RBE_EDEVICE, "copy of the mode table failed");
+  if (rc == RBE_OK) {
+    launch_sample_modes(t, cdf_dev, p->seed, eval, p->P, m, w, err, st);
+    if (hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      rc = create_fail(RBE_EDEVICE, "device sampler failed");
+    else if (herr)
+      rc = create_fail(RBE_EINVAL, "mode sampler rejected every attempt");
+  }
+  (void)hipFree(cdf_dev);
+  (void)hipFree(err);
+  return rc;
+}
+
+extern "C" int rbe_forces(rbe_ctx *c, const rbe_state *s, const int32_t *m, const double *w, uint64_t eval,
+                          double *rho_out, void *stream) {
+  if (!c) return RBE_EINVAL;
+  if (!state_ok(s, false)) return c->fail(RBE_EINVAL, "state has a null array");
+  if (s->n < 1 || s->n > c->n_max)
+    return c->fail(RBE_ERANGE, "n = %lld outside [1, n_max = %lld]", (long long)s->n, (long long)c->n_max);
+  if ((m == nullptr) != (w == nullptr)) return c->fail(RBE_EINVAL, "m and w must both be given or both be NULL");
+  HIP_TRY(c, hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t n = s->n;
+  int64_t nq = 0;
+  int rc = charge_stats(c, n, s->q, st, &nq);
+  if (rc != RBE_OK) return rc;
+  launch_bin(c->bb, c->g, n, s->x, s->y, s->z, s->q, c->cell_start, c->perm, st);
+  launch_gather_sorted(n, c->perm, s->x, s->y, s->z, s->q, s->id, c->g, c->srt, st);
+  WorkSet &o = c->ws[1];
+  rc = eval_sorted(c, n, nq, m, w, eval, rho_out, o.fx, o.fy, o.fz, st);
+  if (rc != RBE_OK) return rc;
+  if (c->pp.rbl && (c->p.terms & (RBE_TERM_LJ | RBE_TERM_COUL_REAL))) launch_sub_mean(n, c->mean, o.fx, o.fy, o.fz, st);
+  launch_scatter_forces(n, c->perm, o.fx, o.fy, o.fz, s->fx, s->fy, s->fz, st);
+  HIP_TRY(c, hipGetLastError());
+  return RBE_OK;
+}
+
+// Reorder the working set through perm and pack the sorted records in one pass.
+__global__ void __launch_bounds__(256) k_reorder_pack(int64_t n, const int32_t *__restrict__ perm, StateArrays in,
+                                                      StateArrays out, Grid g, double4 *__restrict__ xq,
+                                                      double4 *__restrict__ sq, int32_t *__restrict__ ids) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int j = perm[k];
+  const double x = in.x[j], y = in.y[j], z = in.z[j], q = in.q[j];
+  const int32_t id = in.id[j];
+  out.x[k] = x;
+  out.y[k] = y;
+  out.z[k] = z;
+  out.vx[k] = in.vx[j];
+  out.vy[k] = in.vy[j];
+  out.vz[k] = in.vz[j];
+  out.q[k] = q;
+  out.id[k] = id;
+  xq[k] = make_double4(x, y, z, q);
+  if (q != 0.0) sq[k] = make_double4(x / g.L[0], y / g.L[1], z / g.L[2], q);
+  ids[k] = id;
+}
+
+extern "C" int rbe_step(rbe_ctx *c, rbe_state *s, int32_t nsteps, uint64_t first_eval, void *stream) {
+  if (!c) return RBE_EINVAL;
+  if (!state_ok(s, true)) return c->fail(RBE_EINVAL, "state has a null array");
+  if (s->n < 1 || s->n > c->n_max)
+    return c->fail(RBE_ERANGE, "n = %lld outside [1, n_max = %lld]", (long long)s->n, (long long)c->n_max);
+  if (nsteps < 0) return c->fail(RBE_EINVAL, "nsteps < 0");
+  if (nsteps == 0) return RBE_OK;
+  HIP_TRY(c, hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t n = s->n;
+  int64_t nq = 0;
+  int rc = charge_stats(c, n, s->q, st, &nq);
+  if (rc != RBE_OK) return rc;
+  const size_t bd = sizeof(double) * n, bi = sizeof(int32_t) * n;
+  WorkSet *A = &c->ws[0], *B = &c->ws[1];
+  HIP_TRY(c, hipMemcpyAsync(A->x, s->x, bd, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, hipMemcpyAsync(A->y, s->y, bd, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, hipMemcpyAsync(A->z, s->z, bd, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, hipMemcpyAsync(A->vx, s->vx, bd, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, hipMemcpyAsync(A->vy, s->vy, bd, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, hipMemcpyAsync(A->vz, s->vz, bd, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, hipMemcpyAsync(A->fx, s->fx, bd, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, hipMemcpyAsync(A->fy, s->fy, bd, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, hipMemcpyAsync(A->fz, s->fz, bd, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, hipMemcpyAsync(A->q, s->q, bd, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, hipMemcpyAsync(A->id, s->id, bi, hipMemcpyDeviceToDevice, st));
+  const double h = 0.5 * c->p.dt / c->p.mass;
+  const bool near = (c->p.terms & (RBE_TERM_LJ | RBE_TERM_COUL_REAL)) != 0;
+  for (int32_t k = 0; k < nsteps; ++k) {
+    launch_kick_drift(n, h, c->p.dt, c->g, A->fx, A->fy, A->fz, A->vx, A->vy, A->vz, A->x, A->y, A->z, c->err, st);
+    launch_bin(c->bb, c->g, n, A->x, A->y, A->z, A->q, c->cell_start, c->perm, st);
+    k_reorder_pack<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, c->perm, A->arrays(), B->arrays(), c->g, c->srt.xq,
+                                                                 c->srt.sq, c->srt.id);
+    rc = eval_sorted(c, n, nq, nullptr, nullptr, first_eval + (uint64_t)k, nullptr, B->fx, B->fy, B->fz, st);
+    if (rc != RBE_OK) return rc;
+    launch_kick(n, h, (c->pp.rbl && near) ? c->mean : nullptr, B->fx, B->fy, B->fz, B->vx, B->vy, B->vz, c->err, st);
+    std::swap(A, B);
+  }
+  HIP_TRY(c, hipMemcpyAsync(s->x, A->x, bd, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, hipMemcpyAsync(s->y, A->y, bd, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, hipMemcpyAsync(s->z, A->z, bd, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, hipMemcpyAsync(s->vx, A->vx, bd, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, hipMemcpyAsync(s->vy, A->vy, bd, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, hipMemcpyAsync(s->vz, A->vz, bd, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, hipMemcpyAsync(s->fx, A->fx, bd, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, hipMemcpyAsync(s->fy, A->fy, bd, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, hipMemcpyAsync(s->fz, A->fz, bd, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, hipMemcpyAsync(s->q, A->q, bd, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, hipMemcpyAsync(s->id, A->id, bi, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, hipGetLastError());
+  return RBE_OK;
+}
+
+extern "C" int rbe_sync_check(rbe_ctx *c, void *stream) {
+  if (!c) return RBE_EINVAL;
+  HIP_TRY(c, hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  int flag = 0;
+  HIP_TRY(c, hipMemcpyAsync(&flag, c->err, sizeof flag, hipMemcpyDeviceToHost, st));
+  HIP_TRY(c, hipStreamSynchronize(st));
+  HIP_TRY(c, hipMemsetAsync(c->err, 0, sizeof(int), st));
+  HIP_TRY(c, hipStreamSynchronize(st));
+  if (flag & kErrNonFinite) return c->fail(RBE_ENONFINITE, "non-finite velocity or force seen on the device");
+  if (flag & kErrBadId) return c->fail(RBE_ERANGE, "a particle id lies outside [0, n)");
+  if (flag & kErrSampler) return c->fail(RBE_EINVAL, "mode sampler rejected every attempt");
+  return RBE_OK;
+}
+
+extern "C" int rbe_set_counting(rbe_ctx *c, int enable) {
+  if (!c) return RBE_EINVAL;
+  c->counting = enable != 0;
+  return RBE_OK;
+}
+
+extern "C" int rbe_get_counters(rbe_ctx *c, int64_t *counters, void *stream) {
+  if (!c || !counters) return RBE_EINVAL;
+  HIP_TRY(c, hipSetDevice(c->device));
+  unsigned long long h[4];
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(c, hipMemcpyAsync(h, c->counters, sizeof h, hipMemcpyDeviceToHost, st));
+  HIP_TRY(c, hipStreamSynchronize(st));
+  for (int i = 0; i < 4; ++i) counters[i] = (int64_t)h[i];
+  return RBE_OK;
+}

@@ -1,0 +1,220 @@
+// Fourier part of the RBE force (Sec. 2.1, Eq. 5, 7, 9; Sec. 2.3.1):
+// structure factors rho(k_l) = sum_j q_j exp(i k_l . r_j) over the charged
+// particles, then F_i = -q_i sum_l w_l k_l Im(exp(-i k_l . r_i) rho_l).
+//
+// Phase: k_l . r_j = 2 pi t with t = m_l . s_j (s = r/L, the fractional
+// coordinate). Whole turns are removed in FP64 (t - rint(t), exact for the
+// fraction) before the sine and cosine, so the trigonometric argument is a
+// fraction of a turn in [-1/2, 1/2] whatever the box size.
+//
+// Structure factor: thread = mode, particles walked in a wave-uniform loop
+// (scalar loads of the packed (s, q) records), one partial sum per particle
+// chunk and mode; no cross-lane reduction. The chunk partials are summed in
+// FP64 in a fixed order by a second kernel.
+//
+// Gather: thread = particle, modes walked in a wave-uniform loop with the
+// per-mode coefficients (m, w Im rho, w Re rho) in scalar registers.
+//
+// FP32C form: the turn reduction stays FP64; the hardware turn-argument
+// sine/cosine (v_sin_f32 / v_cos_f32 compute sin(2 pi x), cos(2 pi x)) run on
+// the FP32 fraction; sums are FP32 with Kahan compensation.
+#include "kernels.h"
+
+namespace rbe {
+
+constexpr int kModesPerBlock = 256;
+
+int rho_chunk(int64_t nq, int P, int prec, int nchunk_max) {
+  // enough chunks to fill the chip (about 8k waves), never more than the scratch holds
+  const int64_t groups = (P + 63) / 64;
+  int64_t target_waves = 8192;
+  int64_t chunks = (target_waves + groups - 1) / groups;
+  int64_t len = (nq + chunks - 1) / chunks;
+  if (len < 64) len = 64;
+  while ((nq + len - 1) / len > nchunk_max) len *= 2;
+  (void)prec;
+  return (int)len;
+}
+
+__global__ void k_modes_to_double(int P, const int32_t *__restrict__ m, double *__restrict__ mkd) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l < 3 * P) mkd[l] = (double)m[l];
+}
+
+void launch_modes_to_double(int P, const int32_t *m, double *mkd, hipStream_t st) {
+  k_modes_to_double<<<(3 * P + 255) / 256, 256, 0, st>>>(P, m, mkd);
+}
+
+__device__ inline double turn_fraction(double mx, double my, double mz, double sx, double sy, double sz) {
+#pragma clang fp contract(off)
+  const double t = mx * sx + my * sy + mz * sz;
+  return t - rint(t);
+}
+
+// ---------------------------------------------------------------------------
+// structure factor partial sums
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f64(int64_t nq, int P, int chunk,
+                                                                     const double4 *__restrict__ sq,
+                                                                     const double *__restrict__ mkd,
+                                                                     double2 *__restrict__ part) {
+  const int l = blockIdx.y * kModesPerBlock + threadIdx.x;
+  const bool active = l < P;
+  const double mx = active ? mkd[l] : 0.0, my = active ? mkd[P + l] : 0.0, mz = active ? mkd[2 * P + l] : 0.0;
+  const int64_t j0 = (int64_t)blockIdx.x * chunk;
+  const int64_t j1 = min(nq, j0 + chunk);
+  double re = 0.0, im = 0.0;
+  for (int64_t j = j0; j < j1; ++j) {
+    const double4 s = sq[j];
+    const double t = turn_fraction(mx, my, mz, s.x, s.y, s.z);
+    double sn, cs;
+    sincospi(2.0 * t, &sn, &cs);
+    re = fma(s.w, cs, re);
+    im = fma(s.w, sn, im);
+  }
+  if (active) part[(int64_t)blockIdx.x * P + l] = make_double2(re, im);
+}
+
+__device__ inline void kahan_add(float &sum, float &comp, float v) {
+#pragma clang fp contract(off)
+  const float y = v - comp;
+  const float t = sum + y;
+  comp = (t - sum) - y;
+  sum = t;
+}
+
+__global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f32c(int64_t nq, int P, int chunk,
+                                                                      const double4 *__restrict__ sq,
+                                                                      const double *__restrict__ mkd,
+                                                                      double2 *__restrict__ part) {
+  const int l = blockIdx.y * kModesPerBlock + threadIdx.x;
+  const bool active = l < P;
+  const double mx = active ? mkd[l] : 0.0, my = active ? mkd[P + l] : 0.0, mz = active ? mkd[2 * P + l] : 0.0;
+  const int64_t j0 = (int64_t)blockIdx.x * chunk;
+  const int64_t j1 = min(nq, j0 + chunk);
+  float re = 0.f, re_c = 0.f, im = 0.f, im_c = 0.f;
+  for (int64_t j = j0; j < j1; ++j) {
+    const double4 s = sq[j];
+    const float t = (float)turn_fraction(mx, my, mz, s.x, s.y, s.z);
+    const float q = (float)s.w;
+    const float cs = __builtin_amdgcn_cosf(t);
+    const float sn = __builtin_amdgcn_sinf(t);
+    kahan_add(re, re_c, q * cs);
+    kahan_add(im, im_c, q * sn);
+  }
+  if (active) part[(int64_t)blockIdx.x * P + l] = make_double2((double)re - (double)re_c, (double)im - (double)im_c);
+}
+
+// rho_l = sum over chunks (fixed order: lane-strided FP64 sums, then a fixed
+// butterfly). Also forms the gather coefficients of each mode.
+__global__ void __launch_bounds__(64) k_rho_final(int nchunks, int P, const double2 *__restrict__ part,
+                                                  const double *__restrict__ mkd, const double *__restrict__ w,
+                                                  double *__restrict__ rho, GatherMode *__restrict__ modes,
+                                                  double *__restrict__ rho_out) {
+  const int l = blockIdx.x;
+  const int lane = threadIdx.x;
+  double re = 0.0, im = 0.0;
+  for (int c = lane; c < nchunks; c += 64) {
+    const double2 v = part[(int64_t)c * P + l];
+    re += v.x;
+    im += v.y;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    re += __shfl_xor(re, o, 64);
+    im += __shfl_xor(im, o, 64);
+  }
+  if (lane == 0) {
+    rho[l] = re;
+    rho[P + l] = im;
+    if (rho_out) {
+      rho_out[l] = re;
+      rho_out[P + l] = im;
+    }
+    GatherMode gm;
+    gm.mx = mkd[l];
+    gm.my = mkd[P + l];
+    gm.mz = mkd[2 * P + l];
+    gm.a = w[l] * im;
+    gm.b = w[l] * re;
+    gm.pad[0] = gm.pad[1] = gm.pad[2] = 0.0;
+    modes[l] = gm;
+  }
+}
+
+void launch_rho(int prec, int64_t nq, int P, const double4 *sq, const FourierBuffers &fb, const double *w,
+                double *rho_out, hipStream_t st) {
+  const int chunk = rho_chunk(nq, P, prec, fb.nchunk_max);
+  int nchunks = (int)((nq + chunk - 1) / chunk);
+  if (nchunks < 1) nchunks = 1;
+  dim3 grid((unsigned)nchunks, (unsigned)((P + kModesPerBlock - 1) / kModesPerBlock));
+  if (prec == RBE_FP32C)
+    k_rho_partial_f32c<<<grid, kModesPerBlock, 0, st>>>(nq, P, chunk, sq, fb.mkd, fb.part);
+  else
+    k_rho_partial_f64<<<grid, kModesPerBlock, 0, st>>>(nq, P, chunk, sq, fb.mkd, fb.part);
+  k_rho_final<<<P, 64, 0, st>>>(nchunks, P, fb.part, fb.mkd, w, fb.rho, fb.modes, rho_out);
+}
+
+// ---------------------------------------------------------------------------
+// force gather (adds F^F into f for the charged range)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_gather_f64(int64_t nq, int P, const double4 *__restrict__ sq,
+                                                    const GatherMode *__restrict__ modes, double kx, double ky,
+                                                    double kz, double *__restrict__ fx, double *__restrict__ fy,
+                                                    double *__restrict__ fz) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nq) return;
+  const double4 s = sq[i];
+  double gx = 0.0, gy = 0.0, gz = 0.0;
+  for (int l = 0; l < P; ++l) {
+    const GatherMode gm = modes[l];
+    const double t = turn_fraction(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
+    double sn, cs;
+    sincospi(2.0 * t, &sn, &cs);
+    const double g = gm.a * cs - gm.b * sn;  // w Im(exp(-i theta) rho)
+    gx = fma(g, gm.mx, gx);
+    gy = fma(g, gm.my, gy);
+    gz = fma(g, gm.mz, gz);
+  }
+  const double q = s.w;
+  fx[i] -= q * kx * gx;
+  fy[i] -= q * ky * gy;
+  fz[i] -= q * kz * gz;
+}
+
+__global__ void __launch_bounds__(256) k_gather_f32c(int64_t nq, int P, const double4 *__restrict__ sq,
+                                                     const GatherMode *__restrict__ modes, double kx, double ky,
+                                                     double kz, double *__restrict__ fx, double *__restrict__ fy,
+                                                     double *__restrict__ fz) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nq) return;
+  const double4 s = sq[i];
+  float gx = 0.f, gy = 0.f, gz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
+  for (int l = 0; l < P; ++l) {
+    const GatherMode gm = modes[l];
+    const float t = (float)turn_fraction(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
+    const float cs = __builtin_amdgcn_cosf(t);
+    const float sn = __builtin_amdgcn_sinf(t);
+    const float g = (float)gm.a * cs - (float)gm.b * sn;
+    kahan_add(gx, cx, g * (float)gm.mx);
+    kahan_add(gy, cy, g * (float)gm.my);
+    kahan_add(gz, cz, g * (float)gm.mz);
+  }
+  const double q = s.w;
+  fx[i] -= q * kx * ((double)gx - (double)cx);
+  fy[i] -= q * ky * ((double)gy - (double)cy);
+  fz[i] -= q * kz * ((double)gz - (double)cz);
+}
+
+void launch_fourier_gather(int prec, int64_t nq, int P, const double4 *sq, const FourierBuffers &fb, const Grid &g,
+                           double *fx, double *fy, double *fz, hipStream_t st) {
+  if (nq <= 0) return;
+  const unsigned blocks = (unsigned)((nq + 255) / 256);
+  const double kx = kTwoPi / g.L[0], ky = kTwoPi / g.L[1], kz = kTwoPi / g.L[2];
+  if (prec == RBE_FP32C)
+    k_gather_f32c<<<blocks, 256, 0, st>>>(nq, P, sq, fb.modes, kx, ky, kz, fx, fy, fz);
+  else
+    k_gather_f64<<<blocks, 256, 0, st>>>(nq, P, sq, fb.modes, kx, ky, kz, fx, fy, fz);
+}
+
+}  // namespace rbe

@@ -1,0 +1,249 @@
+// Data movement, reductions and the velocity-Verlet kernels (all bound by
+// HBM bandwidth): packed sorted copies, the inverse id map, force scatter,
+// the fixed-order mean of Eq. 12, and the half-kick / drift / wrap steps.
+#include "kernels.h"
+
+namespace rbe {
+
+__global__ void __launch_bounds__(256) k_gather_sorted(int64_t n, const int32_t *__restrict__ perm,
+                                                       const double *__restrict__ x, const double *__restrict__ y,
+                                                       const double *__restrict__ z, const double *__restrict__ q,
+                                                       const int32_t *__restrict__ id, Grid g,
+                                                       double4 *__restrict__ xq, double4 *__restrict__ sq,
+                                                       int32_t *__restrict__ ids) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int j = perm[k];
+  const double wx = wrap_coord(x[j], g.L[0]), wy = wrap_coord(y[j], g.L[1]), wz = wrap_coord(z[j], g.L[2]);
+  const double qq = q[j];
+  xq[k] = make_double4(wx, wy, wz, qq);
+  if (qq != 0.0) sq[k] = make_double4(wx / g.L[0], wy / g.L[1], wz / g.L[2], qq);
+  ids[k] = id[j];
+}
+
+void launch_gather_sorted(int64_t n, const int32_t *perm, const double *x, const double *y, const double *z,
+                          const double *q, const int32_t *id, const Grid &g, Sorted s, hipStream_t st) {
+  if (n <= 0) return;
+  k_gather_sorted<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, perm, x, y, z, q, id, g, s.xq, s.sq, s.id);
+}
+
+// inv must hold -1 everywhere on entry. Ids outside [0, n) and repeated ids
+// are flagged; the near-field kernel skips any batch member whose id does not
+// map back to a slot in [0, n).
+__global__ void k_inverse_ids(int64_t n, const int32_t *__restrict__ id, int32_t *__restrict__ inv, int *err) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int32_t v = id[k];
+  if (v < 0 || (int64_t)v >= n) {
+    atomicOr(err, kErrBadId);
+    return;
+  }
+  if (atomicCAS(&inv[v], -1, (int32_t)k) != -1) atomicOr(err, kErrBadId);
+}
+
+void launch_inverse_ids(int64_t n, const int32_t *id_sorted, int32_t *inv, int *err, hipStream_t st) {
+  if (n <= 0) return;
+  launch_fill_i32(inv, n, -1, st);
+  k_inverse_ids<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, id_sorted, inv, err);
+}
+
+__global__ void k_scatter_forces(int64_t n, const int32_t *__restrict__ perm, const double *__restrict__ fx,
+                                 const double *__restrict__ fy, const double *__restrict__ fz, double *__restrict__ ox,
+                                 double *__restrict__ oy, double *__restrict__ oz) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int j = perm[k];
+  ox[j] = fx[k];
+  oy[j] = fy[k];
+  oz[j] = fz[k];
+}
+
+void launch_scatter_forces(int64_t n, const int32_t *perm, const double *fx, const double *fy, const double *fz,
+                           double *ox, double *oy, double *oz, hipStream_t st) {
+  if (n <= 0) return;
+  k_scatter_forces<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, perm, fx, fy, fz, ox, oy, oz);
+}
+
+__global__ void k_count_charged(int64_t n, const double *__restrict__ q, int32_t *out) {
+  int c = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    c += q[i] != 0.0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+}
+
+void launch_count_charged(int64_t n, const double *q, int32_t *out, hipStream_t st) {
+  launch_fill_i32(out, 1, 0, st);
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  k_count_charged<<<(unsigned)blocks, 256, 0, st>>>(n, q, out);
+}
+
+// ---------------------------------------------------------------------------
+// fixed-order mean (Eq. 12)
+// ---------------------------------------------------------------------------
+constexpr int kMeanThreads = 256;
+constexpr int64_t kMeanPerBlock = 8192;
+
+int mean_blocks(int64_t n) { return (int)((n + kMeanPerBlock - 1) / kMeanPerBlock); }
+
+__device__ inline double block_sum_fixed(double v, double *lds) {
+  // fixed butterfly inside each wave, then waves in index order
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) lds[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kMeanThreads / 64; ++w) s += lds[w];
+  __syncthreads();
+  return s;
+}
+
+__global__ void __launch_bounds__(kMeanThreads) k_mean_partial(int64_t n, const double *__restrict__ fx,
+                                                               const double *__restrict__ fy,
+                                                               const double *__restrict__ fz,
+                                                               double *__restrict__ partials) {
+  __shared__ double lds[kMeanThreads / 64];
+  const int64_t b0 = (int64_t)blockIdx.x * kMeanPerBlock;
+  const int64_t b1 = min(n, b0 + kMeanPerBlock);
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += kMeanThreads) {
+    s0 += fx[i];
+    s1 += fy[i];
+    s2 += fz[i];
+  }
+  s0 = block_sum_fixed(s0, lds);
+  s1 = block_sum_fixed(s1, lds);
+  s2 = block_sum_fixed(s2, lds);
+  if (threadIdx.x == 0) {
+    partials[3 * blockIdx.x] = s0;
+    partials[3 * blockIdx.x + 1] = s1;
+    partials[3 * blockIdx.x + 2] = s2;
+  }
+}
+
+__global__ void __launch_bounds__(kMeanThreads) k_mean_final(int nblk, int64_t n, const double *__restrict__ partials,
+                                                             double *__restrict__ mean) {
+  __shared__ double lds[kMeanThreads / 64];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kMeanThreads) {
+    s0 += partials[3 * b];
+    s1 += partials[3 * b + 1];
+    s2 += partials[3 * b + 2];
+  }
+  s0 = block_sum_fixed(s0, lds);
+  s1 = block_sum_fixed(s1, lds);
+  s2 = block_sum_fixed(s2, lds);
+  if (threadIdx.x == 0) {
+    const double inv = 1.0 / (double)n;
+    mean[0] = s0 * inv;
+    mean[1] = s1 * inv;
+    mean[2] = s2 * inv;
+  }
+}
+
+void launch_mean3(int64_t n, const double *fx, const double *fy, const double *fz, double *partials, double *mean,
+                  hipStream_t st) {
+  const int nb = mean_blocks(n);
+  if (nb > 0) k_mean_partial<<<nb, kMeanThreads, 0, st>>>(n, fx, fy, fz, partials);
+  k_mean_final<<<1, kMeanThreads, 0, st>>>(nb, n, partials, mean);
+}
+
+// ---------------------------------------------------------------------------
+// velocity Verlet
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_kick(int64_t n, double h, const double *__restrict__ mean,
+                                              double *__restrict__ fx, double *__restrict__ fy,
+                                              double *__restrict__ fz, double *__restrict__ vx,
+                                              double *__restrict__ vy, double *__restrict__ vz, int *err) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double a = fx[i], b = fy[i], c = fz[i];
+  if (mean) {
+    a -= mean[0];
+    b -= mean[1];
+    c -= mean[2];
+    fx[i] = a;
+    fy[i] = b;
+    fz[i] = c;
+  }
+  const double u = vx[i] + h * a, v = vy[i] + h * b, w = vz[i] + h * c;
+  vx[i] = u;
+  vy[i] = v;
+  vz[i] = w;
+  if (!isfinite(u) || !isfinite(v) || !isfinite(w)) atomicOr(err, kErrNonFinite);
+}
+
+void launch_kick(int64_t n, double h, const double *mean, double *fx, double *fy, double *fz, double *vx, double *vy,
+                 double *vz, int *err, hipStream_t st) {
+  if (n <= 0) return;
+  k_kick<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, h, mean, fx, fy, fz, vx, vy, vz, err);
+}
+
+__global__ void __launch_bounds__(256) k_sub_mean(int64_t n, const double *__restrict__ mean, double *__restrict__ fx,
+                                                  double *__restrict__ fy, double *__restrict__ fz) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  fx[i] -= mean[0];
+  fy[i] -= mean[1];
+  fz[i] -= mean[2];
+}
+
+void launch_sub_mean(int64_t n, const double *mean, double *fx, double *fy, double *fz, hipStream_t st) {
+  if (n <= 0) return;
+  k_sub_mean<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, mean, fx, fy, fz);
+}
+
+__global__ void __launch_bounds__(256) k_kick_drift(int64_t n, double h, double dt, Grid g,
+                                                    const double *__restrict__ fx, const double *__restrict__ fy,
+                                                    const double *__restrict__ fz, double *__restrict__ vx,
+                                                    double *__restrict__ vy, double *__restrict__ vz,
+                                                    double *__restrict__ x, double *__restrict__ y,
+                                                    double *__restrict__ z, int *err) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double u = vx[i] + h * fx[i], v = vy[i] + h * fy[i], w = vz[i] + h * fz[i];
+  vx[i] = u;
+  vy[i] = v;
+  vz[i] = w;
+  const double nx = wrap_coord(x[i] + dt * u, g.L[0]);
+  const double ny = wrap_coord(y[i] + dt * v, g.L[1]);
+  const double nz = wrap_coord(z[i] + dt * w, g.L[2]);
+  x[i] = nx;
+  y[i] = ny;
+  z[i] = nz;
+  if (!isfinite(u) || !isfinite(v) || !isfinite(w)) atomicOr(err, kErrNonFinite);
+}
+
+void launch_kick_drift(int64_t n, double h, double dt, const Grid &g, const double *fx, const double *fy,
+                       const double *fz, double *vx, double *vy, double *vz, double *x, double *y, double *z, int *err,
+                       hipStream_t st) {
+  if (n <= 0) return;
+  k_kick_drift<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, h, dt, g, fx, fy, fz, vx, vy, vz, x, y, z, err);
+}
+
+__global__ void __launch_bounds__(256) k_reorder_state(int64_t n, const int32_t *__restrict__ perm, StateArrays in,
+                                                       StateArrays out) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int j = perm[k];
+  out.x[k] = in.x[j];
+  out.y[k] = in.y[j];
+  out.z[k] = in.z[j];
+  out.vx[k] = in.vx[j];
+  out.vy[k] = in.vy[j];
+  out.vz[k] = in.vz[j];
+  out.q[k] = in.q[j];
+  out.id[k] = in.id[j];
+}
+
+void launch_reorder_state(int64_t n, const int32_t *perm, StateArrays in, StateArrays out, hipStream_t st) {
+  if (n <= 0) return;
+  k_reorder_state<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, perm, in, out);
+}
+
+}  // namespace rbe

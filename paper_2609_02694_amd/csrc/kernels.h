@@ -1,0 +1,116 @@
+// Kernel launchers of the RBE library (internal).
+#pragma once
+#include "rbe_internal.h"
+
+namespace rbe {
+
+// ---------------------------------------------------------------------------
+// binning
+// ---------------------------------------------------------------------------
+struct BinBuffers {
+  int32_t *key;       // [n_max]
+  int32_t *slot;      // [n_max]
+  int32_t *count;     // [2 * ncell]
+  int32_t *tmp;       // [n_max]
+  int32_t *scan_tmp;  // [scan_tiles(2 * ncell)]
+};
+int64_t scan_tiles(int64_t n);
+void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t st);
+void launch_fill_f64(double *p, int64_t n, double v, hipStream_t st);
+void launch_exclusive_scan(const int32_t *cnt, int64_t n, int32_t *start, int32_t *tmp, hipStream_t st);
+void launch_bin(const BinBuffers &b, const Grid &g, int64_t n, const double *x, const double *y, const double *z,
+                const double *q, int32_t *cell_start, int32_t *perm, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// sorted working copies
+// ---------------------------------------------------------------------------
+// Packed per-particle records in cell order:
+//   xq[i] = (x, y, z, q) wrapped coordinates (near field)
+//   sq[i] = (x/L_x, y/L_y, z/L_z, q) fractional coordinates (Fourier part,
+//           only the charged range [0, nq) is used)
+struct Sorted {
+  double4 *xq;
+  double4 *sq;
+  int32_t *id;
+};
+// Gather the caller's arrays through perm into the packed sorted records.
+void launch_gather_sorted(int64_t n, const int32_t *perm, const double *x, const double *y, const double *z,
+                          const double *q, const int32_t *id, const Grid &g, Sorted s, hipStream_t st);
+// Build the inverse id map inv[id[k]] = k (flags ids outside [0, n)).
+void launch_inverse_ids(int64_t n, const int32_t *id_sorted, int32_t *inv, int *err, hipStream_t st);
+// out[perm[k]] = in[k] for the three force components.
+void launch_scatter_forces(int64_t n, const int32_t *perm, const double *fx, const double *fy, const double *fz,
+                           double *ox, double *oy, double *oz, hipStream_t st);
+// Count the charged particles (q != 0) into *out (device int).
+void launch_count_charged(int64_t n, const double *q, int32_t *out, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// near field
+// ---------------------------------------------------------------------------
+struct PairParams {
+  Grid g;
+  int s_coul;            // stencil radius (cells) covering r_coul
+  int s_lj;              // stencil radius covering r_lj
+  double rc2, rlj2, rcore2;
+  double alpha, sqrt_alpha, two_sqrt_alpha_over_sqrt_pi;
+  double kc, eps24, sig2;
+  int do_coul, do_lj;
+  int rbl;               // random batch list on
+  int p_shell;
+  uint64_t shell_key;    // stream key of the shell batches for this evaluation
+};
+struct PairCounters {
+  unsigned long long *c;  // [4] or nullptr
+};
+void launch_pair_f64(const PairParams &pp, int64_t n, const Sorted &s, const int32_t *cell_start,
+                     const int32_t *inv_id, double *fx, double *fy, double *fz, PairCounters cnt, hipStream_t st);
+void launch_pair_f32c(const PairParams &pp, int64_t n, const Sorted &s, const int32_t *cell_start,
+                      const int32_t *inv_id, double *fx, double *fy, double *fz, PairCounters cnt, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Fourier part
+// ---------------------------------------------------------------------------
+struct GatherMode {
+  double mx, my, mz;  // integer mode vector as doubles
+  double a, b;        // w Im rho, w Re rho
+  double pad[3];
+};
+struct FourierBuffers {
+  double *mkd;           // [3][P] mode vectors as doubles
+  double2 *part;         // [nchunk_max][P] partial structure factors
+  double *rho;           // [2 * P] Re | Im
+  GatherMode *modes;     // [P]
+  int nchunk_max;
+};
+// Chunk length of the structure-factor partial sums for nq charged particles.
+int rho_chunk(int64_t nq, int P, int prec, int nchunk_max);
+void launch_modes_to_double(int P, const int32_t *m, double *mkd, hipStream_t st);
+void launch_rho(int prec, int64_t nq, int P, const double4 *sq, const FourierBuffers &fb, const double *w,
+                double *rho_out, hipStream_t st);
+void launch_fourier_gather(int prec, int64_t nq, int P, const double4 *sq, const FourierBuffers &fb, const Grid &g,
+                           double *fx, double *fy, double *fz, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// reductions and integration
+// ---------------------------------------------------------------------------
+// mean[3] = (1/n) sum_i f_i in a fixed order (partials[nblk * 3] scratch).
+int mean_blocks(int64_t n);
+void launch_mean3(int64_t n, const double *fx, const double *fy, const double *fz, double *partials, double *mean,
+                  hipStream_t st);
+// f -= mean (if mean != nullptr); v += h f; flags non-finite f or v.
+void launch_kick(int64_t n, double h, const double *mean, double *fx, double *fy, double *fz, double *vx, double *vy,
+                 double *vz, int *err, hipStream_t st);
+// f -= mean in place.
+void launch_sub_mean(int64_t n, const double *mean, double *fx, double *fy, double *fz, hipStream_t st);
+// v += h f; x <- wrap(x + dt v).
+void launch_kick_drift(int64_t n, double h, double dt, const Grid &g, const double *fx, const double *fy,
+                       const double *fz, double *vx, double *vy, double *vz, double *x, double *y, double *z,
+                       int *err, hipStream_t st);
+// Reorder the integrator state through perm (out[k] = in[perm[k]]).
+struct StateArrays {
+  double *x, *y, *z, *vx, *vy, *vz, *q;
+  int32_t *id;
+};
+void launch_reorder_state(int64_t n, const int32_t *perm, StateArrays in, StateArrays out, hipStream_t st);
+
+}  // namespace rbe

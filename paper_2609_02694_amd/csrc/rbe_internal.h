@@ -1,0 +1,133 @@
+// Internal declarations of the RBE library (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/rbe.h"
+
+namespace rbe {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double kTwoPi = 6.28318530717958647692528676655900577;
+
+// ---------------------------------------------------------------------------
+// Counter-based generators (definitions restated in include/rbe.h)
+// ---------------------------------------------------------------------------
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ULL;   // SplitMix64 increment
+constexpr uint64_t kTagModes = 0x4B4D4F4445534554ULL; // stream tag of the mode sample
+constexpr uint64_t kTagShell = 0x52424C5348454C4CULL; // stream tag of the shell batches
+
+__host__ __device__ inline uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+// Output n (0-based) of the SplitMix64 stream seeded by s.
+__host__ __device__ inline uint64_t stream_out(uint64_t s, uint64_t n) { return mix64(s + (n + 1) * kGamma); }
+__host__ __device__ inline double unit53(uint64_t h) { return (double)(h >> 11) * 0x1.0p-53; }
+
+// lowbias32 (Wellons) and its inverse: bijections of 32-bit integers.
+__host__ __device__ inline uint32_t lowbias32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352dU;
+  x ^= x >> 15;
+  x *= 0x846ca68bU;
+  x ^= x >> 16;
+  return x;
+}
+__host__ __device__ inline uint32_t lowbias32_inv(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x43021123U;  // inverse of 0x846ca68b modulo 2^32
+  x ^= (x >> 15) ^ (x >> 30);
+  x *= 0x1d69e2a5U;  // inverse of 0x7feb352d modulo 2^32
+  x ^= x >> 16;
+  return x;
+}
+
+// Shell ranking key of Eq. 11's batch: key(j) = lowbias32(lowbias32(id_j ^ a) ^ b)
+// with (a, b) = low/high halves of stream_out(stream_out(seed ^ tag, eval), id_i).
+struct ShellKey {
+  uint32_t a, b;
+};
+__host__ __device__ inline uint64_t shell_eval_key(uint64_t seed, uint64_t eval) {
+  return stream_out(seed ^ kTagShell, eval);
+}
+__host__ __device__ inline ShellKey shell_key_of(uint64_t eval_key, int32_t id_i) {
+  uint64_t h = stream_out(eval_key, (uint64_t)(uint32_t)id_i);
+  return ShellKey{(uint32_t)h, (uint32_t)(h >> 32)};
+}
+__host__ __device__ inline uint32_t shell_rank(ShellKey k, int32_t id_j) {
+  return lowbias32(lowbias32((uint32_t)id_j ^ k.a) ^ k.b);
+}
+__host__ __device__ inline int32_t shell_id_of(ShellKey k, uint32_t rank) {
+  return (int32_t)(lowbias32_inv(lowbias32_inv(rank) ^ k.b) ^ k.a);
+}
+
+// ---------------------------------------------------------------------------
+// Geometry
+// ---------------------------------------------------------------------------
+struct Grid {
+  int nx, ny, nz;     // cells per axis
+  int ncell;          // nx * ny * nz (keys run over 2 * ncell: charged, then neutral)
+  double L[3];        // box
+  double inv_h[3];    // n_d / L_d (cell scale used by the binning key)
+};
+
+// Wrap into [0, L): w = x - L floor(x / L); values pushed to L or below 0 by
+// rounding map to 0. Written without contraction so every caller gets the
+// same bits.
+__host__ __device__ inline double wrap_coord(double x, double L) {
+#pragma clang fp contract(off)
+  double w = x - L * floor(x / L);
+  if (w < 0.0 || w >= L) w = 0.0;
+  return w;
+}
+
+// Cell index of a wrapped coordinate: min(n - 1, floor(w * inv_h)). Written
+// so that a NaN (a failed step) lands in cell 0 instead of an undefined
+// conversion: every cell index stays inside the grid.
+__host__ __device__ inline int cell_coord(double w, double inv_h, int n) {
+  const double t = w * inv_h;
+  if (t >= 0.0 && t < (double)n) {
+    const int c = (int)t;
+    return c >= n ? n - 1 : c;
+  }
+  return t >= (double)n ? n - 1 : 0;
+}
+
+__host__ __device__ inline int floor_div(int a, int n) { return a >= 0 ? a / n : -((-a + n - 1) / n); }
+
+// ---------------------------------------------------------------------------
+// Mode tables for the sampler (host-built, copied to the device)
+// ---------------------------------------------------------------------------
+struct ModeTable {
+  int M[3];        // |m_d| <= M[d]
+  int off[3];      // offset of axis d in the cdf array
+  double S;        // normalizer of Eq. 9
+  double V;        // box volume
+  double L[3];
+  int total;       // total cdf entries
+};
+
+int axis_cutoff(double L, double alpha);
+// Builds the per-axis cumulative tables (host). cdf must hold table.total entries.
+void build_mode_table(const double L[3], double alpha, ModeTable *t, double *cdf);
+// Host sampler: draws P modes for (seed, eval).
+int sample_modes_host(const ModeTable &t, const double *cdf, uint64_t seed, uint64_t eval, int P, int32_t *m,
+                      double *w);
+// Device sampler launch (cdf is a device copy of the host table).
+void launch_sample_modes(const ModeTable &t, const double *cdf_dev, uint64_t seed, uint64_t eval, int P,
+                         int32_t *m, double *w, int *err_flag, hipStream_t st);
+// Variant that reads eval from device memory (for a captured step loop).
+void launch_sample_modes_dev_eval(const ModeTable &t, const double *cdf_dev, uint64_t seed,
+                                  const uint64_t *eval_dev, int P, int32_t *m, double *w, int *err_flag,
+                                  hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Error flag bits (device int)
+// ---------------------------------------------------------------------------
+enum : int { kErrNonFinite = 1, kErrBadId = 2, kErrSampler = 4 };
+
+}  // namespace rbe

@@ -1,0 +1,126 @@
+// Importance sampling of Fourier modes for the RBE estimator (Sec. 2.1,
+// Eq. 9): P i.i.d. modes k = 2 pi m / L, m != 0, with probability
+// proportional to exp(-k^2/(4 alpha)).
+//
+// The Gaussian factorizes over the axes, so each component is drawn from its
+// own one-dimensional discrete Gaussian exp(-(pi m / L_d)^2 / alpha) by
+// inverse CDF, and the all-zero vector is rejected. The normalizer is
+// S = H_x H_y H_z - 1 with H_d the one-dimensional sums. The table keeps
+// |m| <= M_d = ceil(L_d sqrt(40 alpha) / pi) (the dropped factors are below
+// e^-40). Weight of a drawn mode: w = (S/P) 4 pi / (V k^2).
+//
+// The host and device samplers consume the same counter-based draws and the
+// same table bits, so they agree bit for bit.
+#include <cmath>
+#include <vector>
+
+#include "rbe_internal.h"
+
+namespace rbe {
+
+int axis_cutoff(double L, double alpha) { return (int)std::ceil(L * std::sqrt(40.0 * alpha) / kPi); }
+
+void build_mode_table(const double L[3], double alpha, ModeTable *t, double *cdf) {
+  int off = 0;
+  double H[3];
+  for (int d = 0; d < 3; ++d) {
+    const int M = axis_cutoff(L[d], alpha);
+    t->M[d] = M;
+    t->off[d] = off;
+    const int len = 2 * M + 1;
+    double acc = 0.0;
+    for (int i = 0; i < len; ++i) {
+      const double a = kPi * (double)(i - M) / L[d];
+      acc += std::exp(-(a * a) / alpha);
+      if (cdf) cdf[off + i] = acc;
+    }
+    H[d] = acc;
+    if (cdf)
+      for (int i = 0; i < len; ++i) cdf[off + i] = cdf[off + i] / acc;
+    off += len;
+    t->L[d] = L[d];
+  }
+  t->total = off;
+  t->S = H[0] * H[1] * H[2] - 1.0;
+  t->V = L[0] * L[1] * L[2];
+}
+
+// First index i of cdf[0..len) with u < cdf[i] (cdf nondecreasing, last = 1 > u).
+__host__ __device__ inline int upper_index(const double *cdf, int len, double u) {
+  int lo = 0, hi = len - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (u < cdf[mid]) hi = mid;
+    else lo = mid + 1;
+  }
+  return lo;
+}
+
+__host__ __device__ inline double mode_weight(const ModeTable &t, int P, int mx, int my, int mz) {
+#pragma clang fp contract(off)
+  const double kx = kTwoPi * (double)mx / t.L[0];
+  const double ky = kTwoPi * (double)my / t.L[1];
+  const double kz = kTwoPi * (double)mz / t.L[2];
+  const double k2 = kx * kx + ky * ky + kz * kz;
+  return (t.S / (double)P) * (4.0 * kPi / (t.V * k2));
+}
+
+constexpr int kMaxAttempts = 4096;
+
+// Draw mode l; returns false if every attempt gave m = 0.
+__host__ __device__ inline bool draw_mode(const ModeTable &t, const double *cdf, uint64_t eval_key, int l, int *mv) {
+  const uint64_t kl = stream_out(eval_key, (uint64_t)l);
+  for (int a = 0; a < kMaxAttempts; ++a) {
+    for (int d = 0; d < 3; ++d) {
+      const double u = unit53(stream_out(kl, (uint64_t)(3 * a + d)));
+      mv[d] = upper_index(cdf + t.off[d], 2 * t.M[d] + 1, u) - t.M[d];
+    }
+    if (mv[0] != 0 || mv[1] != 0 || mv[2] != 0) return true;
+  }
+  return false;
+}
+
+int sample_modes_host(const ModeTable &t, const double *cdf, uint64_t seed, uint64_t eval, int P, int32_t *m,
+                      double *w) {
+  const uint64_t ek = stream_out(seed ^ kTagModes, eval);
+  for (int l = 0; l < P; ++l) {
+    int mv[3];
+    if (!draw_mode(t, cdf, ek, l, mv)) return -1;
+    m[l] = mv[0];
+    m[P + l] = mv[1];
+    m[2 * P + l] = mv[2];
+    w[l] = mode_weight(t, P, mv[0], mv[1], mv[2]);
+  }
+  return 0;
+}
+
+__global__ void __launch_bounds__(256) k_sample_modes(ModeTable t, const double *__restrict__ cdf, uint64_t seed,
+                                                      const uint64_t *eval_dev, uint64_t eval, int P,
+                                                      int32_t *__restrict__ m, double *__restrict__ w,
+                                                      int *err) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= P) return;
+  const uint64_t ev = eval_dev ? *eval_dev : eval;
+  const uint64_t ek = stream_out(seed ^ kTagModes, ev);
+  int mv[3];
+  if (!draw_mode(t, cdf, ek, l, mv)) {
+    atomicOr(err, kErrSampler);
+    mv[0] = 1; mv[1] = 0; mv[2] = 0;
+  }
+  m[l] = mv[0];
+  m[P + l] = mv[1];
+  m[2 * P + l] = mv[2];
+  w[l] = mode_weight(t, P, mv[0], mv[1], mv[2]);
+}
+
+void launch_sample_modes(const ModeTable &t, const double *cdf_dev, uint64_t seed, uint64_t eval, int P, int32_t *m,
+                         double *w, int *err_flag, hipStream_t st) {
+  k_sample_modes<<<(P + 255) / 256, 256, 0, st>>>(t, cdf_dev, seed, nullptr, eval, P, m, w, err_flag);
+}
+
+void launch_sample_modes_dev_eval(const ModeTable &t, const double *cdf_dev, uint64_t seed, const uint64_t *eval_dev,
+                                  int P, int32_t *m, double *w, int *err_flag, hipStream_t st) {
+  k_sample_modes<<<(P + 255) / 256, 256, 0, st>>>(t, cdf_dev, seed, eval_dev, 0, P, m, w, err_flag);
+}
+
+}  // namespace rbe

@@ -1,0 +1,76 @@
+"""CPU checks of the C ABI: the library loads, exports every declared entry
+point, and rejects bad arguments on the host before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2609_02694_amd as rbe
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "rbe.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*\*?\s*(rbe_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_documented_calls():
+    syms = declared_symbols()
+    for s in ("rbe_create", "rbe_build_cells", "rbe_sample_k", "rbe_forces", "rbe_step", "rbe_sync_check"):
+        assert s in syms
+    assert set(syms) == set(rbe.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = rbe.load()
+    for s in declared_symbols():
+        assert hasattr(lib, s), s
+
+
+def _create(p, n=100):
+    lib = rbe.load()
+    h = ctypes.c_void_p()
+    rc = lib.rbe_create(ctypes.byref(h), ctypes.byref(p), n, 0)
+    msg = lib.rbe_last_error(None).decode()
+    return rc, msg
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("alpha", 0.0, rbe.RBE_EINVAL),
+    ("P", 0, rbe.RBE_EINVAL),
+    ("P", rbe.MAX_P + 1, rbe.RBE_EINVAL),
+    ("r_coul", 16.0, rbe.RBE_EBOX),
+    ("r_lj", 15.5, rbe.RBE_EBOX),
+    ("prec", 7, rbe.RBE_EINVAL),
+    ("kdist", 1, rbe.RBE_EINVAL),
+    ("mass", 0.0, rbe.RBE_EINVAL),
+    ("ghost_width", 1e-3, rbe.RBE_EINVAL),
+])
+def test_create_rejects_bad_params(field, value, code):
+    p = rbe.make_params(30.0, 0.3, 8.0, 2.5, 100)
+    setattr(p, field, value)
+    rc, msg = _create(p)
+    assert rc == code and msg
+
+
+def test_create_rejects_bad_shell_batch():
+    p = rbe.make_params(30.0, 0.35, 6.0, 2.5, 100, r_core=3.0, p_shell=33)
+    assert _create(p)[0] == rbe.RBE_EINVAL
+    p = rbe.make_params(30.0, 0.35, 6.0, 2.5, 100, r_core=7.0, p_shell=20)
+    assert _create(p)[0] == rbe.RBE_EINVAL
+
+
+def test_create_rejects_bad_capacity():
+    p = rbe.make_params(30.0, 0.3, 8.0, 2.5, 100)
+    assert _create(p, n=0)[0] == rbe.RBE_EINVAL
+
+
+def test_null_arguments():
+    lib = rbe.load()
+    assert lib.rbe_create(None, None, 10, 0) == rbe.RBE_EINVAL
+    assert lib.rbe_forces(None, None, None, None, 0, None, None) == rbe.RBE_EINVAL
+    assert lib.rbe_step(None, None, 1, 0, None) == rbe.RBE_EINVAL
+    assert lib.rbe_sync_check(None, None) == rbe.RBE_EINVAL

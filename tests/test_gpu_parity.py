@@ -1,0 +1,234 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+FP64 path: RMS relative force error <= 1e-12 (per term and total).
+FP32C path: <= 1e-5. Integer work (binning, mode sample, batch selection):
+bit-exact.
+"""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from gpu_common import gpu_forces, oracle_forces, rel_err, system, to_device
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2609_02694_amd as rbe  # noqa: E402
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rbe.load()
+
+
+# ---------------------------------------------------------------------------
+# mode sampler
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("L,alpha,P", [(30.0, 0.3, 100), (107.72, 0.35, 200), (416.02, 0.3, 500), (12.6, 0.3, 7)])
+def test_sample_k_device_equals_host_and_oracle(L, alpha, P):
+    p = rbe.make_params(L, alpha, 2.0, 1.0, P, seed=1234)
+    for ev in (0, 1, 977):
+        mh, wh = rbe.sample_k(p, ev)
+        md, wd = rbe.sample_k(p, ev, on_device=True)
+        assert np.array_equal(mh, md.cpu().numpy()) and np.array_equal(wh, wd.cpu().numpy())
+        mo, wo = oracle.sample_k(1234, ev, L, alpha, P)
+        assert np.array_equal(mh, mo) and np.array_equal(wh, wo)
+
+
+# ---------------------------------------------------------------------------
+# binning
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,ncell", [(1, (3, 3, 3)), (777, (5, 4, 6)), (20000, (9, 9, 9)), (65537, (1, 2, 3))])
+def test_build_cells_bit_exact(n, ncell):
+    L = (n / 0.5) ** (1 / 3) if n > 1 else 3.0
+    p = gen.preset("replica", n=n)
+    s = gen.make_system(p) if n > 1 else dict(x=np.array([1.0]), y=np.array([2.0]), z=np.array([0.5]),
+                                               q=np.array([0.0]), id=np.zeros(1, np.int32))
+    L = p["L"] if n > 1 else 3.0
+    x = s["x"].copy()
+    if n > 5:  # boundary values: exactly 0, just below L, slightly negative, L itself, beyond L
+        x[:5] = [0.0, L - 1e-13, -1e-18, L, 2 * L + 0.25]
+    params = rbe.make_params(L, 0.3, 0.4 * L / 1.0 if n == 1 else 1.0, 0.5, 4, ncell=ncell)
+    ctx = rbe.Context(params, n)
+    t = lambda a: torch.as_tensor(a).cuda()  # noqa: E731
+    cs, perm = ctx.build_cells(t(x), t(s["y"]), t(s["z"]), t(s["q"]))
+    cs_o, perm_o = oracle.bin_cells(x, s["y"], s["z"], s["q"], L, ncell)
+    assert np.array_equal(cs.cpu().numpy(), cs_o)
+    assert np.array_equal(perm.cpu().numpy(), perm_o)
+    ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# FP64 forces: the 3k-ion configuration (all terms and each term alone)
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def plain3k():
+    p, s = system("plain3k")
+    m, w = oracle.sample_k(p["seed"], 0, p["L"], p["alpha"], p["P"])
+    ref = oracle_forces(p, s, m, w)
+    return p, s, m, w, ref
+
+
+def test_forces_fp64_plain3k_total_and_rho(plain3k):
+    p, s, m, w, ref = plain3k
+    F, re, im = gpu_forces(p, s, m=m, w=w, want_rho=True)
+    assert rel_err(re, ref["rho_re"]) < TOL64 and rel_err(im, ref["rho_im"]) < TOL64
+    e = rel_err(F, ref["F"])
+    print(f"plain3k FP64 total rel err {e:.3e}")
+    assert e < TOL64
+
+
+@pytest.mark.parametrize("term,key", [(rbe.TERM_LJ, "lj"), (rbe.TERM_COUL_REAL, "coul"), (rbe.TERM_FOURIER, "fourier")])
+def test_forces_fp64_plain3k_each_term(plain3k, term, key):
+    p, s, m, w, ref = plain3k
+    F = gpu_forces(p, s, terms=term, m=m, w=w)
+    e = rel_err(F, ref[key])
+    print(f"plain3k FP64 {key} rel err {e:.3e}")
+    assert e < TOL64
+
+
+@pytest.mark.parametrize("ncell", [(3, 3, 3), (7, 7, 7), (13, 11, 12)])
+def test_forces_fp64_independent_of_cell_grid(plain3k, ncell):
+    p, s, m, w, ref = plain3k
+    F = gpu_forces(p, s, m=m, w=w, ncell=ncell)
+    assert rel_err(F, ref["F"]) < TOL64
+
+
+def test_forces_fp64_device_drawn_modes_match(plain3k):
+    p, s, m, w, ref = plain3k
+    F = gpu_forces(p, s, m=None, w=None, ev=0)  # library draws the modes for eval 0 itself
+    assert rel_err(F, ref["F"]) < TOL64
+
+
+def test_forces_deterministic(plain3k):
+    p, s, m, w, _ = plain3k
+    F1 = gpu_forces(p, s, m=m, w=w)
+    F2 = gpu_forces(p, s, m=m, w=w)
+    assert np.array_equal(F1, F2)
+
+
+# ---------------------------------------------------------------------------
+# FP64 forces with the random batch list (electrolyte shape, 20k particles)
+# ---------------------------------------------------------------------------
+def test_forces_fp64_rbl_electrolyte_20k():
+    p, s = system("electrolyte1m", n=20000)
+    for ev in (0, 3):
+        m, w = oracle.sample_k(p["seed"], ev, p["L"], p["alpha"], p["P"])
+        ref = oracle_forces(p, s, m, w, ev=ev, cells=False)
+        F = gpu_forces(p, s, m=m, w=w, ev=ev)
+        e = rel_err(F, ref["F"])
+        print(f"electrolyte20k FP64 ev={ev} rel err {e:.3e}")
+        assert e < TOL64
+        assert np.abs(F.sum(axis=0)).max() < 1e-8 * np.abs(F).sum() / len(F)  # Eq. 12 + zero net Fourier force
+
+
+def test_forces_fp64_rbl_small_box_wrapping_stencil():
+    """Fewer than 2s+1 cells per axis: stencil rows revisit cells with other images."""
+    p, s = system("electrolyte1m", n=1500)  # L = 12.3, r_coul = 6
+    m, w = oracle.sample_k(p["seed"], 1, p["L"], p["alpha"], p["P"])
+    ref = oracle_forces(p, s, m, w, ev=1, cells=False)
+    for ncell in ((0, 0, 0), (2, 2, 2), (1, 1, 1), (5, 3, 4)):
+        F = gpu_forces(p, s, m=m, w=w, ev=1, ncell=ncell)
+        assert rel_err(F, ref["F"]) < TOL64, ncell
+
+
+# ---------------------------------------------------------------------------
+# FP32-compensated form
+# ---------------------------------------------------------------------------
+def test_forces_fp32c_plain3k(plain3k):
+    p, s, m, w, ref = plain3k
+    for term, key in ((rbe.TERM_LJ, "lj"), (rbe.TERM_COUL_REAL, "coul"), (rbe.TERM_FOURIER, "fourier"),
+                      (rbe.TERM_ALL, "F")):
+        F = gpu_forces(p, s, prec=rbe.FP32C, terms=term, m=m, w=w)
+        e = rel_err(F, ref[key])
+        print(f"plain3k FP32C {key} rel err {e:.3e}")
+        assert e < TOL32
+
+
+def test_forces_fp32c_rbl_electrolyte_20k():
+    p, s = system("electrolyte1m", n=20000)
+    m, w = oracle.sample_k(p["seed"], 2, p["L"], p["alpha"], p["P"])
+    ref = oracle_forces(p, s, m, w, ev=2, cells=False)
+    F = gpu_forces(p, s, prec=rbe.FP32C, m=m, w=w, ev=2)
+    e = rel_err(F, ref["F"])
+    print(f"electrolyte20k FP32C rel err {e:.3e}")
+    assert e < TOL32
+
+
+# ---------------------------------------------------------------------------
+# velocity Verlet: 10 steps of the 3k configuration
+# ---------------------------------------------------------------------------
+def test_step_fp64_plain3k_trajectory():
+    p, s = system("plain3k")
+    n = p["n"]
+    params = rbe.params_from_preset(p)
+    ctx = rbe.Context(params, n)
+    st = to_device(s)
+    ctx.forces(st, None, None, 0)  # eval 0: initial force
+    ctx.step(st, 10, 1)
+    torch.cuda.synchronize()
+    ctx.sync_check()
+    ids = st.id.cpu().numpy()
+    assert np.array_equal(np.sort(ids), np.arange(n))
+    # oracle trajectory (eval e draws its own modes)
+    osys = oracle.sys_from_preset(p)
+    r = np.stack([s["x"], s["y"], s["z"]], axis=1)
+    v = np.stack([s["vx"], s["vy"], s["vz"]], axis=1)
+
+    def force(r, ev):
+        m, w = oracle.sample_k(p["seed"], ev, p["L"], p["alpha"], p["P"])
+        return oracle.total_force(r[:, 0], r[:, 1], r[:, 2], s["q"], s["id"], osys, m, w, seed=p["seed"], ev=ev)["F"]
+
+    F = force(r, 0)
+    for k in range(10):
+        v = oracle.kick(F, v, p["dt"] / 2)
+        r = oracle.drift_wrap(r, v, p["dt"], p["L"])
+        F = force(r, k + 1)
+        v = oracle.kick(F, v, p["dt"] / 2)
+    gx = np.empty((n, 3)); gv = np.empty((n, 3)); gf = np.empty((n, 3))
+    gx[ids] = np.stack([st.x.cpu().numpy(), st.y.cpu().numpy(), st.z.cpu().numpy()], axis=1)
+    gv[ids] = np.stack([st.vx.cpu().numpy(), st.vy.cpu().numpy(), st.vz.cpu().numpy()], axis=1)
+    gf[ids] = np.stack([st.fx.cpu().numpy(), st.fy.cpu().numpy(), st.fz.cpu().numpy()], axis=1)
+    d = (gx - r + p["L"] / 2) % p["L"] - p["L"] / 2
+    assert np.abs(d).max() < 1e-12 * p["L"]
+    assert rel_err(gv, v) < TOL64
+    assert rel_err(gf, F) < TOL64
+    ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# errors reported through the ABI
+# ---------------------------------------------------------------------------
+def test_non_neutral_rejected(plain3k):
+    p, s, m, w, _ = plain3k
+    s2 = dict(s)
+    s2["q"] = s["q"].copy()
+    s2["q"][0] = 0.0
+    with pytest.raises(rbe.RbeError) as e:
+        gpu_forces(p, s2, m=m, w=w)
+    assert e.value.code == rbe.RBE_ENONNEUTRAL
+
+
+def test_capacity_and_nonfinite_reported(plain3k):
+    p, s, m, w, _ = plain3k
+    params = rbe.params_from_preset(p)
+    ctx = rbe.Context(params, 100)
+    with pytest.raises(rbe.RbeError) as e:
+        ctx.forces(to_device(s), None, None, 0)
+    assert e.value.code == rbe.RBE_ERANGE
+    ctx.close()
+    ctx = rbe.Context(params, p["n"])
+    st = to_device(s)
+    ctx.forces(st, None, None, 0)
+    st.vx[5] = float("nan")
+    ctx.step(st, 1, 1)
+    with pytest.raises(rbe.RbeError) as e:
+        ctx.sync_check()
+    assert e.value.code == rbe.RBE_ENONFINITE
+    ctx.close()
