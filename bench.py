@@ -1,0 +1,205 @@
+"""Throughput of the RBE nonbonded force + velocity-Verlet step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--prec fp64|fp32c]
+
+A step is one pass of the whole hot path over the system: half-kick + drift
++ wrap, cell binning and reorder, mode sample, near field (with the core-shell
+random batch list where the workload has one), structure factors, Fourier
+gather and the second half-kick. Inputs are synthetic (seeded generator) and
+resident in HBM before the timed region. Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s RBE nonbonded force, FP32-comp & batched vs FP64, ≤1e-5 err"
+
+# MI355X published peaks
+PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+# Algorithmic work per unit ("Roofline accounting"):
+#   near field: per Coulomb pair term 27 flops, per LJ pair term 22 flops,
+#               per ranked shell member 20 ops
+#   structure factor: 13 flops per (charged particle, mode)
+#   gather: 18 flops per (charged particle, mode)
+FLOPS_COUL_PAIR = 27
+FLOPS_LJ_PAIR = 22
+OPS_SHELL_MEMBER = 20
+FLOPS_RHO_IK = 13
+FLOPS_GATHER_IK = 18
+# HBM bytes per particle of the streaming kernels
+BYTES_KICK_DRIFT = 120   # read f (24) v (24) x (24), write v (24) x (24)
+BYTES_KICK = 96          # read f (24) v (24), write v (24) f (24)
+
+DEFAULT_NCELL_H = {"plain3k": 4.3, "electrolyte1m": 3.08, "ions8m": 4.0, "subdomain64m": 2.5, "replica": 3.0}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="electrolyte1m")
+    ap.add_argument("--prec", default=None, choices=["fp64", "fp32c"])
+    ap.add_argument("--n", type=int, default=None, help="override the particle count (same density)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel HIP event timing")
+    return ap.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {a.gpus} is not supported "
+              "(the multi-GPU sharding is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2609_02694_amd as rbe
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    rbe.load()
+    p = gen.preset(a.workload, n=a.n)
+    prec_name = a.prec or ("fp64" if a.workload in ("plain3k", "electrolyte1m") else "fp32c")
+    prec = rbe.FP64 if prec_name == "fp64" else rbe.FP32C
+    h = DEFAULT_NCELL_H.get(a.workload, 3.0)
+    nc = max(1, int(p["L"] // h))
+    t0 = time.time()
+    s = gen.make_system(p)
+    t_gen = time.time() - t0
+    n = p["n"]
+    params = rbe.params_from_preset(p, prec=prec, ncell=(nc, nc, nc))
+    ctx = rbe.Context(params, n)
+    st = rbe.Particles.from_numpy(s)
+    stream = torch.cuda.current_stream()
+
+    # algorithmic counts of one force evaluation (counting pass, untimed)
+    ctx.set_counting(True)
+    ctx.forces(st, None, None, 0)
+    cnt = ctx.counters()
+    ctx.set_counting(False)
+    nq = int(np.count_nonzero(s["q"]))
+    ctx.forces(st, None, None, 0)  # initial force, eval 0
+    ctx.sync_check()
+
+    K, W = a.steps, a.warmup
+    if W > 0:
+        ctx.step(st, W, 1)
+    torch.cuda.synchronize()
+    ctx.sync_check()
+    if not a.no_timing:
+        ctx.set_timing(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    ctx.step(st, K, 1 + W)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    w1 = time.perf_counter()
+    kt = ctx.timing() if not a.no_timing else {}
+    ctx.set_timing(False)
+    ctx.sync_check()
+    wall_s = w1 - w0
+    ev_ms = ev0.elapsed_time(ev1)
+    value = n * K / wall_s
+
+    kernels = {k: {"total_ms": round(v[0], 4), "launches": v[1], "avg_us": round(1000 * v[0] / v[1], 3)}
+               for k, v in kt.items() if v[1] > 0}
+    roof = roofline(kernels, cnt, nq, p, prec, K)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": 1000.0 * wall_s / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == rbe.FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "n": n, "n_charged": nq, "L": round(p["L"], 4), "alpha": p["alpha"],
+                   "r_coul": p["r_coul"], "r_lj": p["r_lj"], "r_core": p["r_core"], "p_shell": p["p_shell"],
+                   "P": p["P"], "dt": p["dt"], "form": prec_name, "ncell": nc, "parallelism": "single GPU"},
+        "event_ms_per_step": ev_ms / K,
+        "kernels": kernels,
+        "counts_per_eval": {"coul_pairs": cnt[0], "lj_pairs": cnt[1], "candidates": cnt[2], "shell_members": cnt[3]},
+        "roofline": roof,
+        "gen_s": round(t_gen, 2),
+    }
+    ctx.close()
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, s)
+    print(json.dumps(out), flush=True)
+
+
+def roofline(kernels, cnt, nq, p, prec, K):
+    """Roofline figure of the dominant kernel (largest summed time)."""
+    if not kernels:
+        return None
+    name = max(kernels, key=lambda k: kernels[k]["total_ms"])
+    avg_s = kernels[name]["avg_us"] * 1e-6
+    peak_alu = PEAK_FP64_TFLOPS if prec == 0 else PEAK_FP32_TFLOPS
+    n, P = p["n"], p["P"]
+    if name == "pair":
+        work = FLOPS_COUL_PAIR * cnt[0] + FLOPS_LJ_PAIR * cnt[1] + OPS_SHELL_MEMBER * cnt[3]
+        ach = work / avg_s / 1e12
+        return dict(kernel=name, bound="alu", achieved=ach, peak=peak_alu, unit="TFLOP/s", frac=ach / peak_alu,
+                    traffic=None, work_per_launch=work)
+    if name in ("rho_partial", "gather"):
+        per = FLOPS_RHO_IK if name == "rho_partial" else FLOPS_GATHER_IK
+        work = per * nq * P
+        ach = work / avg_s / 1e12
+        return dict(kernel=name, bound="alu", achieved=ach, peak=peak_alu, unit="TFLOP/s", frac=ach / peak_alu,
+                    traffic=None, work_per_launch=work)
+    per_bytes = {"kick_drift": BYTES_KICK_DRIFT, "kick": BYTES_KICK}.get(name)
+    if per_bytes is None:
+        return dict(kernel=name, bound="hbm", achieved=None, peak=PEAK_HBM_GBS, unit="GB/s", frac=None, traffic=None)
+    ach = per_bytes * n / avg_s / 1e9
+    return dict(kernel=name, bound="hbm", achieved=ach, peak=PEAK_HBM_GBS, unit="GB/s", frac=ach / PEAK_HBM_GBS,
+                traffic=None)
+
+
+def cpu_baseline(p, s):
+    """The FP64 CPU oracle on one velocity-Verlet step of the same system."""
+    import numpy as np
+
+    import oracle
+
+    osys = oracle.sys_from_preset(p)
+    t0 = time.perf_counter()
+    m, w = oracle.sample_k(p["seed"], 1, p["L"], p["alpha"], p["P"])
+    r = np.stack([s["x"], s["y"], s["z"]], axis=1)
+    v = np.stack([s["vx"], s["vy"], s["vz"]], axis=1)
+    F0 = np.zeros_like(r)
+    v = oracle.kick(F0, v, p["dt"] / 2)
+    r = oracle.drift_wrap(r, v, p["dt"], p["L"])
+    F = oracle.total_force(r[:, 0], r[:, 1], r[:, 2], s["q"], s["id"], osys, m, w, seed=p["seed"], ev=1,
+                             components=False)["F"]
+    v = oracle.kick(F, v, p["dt"] / 2)
+    dt = time.perf_counter() - t0
+    return {"value": p["n"] / dt, "unit": "particle-steps/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"one velocity-Verlet step (one force evaluation) of the full {p['n']}-particle system",
+            "seconds": round(dt, 2)}
+
+
+if __name__ == "__main__":
+    main()

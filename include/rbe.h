@@ -159,13 +159,35 @@ int rbe_step(rbe_ctx *ctx, rbe_state *s, int32_t nsteps, uint64_t first_eval, vo
 int rbe_sync_check(rbe_ctx *ctx, void *stream);
 
 /* Diagnostic counters of the last rbe_forces/rbe_step force evaluation
-   (host, 4 entries): [0] near-field pairs inside a cutoff, [1] shell
-   candidates, [2] candidates tested, [3] particles with a shell batch.
+   (host, 4 entries): [0] Coulomb pair terms evaluated (both charged, inside
+   r_coul), [1] LJ pair terms evaluated (inside r_lj), [2] candidate pairs
+   tested, [3] shell members ranked (sum of #S_i, Eq. 10).
    Only filled when counting was enabled with rbe_set_counting(ctx, 1); the
    counting adds atomics to the near-field kernel and is meant for the
    roofline figures, not for timed runs. */
 int rbe_set_counting(rbe_ctx *ctx, int enable);
 int rbe_get_counters(rbe_ctx *ctx, int64_t *counters /* host, 4 */, void *stream);
+
+/* Per-kernel timing with HIP events recorded on the call's stream around
+   every launch of the kinds below (enable = 1 starts and clears the
+   accumulation; 0 stops it). rbe_get_timing synchronizes `stream`, then
+   writes, per kind, the summed duration in ms (ms_out) and the launch count
+   (launches_out), host arrays of RBE_TIMING_KINDS entries. */
+enum {
+  RBE_TK_BIN = 0,         /* keys, histogram, scan, stable placement        */
+  RBE_TK_REORDER = 1,     /* reorder + packing of the sorted records        */
+  RBE_TK_PAIR = 2,        /* near-field kernel                              */
+  RBE_TK_MEAN = 3,        /* Eq. 12 mean                                    */
+  RBE_TK_SAMPLE = 4,      /* device mode sampler + mode conversion          */
+  RBE_TK_RHO_PARTIAL = 5, /* structure-factor chunk partials                */
+  RBE_TK_RHO_FINAL = 6,   /* fixed-order final sum                          */
+  RBE_TK_GATHER = 7,      /* Fourier force gather                           */
+  RBE_TK_KICK_DRIFT = 8,  /* first half-kick + drift + wrap                 */
+  RBE_TK_KICK = 9,        /* second half-kick (+ mean subtraction)          */
+  RBE_TIMING_KINDS = 10
+};
+int rbe_set_timing(rbe_ctx *ctx, int enable);
+int rbe_get_timing(rbe_ctx *ctx, double *ms_out /* host */, int64_t *launches_out /* host */, void *stream);
 
 #ifdef __cplusplus
 }

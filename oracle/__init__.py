@@ -282,18 +282,19 @@ def drift_wrap(r, v, dt, L):
 # --------------------------------------------------------------------------
 # Composite evaluations used by the tests and the CPU baseline
 # --------------------------------------------------------------------------
-def total_force(x, y, z, q, ids, sys: OrcSys, m, w, seed=0, ev=0, terms=LJ | COUL_REAL | FOURIER, cells=None):
+def total_force(x, y, z, q, ids, sys: OrcSys, m, w, seed=0, ev=0, terms=LJ | COUL_REAL | FOURIER, cells=None,
+                components=True):
     """F = F^N (Eq. 7 near field, with Eq. 11-12 when the list is on) + F^F (Eq. 9).
 
-    Returns dict with the total and each component."""
+    Returns dict with the total and (components=True) each near-field term."""
     n = len(x)
     if cells is None:
         cells = n > 20000
     out = {}
     FN = np.zeros((n, 3))
-    if terms & LJ:
+    if components and terms & LJ:
         out["lj"] = real_force(x, y, z, q, ids, sys, LJ, seed, ev, cells=cells)
-    if terms & COUL_REAL:
+    if components and terms & COUL_REAL:
         out["coul"] = real_force(x, y, z, q, ids, sys, COUL_REAL, seed, ev, cells=cells)
     if terms & (LJ | COUL_REAL):
         FN = real_force(x, y, z, q, ids, sys, terms & (LJ | COUL_REAL), seed, ev, cells=cells)

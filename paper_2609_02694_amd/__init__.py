@@ -23,7 +23,10 @@ MAX_P = 4096
 MAX_SHELL_BATCH = 32
 
 EXPORTED = ["rbe_create", "rbe_create_batch", "rbe_destroy", "rbe_last_error", "rbe_build_cells", "rbe_sample_k",
-            "rbe_forces", "rbe_step", "rbe_sync_check", "rbe_set_counting", "rbe_get_counters"]
+            "rbe_forces", "rbe_step", "rbe_sync_check", "rbe_set_counting", "rbe_get_counters", "rbe_set_timing",
+            "rbe_get_timing"]
+TIMING_KINDS = ["bin", "reorder", "pair", "mean", "sample", "rho_partial", "rho_final", "gather", "kick_drift",
+                "kick"]
 
 
 class RbeError(RuntimeError):
@@ -81,6 +84,8 @@ def load():
         "rbe_sync_check": [vp, vp],
         "rbe_set_counting": [vp, ctypes.c_int],
         "rbe_get_counters": [vp, ctypes.POINTER(i64), vp],
+        "rbe_set_timing": [vp, ctypes.c_int],
+        "rbe_get_timing": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -252,3 +257,13 @@ class Context:
         arr = (ctypes.c_int64 * 4)()
         self._ok(self.lib.rbe_get_counters(self.h, arr, _stream(stream)))
         return list(arr)
+
+    def set_timing(self, on: bool):
+        self._ok(self.lib.rbe_set_timing(self.h, 1 if on else 0))
+
+    def timing(self, stream=None):
+        """Per-kernel-kind (summed ms, launch count) since set_timing(True)."""
+        ms = (ctypes.c_double * len(TIMING_KINDS))()
+        cnt = (ctypes.c_int64 * len(TIMING_KINDS))()
+        self._ok(self.lib.rbe_get_timing(self.h, ms, cnt, _stream(stream)))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(TIMING_KINDS)}

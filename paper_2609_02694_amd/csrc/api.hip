@@ -41,6 +41,16 @@ struct WorkSet {
 
 thread_local std::string g_create_error;
 
+// Event pairs recorded around launches when timing is on; summed per kind.
+struct Timer {
+  bool on = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> kind;  // kind of each recorded pair
+  size_t used = 0;
+  double ms[RBE_TIMING_KINDS] = {};
+  int64_t launches[RBE_TIMING_KINDS] = {};
+};
+
 }  // namespace
 
 struct rbe_ctx {
@@ -66,6 +76,7 @@ struct rbe_ctx {
   double *qstats = nullptr;  // [sum q, sum |q|]
   unsigned long long *counters = nullptr;
   bool counting = false;
+  Timer tm;
   std::string last_error;
 
   int fail(int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
@@ -92,6 +103,43 @@ static int create_fail(int code, const char *msg) {
     if (e_ != hipSuccess)                                                                      \
       return (ctx)->fail(RBE_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));          \
   } while (0)
+
+// ---------------------------------------------------------------------------
+// per-kernel timing
+// ---------------------------------------------------------------------------
+static void timer_flush(rbe_ctx *c, hipStream_t st) {
+  Timer &t = c->tm;
+  if (t.used == 0) return;
+  (void)hipStreamSynchronize(st);
+  for (size_t k = 0; k < t.used / 2; ++k) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t.ev[2 * k], t.ev[2 * k + 1]) == hipSuccess) {
+      t.ms[t.kind[k]] += ms;
+      t.launches[t.kind[k]] += 1;
+    }
+  }
+  t.used = 0;
+  t.kind.clear();
+}
+
+struct TScope {
+  rbe_ctx *c;
+  hipStream_t st;
+  bool on;
+  TScope(rbe_ctx *c_, int kind, hipStream_t st_) : c(c_), st(st_), on(c_->tm.on) {
+    if (!on) return;
+    Timer &t = c->tm;
+    if (t.used + 2 > t.ev.size()) timer_flush(c, st);
+    t.kind.push_back(kind);
+    (void)hipEventRecord(t.ev[t.used], st);
+  }
+  ~TScope() {
+    if (!on) return;
+    Timer &t = c->tm;
+    (void)hipEventRecord(t.ev[t.used + 1], st);
+    t.used += 2;
+  }
+};
 
 // ---------------------------------------------------------------------------
 // validation
@@ -126,6 +174,8 @@ static int validate_params(const rbe_params *p, std::string *why) {
     }
   for (int d = 0; d < 3; ++d)
     if (p->ncell[d] < 0) return bad(RBE_EINVAL, "ncell must be >= 0");
+  if (std::sqrt(p->alpha) * p->r_coul > 8.0)
+    return bad(RBE_EINVAL, "sqrt(alpha) r_coul must not exceed 8 (range of the erfc approximation)");
   return RBE_OK;
 }
 
@@ -191,9 +241,11 @@ extern "C" int rbe_create(rbe_ctx **out, const rbe_params *p, int64_t n_max, int
   const double rq = std::fmax(p->r_coul, p->r_lj);
   pp.s_coul = 0;
   pp.s_lj = 0;
+  pp.s_core = 0;
   for (int d = 0; d < 3; ++d) {
     pp.s_coul = std::max(pp.s_coul, stencil_radius(rq, p->L[d], nc[d]));
     pp.s_lj = std::max(pp.s_lj, stencil_radius(p->r_lj, p->L[d], nc[d]));
+    pp.s_core = std::max(pp.s_core, stencil_radius(std::fmax(p->r_core, p->r_lj), p->L[d], nc[d]));
   }
   pp.rc2 = p->r_coul * p->r_coul;
   pp.rlj2 = p->r_lj * p->r_lj;
@@ -290,6 +342,7 @@ extern "C" void rbe_destroy(rbe_ctx *ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   ctx->buf.release();
+  for (auto &e : ctx->tm.ev) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -354,28 +407,48 @@ static int eval_sorted(rbe_ctx *c, int64_t n, int64_t nq, const int32_t *m, cons
   if (terms & (RBE_TERM_LJ | RBE_TERM_COUL_REAL)) {
     PairParams pp = c->pp;
     pp.shell_key = shell_eval_key(c->p.seed, eval);
-    if (pp.rbl) launch_inverse_ids(n, c->srt.id, c->inv_id, c->err, st);
+    if (pp.rbl) {
+      TScope ts(c, RBE_TK_REORDER, st);
+      launch_inverse_ids(n, c->srt.id, c->inv_id, c->err, st);
+    }
     PairCounters cnt{c->counting ? c->counters : nullptr};
-    if (c->counting) HIP_TRY(c, hipMemsetAsync(c->counters, 0, 4 * sizeof(unsigned long long), st));
-    if (c->p.prec == RBE_FP32C)
-      launch_pair_f32c(pp, n, c->srt, c->cell_start, c->inv_id, fx, fy, fz, cnt, st);
-    else
-      launch_pair_f64(pp, n, c->srt, c->cell_start, c->inv_id, fx, fy, fz, cnt, st);
-    if (pp.rbl) launch_mean3(n, fx, fy, fz, c->mean_part, c->mean, st);
+    if (c->counting) launch_fill_i32((int32_t *)c->counters, 8, 0, st);
+    {
+      TScope ts(c, RBE_TK_PAIR, st);
+      launch_pair(c->p.prec, pp, n, nq, c->srt, c->cell_start, c->inv_id, fx, fy, fz, cnt, st);
+    }
+    if (pp.rbl) {
+      TScope ts(c, RBE_TK_MEAN, st);
+      launch_mean3(n, fx, fy, fz, c->mean_part, c->mean, st);
+    }
   } else {
     launch_fill_f64(fx, n, 0.0, st);
     launch_fill_f64(fy, n, 0.0, st);
     launch_fill_f64(fz, n, 0.0, st);
   }
   if (terms & RBE_TERM_FOURIER) {
-    if (!m) {
-      launch_sample_modes(c->mt, c->cdf_dev, c->p.seed, eval, P, c->m_dev, c->w_dev, c->err, st);
-      m = c->m_dev;
-      w = c->w_dev;
+    {
+      TScope ts(c, RBE_TK_SAMPLE, st);
+      if (!m) {
+        launch_sample_modes(c->mt, c->cdf_dev, c->p.seed, eval, P, c->m_dev, c->w_dev, c->err, st);
+        m = c->m_dev;
+        w = c->w_dev;
+      }
+      launch_modes_to_double(P, m, c->fb.mkd, st);
     }
-    launch_modes_to_double(P, m, c->fb.mkd, st);
-    launch_rho(c->p.prec, nq, P, c->srt.sq, c->fb, w, rho_out, st);
-    launch_fourier_gather(c->p.prec, nq, P, c->srt.sq, c->fb, c->g, fx, fy, fz, st);
+    int nchunks;
+    {
+      TScope ts(c, RBE_TK_RHO_PARTIAL, st);
+      nchunks = launch_rho_partial(c->p.prec, nq, P, c->srt.sq, c->fb, st);
+    }
+    {
+      TScope ts(c, RBE_TK_RHO_FINAL, st);
+      launch_rho_final(nchunks, P, c->fb, w, rho_out, st);
+    }
+    {
+      TScope ts(c, RBE_TK_GATHER, st);
+      launch_fourier_gather(c->p.prec, nq, P, c->srt.sq, c->fb, c->g, fx, fy, fz, st);
+    }
   }
   return RBE_OK;
 }
@@ -454,8 +527,14 @@ extern "C" int rbe_forces(rbe_ctx *c, const rbe_state *s, const int32_t *m, cons
   int64_t nq = 0;
   int rc = charge_stats(c, n, s->q, st, &nq);
   if (rc != RBE_OK) return rc;
-  launch_bin(c->bb, c->g, n, s->x, s->y, s->z, s->q, c->cell_start, c->perm, st);
-  launch_gather_sorted(n, c->perm, s->x, s->y, s->z, s->q, s->id, c->g, c->srt, st);
+  {
+    TScope ts(c, RBE_TK_BIN, st);
+    launch_bin(c->bb, c->g, n, s->x, s->y, s->z, s->q, c->cell_start, c->perm, st);
+  }
+  {
+    TScope ts(c, RBE_TK_REORDER, st);
+    launch_gather_sorted(n, c->perm, s->x, s->y, s->z, s->q, s->id, c->g, c->srt, st);
+  }
   WorkSet &o = c->ws[1];
   rc = eval_sorted(c, n, nq, m, w, eval, rho_out, o.fx, o.fy, o.fz, st);
   if (rc != RBE_OK) return rc;
@@ -516,13 +595,26 @@ extern "C" int rbe_step(rbe_ctx *c, rbe_state *s, int32_t nsteps, uint64_t first
   const double h = 0.5 * c->p.dt / c->p.mass;
   const bool near = (c->p.terms & (RBE_TERM_LJ | RBE_TERM_COUL_REAL)) != 0;
   for (int32_t k = 0; k < nsteps; ++k) {
-    launch_kick_drift(n, h, c->p.dt, c->g, A->fx, A->fy, A->fz, A->vx, A->vy, A->vz, A->x, A->y, A->z, c->err, st);
-    launch_bin(c->bb, c->g, n, A->x, A->y, A->z, A->q, c->cell_start, c->perm, st);
-    k_reorder_pack<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, c->perm, A->arrays(), B->arrays(), c->g, c->srt.xq,
-                                                                 c->srt.sq, c->srt.id);
+    {
+      TScope ts(c, RBE_TK_KICK_DRIFT, st);
+      launch_kick_drift(n, h, c->p.dt, c->g, A->fx, A->fy, A->fz, A->vx, A->vy, A->vz, A->x, A->y, A->z, c->err, st);
+    }
+    {
+      TScope ts(c, RBE_TK_BIN, st);
+      launch_bin(c->bb, c->g, n, A->x, A->y, A->z, A->q, c->cell_start, c->perm, st);
+    }
+    {
+      TScope ts(c, RBE_TK_REORDER, st);
+      k_reorder_pack<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, c->perm, A->arrays(), B->arrays(), c->g,
+                                                                   c->srt.xq, c->srt.sq, c->srt.id);
+    }
     rc = eval_sorted(c, n, nq, nullptr, nullptr, first_eval + (uint64_t)k, nullptr, B->fx, B->fy, B->fz, st);
     if (rc != RBE_OK) return rc;
-    launch_kick(n, h, (c->pp.rbl && near) ? c->mean : nullptr, B->fx, B->fy, B->fz, B->vx, B->vy, B->vz, c->err, st);
+    {
+      TScope ts(c, RBE_TK_KICK, st);
+      launch_kick(n, h, (c->pp.rbl && near) ? c->mean : nullptr, B->fx, B->fy, B->fz, B->vx, B->vy, B->vz, c->err,
+                  st);
+    }
     std::swap(A, B);
   }
   HIP_TRY(c, hipMemcpyAsync(s->x, A->x, bd, hipMemcpyDeviceToDevice, st));
@@ -547,7 +639,7 @@ extern "C" int rbe_sync_check(rbe_ctx *c, void *stream) {
   int flag = 0;
   HIP_TRY(c, hipMemcpyAsync(&flag, c->err, sizeof flag, hipMemcpyDeviceToHost, st));
   HIP_TRY(c, hipStreamSynchronize(st));
-  HIP_TRY(c, hipMemsetAsync(c->err, 0, sizeof(int), st));
+  launch_fill_i32(c->err, 1, 0, st);
   HIP_TRY(c, hipStreamSynchronize(st));
   if (flag & kErrNonFinite) return c->fail(RBE_ENONFINITE, "non-finite velocity or force seen on the device");
   if (flag & kErrBadId) return c->fail(RBE_ERANGE, "a particle id lies outside [0, n)");
@@ -569,5 +661,36 @@ extern "C" int rbe_get_counters(rbe_ctx *c, int64_t *counters, void *stream) {
   HIP_TRY(c, hipMemcpyAsync(h, c->counters, sizeof h, hipMemcpyDeviceToHost, st));
   HIP_TRY(c, hipStreamSynchronize(st));
   for (int i = 0; i < 4; ++i) counters[i] = (int64_t)h[i];
+  return RBE_OK;
+}
+
+extern "C" int rbe_set_timing(rbe_ctx *c, int enable) {
+  if (!c) return RBE_EINVAL;
+  HIP_TRY(c, hipSetDevice(c->device));
+  Timer &t = c->tm;
+  if (enable) {
+    if (t.ev.empty()) {
+      t.ev.resize(16384);
+      for (auto &e : t.ev) HIP_TRY(c, hipEventCreate(&e));
+    }
+    t.used = 0;
+    t.kind.clear();
+    for (int k = 0; k < RBE_TIMING_KINDS; ++k) {
+      t.ms[k] = 0.0;
+      t.launches[k] = 0;
+    }
+  }
+  t.on = enable != 0;
+  return RBE_OK;
+}
+
+extern "C" int rbe_get_timing(rbe_ctx *c, double *ms_out, int64_t *launches_out, void *stream) {
+  if (!c || !ms_out || !launches_out) return RBE_EINVAL;
+  HIP_TRY(c, hipSetDevice(c->device));
+  timer_flush(c, (hipStream_t)stream);
+  for (int k = 0; k < RBE_TIMING_KINDS; ++k) {
+    ms_out[k] = c->tm.ms[k];
+    launches_out[k] = c->tm.launches[k];
+  }
   return RBE_OK;
 }

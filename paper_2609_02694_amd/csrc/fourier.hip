@@ -142,8 +142,7 @@ __global__ void __launch_bounds__(64) k_rho_final(int nchunks, int P, const doub
   }
 }
 
-void launch_rho(int prec, int64_t nq, int P, const double4 *sq, const FourierBuffers &fb, const double *w,
-                double *rho_out, hipStream_t st) {
+int launch_rho_partial(int prec, int64_t nq, int P, const double4 *sq, const FourierBuffers &fb, hipStream_t st) {
   const int chunk = rho_chunk(nq, P, prec, fb.nchunk_max);
   int nchunks = (int)((nq + chunk - 1) / chunk);
   if (nchunks < 1) nchunks = 1;
@@ -152,6 +151,10 @@ void launch_rho(int prec, int64_t nq, int P, const double4 *sq, const FourierBuf
     k_rho_partial_f32c<<<grid, kModesPerBlock, 0, st>>>(nq, P, chunk, sq, fb.mkd, fb.part);
   else
     k_rho_partial_f64<<<grid, kModesPerBlock, 0, st>>>(nq, P, chunk, sq, fb.mkd, fb.part);
+  return nchunks;
+}
+
+void launch_rho_final(int nchunks, int P, const FourierBuffers &fb, const double *w, double *rho_out, hipStream_t st) {
   k_rho_final<<<P, 64, 0, st>>>(nchunks, P, fb.part, fb.mkd, w, fb.rho, fb.modes, rho_out);
 }
 

@@ -49,8 +49,9 @@ void launch_count_charged(int64_t n, const double *q, int32_t *out, hipStream_t 
 // ---------------------------------------------------------------------------
 struct PairParams {
   Grid g;
-  int s_coul;            // stencil radius (cells) covering r_coul
+  int s_coul;            // stencil radius (cells) covering max(r_coul, r_lj)
   int s_lj;              // stencil radius covering r_lj
+  int s_core;            // stencil radius covering max(r_core, r_lj)
   double rc2, rlj2, rcore2;
   double alpha, sqrt_alpha, two_sqrt_alpha_over_sqrt_pi;
   double kc, eps24, sig2;
@@ -62,10 +63,10 @@ struct PairParams {
 struct PairCounters {
   unsigned long long *c;  // [4] or nullptr
 };
-void launch_pair_f64(const PairParams &pp, int64_t n, const Sorted &s, const int32_t *cell_start,
-                     const int32_t *inv_id, double *fx, double *fy, double *fz, PairCounters cnt, hipStream_t st);
-void launch_pair_f32c(const PairParams &pp, int64_t n, const Sorted &s, const int32_t *cell_start,
-                      const int32_t *inv_id, double *fx, double *fy, double *fz, PairCounters cnt, hipStream_t st);
+// Near-field force of every particle; charged particles are [0, nq) of the
+// sorted order, neutral ones [nq, n).
+void launch_pair(int prec, const PairParams &pp, int64_t n, int64_t nq, const Sorted &s, const int32_t *cell_start,
+                 const int32_t *inv_id, double *fx, double *fy, double *fz, PairCounters cnt, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Fourier part
@@ -85,8 +86,9 @@ struct FourierBuffers {
 // Chunk length of the structure-factor partial sums for nq charged particles.
 int rho_chunk(int64_t nq, int P, int prec, int nchunk_max);
 void launch_modes_to_double(int P, const int32_t *m, double *mkd, hipStream_t st);
-void launch_rho(int prec, int64_t nq, int P, const double4 *sq, const FourierBuffers &fb, const double *w,
-                double *rho_out, hipStream_t st);
+// Returns the number of chunk partials written.
+int launch_rho_partial(int prec, int64_t nq, int P, const double4 *sq, const FourierBuffers &fb, hipStream_t st);
+void launch_rho_final(int nchunks, int P, const FourierBuffers &fb, const double *w, double *rho_out, hipStream_t st);
 void launch_fourier_gather(int prec, int64_t nq, int P, const double4 *sq, const FourierBuffers &fb, const Grid &g,
                            double *fx, double *fy, double *fz, hipStream_t st);
 

@@ -28,17 +28,50 @@
 
 namespace rbe {
 
+// FP64 erfc(x) = exp(-x^2) R(x) with R(x) = erfc(x) e^{x^2} a degree-20
+// polynomial in s = 2/(1 + x/2) - 1 (fit over x in [0, 8] by fit_erfcx.py,
+// relative error below 7.2e-15); e = exp(-x^2) is passed in.
+__device__ inline double erfc_scaled_f64(double x) {
+  const double s = 2.0 / fma(0.5, x, 1.0) - 1.0;
+  double r = 1.63618628481317543e-08;
+  r = fma(r, s, -4.60928758649811430e-08);
+  r = fma(r, s, -6.88442333452307132e-08);
+  r = fma(r, s, 4.40190654889049080e-07);
+  r = fma(r, s, -4.46917185831068957e-07);
+  r = fma(r, s, -1.14063358111397811e-06);
+  r = fma(r, s, 3.75537844601685302e-06);
+  r = fma(r, s, -1.41703053499259700e-06);
+  r = fma(r, s, -1.39602653735770222e-05);
+  r = fma(r, s, 2.75867068654632672e-05);
+  r = fma(r, s, 2.75241444094816018e-05);
+  r = fma(r, s, -1.74362281120596591e-04);
+  r = fma(r, s, 4.35557661104548185e-05);
+  r = fma(r, s, 9.81977137355043118e-04);
+  r = fma(r, s, -8.47143262890503600e-04);
+  r = fma(r, s, -6.99746174546772310e-03);
+  r = fma(r, s, 3.73289240473987467e-03);
+  r = fma(r, s, 7.89785810158994406e-02);
+  r = fma(r, s, 2.41658194242463487e-01);
+  r = fma(r, s, 4.27185847413955655e-01);
+  r = fma(r, s, 2.55395676310504194e-01);
+  return r;
+}
+
 __device__ inline double pair_scalar_f64(const PairParams &pp, double r2, double qi, double qj) {
+  const double inv_r2 = 1.0 / r2;
   double f = 0.0;
   if (pp.do_coul && r2 <= pp.rc2 && qi != 0.0 && qj != 0.0) {
     const double r = sqrt(r2);
-    const double G = erfc(pp.sqrt_alpha * r) / (r2 * r) + pp.two_sqrt_alpha_over_sqrt_pi * exp(-pp.alpha * r2) / r2;
-    f += pp.kc * qi * qj * G;
+    const double e = exp(-pp.alpha * r2);
+    const double R = erfc_scaled_f64(pp.sqrt_alpha * r);
+    // G = erfc(x)/r^3 + 2 sqrt(a) e/(sqrt(pi) r^2) = e/r^2 (R/r + 2 sqrt(a)/sqrt(pi))
+    const double G = e * inv_r2 * (R / r + pp.two_sqrt_alpha_over_sqrt_pi);
+    f = pp.kc * qi * qj * G;
   }
   if (pp.do_lj && r2 <= pp.rlj2) {
-    const double s2 = pp.sig2 / r2;
+    const double s2 = pp.sig2 * inv_r2;
     const double s6 = s2 * s2 * s2;
-    f += pp.eps24 * (2.0 * s6 * s6 - s6) / r2;
+    f = fma(pp.eps24 * (2.0 * s6 * s6 - s6), inv_r2, f);
   }
   return f;
 }
@@ -87,6 +120,22 @@ __device__ inline float pair_scalar_f32(const PairParams &pp, const PairF32 &pf,
   return f;
 }
 
+__device__ inline double pair_scalar_lj_f64(const PairParams &pp, double r2) {
+  if (!(pp.do_lj && r2 <= pp.rlj2)) return 0.0;
+  const double inv_r2 = 1.0 / r2;
+  const double s2 = pp.sig2 * inv_r2;
+  const double s6 = s2 * s2 * s2;
+  return pp.eps24 * (2.0 * s6 * s6 - s6) * inv_r2;
+}
+
+__device__ inline float pair_scalar_lj_f32(const PairParams &pp, const PairF32 &pf, double r2d) {
+  if (!(pp.do_lj && r2d <= pp.rlj2)) return 0.f;
+  const float rinv2 = __builtin_amdgcn_rcpf((float)r2d);
+  const float s2 = pf.sig2 * rinv2;
+  const float s6 = s2 * s2 * s2;
+  return pf.eps24 * fmaf(2.0f, s6 * s6, -s6) * rinv2;
+}
+
 // Kahan-compensated FP32 accumulation of a 3-vector.
 struct Kahan3 {
   float s[3] = {0.f, 0.f, 0.f}, c[3] = {0.f, 0.f, 0.f};
@@ -110,12 +159,15 @@ __device__ inline double min_image(double a, double L) {
   return a - L * rint(a / L);
 }
 
-// Calls fn(j, shx, shy, shz) for every particle j of species block `blk` in
-// the (2s+1)^3 cells around (cx, cy, cz); (shx, shy, shz) is the image shift
-// of j (its image lies at r_j + shift).
-template <class Fn>
-__device__ inline void for_stencil(const Grid &g, const int32_t *__restrict__ cell_start, int blk, int cx, int cy,
-                                   int cz, int s, Fn &&fn) {
+// Calls fn(j, p_j, id_j, shx, shy, shz) for every particle j of species block
+// `blk` in the (2s+1)^3 cells around (cx, cy, cz); (shx, shy, shz) is the
+// image shift of j (its image lies at r_j + shift). Records are prefetched
+// four ahead, so several loads are in flight per lane.
+// id_j is loaded only when WITH_ID (else 0).
+template <bool WITH_ID, class Fn>
+__device__ inline void for_stencil(const Grid &g, const int32_t *__restrict__ cell_start,
+                                   const double4 *__restrict__ xq, const int32_t *__restrict__ ids, int blk, int cx,
+                                   int cy, int cz, int s, Fn &&fn) {
   const int base = blk * g.ncell;
   for (int oz = -s; oz <= s; ++oz) {
     const int az = cz + oz;
@@ -136,24 +188,53 @@ __device__ inline void for_stencil(const Grid &g, const int32_t *__restrict__ ce
         const int j0 = cell_start[row + (a - qx * g.nx)];
         const int j1 = cell_start[row + (b - qx * g.nx) + 1];
         const double shx = (double)qx * g.L[0];
-        for (int j = j0; j < j1; ++j) fn(j, shx, shy, shz);
+        if (j0 < j1) {
+          // ring of four records: the load of j + 4 is issued before j is used;
+          // indices past the range are clamped to its last record (always valid)
+          const int last = j1 - 1;
+          double4 r0 = xq[j0], r1 = xq[min(j0 + 1, last)], r2 = xq[min(j0 + 2, last)], r3 = xq[min(j0 + 3, last)];
+          int d0 = 0, d1 = 0, d2 = 0, d3 = 0;
+          if (WITH_ID) {
+            d0 = ids[j0];
+            d1 = ids[min(j0 + 1, last)];
+            d2 = ids[min(j0 + 2, last)];
+            d3 = ids[min(j0 + 3, last)];
+          }
+#pragma unroll 1
+          for (int j = j0; j < j1; ++j) {
+            const double4 cur = r0;
+            const int cid = d0;
+            const int jn = min(j + 4, last);
+            r0 = r1;
+            r1 = r2;
+            r2 = r3;
+            r3 = xq[jn];
+            if (WITH_ID) {
+              d0 = d1;
+              d1 = d2;
+              d2 = d3;
+              d3 = ids[jn];
+            }
+            fn(j, cur, cid, shx, shy, shz);
+          }
+        }
         a = b + 1;
       }
     }
   }
 }
 
-constexpr int kShellCap = RBE_MAX_SHELL_BATCH;
-
 // Accumulator of the per-particle force in the two precision forms.
+// add<true> evaluates Coulomb + LJ, add<false> LJ only (j neutral).
 template <bool F32>
 struct ForceAcc;
 template <>
 struct ForceAcc<false> {
   double v[3] = {0.0, 0.0, 0.0};
+  template <bool COUL>
   __device__ inline void add(const PairParams &pp, const PairF32 &, double r2, double qi, double qj, double dx,
                              double dy, double dz) {
-    const double sc = pair_scalar_f64(pp, r2, qi, qj);
+    const double sc = COUL ? pair_scalar_f64(pp, r2, qi, qj) : pair_scalar_lj_f64(pp, r2);
     v[0] = fma(sc, dx, v[0]);
     v[1] = fma(sc, dy, v[1]);
     v[2] = fma(sc, dz, v[2]);
@@ -163,9 +244,10 @@ struct ForceAcc<false> {
 template <>
 struct ForceAcc<true> {
   Kahan3 k;
+  template <bool COUL>
   __device__ inline void add(const PairParams &pp, const PairF32 &pf, double r2, double qi, double qj, double dx,
                              double dy, double dz) {
-    const float sc = pair_scalar_f32(pp, pf, r2, (float)(qi * qj));
+    const float sc = COUL ? pair_scalar_f32(pp, pf, r2, (float)(qi * qj)) : pair_scalar_lj_f32(pp, pf, r2);
     k.add(0, sc * (float)dx);
     k.add(1, sc * (float)dy);
     k.add(2, sc * (float)dz);
@@ -173,125 +255,237 @@ struct ForceAcc<true> {
   __device__ inline double get(int c) const { return k.get(c); }
 };
 
-template <bool F32, bool COUNT>
-__global__ void __launch_bounds__(256) k_pair(PairParams pp, PairF32 pf, int64_t n, const double4 *__restrict__ xq,
-                                              const int32_t *__restrict__ ids,
-                                              const int32_t *__restrict__ cell_start,
-                                              const int32_t *__restrict__ inv_id, double *__restrict__ fx,
-                                              double *__restrict__ fy, double *__restrict__ fz,
-                                              unsigned long long *__restrict__ counters) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
+struct PairCtx {
+  PairParams pp;
+  PairF32 pf;
+  const double4 *__restrict__ xq;
+  const int32_t *__restrict__ ids;
+  const int32_t *__restrict__ cell_start;
+  const int32_t *__restrict__ inv_id;
+  double *__restrict__ fx;
+  double *__restrict__ fy;
+  double *__restrict__ fz;
+  unsigned long long *__restrict__ counters;  // [4] when counting
+  int64_t i0, i1;                             // particle range of this launch
+  int64_t n;                                  // all particles
+};
+
+template <bool COUNT>
+__device__ inline void flush_counts(const PairCtx &c, unsigned long long n_coul, unsigned long long n_lj,
+                                    unsigned long long n_tested, unsigned long long n_shell) {
+  if (COUNT) {
+    atomicAdd(&c.counters[0], n_coul);
+    atomicAdd(&c.counters[1], n_lj);
+    atomicAdd(&c.counters[2], n_tested);
+    atomicAdd(&c.counters[3], n_shell);
+  }
+}
+
+// Plain cutoff sums for particle i. MODE 0: neutral i (LJ over both species
+// blocks out to r_lj); MODE 1: charged i (charged block out to
+// max(r_coul, r_lj), neutral block out to r_lj).
+template <bool F32, bool COUNT, int MODE>
+__global__ void __launch_bounds__(256) k_pair_plain(PairCtx c) {
+  const int64_t i = c.i0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= c.i1) return;
+  const PairParams &pp = c.pp;
   const Grid &g = pp.g;
-  const double4 pi4 = xq[i];
+  const double4 pi4 = c.xq[i];
   const double xi = pi4.x, yi = pi4.y, zi = pi4.z, qi = pi4.w;
   const int cx = cell_coord(xi, g.inv_h[0], g.nx);
   const int cy = cell_coord(yi, g.inv_h[1], g.ny);
   const int cz = cell_coord(zi, g.inv_h[2], g.nz);
   ForceAcc<F32> acc;
-  unsigned long long n_coul = 0, n_lj = 0, n_tested = 0, n_shell = 0;
-  const bool charged = qi != 0.0;
-  const bool shell_on = pp.rbl && (charged || pp.rlj2 > pp.rcore2);
-  auto count_pair = [&](double r2, double qj) {
-    if (COUNT) {
-      n_coul += (pp.do_coul && r2 <= pp.rc2 && charged && qj != 0.0);
-      n_lj += (pp.do_lj && r2 <= pp.rlj2);
+  unsigned long long n_coul = 0, n_lj = 0, n_tested = 0;
+  // Coulomb + LJ against charged j (block 0 of a charged i)
+  auto visit_q = [&](int j, const double4 &pj, int, double shx, double shy, double shz) {
+    const double dx = (xi - pj.x) - shx, dy = (yi - pj.y) - shy, dz = (zi - pj.z) - shz;
+    const double r2 = sq_dist(dx, dy, dz);
+    if (COUNT) ++n_tested;
+    if (r2 == 0.0 && j == (int)i) return;
+    if (r2 <= pp.rc2 || r2 <= pp.rlj2) {
+      acc.template add<true>(pp, c.pf, r2, qi, pj.w, dx, dy, dz);
+      if (COUNT) {
+        n_coul += (pp.do_coul && r2 <= pp.rc2);
+        n_lj += (pp.do_lj && r2 <= pp.rlj2);
+      }
     }
   };
+  // LJ only (every other species pairing)
+  auto visit_lj = [&](int j, const double4 &pj, int, double shx, double shy, double shz) {
+    const double dx = (xi - pj.x) - shx, dy = (yi - pj.y) - shy, dz = (zi - pj.z) - shz;
+    const double r2 = sq_dist(dx, dy, dz);
+    if (COUNT) ++n_tested;
+    if (r2 == 0.0 && j == (int)i) return;
+    if (r2 <= pp.rlj2) {
+      acc.template add<false>(pp, c.pf, r2, qi, pj.w, dx, dy, dz);
+      if (COUNT) n_lj += pp.do_lj;
+    }
+  };
+  if (MODE == 1) {
+    for_stencil<false>(g, c.cell_start, c.xq, c.ids, 0, cx, cy, cz, pp.s_coul, visit_q);
+    if (pp.do_lj) for_stencil<false>(g, c.cell_start, c.xq, c.ids, 1, cx, cy, cz, pp.s_lj, visit_lj);
+  } else if (pp.do_lj) {
+    for_stencil<false>(g, c.cell_start, c.xq, c.ids, 0, cx, cy, cz, pp.s_lj, visit_lj);
+    for_stencil<false>(g, c.cell_start, c.xq, c.ids, 1, cx, cy, cz, pp.s_lj, visit_lj);
+  }
+  c.fx[i] = acc.get(0);
+  c.fy[i] = acc.get(1);
+  c.fz[i] = acc.get(2);
+  flush_counts<COUNT>(c, n_coul, n_lj, n_tested, 0);
+}
 
-  if (!shell_on) {
-    // plain cutoff sums
-    auto plain = [&](int j, double shx, double shy, double shz) {
-      const double4 pj = xq[j];
-      const double dx = (xi - pj.x) - shx, dy = (yi - pj.y) - shy, dz = (zi - pj.z) - shz;
-      const double r2 = sq_dist(dx, dy, dz);
-      if (COUNT) ++n_tested;
-      if (r2 == 0.0 && j == (int)i) return;
-      if (r2 <= pp.rc2 || r2 <= pp.rlj2) {
-        acc.add(pp, pf, r2, qi, pj.w, dx, dy, dz);
-        count_pair(r2, pj.w);
+// Random batch list (Eq. 10-11) for particle i: exact core, ranked shell.
+// CAP >= p slots hold the smallest shell keys in ascending order.
+template <bool F32, bool COUNT, int CAP>
+__global__ void __launch_bounds__(256) k_pair_rbl(PairCtx c) {
+  const int64_t i = c.i0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= c.i1) return;
+  const PairParams &pp = c.pp;
+  const Grid &g = pp.g;
+  const double4 pi4 = c.xq[i];
+  const double xi = pi4.x, yi = pi4.y, zi = pi4.z, qi = pi4.w;
+  const int cx = cell_coord(xi, g.inv_h[0], g.nx);
+  const int cy = cell_coord(yi, g.inv_h[1], g.ny);
+  const int cz = cell_coord(zi, g.inv_h[2], g.nz);
+  ForceAcc<F32> acc;
+  unsigned long long n_coul = 0, n_lj = 0, n_tested = 0;
+  uint32_t keys[CAP];
+#pragma unroll
+  for (int t = 0; t < CAP; ++t) keys[t] = 0xFFFFFFFFu;
+  const ShellKey sk = shell_key_of(pp.shell_key, c.ids[i]);
+  int ns = 0;
+  auto visit = [&](int j, const double4 &pj, int idj, double shx, double shy, double shz) {
+    const double dx = (xi - pj.x) - shx, dy = (yi - pj.y) - shy, dz = (zi - pj.z) - shz;
+    const double r2 = sq_dist(dx, dy, dz);
+    if (COUNT) ++n_tested;
+    if (r2 == 0.0 && j == (int)i) return;
+    if (r2 <= pp.rcore2) {
+      acc.template add<true>(pp, c.pf, r2, qi, pj.w, dx, dy, dz);
+      if (COUNT) {
+        n_coul += (pp.do_coul && qi != 0.0 && pj.w != 0.0);
+        n_lj += (pp.do_lj && r2 <= pp.rlj2);
       }
-    };
-    if (charged) {
-      for_stencil(g, cell_start, 0, cx, cy, cz, pp.s_coul, plain);
-      if (pp.do_lj) for_stencil(g, cell_start, 1, cx, cy, cz, pp.s_lj, plain);
-    } else if (pp.do_lj) {
-      for_stencil(g, cell_start, 0, cx, cy, cz, pp.s_lj, plain);
-      for_stencil(g, cell_start, 1, cx, cy, cz, pp.s_lj, plain);
-    }
-  } else {
-    // random batch list: exact core, ranked shell
-    uint32_t keys[kShellCap];
+    } else if (r2 <= pp.rc2) {
+      ++ns;
+      const uint32_t k = shell_rank(sk, idj);
+      if (k < keys[CAP - 1]) {
+        uint32_t carry = k;
 #pragma unroll
-    for (int t = 0; t < kShellCap; ++t) keys[t] = 0xFFFFFFFFu;
-    const ShellKey sk = shell_key_of(pp.shell_key, ids[i]);
-    int ns = 0;
-    auto rbl = [&](int j, double shx, double shy, double shz) {
-      const double4 pj = xq[j];
-      const double dx = (xi - pj.x) - shx, dy = (yi - pj.y) - shy, dz = (zi - pj.z) - shz;
-      const double r2 = sq_dist(dx, dy, dz);
-      if (COUNT) ++n_tested;
-      if (r2 == 0.0 && j == (int)i) return;
-      if (r2 <= pp.rcore2) {
-        acc.add(pp, pf, r2, qi, pj.w, dx, dy, dz);
-        count_pair(r2, pj.w);
-      } else if (r2 <= pp.rc2) {
-        ++ns;
-        const uint32_t k = shell_rank(sk, ids[j]);
-        if (k < keys[kShellCap - 1]) {
-          uint32_t carry = k;
-#pragma unroll
-          for (int t = 0; t < kShellCap; ++t) {
-            const uint32_t lo = min(keys[t], carry);
-            carry = max(keys[t], carry);
-            keys[t] = lo;
-          }
+        for (int t = 0; t < CAP; ++t) {
+          const uint32_t lo = min(keys[t], carry);
+          carry = max(keys[t], carry);
+          keys[t] = lo;
         }
       }
-    };
-    for_stencil(g, cell_start, 0, cx, cy, cz, pp.s_coul, rbl);
-    for_stencil(g, cell_start, 1, cx, cy, cz, pp.s_coul, rbl);
-    if (ns > 0) {
-      const int nb = ns < pp.p_shell ? ns : pp.p_shell;
-      ForceAcc<F32> sh;
+    }
+  };
+  for_stencil<true>(g, c.cell_start, c.xq, c.ids, 0, cx, cy, cz, pp.s_coul, visit);
+  for_stencil<true>(g, c.cell_start, c.xq, c.ids, 1, cx, cy, cz, pp.s_coul, visit);
+  double f0 = acc.get(0), f1 = acc.get(1), f2 = acc.get(2);
+  if (ns > 0) {
+    const int nb = ns < pp.p_shell ? ns : pp.p_shell;
+    ForceAcc<F32> sh;
 #pragma unroll
-      for (int t = 0; t < kShellCap; ++t) {
-        if (t < nb) {
-          const int32_t idj = shell_id_of(sk, keys[t]);
-          if ((uint32_t)idj >= (uint32_t)n) continue;  // bad ids (flagged by the inverse map)
-          const int j = inv_id[idj];
-          if ((uint32_t)j >= (uint32_t)n) continue;
-          const double4 pj = xq[j];
-          const double dx = min_image(xi - pj.x, g.L[0]);
-          const double dy = min_image(yi - pj.y, g.L[1]);
-          const double dz = min_image(zi - pj.z, g.L[2]);
-          const double r2 = sq_dist(dx, dy, dz);
-          sh.add(pp, pf, r2, qi, pj.w, dx, dy, dz);
-          count_pair(r2, pj.w);
+    for (int t = 0; t < CAP; ++t) {
+      if (t < nb) {
+        const int32_t idj = shell_id_of(sk, keys[t]);
+        if ((uint32_t)idj >= (uint32_t)c.n) continue;  // bad ids (flagged by the inverse map)
+        const int j = c.inv_id[idj];
+        if ((uint32_t)j >= (uint32_t)c.n) continue;
+        const double4 pj = c.xq[j];
+        const double dx = min_image(xi - pj.x, g.L[0]);
+        const double dy = min_image(yi - pj.y, g.L[1]);
+        const double dz = min_image(zi - pj.z, g.L[2]);
+        const double r2 = sq_dist(dx, dy, dz);
+        sh.template add<true>(pp, c.pf, r2, qi, pj.w, dx, dy, dz);
+        if (COUNT) {
+          n_coul += (pp.do_coul && qi != 0.0 && pj.w != 0.0);
+          n_lj += (pp.do_lj && r2 <= pp.rlj2);
         }
       }
-      const double scale = (double)ns / (double)nb;
-      fx[i] = fma(scale, sh.get(0), acc.get(0));
-      fy[i] = fma(scale, sh.get(1), acc.get(1));
-      fz[i] = fma(scale, sh.get(2), acc.get(2));
-    } else {
-      fx[i] = acc.get(0);
-      fy[i] = acc.get(1);
-      fz[i] = acc.get(2);
     }
-    if (COUNT) n_shell = (unsigned long long)ns;
+    const double scale = (double)ns / (double)nb;
+    f0 = fma(scale, sh.get(0), f0);
+    f1 = fma(scale, sh.get(1), f1);
+    f2 = fma(scale, sh.get(2), f2);
   }
-  if (!shell_on) {
-    fx[i] = acc.get(0);
-    fy[i] = acc.get(1);
-    fz[i] = acc.get(2);
+  c.fx[i] = f0;
+  c.fy[i] = f1;
+  c.fz[i] = f2;
+  flush_counts<COUNT>(c, n_coul, n_lj, n_tested, (unsigned long long)ns);
+}
+
+// Shell part of the random batch list (Eq. 10-11) for a charged i whose core
+// terms were summed by the plain kernel with the Coulomb cutoff set to r_core:
+// every j with r_core^2 < r^2 <= r_coul^2 (same contraction-free r^2 as the
+// core test) is counted and ranked; the p smallest keys form the batch, whose
+// terms are added to f_i with the weight #S_i/|B_i|.
+template <bool F32, bool COUNT, int CAP>
+__global__ void __launch_bounds__(256) k_pair_shell(PairCtx c) {
+  const int64_t i = c.i0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= c.i1) return;
+  const PairParams &pp = c.pp;
+  const Grid &g = pp.g;
+  const double4 pi4 = c.xq[i];
+  const double xi = pi4.x, yi = pi4.y, zi = pi4.z, qi = pi4.w;
+  const int cx = cell_coord(xi, g.inv_h[0], g.nx);
+  const int cy = cell_coord(yi, g.inv_h[1], g.ny);
+  const int cz = cell_coord(zi, g.inv_h[2], g.nz);
+  uint32_t keys[CAP];
+#pragma unroll
+  for (int t = 0; t < CAP; ++t) keys[t] = 0xFFFFFFFFu;
+  const ShellKey sk = shell_key_of(pp.shell_key, c.ids[i]);
+  int ns = 0;
+  unsigned long long n_tested = 0, n_coul = 0, n_lj = 0;
+  auto visit = [&](int, const double4 &pj, int idj, double shx, double shy, double shz) {
+    const double dx = (xi - pj.x) - shx, dy = (yi - pj.y) - shy, dz = (zi - pj.z) - shz;
+    const double r2 = sq_dist(dx, dy, dz);
+    if (COUNT) ++n_tested;
+    if (r2 > pp.rcore2 && r2 <= pp.rc2) {
+      ++ns;
+      const uint32_t k = shell_rank(sk, idj);
+      if (k < keys[CAP - 1]) {
+        uint32_t carry = k;
+#pragma unroll
+        for (int t = 0; t < CAP; ++t) {
+          const uint32_t lo = min(keys[t], carry);
+          carry = max(keys[t], carry);
+          keys[t] = lo;
+        }
+      }
+    }
+  };
+  for_stencil<true>(g, c.cell_start, c.xq, c.ids, 0, cx, cy, cz, pp.s_coul, visit);
+  for_stencil<true>(g, c.cell_start, c.xq, c.ids, 1, cx, cy, cz, pp.s_coul, visit);
+  if (ns > 0) {
+    const int nb = ns < pp.p_shell ? ns : pp.p_shell;
+    ForceAcc<F32> sh;
+#pragma unroll
+    for (int t = 0; t < CAP; ++t) {
+      if (t < nb) {
+        const int32_t idj = shell_id_of(sk, keys[t]);
+        if ((uint32_t)idj >= (uint32_t)c.n) continue;  // bad ids (flagged by the inverse map)
+        const int j = c.inv_id[idj];
+        if ((uint32_t)j >= (uint32_t)c.n) continue;
+        const double4 pj = c.xq[j];
+        const double dx = min_image(xi - pj.x, g.L[0]);
+        const double dy = min_image(yi - pj.y, g.L[1]);
+        const double dz = min_image(zi - pj.z, g.L[2]);
+        const double r2 = sq_dist(dx, dy, dz);
+        sh.template add<true>(pp, c.pf, r2, qi, pj.w, dx, dy, dz);
+        if (COUNT) {
+          n_coul += (pp.do_coul && qi != 0.0 && pj.w != 0.0);
+          n_lj += (pp.do_lj && r2 <= pp.rlj2);
+        }
+      }
+    }
+    const double scale = (double)ns / (double)nb;
+    c.fx[i] = fma(scale, sh.get(0), c.fx[i]);
+    c.fy[i] = fma(scale, sh.get(1), c.fy[i]);
+    c.fz[i] = fma(scale, sh.get(2), c.fz[i]);
   }
-  if (COUNT) {
-    atomicAdd(&counters[0], n_coul);
-    atomicAdd(&counters[1], n_lj);
-    atomicAdd(&counters[2], n_tested);
-    atomicAdd(&counters[3], n_shell);
-  }
+  flush_counts<COUNT>(c, n_coul, n_lj, n_tested, (unsigned long long)ns);
 }
 
 static PairF32 make_f32(const PairParams &pp) {
@@ -305,26 +499,79 @@ static PairF32 make_f32(const PairParams &pp) {
   return pf;
 }
 
-template <bool F32>
-static void launch_pair(const PairParams &pp, int64_t n, const Sorted &s, const int32_t *cell_start,
-                        const int32_t *inv_id, double *fx, double *fy, double *fz, PairCounters cnt, hipStream_t st) {
+template <class K>
+static void launch_range(K kernel, PairCtx c, int64_t i0, int64_t i1, hipStream_t st) {
+  if (i1 <= i0) return;
+  c.i0 = i0;
+  c.i1 = i1;
+  const unsigned blocks = (unsigned)((i1 - i0 + 255) / 256);
+  kernel<<<blocks, 256, 0, st>>>(c);
+}
+
+template <bool F32, bool COUNT>
+static void launch_rbl(PairCtx c, int64_t i0, int64_t i1, bool split, hipStream_t st) {
+  const int p = c.pp.p_shell;
+  if (split) {
+    if (p <= 8) launch_range(k_pair_shell<F32, COUNT, 8>, c, i0, i1, st);
+    else if (p <= 16) launch_range(k_pair_shell<F32, COUNT, 16>, c, i0, i1, st);
+    else if (p <= 24) launch_range(k_pair_shell<F32, COUNT, 24>, c, i0, i1, st);
+    else launch_range(k_pair_shell<F32, COUNT, 32>, c, i0, i1, st);
+    return;
+  }
+  if (p <= 8) launch_range(k_pair_rbl<F32, COUNT, 8>, c, i0, i1, st);
+  else if (p <= 16) launch_range(k_pair_rbl<F32, COUNT, 16>, c, i0, i1, st);
+  else if (p <= 24) launch_range(k_pair_rbl<F32, COUNT, 24>, c, i0, i1, st);
+  else launch_range(k_pair_rbl<F32, COUNT, 32>, c, i0, i1, st);
+}
+
+// Charged particles occupy [0, nq) of the sorted order, neutral ones [nq, n).
+// With the random batch list and r_lj <= r_core, a charged particle's core is
+// the plain sum with the Coulomb cutoff set to r_core (same r^2 test), and its
+// shell is added by the shell kernel; otherwise one fused kernel does both.
+template <bool F32, bool COUNT>
+static void launch_all(PairCtx c, int64_t nq, hipStream_t st) {
+  const PairParams pp = c.pp;
+  if (pp.rbl) {
+    if (pp.rlj2 <= pp.rcore2) {
+      PairCtx core = c;
+      core.pp.rc2 = pp.rcore2;
+      core.pp.s_coul = pp.s_core;
+      launch_range(k_pair_plain<F32, COUNT, 1>, core, 0, nq, st);
+      launch_rbl<F32, COUNT>(c, 0, nq, true, st);
+      launch_range(k_pair_plain<F32, COUNT, 0>, c, nq, c.n, st);
+    } else {
+      launch_rbl<F32, COUNT>(c, 0, c.n, false, st);
+    }
+  } else {
+    launch_range(k_pair_plain<F32, COUNT, 1>, c, 0, nq, st);
+    launch_range(k_pair_plain<F32, COUNT, 0>, c, nq, c.n, st);
+  }
+}
+
+void launch_pair(int prec, const PairParams &pp, int64_t n, int64_t nq, const Sorted &s, const int32_t *cell_start,
+                 const int32_t *inv_id, double *fx, double *fy, double *fz, PairCounters cnt, hipStream_t st) {
   if (n <= 0) return;
-  const unsigned blocks = (unsigned)((n + 255) / 256);
-  const PairF32 pf = make_f32(pp);
-  if (cnt.c)
-    k_pair<F32, true><<<blocks, 256, 0, st>>>(pp, pf, n, s.xq, s.id, cell_start, inv_id, fx, fy, fz, cnt.c);
-  else
-    k_pair<F32, false><<<blocks, 256, 0, st>>>(pp, pf, n, s.xq, s.id, cell_start, inv_id, fx, fy, fz, nullptr);
-}
-
-void launch_pair_f64(const PairParams &pp, int64_t n, const Sorted &s, const int32_t *cell_start,
-                     const int32_t *inv_id, double *fx, double *fy, double *fz, PairCounters cnt, hipStream_t st) {
-  launch_pair<false>(pp, n, s, cell_start, inv_id, fx, fy, fz, cnt, st);
-}
-
-void launch_pair_f32c(const PairParams &pp, int64_t n, const Sorted &s, const int32_t *cell_start,
-                      const int32_t *inv_id, double *fx, double *fy, double *fz, PairCounters cnt, hipStream_t st) {
-  launch_pair<true>(pp, n, s, cell_start, inv_id, fx, fy, fz, cnt, st);
+  PairCtx c;
+  c.pp = pp;
+  c.pf = make_f32(pp);
+  c.xq = s.xq;
+  c.ids = s.id;
+  c.cell_start = cell_start;
+  c.inv_id = inv_id;
+  c.fx = fx;
+  c.fy = fy;
+  c.fz = fz;
+  c.counters = cnt.c;
+  c.n = n;
+  c.i0 = 0;
+  c.i1 = n;
+  if (prec == RBE_FP32C) {
+    if (cnt.c) launch_all<true, true>(c, nq, st);
+    else launch_all<true, false>(c, nq, st);
+  } else {
+    if (cnt.c) launch_all<false, true>(c, nq, st);
+    else launch_all<false, false>(c, nq, st);
+  }
 }
 
 }  // namespace rbe

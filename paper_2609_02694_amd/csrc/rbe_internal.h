@@ -97,7 +97,20 @@ __host__ __device__ inline int cell_coord(double w, double inv_h, int n) {
   return t >= (double)n ? n - 1 : 0;
 }
 
-__host__ __device__ inline int floor_div(int a, int n) { return a >= 0 ? a / n : -((-a + n - 1) / n); }
+// floor(a / n) for the small offsets of a stencil (|a| within a few n): a
+// compare-and-step loop instead of an integer division.
+__host__ __device__ inline int floor_div(int a, int n) {
+  int q = 0;
+  while (a < 0) {
+    a += n;
+    --q;
+  }
+  while (a >= n) {
+    a -= n;
+    ++q;
+  }
+  return q;
+}
 
 // ---------------------------------------------------------------------------
 // Mode tables for the sampler (host-built, copied to the device)
