@@ -40,7 +40,8 @@ FLOPS_GATHER_IK = 18
 BYTES_KICK_DRIFT = 120   # read f (24) v (24) x (24), write v (24) x (24)
 BYTES_KICK = 96          # read f (24) v (24), write v (24) f (24)
 
-DEFAULT_NCELL_H = {"plain3k": 4.3, "electrolyte1m": 3.08, "ions8m": 4.0, "subdomain64m": 2.5, "replica": 3.0}
+# cell edges picked by paper_2609_02694_amd.tune on MI355X
+DEFAULT_NCELL_H = {"plain3k": 4.29, "electrolyte1m": 3.078, "ions8m": 4.0, "subdomain64m": 2.5, "replica": 3.0}
 
 
 def parse():
@@ -141,7 +142,8 @@ def main():
                    "P": p["P"], "dt": p["dt"], "form": prec_name, "ncell": nc, "parallelism": "single GPU"},
         "event_ms_per_step": ev_ms / K,
         "kernels": kernels,
-        "counts_per_eval": {"coul_pairs": cnt[0], "lj_pairs": cnt[1], "candidates": cnt[2], "shell_members": cnt[3]},
+        "counts_per_eval": {k: dict(zip(("coul_pairs", "lj_pairs", "candidates", "shell_members"), v))
+                            for k, v in cnt.items()},
         "roofline": roof,
         "gen_s": round(t_gen, 2),
     }
@@ -159,8 +161,9 @@ def roofline(kernels, cnt, nq, p, prec, K):
     avg_s = kernels[name]["avg_us"] * 1e-6
     peak_alu = PEAK_FP64_TFLOPS if prec == 0 else PEAK_FP32_TFLOPS
     n, P = p["n"], p["P"]
-    if name == "pair":
-        work = FLOPS_COUL_PAIR * cnt[0] + FLOPS_LJ_PAIR * cnt[1] + OPS_SHELL_MEMBER * cnt[3]
+    if name.startswith("pair"):
+        c = cnt[name]
+        work = FLOPS_COUL_PAIR * c[0] + FLOPS_LJ_PAIR * c[1] + OPS_SHELL_MEMBER * c[3]
         ach = work / avg_s / 1e12
         return dict(kernel=name, bound="alu", achieved=ach, peak=peak_alu, unit="TFLOP/s", frac=ach / peak_alu,
                     traffic=None, work_per_launch=work)

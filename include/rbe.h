@@ -159,14 +159,17 @@ int rbe_step(rbe_ctx *ctx, rbe_state *s, int32_t nsteps, uint64_t first_eval, vo
 int rbe_sync_check(rbe_ctx *ctx, void *stream);
 
 /* Diagnostic counters of the last rbe_forces/rbe_step force evaluation
-   (host, 4 entries): [0] Coulomb pair terms evaluated (both charged, inside
-   r_coul), [1] LJ pair terms evaluated (inside r_lj), [2] candidate pairs
-   tested, [3] shell members ranked (sum of #S_i, Eq. 10).
+   (host, 12 entries = 3 near-field launches x 4): launch k in {0: charged
+   particles (plain sums or core), 1: shell of the random batch list,
+   2: neutral particles}; entry [4k + 0] Coulomb pair terms evaluated (both
+   charged, inside the cutoff), [4k + 1] LJ pair terms evaluated (inside
+   r_lj), [4k + 2] candidate pairs tested, [4k + 3] shell members ranked
+   (sum of #S_i, Eq. 10).
    Only filled when counting was enabled with rbe_set_counting(ctx, 1); the
    counting adds atomics to the near-field kernel and is meant for the
    roofline figures, not for timed runs. */
 int rbe_set_counting(rbe_ctx *ctx, int enable);
-int rbe_get_counters(rbe_ctx *ctx, int64_t *counters /* host, 4 */, void *stream);
+int rbe_get_counters(rbe_ctx *ctx, int64_t *counters /* host, 12 */, void *stream);
 
 /* Per-kernel timing with HIP events recorded on the call's stream around
    every launch of the kinds below (enable = 1 starts and clears the
@@ -176,7 +179,7 @@ int rbe_get_counters(rbe_ctx *ctx, int64_t *counters /* host, 4 */, void *stream
 enum {
   RBE_TK_BIN = 0,         /* keys, histogram, scan, stable placement        */
   RBE_TK_REORDER = 1,     /* reorder + packing of the sorted records        */
-  RBE_TK_PAIR = 2,        /* near-field kernel                              */
+  RBE_TK_PAIR = 2,        /* near field of the neutral particles            */
   RBE_TK_MEAN = 3,        /* Eq. 12 mean                                    */
   RBE_TK_SAMPLE = 4,      /* device mode sampler + mode conversion          */
   RBE_TK_RHO_PARTIAL = 5, /* structure-factor chunk partials                */
@@ -184,7 +187,9 @@ enum {
   RBE_TK_GATHER = 7,      /* Fourier force gather                           */
   RBE_TK_KICK_DRIFT = 8,  /* first half-kick + drift + wrap                 */
   RBE_TK_KICK = 9,        /* second half-kick (+ mean subtraction)          */
-  RBE_TIMING_KINDS = 10
+  RBE_TK_PAIR_CHARGED = 10, /* near field of the charged particles (core)   */
+  RBE_TK_PAIR_SHELL = 11, /* shell ranking and batch of Eq. 11              */
+  RBE_TIMING_KINDS = 12
 };
 int rbe_set_timing(rbe_ctx *ctx, int enable);
 int rbe_get_timing(rbe_ctx *ctx, double *ms_out /* host */, int64_t *launches_out /* host */, void *stream);

@@ -25,8 +25,8 @@ MAX_SHELL_BATCH = 32
 EXPORTED = ["rbe_create", "rbe_create_batch", "rbe_destroy", "rbe_last_error", "rbe_build_cells", "rbe_sample_k",
             "rbe_forces", "rbe_step", "rbe_sync_check", "rbe_set_counting", "rbe_get_counters", "rbe_set_timing",
             "rbe_get_timing"]
-TIMING_KINDS = ["bin", "reorder", "pair", "mean", "sample", "rho_partial", "rho_final", "gather", "kick_drift",
-                "kick"]
+TIMING_KINDS = ["bin", "reorder", "pair_neutral", "mean", "sample", "rho_partial", "rho_final", "gather",
+                "kick_drift", "kick", "pair_charged", "pair_shell"]
 
 
 class RbeError(RuntimeError):
@@ -254,9 +254,12 @@ class Context:
         self._ok(self.lib.rbe_set_counting(self.h, 1 if on else 0))
 
     def counters(self, stream=None):
-        arr = (ctypes.c_int64 * 4)()
+        """Counters of the last evaluation: {part: (coul_pairs, lj_pairs, candidates, shell_members)}."""
+        arr = (ctypes.c_int64 * 12)()
         self._ok(self.lib.rbe_get_counters(self.h, arr, _stream(stream)))
-        return list(arr)
+        v = list(arr)
+        return {name: tuple(v[4 * k: 4 * k + 4]) for k, name in enumerate(("pair_charged", "pair_shell",
+                                                                           "pair_neutral"))}
 
     def set_timing(self, on: bool):
         self._ok(self.lib.rbe_set_timing(self.h, 1 if on else 0))

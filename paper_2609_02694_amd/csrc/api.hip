@@ -310,7 +310,7 @@ extern "C" int rbe_create(rbe_ctx **out, const rbe_params *p, int64_t n_max, int
   c->err = b.alloc<int>(1);
   c->nq_dev = b.alloc<int32_t>(1);
   c->qstats = b.alloc<double>(2);
-  c->counters = b.alloc<unsigned long long>(4);
+  c->counters = b.alloc<unsigned long long>(12);
   if (!b.ok) {
     b.release();
     delete c;
@@ -318,7 +318,7 @@ extern "C" int rbe_create(rbe_ctx **out, const rbe_params *p, int64_t n_max, int
   }
   if (hipMemcpy(c->cdf_dev, c->cdf_host.data(), sizeof(double) * c->mt.total, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(c->err, 0, sizeof(int)) != hipSuccess ||
-      hipMemset(c->counters, 0, 4 * sizeof(unsigned long long)) != hipSuccess ||
+      hipMemset(c->counters, 0, 12 * sizeof(unsigned long long)) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
     b.release();
     delete c;
@@ -411,11 +411,22 @@ static int eval_sorted(rbe_ctx *c, int64_t n, int64_t nq, const int32_t *m, cons
       TScope ts(c, RBE_TK_REORDER, st);
       launch_inverse_ids(n, c->srt.id, c->inv_id, c->err, st);
     }
-    PairCounters cnt{c->counting ? c->counters : nullptr};
-    if (c->counting) launch_fill_i32((int32_t *)c->counters, 8, 0, st);
+    if (c->counting) launch_fill_i32((int32_t *)c->counters, 24, 0, st);
+    auto part_cnt = [&](int part) { return PairCounters{c->counting ? c->counters + 4 * part : nullptr}; };
+    {
+      TScope ts(c, RBE_TK_PAIR_CHARGED, st);
+      launch_pair(c->p.prec, PAIR_PART_CHARGED, pp, n, nq, c->srt, c->cell_start, c->inv_id, fx, fy, fz,
+                  part_cnt(PAIR_PART_CHARGED), st);
+    }
+    if (pp.rbl) {
+      TScope ts(c, RBE_TK_PAIR_SHELL, st);
+      launch_pair(c->p.prec, PAIR_PART_SHELL, pp, n, nq, c->srt, c->cell_start, c->inv_id, fx, fy, fz,
+                  part_cnt(PAIR_PART_SHELL), st);
+    }
     {
       TScope ts(c, RBE_TK_PAIR, st);
-      launch_pair(c->p.prec, pp, n, nq, c->srt, c->cell_start, c->inv_id, fx, fy, fz, cnt, st);
+      launch_pair(c->p.prec, PAIR_PART_NEUTRAL, pp, n, nq, c->srt, c->cell_start, c->inv_id, fx, fy, fz,
+                  part_cnt(PAIR_PART_NEUTRAL), st);
     }
     if (pp.rbl) {
       TScope ts(c, RBE_TK_MEAN, st);
@@ -656,11 +667,11 @@ extern "C" int rbe_set_counting(rbe_ctx *c, int enable) {
 extern "C" int rbe_get_counters(rbe_ctx *c, int64_t *counters, void *stream) {
   if (!c || !counters) return RBE_EINVAL;
   HIP_TRY(c, hipSetDevice(c->device));
-  unsigned long long h[4];
+  unsigned long long h[12];
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(c, hipMemcpyAsync(h, c->counters, sizeof h, hipMemcpyDeviceToHost, st));
   HIP_TRY(c, hipStreamSynchronize(st));
-  for (int i = 0; i < 4; ++i) counters[i] = (int64_t)h[i];
+  for (int i = 0; i < 12; ++i) counters[i] = (int64_t)h[i];
   return RBE_OK;
 }
 

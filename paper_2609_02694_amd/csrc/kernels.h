@@ -63,10 +63,14 @@ struct PairParams {
 struct PairCounters {
   unsigned long long *c;  // [4] or nullptr
 };
-// Near-field force of every particle; charged particles are [0, nq) of the
-// sorted order, neutral ones [nq, n).
-void launch_pair(int prec, const PairParams &pp, int64_t n, int64_t nq, const Sorted &s, const int32_t *cell_start,
-                 const int32_t *inv_id, double *fx, double *fy, double *fz, PairCounters cnt, hipStream_t st);
+// Near-field force; charged particles are [0, nq) of the sorted order,
+// neutral ones [nq, n). Launched in three parts, in this order: charged
+// particles (plain sums, or the core of the random batch list), the shell of
+// the random batch list (adds to the charged forces), neutral particles.
+enum { PAIR_PART_CHARGED = 0, PAIR_PART_SHELL = 1, PAIR_PART_NEUTRAL = 2 };
+void launch_pair(int prec, int part, const PairParams &pp, int64_t n, int64_t nq, const Sorted &s,
+                 const int32_t *cell_start, const int32_t *inv_id, double *fx, double *fy, double *fz, PairCounters cnt,
+                 hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Fourier part

@@ -189,8 +189,10 @@ __device__ inline void for_stencil(const Grid &g, const int32_t *__restrict__ ce
         const int j1 = cell_start[row + (b - qx * g.nx) + 1];
         const double shx = (double)qx * g.L[0];
         if (j0 < j1) {
-          // ring of four records: the load of j + 4 is issued before j is used;
-          // indices past the range are clamped to its last record (always valid)
+          // four fixed slots: slot k holds record j + k and is reloaded with
+          // j + k + 4 right after use, so each load has three candidates of
+          // work to complete behind it. Indices past the range are clamped to
+          // its last record (always a valid address).
           const int last = j1 - 1;
           double4 r0 = xq[j0], r1 = xq[min(j0 + 1, last)], r2 = xq[min(j0 + 2, last)], r3 = xq[min(j0 + 3, last)];
           int d0 = 0, d1 = 0, d2 = 0, d3 = 0;
@@ -201,21 +203,19 @@ __device__ inline void for_stencil(const Grid &g, const int32_t *__restrict__ ce
             d3 = ids[min(j0 + 3, last)];
           }
 #pragma unroll 1
-          for (int j = j0; j < j1; ++j) {
-            const double4 cur = r0;
-            const int cid = d0;
-            const int jn = min(j + 4, last);
-            r0 = r1;
-            r1 = r2;
-            r2 = r3;
-            r3 = xq[jn];
-            if (WITH_ID) {
-              d0 = d1;
-              d1 = d2;
-              d2 = d3;
-              d3 = ids[jn];
-            }
-            fn(j, cur, cid, shx, shy, shz);
+          for (int j = j0; j < j1; j += 4) {
+            fn(j, r0, d0, shx, shy, shz);
+            r0 = xq[min(j + 4, last)];
+            if (WITH_ID) d0 = ids[min(j + 4, last)];
+            if (j + 1 < j1) fn(j + 1, r1, d1, shx, shy, shz);
+            r1 = xq[min(j + 5, last)];
+            if (WITH_ID) d1 = ids[min(j + 5, last)];
+            if (j + 2 < j1) fn(j + 2, r2, d2, shx, shy, shz);
+            r2 = xq[min(j + 6, last)];
+            if (WITH_ID) d2 = ids[min(j + 6, last)];
+            if (j + 3 < j1) fn(j + 3, r3, d3, shx, shy, shz);
+            r3 = xq[min(j + 7, last)];
+            if (WITH_ID) d3 = ids[min(j + 7, last)];
           }
         }
         a = b + 1;
@@ -335,6 +335,16 @@ __global__ void __launch_bounds__(256) k_pair_plain(PairCtx c) {
   flush_counts<COUNT>(c, n_coul, n_lj, n_tested, 0);
 }
 
+// Sorted insertion of k into the ascending list L[0..CAP), dropping the
+// largest: the new L[t] is the (t+1)-th smallest of L and k, which is
+// min(L[t], max(L[t-1], k)); walking t downwards updates L in place.
+template <int CAP>
+__device__ inline void sorted_insert(uint32_t (&L)[CAP], uint32_t k) {
+#pragma unroll
+  for (int t = CAP - 1; t > 0; --t) L[t] = min(L[t], max(L[t - 1], k));
+  L[0] = min(L[0], k);
+}
+
 // Random batch list (Eq. 10-11) for particle i: exact core, ranked shell.
 // CAP >= p slots hold the smallest shell keys in ascending order.
 template <bool F32, bool COUNT, int CAP>
@@ -369,15 +379,7 @@ __global__ void __launch_bounds__(256) k_pair_rbl(PairCtx c) {
     } else if (r2 <= pp.rc2) {
       ++ns;
       const uint32_t k = shell_rank(sk, idj);
-      if (k < keys[CAP - 1]) {
-        uint32_t carry = k;
-#pragma unroll
-        for (int t = 0; t < CAP; ++t) {
-          const uint32_t lo = min(keys[t], carry);
-          carry = max(keys[t], carry);
-          keys[t] = lo;
-        }
-      }
+      if (k < keys[CAP - 1]) sorted_insert<CAP>(keys, k);
     }
   };
   for_stencil<true>(g, c.cell_start, c.xq, c.ids, 0, cx, cy, cz, pp.s_coul, visit);
@@ -416,28 +418,54 @@ __global__ void __launch_bounds__(256) k_pair_rbl(PairCtx c) {
   flush_counts<COUNT>(c, n_coul, n_lj, n_tested, (unsigned long long)ns);
 }
 
+constexpr int kShellThreads = 256;
+constexpr int kShellRoom = 16;  // buffer slots beyond the batch capacity
+
 // Shell part of the random batch list (Eq. 10-11) for a charged i whose core
 // terms were summed by the plain kernel with the Coulomb cutoff set to r_core:
 // every j with r_core^2 < r^2 <= r_coul^2 (same contraction-free r^2 as the
 // core test) is counted and ranked; the p smallest keys form the batch, whose
 // terms are added to f_i with the weight #S_i/|B_i|.
+//
+// Selection: each lane appends the keys below its threshold tau to its own
+// LDS buffer (CAP + kShellRoom slots). When a buffer fills, the buffers of the
+// wave are reduced to their p smallest keys and a full lane's tau becomes the
+// largest of them: any later key above tau has p smaller keys before it and
+// cannot be in the batch (keys are distinct). So a buffer always contains the
+// p smallest keys its lane has seen.
 template <bool F32, bool COUNT, int CAP>
-__global__ void __launch_bounds__(256) k_pair_shell(PairCtx c) {
-  const int64_t i = c.i0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(kShellThreads) k_pair_shell(PairCtx c) {
+  constexpr int B = CAP + kShellRoom;
+  __shared__ uint32_t sbuf[B * kShellThreads];
+  const int tid = threadIdx.x;
+  const int64_t i = c.i0 + blockIdx.x * (int64_t)blockDim.x + tid;
   if (i >= c.i1) return;
   const PairParams &pp = c.pp;
   const Grid &g = pp.g;
+  const int p = pp.p_shell;
   const double4 pi4 = c.xq[i];
   const double xi = pi4.x, yi = pi4.y, zi = pi4.z, qi = pi4.w;
   const int cx = cell_coord(xi, g.inv_h[0], g.nx);
   const int cy = cell_coord(yi, g.inv_h[1], g.ny);
   const int cz = cell_coord(zi, g.inv_h[2], g.nz);
-  uint32_t keys[CAP];
-#pragma unroll
-  for (int t = 0; t < CAP; ++t) keys[t] = 0xFFFFFFFFu;
   const ShellKey sk = shell_key_of(pp.shell_key, c.ids[i]);
-  int ns = 0;
+  int ns = 0, cnt = 0;
+  int sorted = 0;  // buf[0..sorted) is ascending (left by the last reduction)
+  uint32_t tau = 0xFFFFFFFFu;
+  bool have_tau = false;
   unsigned long long n_tested = 0, n_coul = 0, n_lj = 0;
+  // reduce the buffer to its min(p, cnt) smallest keys, sorted; returns them in L
+  auto reduce = [&](uint32_t (&L)[CAP]) {
+#pragma unroll
+    for (int t = 0; t < CAP; ++t) L[t] = t < sorted ? sbuf[t * kShellThreads + tid] : 0xFFFFFFFFu;
+    for (int t = sorted; t < cnt; ++t) sorted_insert<CAP>(L, sbuf[t * kShellThreads + tid]);
+    const int keep = cnt < p ? cnt : p;
+#pragma unroll
+    for (int t = 0; t < CAP; ++t)
+      if (t < keep) sbuf[t * kShellThreads + tid] = L[t];
+    cnt = keep;
+    sorted = keep;
+  };
   auto visit = [&](int, const double4 &pj, int idj, double shx, double shy, double shz) {
     const double dx = (xi - pj.x) - shx, dy = (yi - pj.y) - shy, dz = (zi - pj.z) - shz;
     const double r2 = sq_dist(dx, dy, dz);
@@ -445,26 +473,32 @@ __global__ void __launch_bounds__(256) k_pair_shell(PairCtx c) {
     if (r2 > pp.rcore2 && r2 <= pp.rc2) {
       ++ns;
       const uint32_t k = shell_rank(sk, idj);
-      if (k < keys[CAP - 1]) {
-        uint32_t carry = k;
+      if (!have_tau || k < tau) sbuf[cnt++ * kShellThreads + tid] = k;
+    }
+    // every active lane reduces when one lane's buffer is full (one pass of
+    // the wave instead of one per lane)
+    if (__any(cnt == B)) {
+      uint32_t L[CAP];
+      reduce(L);
+      if (cnt == p) {
 #pragma unroll
-        for (int t = 0; t < CAP; ++t) {
-          const uint32_t lo = min(keys[t], carry);
-          carry = max(keys[t], carry);
-          keys[t] = lo;
-        }
+        for (int t = 0; t < CAP; ++t)
+          if (t == p - 1) tau = L[t];
+        have_tau = true;
       }
     }
   };
   for_stencil<true>(g, c.cell_start, c.xq, c.ids, 0, cx, cy, cz, pp.s_coul, visit);
   for_stencil<true>(g, c.cell_start, c.xq, c.ids, 1, cx, cy, cz, pp.s_coul, visit);
   if (ns > 0) {
-    const int nb = ns < pp.p_shell ? ns : pp.p_shell;
+    uint32_t L[CAP];
+    reduce(L);
+    const int nb = cnt;  // = min(ns, p)
     ForceAcc<F32> sh;
 #pragma unroll
     for (int t = 0; t < CAP; ++t) {
       if (t < nb) {
-        const int32_t idj = shell_id_of(sk, keys[t]);
+        const int32_t idj = shell_id_of(sk, L[t]);
         if ((uint32_t)idj >= (uint32_t)c.n) continue;  // bad ids (flagged by the inverse map)
         const int j = c.inv_id[idj];
         if ((uint32_t)j >= (uint32_t)c.n) continue;
@@ -528,28 +562,32 @@ static void launch_rbl(PairCtx c, int64_t i0, int64_t i1, bool split, hipStream_
 // With the random batch list and r_lj <= r_core, a charged particle's core is
 // the plain sum with the Coulomb cutoff set to r_core (same r^2 test), and its
 // shell is added by the shell kernel; otherwise one fused kernel does both.
+// part: PAIR_PART_CHARGED, PAIR_PART_SHELL (after CHARGED) or PAIR_PART_NEUTRAL.
 template <bool F32, bool COUNT>
-static void launch_all(PairCtx c, int64_t nq, hipStream_t st) {
+static void launch_part(PairCtx c, int64_t nq, int part, hipStream_t st) {
   const PairParams pp = c.pp;
-  if (pp.rbl) {
-    if (pp.rlj2 <= pp.rcore2) {
-      PairCtx core = c;
+  const bool split = pp.rbl && pp.rlj2 <= pp.rcore2;
+  if (pp.rbl && !split) {
+    if (part == PAIR_PART_CHARGED) launch_rbl<F32, COUNT>(c, 0, c.n, false, st);
+    return;
+  }
+  if (part == PAIR_PART_CHARGED) {
+    PairCtx core = c;
+    if (split) {
       core.pp.rc2 = pp.rcore2;
       core.pp.s_coul = pp.s_core;
-      launch_range(k_pair_plain<F32, COUNT, 1>, core, 0, nq, st);
-      launch_rbl<F32, COUNT>(c, 0, nq, true, st);
-      launch_range(k_pair_plain<F32, COUNT, 0>, c, nq, c.n, st);
-    } else {
-      launch_rbl<F32, COUNT>(c, 0, c.n, false, st);
     }
+    launch_range(k_pair_plain<F32, COUNT, 1>, core, 0, nq, st);
+  } else if (part == PAIR_PART_SHELL) {
+    if (split) launch_rbl<F32, COUNT>(c, 0, nq, true, st);
   } else {
-    launch_range(k_pair_plain<F32, COUNT, 1>, c, 0, nq, st);
     launch_range(k_pair_plain<F32, COUNT, 0>, c, nq, c.n, st);
   }
 }
 
-void launch_pair(int prec, const PairParams &pp, int64_t n, int64_t nq, const Sorted &s, const int32_t *cell_start,
-                 const int32_t *inv_id, double *fx, double *fy, double *fz, PairCounters cnt, hipStream_t st) {
+void launch_pair(int prec, int part, const PairParams &pp, int64_t n, int64_t nq, const Sorted &s,
+                 const int32_t *cell_start, const int32_t *inv_id, double *fx, double *fy, double *fz, PairCounters cnt,
+                 hipStream_t st) {
   if (n <= 0) return;
   PairCtx c;
   c.pp = pp;
@@ -566,11 +604,11 @@ void launch_pair(int prec, const PairParams &pp, int64_t n, int64_t nq, const So
   c.i0 = 0;
   c.i1 = n;
   if (prec == RBE_FP32C) {
-    if (cnt.c) launch_all<true, true>(c, nq, st);
-    else launch_all<true, false>(c, nq, st);
+    if (cnt.c) launch_part<true, true>(c, nq, part, st);
+    else launch_part<true, false>(c, nq, part, st);
   } else {
-    if (cnt.c) launch_all<false, true>(c, nq, st);
-    else launch_all<false, false>(c, nq, st);
+    if (cnt.c) launch_part<false, true>(c, nq, part, st);
+    else launch_part<false, false>(c, nq, part, st);
   }
 }
 
