@@ -22,7 +22,8 @@ _lib = None
 
 def build() -> str:
     """Compile the generator with gcc (always recompiles)."""
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", _SRC, "-o", _LIB + ".tmp", "-lm"]
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", _SRC, "-o", _LIB + ".tmp",
+           "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(_LIB + ".tmp", _LIB)
     return _LIB
@@ -38,9 +39,10 @@ def _load():
     d, i64, u64 = ctypes.c_double, ctypes.c_int64, ctypes.c_uint64
     dp = ctypes.POINTER(ctypes.c_double)
     lib.gen_rsa_positions.argtypes = [u64, u64, i64, dp, d, i64, dp, dp, dp]
+    lib.gen_rsa_blocked.argtypes = [u64, u64, i64, dp, d, d, i64, dp, dp, dp]
     lib.gen_charges.argtypes = [u64, u64, i64, i64, i64, d, dp]
     lib.gen_velocities.argtypes = [u64, u64, i64, d, d, dp, dp, dp]
-    for f in (lib.gen_rsa_positions, lib.gen_charges, lib.gen_velocities):
+    for f in (lib.gen_rsa_positions, lib.gen_rsa_blocked, lib.gen_charges, lib.gen_velocities):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -59,6 +61,22 @@ def rsa_positions(seed: int, replica: int, n: int, L, dmin: float = 0.8, max_att
     if rc != 0:
         raise RuntimeError(f"gen_rsa_positions failed with status {rc}")
     return x, y, z
+
+
+def rsa_blocked(seed: int, replica: int, n: int, L, dmin: float = 0.8, block_edge: float = 4.0,
+                max_attempts: int = 100000):
+    """Blocked RSA (parallel, deterministic): see gen_rsa_blocked in rbe_gen.c."""
+    lib = _load()
+    Lv = np.ascontiguousarray(np.broadcast_to(np.asarray(L, dtype=np.float64), (3,)))
+    x, y, z = (np.empty(n, np.float64) for _ in range(3))
+    rc = lib.gen_rsa_blocked(seed, replica, n, _ptr(Lv), dmin, block_edge, max_attempts, _ptr(x), _ptr(y), _ptr(z))
+    if rc != 0:
+        raise RuntimeError(f"gen_rsa_blocked failed with status {rc}")
+    return x, y, z
+
+
+# systems at or above this size use the blocked RSA
+BLOCKED_RSA_MIN_N = 2_000_000
 
 
 def charges(seed: int, replica: int, n: int, n_plus: int, n_minus: int, qmag: float = 1.0):
@@ -147,7 +165,10 @@ def make_system(p: dict, replica: int = 0, dmin: float = 0.8) -> dict:
     n = p["n"]
     L = p["L"]
     seed = p["seed"]
-    x, y, z = rsa_positions(seed, replica, n, [L, L, L], dmin)
+    if n >= BLOCKED_RSA_MIN_N:
+        x, y, z = rsa_blocked(seed, replica, n, [L, L, L], dmin)
+    else:
+        x, y, z = rsa_positions(seed, replica, n, [L, L, L], dmin)
     nq = int(round(n * p["frac_charged"] / 2.0))
     q = charges(seed, replica, n, nq, nq)
     vx, vy, vz = velocities(seed, replica, n)

@@ -19,6 +19,8 @@
  *
  * Velocities: Maxwell-Boltzmann at temperature T for mass m (Box-Muller),
  * then the mean velocity is removed so the net momentum is zero.
+ *
+ * Large systems use the blocked RSA below (parallel, deterministic).
  */
 #include <math.h>
 #include <stdint.h>
@@ -122,6 +124,115 @@ int gen_rsa_positions(uint64_t seed, uint64_t replica, int64_t n, const double L
 }
 
 /* --------------------------------------------------------------------- */
+/* Blocked RSA for large systems                                          */
+/* --------------------------------------------------------------------- */
+/* The box is cut into an even number of blocks per axis (edge >= block_edge
+   >= d_min), each block receiving floor(N/NB) or floor(N/NB)+1 particles
+   (the first N mod NB blocks get one more). Blocks are filled colour by
+   colour (8 colours by the parity of the block indices); blocks of one colour
+   never touch, so they are filled in parallel, each by RSA inside the block
+   against every particle already placed within d_min (own block and earlier
+   colours). Every block draws from its own SplitMix64 stream, so the result
+   does not depend on the thread count. Finally the particle order is
+   shuffled (seeded Fisher-Yates) so that indices carry no spatial order. */
+#define TAG_BLK 0x424C4F434B525341ULL /* "BLOCKRSA" */
+
+int gen_rsa_blocked(uint64_t seed, uint64_t replica, int64_t n, const double L[3], double dmin, double block_edge,
+                    int64_t max_attempts, double *x, double *y, double *z) {
+  if (n < 0 || !(dmin > 0) || !(block_edge >= dmin)) return -1;
+  for (int d = 0; d < 3; ++d)
+    if (!(L[d] >= 2 * block_edge)) return -1;
+  int nb[3], nf[3], kf[3];
+  for (int d = 0; d < 3; ++d) {
+    nb[d] = 2 * (int)floor(L[d] / (2.0 * block_edge));
+    kf[d] = (int)floor(L[d] / nb[d] / dmin);
+    if (kf[d] < 1) kf[d] = 1;
+    nf[d] = nb[d] * kf[d];
+  }
+  const int64_t NB = (int64_t)nb[0] * nb[1] * nb[2];
+  const int64_t NF = (int64_t)nf[0] * nf[1] * nf[2];
+  int64_t *bstart = (int64_t *)malloc(sizeof(int64_t) * (NB + 1));
+  int64_t *head = (int64_t *)malloc(sizeof(int64_t) * NF);
+  int64_t *next = (int64_t *)malloc(sizeof(int64_t) * (n > 0 ? n : 1));
+  double *px = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+  double *py = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+  double *pz = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+  if (!bstart || !head || !next || !px || !py || !pz) {
+    free(bstart); free(head); free(next); free(px); free(py); free(pz);
+    return -2;
+  }
+  const int64_t base = n / NB, extra = n % NB;
+  bstart[0] = 0;
+  for (int64_t b = 0; b < NB; ++b) bstart[b + 1] = bstart[b] + base + (b < extra ? 1 : 0);
+  for (int64_t c = 0; c < NF; ++c) head[c] = -1;
+  const double d2min = dmin * dmin;
+  int failed = 0;
+  for (int color = 0; color < 8; ++color) {
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : failed)
+    for (int64_t b = 0; b < NB; ++b) {
+      const int bx = (int)(b % nb[0]), by = (int)((b / nb[0]) % nb[1]), bz = (int)(b / ((int64_t)nb[0] * nb[1]));
+      if ((bx & 1) + 2 * (by & 1) + 4 * (bz & 1) != color) continue;
+      const int bc[3] = {bx, by, bz};
+      uint64_t key = stream_key(seed, TAG_BLK, replica, (uint64_t)b);
+      uint64_t draw = 0;
+      for (int64_t i = bstart[b]; i < bstart[b + 1]; ++i) {
+        int placed = 0;
+        for (int64_t a = 0; a < max_attempts && !placed; ++a) {
+          double p[3];
+          int f[3];
+          for (int d = 0; d < 3; ++d) {
+            const double lo = L[d] * bc[d] / nb[d], hi = L[d] * (bc[d] + 1) / nb[d];
+            p[d] = lo + (hi - lo) * u53(sm_out(key, draw++));
+            if (p[d] >= hi) p[d] = lo;
+            int fc = (int)(p[d] / L[d] * nf[d]);
+            if (fc < bc[d] * kf[d]) fc = bc[d] * kf[d];
+            if (fc > (bc[d] + 1) * kf[d] - 1) fc = (bc[d] + 1) * kf[d] - 1;
+            f[d] = fc;
+          }
+          int ok = 1;
+          for (int oz = -1; oz <= 1 && ok; ++oz)
+            for (int oy = -1; oy <= 1 && ok; ++oy)
+              for (int ox = -1; ox <= 1 && ok; ++ox) {
+                const int wx = (f[0] + ox + nf[0]) % nf[0], wy = (f[1] + oy + nf[1]) % nf[1],
+                          wz = (f[2] + oz + nf[2]) % nf[2];
+                for (int64_t j = head[((int64_t)wz * nf[1] + wy) * nf[0] + wx]; j >= 0; j = next[j]) {
+                  double dx = p[0] - px[j], dy = p[1] - py[j], dz = p[2] - pz[j];
+                  dx -= L[0] * rint(dx / L[0]);
+                  dy -= L[1] * rint(dy / L[1]);
+                  dz -= L[2] * rint(dz / L[2]);
+                  if (dx * dx + dy * dy + dz * dz < d2min) { ok = 0; break; }
+                }
+              }
+          if (ok) {
+            px[i] = p[0]; py[i] = p[1]; pz[i] = p[2];
+            const int64_t cell = ((int64_t)f[2] * nf[1] + f[1]) * nf[0] + f[0];
+            next[i] = head[cell];
+            head[cell] = i;
+            placed = 1;
+          }
+        }
+        if (!placed) { failed = 1; break; }
+      }
+    }
+    if (failed) break;
+  }
+  if (!failed) {
+    /* seeded shuffle of the particle order */
+    uint64_t skey = stream_key(seed, TAG_BLK, replica, (uint64_t)NB + 1);
+    int64_t *perm = next; /* reuse */
+    for (int64_t i = 0; i < n; ++i) perm[i] = i;
+    for (int64_t i = n - 1; i > 0; --i) {
+      int64_t j = (int64_t)(u53(sm_out(skey, (uint64_t)i)) * (double)(i + 1));
+      if (j > i) j = i;
+      int64_t t = perm[i]; perm[i] = perm[j]; perm[j] = t;
+    }
+    for (int64_t i = 0; i < n; ++i) { x[i] = px[perm[i]]; y[i] = py[perm[i]]; z[i] = pz[perm[i]]; }
+  }
+  free(bstart); free(head); free(next); free(px); free(py); free(pz);
+  return failed ? -3 : 0;
+}
+
+/* --------------------------------------------------------------------- */
 /* Charges                                                                */
 /* --------------------------------------------------------------------- */
 
@@ -150,6 +261,7 @@ int gen_velocities(uint64_t seed, uint64_t replica, int64_t n, double kT, double
   const double sd = sqrt(kT / mass);
   const double two_pi = 6.283185307179586476925286766559;
   double *v[3] = {vx, vy, vz};
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     uint64_t key = stream_key(seed, TAG_VEL, replica, (uint64_t)i);
     for (int d = 0; d < 3; ++d) {

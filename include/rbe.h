@@ -189,7 +189,8 @@ enum {
   RBE_TK_KICK = 9,        /* second half-kick (+ mean subtraction)          */
   RBE_TK_PAIR_CHARGED = 10, /* near field of the charged particles (core)   */
   RBE_TK_PAIR_SHELL = 11, /* shell ranking and batch of Eq. 11              */
-  RBE_TIMING_KINDS = 12
+  RBE_TK_GHOST = 12,      /* ghost shell build and sort                     */
+  RBE_TIMING_KINDS = 13
 };
 int rbe_set_timing(rbe_ctx *ctx, int enable);
 int rbe_get_timing(rbe_ctx *ctx, double *ms_out /* host */, int64_t *launches_out /* host */, void *stream);

@@ -26,7 +26,7 @@ EXPORTED = ["rbe_create", "rbe_create_batch", "rbe_destroy", "rbe_last_error", "
             "rbe_forces", "rbe_step", "rbe_sync_check", "rbe_set_counting", "rbe_get_counters", "rbe_set_timing",
             "rbe_get_timing"]
 TIMING_KINDS = ["bin", "reorder", "pair_neutral", "mean", "sample", "rho_partial", "rho_final", "gather",
-                "kick_drift", "kick", "pair_charged", "pair_shell"]
+                "kick_drift", "kick", "pair_charged", "pair_shell", "ghost"]
 
 
 class RbeError(RuntimeError):

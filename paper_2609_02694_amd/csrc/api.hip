@@ -68,6 +68,8 @@ struct rbe_ctx {
   Sorted srt{};
   WorkSet ws[2]{};
   FourierBuffers fb{};
+  GhostBuffers gb{};
+  bool ghosts = false;
   int32_t *m_dev = nullptr;
   double *w_dev = nullptr;
   double *mean_part = nullptr, *mean = nullptr;
@@ -165,8 +167,13 @@ static int validate_params(const rbe_params *p, std::string *why) {
   }
   if (!(p->mass > 0) || !(p->dt >= 0)) return bad(RBE_EINVAL, "mass must be positive and dt non-negative");
   if (!(p->lj_sigma > 0) || !(p->lj_eps >= 0)) return bad(RBE_EINVAL, "bad LJ parameters");
-  if (p->ghost_width != 0.0) return bad(RBE_EINVAL, "ghost_width > 0 is not supported by this build");
   const double rmax = std::fmax(p->r_coul, p->r_lj);
+  if (!(p->ghost_width >= 0.0)) return bad(RBE_EINVAL, "ghost_width must be >= 0");
+  if (p->ghost_width > 0.0) {
+    if (p->ghost_width < rmax) return bad(RBE_EINVAL, "ghost_width must cover the largest cutoff");
+    for (int d = 0; d < 3; ++d)
+      if (p->ghost_width > 0.5 * p->L[d]) return bad(RBE_EBOX, "ghost_width exceeds half the box edge");
+  }
   for (int d = 0; d < 3; ++d)
     if (rmax > 0.5 * p->L[d]) {
       snprintf(msg, sizeof msg, "cutoff %.6g exceeds half the box edge %.6g (minimum image)", rmax, p->L[d]);
@@ -235,6 +242,17 @@ extern "C" int rbe_create(rbe_ctx **out, const rbe_params *p, int64_t n_max, int
     g.L[d] = p->L[d];
     g.inv_h[d] = (double)nc[d] / p->L[d];
     c->p.ncell[d] = nc[d];
+    // ghost layers: enough cells to hold every image within ghost_width
+    g.goff[d] = p->ghost_width > 0 ? (int)std::ceil(p->ghost_width * g.inv_h[d] * (1.0 + 1e-12)) : 0;
+  }
+  g.ghost_width = p->ghost_width;
+  g.pnx = g.nx + 2 * g.goff[0];
+  g.pny = g.ny + 2 * g.goff[1];
+  g.pnz = g.nz + 2 * g.goff[2];
+  g.pncell = g.pnx * g.pny * g.pnz;
+  if (p->ghost_width > 0 && (int64_t)g.pnx * g.pny * g.pnz >= (1LL << 29)) {
+    delete c;
+    return create_fail(RBE_EINVAL, "padded cell grid too large");
   }
   PairParams &pp = c->pp;
   pp.g = g;
@@ -311,6 +329,33 @@ extern "C" int rbe_create(rbe_ctx **out, const rbe_params *p, int64_t n_max, int
   c->nq_dev = b.alloc<int32_t>(1);
   c->qstats = b.alloc<double>(2);
   c->counters = b.alloc<unsigned long long>(12);
+  if (p->ghost_width > 0) {
+    // ghost capacity: the expected image count of a uniform fluid with 30 %
+    // headroom (at most 7 images per native); overflow is flagged, not written
+    double vol = 1.0;
+    for (int d = 0; d < 3; ++d) vol *= 1.0 + 2.0 * p->ghost_width / p->L[d];
+    int64_t cap = (int64_t)std::ceil(1.3 * (double)n_max * (vol - 1.0)) + 4096;
+    if (cap > 7 * n_max + 4096) cap = 7 * n_max + 4096;
+    if (cap + n_max >= (int64_t)0x7FFFFFFF) cap = (int64_t)0x7FFFFFFF - n_max - 1;
+    GhostBuffers &gb = c->gb;
+    gb.cap = cap;
+    const int64_t pkeys = 2 * (int64_t)g.pncell;
+    gb.raw_xq = b.alloc<double4>(cap);
+    gb.raw_id = b.alloc<int32_t>(cap);
+    gb.xq = b.alloc<double4>(cap);
+    gb.id = b.alloc<int32_t>(cap);
+    gb.cell_start = b.alloc<int32_t>(pkeys + 1);
+    gb.cell_count = b.alloc<int32_t>(pkeys);
+    gb.cell_scan_tmp = b.alloc<int32_t>(scan_tiles(pkeys));
+    gb.flags = b.alloc<int32_t>(n_max + cap);
+    gb.offs = b.alloc<int32_t>(n_max + cap + 1);
+    gb.scan_tmp = b.alloc<int32_t>(scan_tiles(n_max + cap));
+    gb.count = b.alloc<int32_t>(1);
+    gb.key = b.alloc<int32_t>(cap);
+    gb.slot = b.alloc<int32_t>(cap);
+    gb.tmp = b.alloc<int32_t>(cap);
+    c->ghosts = true;
+  }
   if (!b.ok) {
     b.release();
     delete c;
@@ -411,21 +456,27 @@ static int eval_sorted(rbe_ctx *c, int64_t n, int64_t nq, const int32_t *m, cons
       TScope ts(c, RBE_TK_REORDER, st);
       launch_inverse_ids(n, c->srt.id, c->inv_id, c->err, st);
     }
+    const GhostBuffers *gb = nullptr;
+    if (c->ghosts) {
+      TScope ts(c, RBE_TK_GHOST, st);
+      launch_build_ghosts(c->g, n, c->srt, c->gb, c->err, st);
+      gb = &c->gb;
+    }
     if (c->counting) launch_fill_i32((int32_t *)c->counters, 24, 0, st);
     auto part_cnt = [&](int part) { return PairCounters{c->counting ? c->counters + 4 * part : nullptr}; };
     {
       TScope ts(c, RBE_TK_PAIR_CHARGED, st);
-      launch_pair(c->p.prec, PAIR_PART_CHARGED, pp, n, nq, c->srt, c->cell_start, c->inv_id, fx, fy, fz,
+      launch_pair(c->p.prec, PAIR_PART_CHARGED, pp, n, nq, c->srt, c->cell_start, c->inv_id, gb, fx, fy, fz,
                   part_cnt(PAIR_PART_CHARGED), st);
     }
     if (pp.rbl) {
       TScope ts(c, RBE_TK_PAIR_SHELL, st);
-      launch_pair(c->p.prec, PAIR_PART_SHELL, pp, n, nq, c->srt, c->cell_start, c->inv_id, fx, fy, fz,
+      launch_pair(c->p.prec, PAIR_PART_SHELL, pp, n, nq, c->srt, c->cell_start, c->inv_id, gb, fx, fy, fz,
                   part_cnt(PAIR_PART_SHELL), st);
     }
     {
       TScope ts(c, RBE_TK_PAIR, st);
-      launch_pair(c->p.prec, PAIR_PART_NEUTRAL, pp, n, nq, c->srt, c->cell_start, c->inv_id, fx, fy, fz,
+      launch_pair(c->p.prec, PAIR_PART_NEUTRAL, pp, n, nq, c->srt, c->cell_start, c->inv_id, gb, fx, fy, fz,
                   part_cnt(PAIR_PART_NEUTRAL), st);
     }
     if (pp.rbl) {
@@ -655,6 +706,7 @@ extern "C" int rbe_sync_check(rbe_ctx *c, void *stream) {
   if (flag & kErrNonFinite) return c->fail(RBE_ENONFINITE, "non-finite velocity or force seen on the device");
   if (flag & kErrBadId) return c->fail(RBE_ERANGE, "a particle id lies outside [0, n)");
   if (flag & kErrSampler) return c->fail(RBE_EINVAL, "mode sampler rejected every attempt");
+  if (flag & kErrGhostOverflow) return c->fail(RBE_ERANGE, "the ghost shell exceeded its capacity");
   return RBE_OK;
 }
 

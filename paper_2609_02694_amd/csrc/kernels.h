@@ -45,6 +45,28 @@ void launch_scatter_forces(int64_t n, const int32_t *perm, const double *fx, con
 void launch_count_charged(int64_t n, const double *q, int32_t *out, hipStream_t st);
 
 // ---------------------------------------------------------------------------
+// ghost shell (ghost_width > 0)
+// ---------------------------------------------------------------------------
+struct GhostBuffers {
+  int64_t cap;             // ghost capacity
+  double4 *raw_xq;         // [cap] ghost records in creation order
+  int32_t *raw_id;         // [cap]
+  double4 *xq;             // [cap] sorted by (species, padded cell)
+  int32_t *id;             // [cap]
+  int32_t *cell_start;     // [2 * pncell + 1]
+  int32_t *cell_count;     // [2 * pncell]
+  int32_t *cell_scan_tmp;  // [scan_tiles(2 * pncell)]
+  int32_t *flags;          // [n_max + cap]
+  int32_t *offs;           // [n_max + cap + 1]
+  int32_t *scan_tmp;       // [scan_tiles(n_max + cap)]
+  int32_t *count;          // [1] ghosts made (device)
+  int32_t *key, *slot, *tmp;  // [cap]
+};
+// Builds and sorts the ghost shell of the sorted natives s[0..n).
+void launch_build_ghosts(const Grid &g, int64_t n, const Sorted &s, const GhostBuffers &gb, int *err,
+                         hipStream_t st);
+
+// ---------------------------------------------------------------------------
 // near field
 // ---------------------------------------------------------------------------
 struct PairParams {
@@ -68,9 +90,10 @@ struct PairCounters {
 // particles (plain sums, or the core of the random batch list), the shell of
 // the random batch list (adds to the charged forces), neutral particles.
 enum { PAIR_PART_CHARGED = 0, PAIR_PART_SHELL = 1, PAIR_PART_NEUTRAL = 2 };
+// gb: ghost shell of the natives (nullptr for the periodic traversal).
 void launch_pair(int prec, int part, const PairParams &pp, int64_t n, int64_t nq, const Sorted &s,
-                 const int32_t *cell_start, const int32_t *inv_id, double *fx, double *fy, double *fz, PairCounters cnt,
-                 hipStream_t st);
+                 const int32_t *cell_start, const int32_t *inv_id, const GhostBuffers *gb, double *fx, double *fy,
+                 double *fz, PairCounters cnt, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Fourier part

@@ -159,11 +159,44 @@ __device__ inline double min_image(double a, double L) {
   return a - L * rint(a / L);
 }
 
-// Calls fn(j, p_j, id_j, shx, shy, shz) for every particle j of species block
-// `blk` in the (2s+1)^3 cells around (cx, cy, cz); (shx, shy, shz) is the
-// image shift of j (its image lies at r_j + shift). Records are prefetched
-// four ahead, so several loads are in flight per lane.
-// id_j is loaded only when WITH_ID (else 0).
+// Calls fn(j, p_j, id_j, shx, shy, shz) for the records j0..j1-1 of xq (and
+// ids when WITH_ID, else id_j = 0). Four fixed slots: slot k holds record
+// j + k and is reloaded with j + k + 4 right after use, so each load has
+// three candidates of work to complete behind it. Indices past the range are
+// clamped to its last record (always a valid address).
+template <bool WITH_ID, class Fn>
+__device__ inline void scan_range(const double4 *__restrict__ xq, const int32_t *__restrict__ ids, int j0, int j1,
+                                  double shx, double shy, double shz, Fn &&fn) {
+  if (j0 >= j1) return;
+  const int last = j1 - 1;
+  double4 r0 = xq[j0], r1 = xq[min(j0 + 1, last)], r2 = xq[min(j0 + 2, last)], r3 = xq[min(j0 + 3, last)];
+  int d0 = 0, d1 = 0, d2 = 0, d3 = 0;
+  if (WITH_ID) {
+    d0 = ids[j0];
+    d1 = ids[min(j0 + 1, last)];
+    d2 = ids[min(j0 + 2, last)];
+    d3 = ids[min(j0 + 3, last)];
+  }
+#pragma unroll 1
+  for (int j = j0; j < j1; j += 4) {
+    fn(j, r0, d0, shx, shy, shz);
+    r0 = xq[min(j + 4, last)];
+    if (WITH_ID) d0 = ids[min(j + 4, last)];
+    if (j + 1 < j1) fn(j + 1, r1, d1, shx, shy, shz);
+    r1 = xq[min(j + 5, last)];
+    if (WITH_ID) d1 = ids[min(j + 5, last)];
+    if (j + 2 < j1) fn(j + 2, r2, d2, shx, shy, shz);
+    r2 = xq[min(j + 6, last)];
+    if (WITH_ID) d2 = ids[min(j + 6, last)];
+    if (j + 3 < j1) fn(j + 3, r3, d3, shx, shy, shz);
+    r3 = xq[min(j + 7, last)];
+    if (WITH_ID) d3 = ids[min(j + 7, last)];
+  }
+}
+
+// Periodic traversal: every particle j of species block `blk` in the
+// (2s+1)^3 cells around (cx, cy, cz); (shx, shy, shz) is the image shift of j
+// (its image lies at r_j + shift).
 template <bool WITH_ID, class Fn>
 __device__ inline void for_stencil(const Grid &g, const int32_t *__restrict__ cell_start,
                                    const double4 *__restrict__ xq, const int32_t *__restrict__ ids, int blk, int cx,
@@ -187,39 +220,35 @@ __device__ inline void for_stencil(const Grid &g, const int32_t *__restrict__ ce
         const int b = min(a_end, (qx + 1) * g.nx - 1);
         const int j0 = cell_start[row + (a - qx * g.nx)];
         const int j1 = cell_start[row + (b - qx * g.nx) + 1];
-        const double shx = (double)qx * g.L[0];
-        if (j0 < j1) {
-          // four fixed slots: slot k holds record j + k and is reloaded with
-          // j + k + 4 right after use, so each load has three candidates of
-          // work to complete behind it. Indices past the range are clamped to
-          // its last record (always a valid address).
-          const int last = j1 - 1;
-          double4 r0 = xq[j0], r1 = xq[min(j0 + 1, last)], r2 = xq[min(j0 + 2, last)], r3 = xq[min(j0 + 3, last)];
-          int d0 = 0, d1 = 0, d2 = 0, d3 = 0;
-          if (WITH_ID) {
-            d0 = ids[j0];
-            d1 = ids[min(j0 + 1, last)];
-            d2 = ids[min(j0 + 2, last)];
-            d3 = ids[min(j0 + 3, last)];
-          }
-#pragma unroll 1
-          for (int j = j0; j < j1; j += 4) {
-            fn(j, r0, d0, shx, shy, shz);
-            r0 = xq[min(j + 4, last)];
-            if (WITH_ID) d0 = ids[min(j + 4, last)];
-            if (j + 1 < j1) fn(j + 1, r1, d1, shx, shy, shz);
-            r1 = xq[min(j + 5, last)];
-            if (WITH_ID) d1 = ids[min(j + 5, last)];
-            if (j + 2 < j1) fn(j + 2, r2, d2, shx, shy, shz);
-            r2 = xq[min(j + 6, last)];
-            if (WITH_ID) d2 = ids[min(j + 6, last)];
-            if (j + 3 < j1) fn(j + 3, r3, d3, shx, shy, shz);
-            r3 = xq[min(j + 7, last)];
-            if (WITH_ID) d3 = ids[min(j + 7, last)];
-          }
-        }
+        scan_range<WITH_ID>(xq, ids, j0, j1, (double)qx * g.L[0], shy, shz, fn);
         a = b + 1;
       }
+    }
+  }
+}
+
+// Ghost-shell traversal (no periodic images): the natives of the stencil
+// rows that lie inside the native grid, then the ghosts of the same rows of
+// the padded grid. (cx, cy, cz) is a native cell.
+template <bool WITH_ID, class Fn>
+__device__ inline void for_stencil_ghost(const Grid &g, const int32_t *__restrict__ cell_start,
+                                         const double4 *__restrict__ xq, const int32_t *__restrict__ ids,
+                                         const int32_t *__restrict__ gcell_start, const double4 *__restrict__ gxq,
+                                         const int32_t *__restrict__ gid, int blk, int cx, int cy, int cz, int s,
+                                         Fn &&fn) {
+  const int base = blk * g.ncell;
+  const int pbase = blk * g.pncell;
+  const int xa = max(cx - s, 0), xb = min(cx + s, g.nx - 1);
+  for (int oz = -s; oz <= s; ++oz) {
+    const int z = cz + oz;
+    for (int oy = -s; oy <= s; ++oy) {
+      const int y = cy + oy;
+      if (z >= 0 && z < g.nz && y >= 0 && y < g.ny) {
+        const int row = base + (z * g.ny + y) * g.nx;
+        scan_range<WITH_ID>(xq, ids, cell_start[row + xa], cell_start[row + xb + 1], 0.0, 0.0, 0.0, fn);
+      }
+      const int prow = pbase + ((z + g.goff[2]) * g.pny + (y + g.goff[1])) * g.pnx + g.goff[0];
+      scan_range<WITH_ID>(gxq, gid, gcell_start[prow + cx - s], gcell_start[prow + cx + s + 1], 0.0, 0.0, 0.0, fn);
     }
   }
 }
@@ -268,7 +297,21 @@ struct PairCtx {
   unsigned long long *__restrict__ counters;  // [4] when counting
   int64_t i0, i1;                             // particle range of this launch
   int64_t n;                                  // all particles
+  // ghost shell (GHOST kernels only)
+  const double4 *__restrict__ gxq;
+  const int32_t *__restrict__ gid;
+  const int32_t *__restrict__ gcell_start;
 };
+
+// Stencil walk of the right kind for the kernel.
+template <bool GHOST, bool WITH_ID, class Fn>
+__device__ inline void stencil(const PairCtx &c, int blk, int cx, int cy, int cz, int s, Fn &&fn) {
+  if (GHOST)
+    for_stencil_ghost<WITH_ID>(c.pp.g, c.cell_start, c.xq, c.ids, c.gcell_start, c.gxq, c.gid, blk, cx, cy, cz, s,
+                               fn);
+  else
+    for_stencil<WITH_ID>(c.pp.g, c.cell_start, c.xq, c.ids, blk, cx, cy, cz, s, fn);
+}
 
 template <bool COUNT>
 __device__ inline void flush_counts(const PairCtx &c, unsigned long long n_coul, unsigned long long n_lj,
@@ -284,7 +327,7 @@ __device__ inline void flush_counts(const PairCtx &c, unsigned long long n_coul,
 // Plain cutoff sums for particle i. MODE 0: neutral i (LJ over both species
 // blocks out to r_lj); MODE 1: charged i (charged block out to
 // max(r_coul, r_lj), neutral block out to r_lj).
-template <bool F32, bool COUNT, int MODE>
+template <bool F32, bool COUNT, int MODE, bool GHOST>
 __global__ void __launch_bounds__(256) k_pair_plain(PairCtx c) {
   const int64_t i = c.i0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= c.i1) return;
@@ -323,11 +366,11 @@ __global__ void __launch_bounds__(256) k_pair_plain(PairCtx c) {
     }
   };
   if (MODE == 1) {
-    for_stencil<false>(g, c.cell_start, c.xq, c.ids, 0, cx, cy, cz, pp.s_coul, visit_q);
-    if (pp.do_lj) for_stencil<false>(g, c.cell_start, c.xq, c.ids, 1, cx, cy, cz, pp.s_lj, visit_lj);
+    stencil<GHOST, false>(c, 0, cx, cy, cz, pp.s_coul, visit_q);
+    if (pp.do_lj) stencil<GHOST, false>(c, 1, cx, cy, cz, pp.s_lj, visit_lj);
   } else if (pp.do_lj) {
-    for_stencil<false>(g, c.cell_start, c.xq, c.ids, 0, cx, cy, cz, pp.s_lj, visit_lj);
-    for_stencil<false>(g, c.cell_start, c.xq, c.ids, 1, cx, cy, cz, pp.s_lj, visit_lj);
+    stencil<GHOST, false>(c, 0, cx, cy, cz, pp.s_lj, visit_lj);
+    stencil<GHOST, false>(c, 1, cx, cy, cz, pp.s_lj, visit_lj);
   }
   c.fx[i] = acc.get(0);
   c.fy[i] = acc.get(1);
@@ -347,7 +390,7 @@ __device__ inline void sorted_insert(uint32_t (&L)[CAP], uint32_t k) {
 
 // Random batch list (Eq. 10-11) for particle i: exact core, ranked shell.
 // CAP >= p slots hold the smallest shell keys in ascending order.
-template <bool F32, bool COUNT, int CAP>
+template <bool F32, bool COUNT, int CAP, bool GHOST>
 __global__ void __launch_bounds__(256) k_pair_rbl(PairCtx c) {
   const int64_t i = c.i0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= c.i1) return;
@@ -382,8 +425,8 @@ __global__ void __launch_bounds__(256) k_pair_rbl(PairCtx c) {
       if (k < keys[CAP - 1]) sorted_insert<CAP>(keys, k);
     }
   };
-  for_stencil<true>(g, c.cell_start, c.xq, c.ids, 0, cx, cy, cz, pp.s_coul, visit);
-  for_stencil<true>(g, c.cell_start, c.xq, c.ids, 1, cx, cy, cz, pp.s_coul, visit);
+  stencil<GHOST, true>(c, 0, cx, cy, cz, pp.s_coul, visit);
+  stencil<GHOST, true>(c, 1, cx, cy, cz, pp.s_coul, visit);
   double f0 = acc.get(0), f1 = acc.get(1), f2 = acc.get(2);
   if (ns > 0) {
     const int nb = ns < pp.p_shell ? ns : pp.p_shell;
@@ -433,7 +476,7 @@ constexpr int kShellRoom = 16;  // buffer slots beyond the batch capacity
 // largest of them: any later key above tau has p smaller keys before it and
 // cannot be in the batch (keys are distinct). So a buffer always contains the
 // p smallest keys its lane has seen.
-template <bool F32, bool COUNT, int CAP>
+template <bool F32, bool COUNT, int CAP, bool GHOST>
 __global__ void __launch_bounds__(kShellThreads) k_pair_shell(PairCtx c) {
   constexpr int B = CAP + kShellRoom;
   __shared__ uint32_t sbuf[B * kShellThreads];
@@ -488,8 +531,8 @@ __global__ void __launch_bounds__(kShellThreads) k_pair_shell(PairCtx c) {
       }
     }
   };
-  for_stencil<true>(g, c.cell_start, c.xq, c.ids, 0, cx, cy, cz, pp.s_coul, visit);
-  for_stencil<true>(g, c.cell_start, c.xq, c.ids, 1, cx, cy, cz, pp.s_coul, visit);
+  stencil<GHOST, true>(c, 0, cx, cy, cz, pp.s_coul, visit);
+  stencil<GHOST, true>(c, 1, cx, cy, cz, pp.s_coul, visit);
   if (ns > 0) {
     uint32_t L[CAP];
     reduce(L);
@@ -542,20 +585,18 @@ static void launch_range(K kernel, PairCtx c, int64_t i0, int64_t i1, hipStream_
   kernel<<<blocks, 256, 0, st>>>(c);
 }
 
-template <bool F32, bool COUNT>
+template <bool F32, bool COUNT, bool GHOST>
 static void launch_rbl(PairCtx c, int64_t i0, int64_t i1, bool split, hipStream_t st) {
   const int p = c.pp.p_shell;
   if (split) {
-    if (p <= 8) launch_range(k_pair_shell<F32, COUNT, 8>, c, i0, i1, st);
-    else if (p <= 16) launch_range(k_pair_shell<F32, COUNT, 16>, c, i0, i1, st);
-    else if (p <= 24) launch_range(k_pair_shell<F32, COUNT, 24>, c, i0, i1, st);
-    else launch_range(k_pair_shell<F32, COUNT, 32>, c, i0, i1, st);
+    if (p <= 8) launch_range(k_pair_shell<F32, COUNT, 8, GHOST>, c, i0, i1, st);
+    else if (p <= 16) launch_range(k_pair_shell<F32, COUNT, 16, GHOST>, c, i0, i1, st);
+    else if (p <= 24) launch_range(k_pair_shell<F32, COUNT, 24, GHOST>, c, i0, i1, st);
+    else launch_range(k_pair_shell<F32, COUNT, 32, GHOST>, c, i0, i1, st);
     return;
   }
-  if (p <= 8) launch_range(k_pair_rbl<F32, COUNT, 8>, c, i0, i1, st);
-  else if (p <= 16) launch_range(k_pair_rbl<F32, COUNT, 16>, c, i0, i1, st);
-  else if (p <= 24) launch_range(k_pair_rbl<F32, COUNT, 24>, c, i0, i1, st);
-  else launch_range(k_pair_rbl<F32, COUNT, 32>, c, i0, i1, st);
+  if (p <= 16) launch_range(k_pair_rbl<F32, COUNT, 16, GHOST>, c, i0, i1, st);
+  else launch_range(k_pair_rbl<F32, COUNT, 32, GHOST>, c, i0, i1, st);
 }
 
 // Charged particles occupy [0, nq) of the sorted order, neutral ones [nq, n).
@@ -563,12 +604,12 @@ static void launch_rbl(PairCtx c, int64_t i0, int64_t i1, bool split, hipStream_
 // the plain sum with the Coulomb cutoff set to r_core (same r^2 test), and its
 // shell is added by the shell kernel; otherwise one fused kernel does both.
 // part: PAIR_PART_CHARGED, PAIR_PART_SHELL (after CHARGED) or PAIR_PART_NEUTRAL.
-template <bool F32, bool COUNT>
+template <bool F32, bool COUNT, bool GHOST>
 static void launch_part(PairCtx c, int64_t nq, int part, hipStream_t st) {
   const PairParams pp = c.pp;
   const bool split = pp.rbl && pp.rlj2 <= pp.rcore2;
   if (pp.rbl && !split) {
-    if (part == PAIR_PART_CHARGED) launch_rbl<F32, COUNT>(c, 0, c.n, false, st);
+    if (part == PAIR_PART_CHARGED) launch_rbl<F32, COUNT, GHOST>(c, 0, c.n, false, st);
     return;
   }
   if (part == PAIR_PART_CHARGED) {
@@ -577,17 +618,28 @@ static void launch_part(PairCtx c, int64_t nq, int part, hipStream_t st) {
       core.pp.rc2 = pp.rcore2;
       core.pp.s_coul = pp.s_core;
     }
-    launch_range(k_pair_plain<F32, COUNT, 1>, core, 0, nq, st);
+    launch_range(k_pair_plain<F32, COUNT, 1, GHOST>, core, 0, nq, st);
   } else if (part == PAIR_PART_SHELL) {
-    if (split) launch_rbl<F32, COUNT>(c, 0, nq, true, st);
+    if (split) launch_rbl<F32, COUNT, GHOST>(c, 0, nq, true, st);
   } else {
-    launch_range(k_pair_plain<F32, COUNT, 0>, c, nq, c.n, st);
+    launch_range(k_pair_plain<F32, COUNT, 0, GHOST>, c, nq, c.n, st);
+  }
+}
+
+template <bool GHOST>
+static void launch_prec(int prec, PairCtx c, int64_t nq, int part, hipStream_t st) {
+  if (prec == RBE_FP32C) {
+    if (c.counters) launch_part<true, true, GHOST>(c, nq, part, st);
+    else launch_part<true, false, GHOST>(c, nq, part, st);
+  } else {
+    if (c.counters) launch_part<false, true, GHOST>(c, nq, part, st);
+    else launch_part<false, false, GHOST>(c, nq, part, st);
   }
 }
 
 void launch_pair(int prec, int part, const PairParams &pp, int64_t n, int64_t nq, const Sorted &s,
-                 const int32_t *cell_start, const int32_t *inv_id, double *fx, double *fy, double *fz, PairCounters cnt,
-                 hipStream_t st) {
+                 const int32_t *cell_start, const int32_t *inv_id, const GhostBuffers *gb, double *fx, double *fy,
+                 double *fz, PairCounters cnt, hipStream_t st) {
   if (n <= 0) return;
   PairCtx c;
   c.pp = pp;
@@ -603,13 +655,11 @@ void launch_pair(int prec, int part, const PairParams &pp, int64_t n, int64_t nq
   c.n = n;
   c.i0 = 0;
   c.i1 = n;
-  if (prec == RBE_FP32C) {
-    if (cnt.c) launch_part<true, true>(c, nq, part, st);
-    else launch_part<true, false>(c, nq, part, st);
-  } else {
-    if (cnt.c) launch_part<false, true>(c, nq, part, st);
-    else launch_part<false, false>(c, nq, part, st);
-  }
+  c.gxq = gb ? gb->xq : nullptr;
+  c.gid = gb ? gb->id : nullptr;
+  c.gcell_start = gb ? gb->cell_start : nullptr;
+  if (gb) launch_prec<true>(prec, c, nq, part, st);
+  else launch_prec<false>(prec, c, nq, part, st);
 }
 
 }  // namespace rbe

@@ -73,6 +73,13 @@ struct Grid {
   int ncell;          // nx * ny * nz (keys run over 2 * ncell: charged, then neutral)
   double L[3];        // box
   double inv_h[3];    // n_d / L_d (cell scale used by the binning key)
+  // ghost shell (ghost_width > 0): the padded grid extends the native grid by
+  // goff[d] cells on both sides; cell c of the native grid is padded cell
+  // c + goff[d]. Zero layers without a ghost shell.
+  int goff[3];
+  int pnx, pny, pnz;  // padded cells per axis
+  int pncell;         // pnx * pny * pnz
+  double ghost_width;
 };
 
 // Wrap into [0, L): w = x - L floor(x / L); values pushed to L or below 0 by
@@ -141,6 +148,6 @@ void launch_sample_modes_dev_eval(const ModeTable &t, const double *cdf_dev, uin
 // ---------------------------------------------------------------------------
 // Error flag bits (device int)
 // ---------------------------------------------------------------------------
-enum : int { kErrNonFinite = 1, kErrBadId = 2, kErrSampler = 4 };
+enum : int { kErrNonFinite = 1, kErrBadId = 2, kErrSampler = 4, kErrGhostOverflow = 8 };
 
 }  // namespace rbe

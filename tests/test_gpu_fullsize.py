@@ -1,0 +1,100 @@
+"""GPU parity at the full workload sizes, on sampled particles.
+
+The oracle computes the near field of a sample of particles one by one
+(through its cell grid) and the Fourier force of the sample from the
+structure factors; the structure factors themselves are checked at sampled
+modes. Properties that hold at any size (zero net force, Eq. 12) cover what a
+sample cannot.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import rel_err, system, to_device
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2609_02694_amd as rbe  # noqa: E402
+
+NCELL_EDGE = {"electrolyte1m": 3.078, "ions8m": 4.0, "subdomain64m": 2.5}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rbe.load()
+
+
+def run_full(name, prec, ev=0, nsample=64, nmodes=8):
+    p, s = system(name)
+    n = p["n"]
+    nc = int(p["L"] // NCELL_EDGE[name])
+    params = rbe.params_from_preset(p, prec=prec, ncell=(nc, nc, nc))
+    ctx = rbe.Context(params, n)
+    st = to_device(s)
+    m, w = oracle.sample_k(p["seed"], ev, p["L"], p["alpha"], p["P"])
+    md = torch.as_tensor(m.ravel()).cuda()
+    wd = torch.as_tensor(w).cuda()
+    rho = torch.zeros(2 * p["P"], dtype=torch.float64, device="cuda")
+    ctx.forces(st, md, wd, ev, rho)
+    torch.cuda.synchronize()
+    ctx.sync_check()
+    F = np.stack([st.fx.cpu().numpy(), st.fy.cpu().numpy(), st.fz.cpu().numpy()], axis=1)
+    rho = rho.cpu().numpy()
+    ctx.close()
+    del st
+    torch.cuda.empty_cache()
+    P = p["P"]
+    rng = np.random.default_rng(7)
+    # structure factors at sampled modes
+    lm = np.sort(rng.choice(P, size=min(nmodes, P), replace=False))
+    re_o, im_o = oracle.rho(s["x"], s["y"], s["z"], s["q"], p["L"], m[:, lm])
+    scale = np.sqrt(np.count_nonzero(s["q"]))
+    tol_rho = 1e-12 if prec == rbe.FP64 else 1e-6
+    assert np.abs(rho[lm] - re_o).max() < tol_rho * scale
+    assert np.abs(rho[P + lm] - im_o).max() < tol_rho * scale
+    # near field + Fourier force of sampled particles (charged and neutral)
+    charged = np.flatnonzero(s["q"] != 0)
+    neutral = np.flatnonzero(s["q"] == 0)
+    idx = np.concatenate([rng.choice(charged, nsample // 2, replace=False),
+                          rng.choice(neutral, nsample // 2, replace=False) if len(neutral) else
+                          rng.choice(charged, nsample // 2, replace=False)])
+    osys = oracle.sys_from_preset(p)
+    FN = oracle.real_force(s["x"], s["y"], s["z"], s["q"], s["id"], osys, seed=p["seed"], ev=ev, idx=idx,
+                           cells=True)
+    FF, _, _ = oracle.fourier_force(s["x"][idx], s["y"][idx], s["z"][idx], s["q"][idx], p["L"], m, w,
+                                    rho[:P], rho[P:])
+    return p, s, F, idx, FN, FF
+
+
+def test_full_electrolyte1m_fp64():
+    """1M particles, core-shell list, FP64. Eq. 12's mean is pinned by
+    sum_i F_i = 0 (the Fourier part sums to zero) and by the sampled
+    differences F_i - F_j, which the mean cancels from."""
+    p, s, F, idx, FN, FF = run_full("electrolyte1m", rbe.FP64)
+    assert np.abs(F.sum(axis=0)).max() < 1e-9 * np.abs(F).sum() / len(F)
+    ref = FN + FF
+    mean_est = (ref - F[idx]).mean(axis=0)  # = (1/N) sum_j F~_j, the same for every i
+    e = rel_err(F[idx] + mean_est, ref)
+    print(f"electrolyte1m FP64 sampled rel err {e:.3e}, mean {mean_est}")
+    assert e < 1e-12
+    assert np.abs(mean_est).max() < 1.0
+
+
+def test_full_ions8m_fp32c():
+    p, s, F, idx, FN, FF = run_full("ions8m", rbe.FP32C)
+    e = rel_err(F[idx], FN + FF)
+    print(f"ions8m FP32C sampled rel err {e:.3e}")
+    assert e < 1e-5
+    # FP32 round-off of independent per-particle errors grows like sqrt(N)
+    rms = np.sqrt((F ** 2).sum() / len(F))
+    assert np.abs(F.sum(axis=0)).max() < 1e-5 * np.sqrt(len(F)) * rms
+
+
+def test_full_subdomain64m_fp32c():
+    p, s, F, idx, FN, FF = run_full("subdomain64m", rbe.FP32C)
+    e = rel_err(F[idx], FN + FF)
+    print(f"subdomain64m FP32C sampled rel err {e:.3e}")
+    assert e < 1e-5

@@ -232,3 +232,52 @@ def test_capacity_and_nonfinite_reported(plain3k):
         ctx.sync_check()
     assert e.value.code == rbe.RBE_ENONFINITE
     ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# ghost shell: the padded, non-periodic traversal equals the periodic sums
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec,tol", [(rbe.FP64, TOL64), (rbe.FP32C, TOL32)])
+def test_forces_ghost_shell_matches_periodic(prec, tol):
+    p, s = system("subdomain64m", n=40000)  # L = 36.8, ghost width 6
+    m, w = oracle.sample_k(p["seed"], 0, p["L"], p["alpha"], p["P"])
+    ref = oracle_forces(p, s, m, w, cells=True)
+    F = gpu_forces(p, s, prec=prec, m=m, w=w)
+    e = rel_err(F, ref["F"])
+    print(f"ghost shell 40k prec={prec} rel err {e:.3e}")
+    assert e < tol
+    # same result as the periodic traversal of the same system
+    pp = dict(p)
+    pp["ghost"] = 0.0
+    F2 = gpu_forces(pp, s, prec=prec, m=m, w=w)
+    assert rel_err(F, F2) < (1e-13 if prec == rbe.FP64 else 1e-6)
+
+
+def test_forces_ghost_shell_with_random_batch_list():
+    p, s = system("electrolyte1m", n=20000, ghost=6.0)
+    m, w = oracle.sample_k(p["seed"], 4, p["L"], p["alpha"], p["P"])
+    ref = oracle_forces(p, s, m, w, ev=4, cells=False)
+    F = gpu_forces(p, s, m=m, w=w, ev=4)
+    e = rel_err(F, ref["F"])
+    print(f"ghost shell + list 20k rel err {e:.3e}")
+    assert e < TOL64
+
+
+def test_step_ghost_shell_fp32c():
+    p, s = system("subdomain64m", n=30000)
+    params = rbe.params_from_preset(p, prec=rbe.FP32C)
+    ctx = rbe.Context(params, p["n"])
+    st = to_device(s)
+    ctx.forces(st, None, None, 0)
+    ctx.step(st, 5, 1)
+    torch.cuda.synchronize()
+    ctx.sync_check()
+    # the final force equals a fresh evaluation at the final positions (eval 5)
+    x = st.x.cpu().numpy(); y = st.y.cpu().numpy(); z = st.z.cpu().numpy()
+    q = st.q.cpu().numpy(); ids = st.id.cpu().numpy()
+    m, w = oracle.sample_k(p["seed"], 5, p["L"], p["alpha"], p["P"])
+    ref = oracle.total_force(x, y, z, q, ids, oracle.sys_from_preset(p), m, w, seed=p["seed"], ev=5, cells=True,
+                             components=False)["F"]
+    F = np.stack([st.fx.cpu().numpy(), st.fy.cpu().numpy(), st.fz.cpu().numpy()], axis=1)
+    assert rel_err(F, ref) < TOL32
+    ctx.close()
