@@ -174,3 +174,26 @@ def make_system(p: dict, replica: int = 0, dmin: float = 0.8) -> dict:
     vx, vy, vz = velocities(seed, replica, n)
     ids = np.arange(n, dtype=np.int32)
     return dict(x=x, y=y, z=z, vx=vx, vy=vy, vz=vz, q=q, id=ids, L=np.array([L, L, L], np.float64))
+
+
+def replica_stream_seed(seed: int, replica: int) -> int:
+    """Stream seed of replica ``replica``'s mode sample (distinct per replica)."""
+    return ((seed << 16) + replica) & ((1 << 64) - 1)
+
+
+def replica_batch(sizes, name: str = "replica"):
+    """Presets and systems of a batch of replicas of the given sizes.
+
+    Replica r draws its particles as replica r of the preset's seed; its
+    mode-sample stream seed is ``replica_stream_seed(seed, r)`` (stored as
+    ``p["stream_seed"]``). Returns the list of (preset, system) pairs, the
+    concatenated system (ids local to each replica) and the offsets."""
+    reps = []
+    for r, n in enumerate(sizes):
+        p = preset(name, n=int(n))
+        p["stream_seed"] = replica_stream_seed(p["seed"], r)
+        reps.append((p, make_system(p, replica=r)))
+    keys = ("x", "y", "z", "vx", "vy", "vz", "q", "id")
+    cat = {k: np.concatenate([s[k] for _, s in reps]) for k in keys}
+    offsets = np.concatenate([[0], np.cumsum([len(s["x"]) for _, s in reps])]).astype(np.int64)
+    return reps, cat, offsets

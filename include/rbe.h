@@ -103,10 +103,21 @@ typedef struct rbe_ctx rbe_ctx;
    r_core <= r_coul. On failure *out is NULL and the status says why. */
 int rbe_create(rbe_ctx **out, const rbe_params *p /* host */, int64_t n_max, int device);
 
-/* Batched form: n_sys independent systems, system s owning particles
-   [offset[s], offset[s+1]) of every state array. All systems share one
-   stream; a step of all of them runs as one persistent fused launch.
-   params and offset are host arrays of n_sys and n_sys + 1 entries. */
+/* Batched form: n_sys independent systems ("replicas"), replica s owning
+   particles [offset[s], offset[s+1]) of every state array (offset[0] = 0,
+   each replica at least one particle, offset[n_sys] < 2^31). params[s]
+   gives replica s its box L, cell grid ncell and stream seed; every other
+   field must be the same in all entries. The random batch list (r_core > 0)
+   and the ghost shell (ghost_width > 0) are not available in this form.
+   Each replica is an independent periodic system: its own cells, its own
+   mode sample of Eq. 9 (drawn from its own seed for the common eval) and its
+   own structure factors. rbe_forces and rbe_step then take the concatenated
+   state (n = offset[n_sys]); rbe_forces requires m, w and rho_out to be NULL.
+   rbe_step runs every velocity-Verlet step of all replicas as ONE persistent
+   launch (captured two steps at a time in a HIP graph) and returns each
+   replica's particles in cell order inside its own range. rbe_build_cells is
+   not available on a batched context. With n_sys == 1 this is rbe_create
+   with n_max = offset[1] - offset[0]. */
 int rbe_create_batch(rbe_ctx **out, int32_t n_sys, const rbe_params *params /* host */,
                      const int64_t *offset /* host */, int device);
 
@@ -190,7 +201,9 @@ enum {
   RBE_TK_PAIR_CHARGED = 10, /* near field of the charged particles (core)   */
   RBE_TK_PAIR_SHELL = 11, /* shell ranking and batch of Eq. 11              */
   RBE_TK_GHOST = 12,      /* ghost shell build and sort                     */
-  RBE_TIMING_KINDS = 13
+  RBE_TK_BATCH = 13,      /* persistent step of a batched context (one entry
+                             per step; the phases are not timed apart)      */
+  RBE_TIMING_KINDS = 14
 };
 int rbe_set_timing(rbe_ctx *ctx, int enable);
 int rbe_get_timing(rbe_ctx *ctx, double *ms_out /* host */, int64_t *launches_out /* host */, void *stream);

@@ -26,7 +26,7 @@ EXPORTED = ["rbe_create", "rbe_create_batch", "rbe_destroy", "rbe_last_error", "
             "rbe_forces", "rbe_step", "rbe_sync_check", "rbe_set_counting", "rbe_get_counters", "rbe_set_timing",
             "rbe_get_timing"]
 TIMING_KINDS = ["bin", "reorder", "pair_neutral", "mean", "sample", "rho_partial", "rho_final", "gather",
-                "kick_drift", "kick", "pair_charged", "pair_shell", "ghost"]
+                "kick_drift", "kick", "pair_charged", "pair_shell", "ghost", "batch"]
 
 
 class RbeError(RuntimeError):
@@ -211,6 +211,25 @@ class Context:
         rc = self.lib.rbe_create(ctypes.byref(h), ctypes.byref(params), n_max, device)
         _check(self.lib, None, rc)
         self.h = h
+
+    @classmethod
+    def batch(cls, params_list, offsets, device: int = 0) -> "Context":
+        """Batched context: replica r owns slots [offsets[r], offsets[r + 1]) of every array."""
+        self = cls.__new__(cls)
+        self.lib = load()
+        n_sys = len(params_list)
+        if len(offsets) != n_sys + 1:
+            raise ValueError("offsets needs n_sys + 1 entries")
+        arr = (Params * n_sys)(*params_list)
+        off = (ctypes.c_int64 * (n_sys + 1))(*[int(o) for o in offsets])
+        self.params = params_list[0]
+        self.params_list = list(params_list)
+        self.offsets = [int(o) for o in offsets]
+        h = ctypes.c_void_p()
+        rc = self.lib.rbe_create_batch(ctypes.byref(h), n_sys, arr, off, device)
+        _check(self.lib, None, rc)
+        self.h = h
+        return self
 
     def close(self):
         if getattr(self, "h", None):

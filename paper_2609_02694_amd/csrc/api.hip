@@ -46,6 +46,7 @@ struct Timer {
   bool on = false;
   std::vector<hipEvent_t> ev;
   std::vector<int> kind;  // kind of each recorded pair
+  std::vector<int> count; // launches inside each recorded pair
   size_t used = 0;
   double ms[RBE_TIMING_KINDS] = {};
   int64_t launches[RBE_TIMING_KINDS] = {};
@@ -80,6 +81,31 @@ struct rbe_ctx {
   bool counting = false;
   Timer tm;
   std::string last_error;
+  // batched form (nrep > 1)
+  struct Batch {
+    int nrep = 0;
+    std::vector<RepDesc> reps;  // host copy (nq and chunk layout refreshed per call)
+    std::vector<int64_t> off;   // [nrep + 1]
+    int64_t ntot = 0, nkeys = 0;
+    int ntiles = 0, blocks = 0;
+    int64_t part_chunks = 0;    // chunk capacity of the partial array
+    RepDesc *reps_dev = nullptr;
+    int32_t *rep_of = nullptr, *key = nullptr, *slot = nullptr, *tmp = nullptr, *count = nullptr;
+    int32_t *tile_sum = nullptr, *nq = nullptr;
+    int64_t *off_dev = nullptr;
+    double *qs = nullptr, *wk = nullptr;
+    GatherMode *modes = nullptr;
+    double2 *part = nullptr;
+    unsigned *bar = nullptr;
+    uint64_t *eval = nullptr;
+    uint64_t eval_stage = 0;
+    int rho_items = 0;
+    BatchArgs node_args[2]{};  // arguments of the two graph nodes
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_rho_items = -1;
+  } bt;
+  bool batched() const { return bt.nrep > 0; }
 
   int fail(int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
 };
@@ -117,22 +143,24 @@ static void timer_flush(rbe_ctx *c, hipStream_t st) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, t.ev[2 * k], t.ev[2 * k + 1]) == hipSuccess) {
       t.ms[t.kind[k]] += ms;
-      t.launches[t.kind[k]] += 1;
+      t.launches[t.kind[k]] += t.count[k];
     }
   }
   t.used = 0;
   t.kind.clear();
+  t.count.clear();
 }
 
 struct TScope {
   rbe_ctx *c;
   hipStream_t st;
   bool on;
-  TScope(rbe_ctx *c_, int kind, hipStream_t st_) : c(c_), st(st_), on(c_->tm.on) {
+  TScope(rbe_ctx *c_, int kind, hipStream_t st_, int launches = 1) : c(c_), st(st_), on(c_->tm.on) {
     if (!on) return;
     Timer &t = c->tm;
     if (t.used + 2 > t.ev.size()) timer_flush(c, st);
     t.kind.push_back(kind);
+    t.count.push_back(launches);
     (void)hipEventRecord(t.ev[t.used], st);
   }
   ~TScope() {
@@ -206,6 +234,53 @@ static int stencil_radius(double r, double L, int n) {
   return s < 1 ? 1 : s;
 }
 
+// Pair constants and stencil radii of one grid (p->terms already defaulted).
+static void make_pair_params(const rbe_params &p, const Grid &g, PairParams *out) {
+  PairParams &pp = *out;
+  pp = PairParams{};
+  pp.g = g;
+  const int nc[3] = {g.nx, g.ny, g.nz};
+  const double rq = std::fmax(p.r_coul, p.r_lj);
+  for (int d = 0; d < 3; ++d) {
+    pp.s_coul = std::max(pp.s_coul, stencil_radius(rq, p.L[d], nc[d]));
+    pp.s_lj = std::max(pp.s_lj, stencil_radius(p.r_lj, p.L[d], nc[d]));
+    pp.s_core = std::max(pp.s_core, stencil_radius(std::fmax(p.r_core, p.r_lj), p.L[d], nc[d]));
+  }
+  pp.rc2 = p.r_coul * p.r_coul;
+  pp.rlj2 = p.r_lj * p.r_lj;
+  pp.rcore2 = p.r_core * p.r_core;
+  pp.alpha = p.alpha;
+  pp.sqrt_alpha = std::sqrt(p.alpha);
+  pp.two_sqrt_alpha_over_sqrt_pi = 2.0 * pp.sqrt_alpha / std::sqrt(kPi);
+  pp.kc = p.coulomb_k;
+  pp.eps24 = 24.0 * p.lj_eps;
+  pp.sig2 = p.lj_sigma * p.lj_sigma;
+  pp.do_coul = (p.terms & RBE_TERM_COUL_REAL) != 0;
+  pp.do_lj = (p.terms & RBE_TERM_LJ) != 0 && p.r_lj > 0;
+  pp.rbl = p.r_core > 0;
+  pp.p_shell = p.p_shell;
+}
+
+// Native cell grid of a box (no ghost layers).
+static Grid make_grid(const rbe_params &p, const int nc[3]) {
+  Grid g{};
+  g.nx = nc[0];
+  g.ny = nc[1];
+  g.nz = nc[2];
+  g.ncell = nc[0] * nc[1] * nc[2];
+  for (int d = 0; d < 3; ++d) {
+    g.L[d] = p.L[d];
+    g.inv_h[d] = (double)nc[d] / p.L[d];
+    g.goff[d] = 0;
+  }
+  g.pnx = g.nx;
+  g.pny = g.ny;
+  g.pnz = g.nz;
+  g.pncell = g.ncell;
+  g.ghost_width = 0.0;
+  return g;
+}
+
 // ---------------------------------------------------------------------------
 // create / destroy
 // ---------------------------------------------------------------------------
@@ -254,30 +329,7 @@ extern "C" int rbe_create(rbe_ctx **out, const rbe_params *p, int64_t n_max, int
     delete c;
     return create_fail(RBE_EINVAL, "padded cell grid too large");
   }
-  PairParams &pp = c->pp;
-  pp.g = g;
-  const double rq = std::fmax(p->r_coul, p->r_lj);
-  pp.s_coul = 0;
-  pp.s_lj = 0;
-  pp.s_core = 0;
-  for (int d = 0; d < 3; ++d) {
-    pp.s_coul = std::max(pp.s_coul, stencil_radius(rq, p->L[d], nc[d]));
-    pp.s_lj = std::max(pp.s_lj, stencil_radius(p->r_lj, p->L[d], nc[d]));
-    pp.s_core = std::max(pp.s_core, stencil_radius(std::fmax(p->r_core, p->r_lj), p->L[d], nc[d]));
-  }
-  pp.rc2 = p->r_coul * p->r_coul;
-  pp.rlj2 = p->r_lj * p->r_lj;
-  pp.rcore2 = p->r_core * p->r_core;
-  pp.alpha = p->alpha;
-  pp.sqrt_alpha = std::sqrt(p->alpha);
-  pp.two_sqrt_alpha_over_sqrt_pi = 2.0 * pp.sqrt_alpha / std::sqrt(kPi);
-  pp.kc = p->coulomb_k;
-  pp.eps24 = 24.0 * p->lj_eps;
-  pp.sig2 = p->lj_sigma * p->lj_sigma;
-  pp.do_coul = (c->p.terms & RBE_TERM_COUL_REAL) != 0;
-  pp.do_lj = (c->p.terms & RBE_TERM_LJ) != 0 && p->r_lj > 0;
-  pp.rbl = p->r_core > 0;
-  pp.p_shell = p->p_shell;
+  make_pair_params(c->p, g, &c->pp);
 
   // mode tables
   build_mode_table(p->L, p->alpha, &c->mt, nullptr);
@@ -373,19 +425,173 @@ extern "C" int rbe_create(rbe_ctx **out, const rbe_params *p, int64_t n_max, int
   return RBE_OK;
 }
 
+// Structure-factor chunk length of the batched form (particles per wave item).
+constexpr int kBatchChunk = 128;
+
+static bool same_shared_physics(const rbe_params &a, const rbe_params &b) {
+  auto t = [](int v) { return v == 0 ? RBE_TERM_ALL : v; };
+  return a.alpha == b.alpha && a.r_coul == b.r_coul && a.r_lj == b.r_lj && a.r_core == b.r_core &&
+         a.p_shell == b.p_shell && a.P == b.P && a.kdist == b.kdist && a.prec == b.prec && t(a.terms) == t(b.terms) &&
+         a.lj_eps == b.lj_eps && a.lj_sigma == b.lj_sigma && a.coulomb_k == b.coulomb_k && a.mass == b.mass &&
+         a.dt == b.dt && a.ghost_width == b.ghost_width;
+}
+
 extern "C" int rbe_create_batch(rbe_ctx **out, int32_t n_sys, const rbe_params *params, const int64_t *offset,
                                 int device) {
   if (!out) return create_fail(RBE_EINVAL, "out is NULL");
   *out = nullptr;
-  if (n_sys == 1 && params && offset) return rbe_create(out, params, offset[1] - offset[0], device);
-  (void)device;
-  return create_fail(RBE_EINVAL, "batched contexts with n_sys > 1 are not supported by this build");
+  if (!params || !offset) return create_fail(RBE_EINVAL, "params or offset is NULL");
+  if (n_sys < 1) return create_fail(RBE_EINVAL, "n_sys must be >= 1");
+  if (offset[0] != 0) return create_fail(RBE_EINVAL, "offset[0] must be 0");
+  for (int32_t r = 0; r < n_sys; ++r)
+    if (offset[r + 1] <= offset[r]) return create_fail(RBE_EINVAL, "every replica needs at least one particle");
+  if (offset[n_sys] >= (int64_t)0x7FFFFFFF) return create_fail(RBE_EINVAL, "total particle count must be < 2^31");
+  if (n_sys == 1) return rbe_create(out, params, offset[1], device);
+  std::string why;
+  char msg[400];
+  for (int32_t r = 0; r < n_sys; ++r) {
+    const int rc = validate_params(&params[r], &why);
+    if (rc != RBE_OK) {
+      snprintf(msg, sizeof msg, "replica %d: %s", (int)r, why.c_str());
+      return create_fail(rc, msg);
+    }
+    if (!same_shared_physics(params[r], params[0])) {
+      snprintf(msg, sizeof msg, "replica %d differs from replica 0 in a field other than L, ncell and seed", (int)r);
+      return create_fail(RBE_EINVAL, msg);
+    }
+  }
+  if (params[0].r_core > 0)
+    return create_fail(RBE_EINVAL, "the random batch list (r_core > 0) is not available in the batched form");
+  if (params[0].ghost_width > 0)
+    return create_fail(RBE_EINVAL, "the ghost shell (ghost_width > 0) is not available in the batched form");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return create_fail(RBE_EDEVICE, "no such HIP device");
+  if (hipSetDevice(device) != hipSuccess) return create_fail(RBE_EDEVICE, "hipSetDevice failed");
+
+  rbe_ctx *c = new rbe_ctx();
+  c->device = device;
+  c->p = params[0];
+  if (c->p.terms == 0) c->p.terms = RBE_TERM_ALL;
+  auto &B = c->bt;
+  B.nrep = n_sys;
+  B.off.assign(offset, offset + n_sys + 1);
+  B.ntot = offset[n_sys];
+  c->n_max = B.ntot;
+  std::vector<double> cdf_all;
+  int64_t key0 = 0, chunks = 0;
+  B.reps.resize(n_sys);
+  for (int32_t r = 0; r < n_sys; ++r) {
+    rbe_params pr = params[r];
+    pr.terms = c->p.terms;
+    int nc[3];
+    choose_grid(&pr, nc);
+    if ((int64_t)nc[0] * nc[1] * nc[2] >= (1LL << 29)) {
+      delete c;
+      return create_fail(RBE_EINVAL, "cell grid too large");
+    }
+    RepDesc &d = B.reps[r];
+    d = RepDesc{};
+    d.g = make_grid(pr, nc);
+    PairParams pr_pp;
+    make_pair_params(pr, d.g, &pr_pp);
+    d.s_coul = pr_pp.s_coul;
+    d.s_lj = pr_pp.s_lj;
+    d.p0 = offset[r];
+    d.n = offset[r + 1] - offset[r];
+    d.c0 = key0;
+    key0 += 2 * (int64_t)d.g.ncell;
+    build_mode_table(pr.L, pr.alpha, &d.mt, nullptr);
+    d.cdf_off = (int)cdf_all.size();
+    cdf_all.resize(cdf_all.size() + d.mt.total);
+    build_mode_table(pr.L, pr.alpha, &d.mt, cdf_all.data() + d.cdf_off);
+    d.seed = pr.seed;
+    chunks += (d.n + kBatchChunk - 1) / kBatchChunk;
+    if (r == 0) {
+      c->g = d.g;
+      c->pp = pr_pp;
+      c->mt = d.mt;
+    }
+  }
+  if (key0 >= (int64_t)0x7FFFFFFF - 1) {
+    delete c;
+    return create_fail(RBE_EINVAL, "cell grids too large");
+  }
+  B.nkeys = key0;
+  B.ntiles = batch_scan_tiles(key0);
+  B.part_chunks = chunks;
+  const int64_t n = B.ntot;
+  const int P = c->p.P;
+
+  Buf &b = c->buf;
+  for (int s = 0; s < 2; ++s) {
+    WorkSet &w = c->ws[s];
+    w.x = b.alloc<double>(n);
+    w.y = b.alloc<double>(n);
+    w.z = b.alloc<double>(n);
+    w.vx = b.alloc<double>(n);
+    w.vy = b.alloc<double>(n);
+    w.vz = b.alloc<double>(n);
+    w.q = b.alloc<double>(n);
+    w.fx = b.alloc<double>(n);
+    w.fy = b.alloc<double>(n);
+    w.fz = b.alloc<double>(n);
+    w.id = b.alloc<int32_t>(n);
+  }
+  c->srt.xq = b.alloc<double4>(n);
+  c->srt.sq = b.alloc<double4>(n);
+  c->srt.id = b.alloc<int32_t>(n);
+  c->perm = b.alloc<int32_t>(n);
+  c->cell_start = b.alloc<int32_t>(B.nkeys + 1);
+  c->cdf_dev = b.alloc<double>((int64_t)cdf_all.size());
+  c->err = b.alloc<int>(1);
+  c->counters = b.alloc<unsigned long long>(12);
+  B.key = b.alloc<int32_t>(n);
+  B.slot = b.alloc<int32_t>(n);
+  B.tmp = b.alloc<int32_t>(n);
+  B.count = b.alloc<int32_t>(B.nkeys);
+  B.tile_sum = b.alloc<int32_t>(B.ntiles);
+  B.rep_of = b.alloc<int32_t>(n);
+  B.reps_dev = b.alloc<RepDesc>(n_sys);
+  B.off_dev = b.alloc<int64_t>(n_sys + 1);
+  B.nq = b.alloc<int32_t>(n_sys);
+  B.qs = b.alloc<double>(2 * (int64_t)n_sys);
+  B.modes = b.alloc<GatherMode>((int64_t)n_sys * P);
+  B.wk = b.alloc<double>((int64_t)n_sys * P);
+  B.part = b.alloc<double2>(chunks * P);
+  B.bar = b.alloc<unsigned>(2);
+  B.eval = b.alloc<uint64_t>(1);
+  if (!b.ok) {
+    b.release();
+    delete c;
+    return create_fail(RBE_ENOMEM, "device allocation failed");
+  }
+  std::vector<int32_t> rep_of(n);
+  for (int32_t r = 0; r < n_sys; ++r)
+    for (int64_t i = offset[r]; i < offset[r + 1]; ++i) rep_of[i] = r;
+  B.blocks = batch_grid_blocks(c->p.prec, device);
+  if (hipMemcpy(c->cdf_dev, cdf_all.data(), sizeof(double) * cdf_all.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(B.rep_of, rep_of.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(B.off_dev, offset, sizeof(int64_t) * (n_sys + 1), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(B.reps_dev, B.reps.data(), sizeof(RepDesc) * n_sys, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(B.count, 0, sizeof(int32_t) * B.nkeys) != hipSuccess ||
+      hipMemset(B.bar, 0, 2 * sizeof(unsigned)) != hipSuccess || hipMemset(c->err, 0, sizeof(int)) != hipSuccess ||
+      hipMemset(c->counters, 0, 12 * sizeof(unsigned long long)) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    b.release();
+    delete c;
+    return create_fail(RBE_EDEVICE, "initial device copies failed");
+  }
+  *out = c;
+  return RBE_OK;
 }
 
 extern "C" void rbe_destroy(rbe_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
+  if (ctx->bt.exec) (void)hipGraphExecDestroy(ctx->bt.exec);
+  if (ctx->bt.graph) (void)hipGraphDestroy(ctx->bt.graph);
   ctx->buf.release();
   for (auto &e : ctx->tm.ev) (void)hipEventDestroy(e);
   delete ctx;
@@ -528,6 +734,7 @@ extern "C" int rbe_build_cells(rbe_ctx *c, const double *x, const double *y, con
                                             (long long)c->n_max);
   if (n > 0 && (!x || !y || !z || !q || !perm)) return c->fail(RBE_EINVAL, "null array");
   if (!cell_start) return c->fail(RBE_EINVAL, "null cell_start");
+  if (c->batched()) return c->fail(RBE_EINVAL, "rbe_build_cells is not available on a batched context");
   HIP_TRY(c, hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
   launch_bin(c->bb, c->g, n, x, y, z, q, cell_start, perm, st);
@@ -576,6 +783,223 @@ extern "C" int rbe_sample_k(const rbe_params *p, uint64_t eval, int32_t *m, doub
   return rc;
 }
 
+// ---------------------------------------------------------------------------
+// batched form
+// ---------------------------------------------------------------------------
+// Per-replica charge statistics, neutrality check and the structure-factor
+// chunk layout of this call; uploads the replica descriptors (synchronizes st).
+static int batch_prepare(rbe_ctx *c, const double *q, hipStream_t st) {
+  auto &B = c->bt;
+  const int nrep = B.nrep;
+  std::vector<int32_t> nq(nrep);
+  std::vector<double> qs(2 * (size_t)nrep);
+  launch_qstats_rep(nrep, B.off_dev, q, B.nq, B.qs, st);
+  HIP_TRY(c, hipMemcpyAsync(nq.data(), B.nq, sizeof(int32_t) * nrep, hipMemcpyDeviceToHost, st));
+  HIP_TRY(c, hipMemcpyAsync(qs.data(), B.qs, sizeof(double) * 2 * nrep, hipMemcpyDeviceToHost, st));
+  HIP_TRY(c, hipStreamSynchronize(st));
+  const int groups = (c->p.P + 63) / 64;
+  int chunk_off = 0;
+  int64_t items = 0;
+  for (int r = 0; r < nrep; ++r) {
+    const double sq = qs[2 * r], sa = qs[2 * r + 1];
+    if (!std::isfinite(sq) || !std::isfinite(sa)) return c->fail(RBE_ENONFINITE, "replica %d: non-finite charges", r);
+    if (std::fabs(sq) > 1e-10 * std::fmax(sa, 1e-300) && std::fabs(sq) > 1e-12)
+      return c->fail(RBE_ENONNEUTRAL, "replica %d: total charge %.3e is not zero (sum |q| = %.3e)", r, sq, sa);
+    RepDesc &d = B.reps[r];
+    d.nq = nq[r];
+    d.chunk_len = kBatchChunk;
+    d.nchunks = (int)((d.nq + kBatchChunk - 1) / kBatchChunk);
+    d.chunk_off = chunk_off;
+    d.rho_item_off = (int)items;
+    chunk_off += d.nchunks;
+    items += (int64_t)d.nchunks * groups;
+  }
+  if (chunk_off > B.part_chunks || items > 0x7FFFFFFF) return c->fail(RBE_ERANGE, "structure-factor layout overflow");
+  B.rho_items = (int)items;
+  HIP_TRY(c, hipMemcpyAsync(B.reps_dev, B.reps.data(), sizeof(RepDesc) * nrep, hipMemcpyHostToDevice, st));
+  return RBE_OK;
+}
+
+// Launch arguments shared by both modes; the caller sets the state arrays.
+static BatchArgs batch_args(rbe_ctx *c, int mode) {
+  auto &B = c->bt;
+  BatchArgs a{};
+  a.nrep = B.nrep;
+  a.reps = B.reps_dev;
+  a.rep_of = B.rep_of;
+  a.ntot = B.ntot;
+  a.nkeys = B.nkeys;
+  a.ntiles = B.ntiles;
+  a.P = c->p.P;
+  a.mode = mode;
+  a.rho_items = B.rho_items;
+  a.do_far = (c->p.terms & RBE_TERM_FOURIER) != 0;
+  a.pp = c->pp;
+  a.pf = make_pair_f32(a.pp);
+  a.h = 0.5 * c->p.dt / c->p.mass;
+  a.dt = c->p.dt;
+  a.xq = c->srt.xq;
+  a.sq = c->srt.sq;
+  a.sid = c->srt.id;
+  a.key = B.key;
+  a.slot = B.slot;
+  a.tmp = B.tmp;
+  a.perm = c->perm;
+  a.count = B.count;
+  a.cell_start = c->cell_start;
+  a.tile_sum = B.tile_sum;
+  a.cdf = c->cdf_dev;
+  a.modes = B.modes;
+  a.wk = B.wk;
+  a.part = B.part;
+  a.err = c->err;
+  a.bar = B.bar;
+  a.eval = B.eval;
+  return a;
+}
+
+static BatchArgs batch_step_args(rbe_ctx *c, const WorkSet &in, const WorkSet &out) {
+  BatchArgs a = batch_args(c, 0);
+  a.ix = in.x;
+  a.iy = in.y;
+  a.iz = in.z;
+  a.ivx = in.vx;
+  a.ivy = in.vy;
+  a.ivz = in.vz;
+  a.iq = in.q;
+  a.ifx = in.fx;
+  a.ify = in.fy;
+  a.ifz = in.fz;
+  a.iid = in.id;
+  a.ox = out.x;
+  a.oy = out.y;
+  a.oz = out.z;
+  a.ovx = out.vx;
+  a.ovy = out.vy;
+  a.ovz = out.vz;
+  a.oq = out.q;
+  a.ofx = out.fx;
+  a.ofy = out.fy;
+  a.ofz = out.fz;
+  a.oid = out.id;
+  return a;
+}
+
+// Start of a batched call: eval, barrier and histogram start from known values.
+static int batch_begin(rbe_ctx *c, uint64_t eval, hipStream_t st) {
+  auto &B = c->bt;
+  B.eval_stage = eval;
+  HIP_TRY(c, hipMemcpyAsync(B.eval, &B.eval_stage, sizeof(uint64_t), hipMemcpyHostToDevice, st));
+  launch_fill_i32((int32_t *)B.bar, 2, 0, st);
+  launch_fill_i32(B.count, B.nkeys, 0, st);
+  return RBE_OK;
+}
+
+// Two-step graph (ws[0] -> ws[1] -> ws[0]); rebuilt when the chunk layout changes.
+static int batch_graph(rbe_ctx *c) {
+  auto &B = c->bt;
+  if (B.exec && B.graph_rho_items == B.rho_items) return RBE_OK;
+  if (B.exec) (void)hipGraphExecDestroy(B.exec);
+  if (B.graph) (void)hipGraphDestroy(B.graph);
+  B.exec = nullptr;
+  B.graph = nullptr;
+  B.graph_rho_items = -1;
+  B.node_args[0] = batch_step_args(c, c->ws[0], c->ws[1]);
+  B.node_args[1] = batch_step_args(c, c->ws[1], c->ws[0]);
+  HIP_TRY(c, hipGraphCreate(&B.graph, 0));
+  hipGraphNode_t n0 = nullptr, n1 = nullptr;
+  HIP_TRY(c, add_batch_node(B.graph, &n0, nullptr, 0, c->p.prec, B.blocks, &B.node_args[0]));
+  HIP_TRY(c, add_batch_node(B.graph, &n1, &n0, 1, c->p.prec, B.blocks, &B.node_args[1]));
+  HIP_TRY(c, hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0));
+  B.graph_rho_items = B.rho_items;
+  return RBE_OK;
+}
+
+static int batch_forces(rbe_ctx *c, const rbe_state *s, const int32_t *m, const double *w, uint64_t eval,
+                        double *rho_out, hipStream_t st) {
+  auto &B = c->bt;
+  if (m || w || rho_out) return c->fail(RBE_EINVAL, "a batched context draws its own modes: m, w, rho_out must be NULL");
+  if (s->n != B.ntot) return c->fail(RBE_ERANGE, "n = %lld, the batch holds %lld", (long long)s->n, (long long)B.ntot);
+  int rc = batch_prepare(c, s->q, st);
+  if (rc != RBE_OK) return rc;
+  rc = batch_begin(c, eval, st);
+  if (rc != RBE_OK) return rc;
+  BatchArgs a = batch_args(c, 1);
+  a.ix = s->x;
+  a.iy = s->y;
+  a.iz = s->z;
+  a.iq = s->q;
+  a.iid = s->id;
+  const WorkSet &o = c->ws[1];
+  a.ox = o.x;
+  a.oy = o.y;
+  a.oz = o.z;
+  a.oq = o.q;
+  a.oid = o.id;
+  a.ofx = o.fx;
+  a.ofy = o.fy;
+  a.ofz = o.fz;
+  a.cfx = s->fx;
+  a.cfy = s->fy;
+  a.cfz = s->fz;
+  {
+    TScope ts(c, RBE_TK_BATCH, st);
+    launch_batch_step(c->p.prec, B.blocks, a, st);
+  }
+  HIP_TRY(c, hipGetLastError());
+  return RBE_OK;
+}
+
+static int copy_state(rbe_ctx *c, const double *const src[10], const int32_t *sid, double *const dst[10],
+                      int32_t *did, int64_t n, hipStream_t st) {
+  for (int k = 0; k < 10; ++k)
+    HIP_TRY(c, hipMemcpyAsync(dst[k], src[k], sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, hipMemcpyAsync(did, sid, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
+  return RBE_OK;
+}
+
+static int batch_step(rbe_ctx *c, rbe_state *s, int32_t nsteps, uint64_t first_eval, hipStream_t st) {
+  auto &B = c->bt;
+  if (s->n != B.ntot) return c->fail(RBE_ERANGE, "n = %lld, the batch holds %lld", (long long)s->n, (long long)B.ntot);
+  int rc = batch_prepare(c, s->q, st);
+  if (rc != RBE_OK) return rc;
+  const int64_t n = s->n;
+  WorkSet &A = c->ws[0];
+  {
+    const double *src[10] = {s->x, s->y, s->z, s->vx, s->vy, s->vz, s->fx, s->fy, s->fz, s->q};
+    double *dst[10] = {A.x, A.y, A.z, A.vx, A.vy, A.vz, A.fx, A.fy, A.fz, A.q};
+    rc = copy_state(c, src, s->id, dst, A.id, n, st);
+    if (rc != RBE_OK) return rc;
+  }
+  rc = batch_begin(c, first_eval, st);
+  if (rc != RBE_OK) return rc;
+  if (nsteps >= 2) {
+    rc = batch_graph(c);
+    if (rc != RBE_OK) return rc;
+    for (int32_t k = 0; k + 1 < nsteps; k += 2) {
+      TScope ts(c, RBE_TK_BATCH, st, 2);
+      HIP_TRY(c, hipGraphLaunch(B.exec, st));
+    }
+  }
+  const WorkSet *fin = &c->ws[0];
+  if (nsteps & 1) {
+    BatchArgs a = batch_step_args(c, c->ws[0], c->ws[1]);
+    {
+      TScope ts(c, RBE_TK_BATCH, st);
+      launch_batch_step(c->p.prec, B.blocks, a, st);
+    }
+    fin = &c->ws[1];
+  }
+  {
+    const double *src[10] = {fin->x, fin->y, fin->z, fin->vx, fin->vy, fin->vz, fin->fx, fin->fy, fin->fz, fin->q};
+    double *dst[10] = {s->x, s->y, s->z, s->vx, s->vy, s->vz, s->fx, s->fy, s->fz, s->q};
+    rc = copy_state(c, src, fin->id, dst, s->id, n, st);
+    if (rc != RBE_OK) return rc;
+  }
+  HIP_TRY(c, hipGetLastError());
+  return RBE_OK;
+}
+
 extern "C" int rbe_forces(rbe_ctx *c, const rbe_state *s, const int32_t *m, const double *w, uint64_t eval,
                           double *rho_out, void *stream) {
   if (!c) return RBE_EINVAL;
@@ -585,6 +1009,7 @@ extern "C" int rbe_forces(rbe_ctx *c, const rbe_state *s, const int32_t *m, cons
   if ((m == nullptr) != (w == nullptr)) return c->fail(RBE_EINVAL, "m and w must both be given or both be NULL");
   HIP_TRY(c, hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
+  if (c->batched()) return batch_forces(c, s, m, w, eval, rho_out, st);
   const int64_t n = s->n;
   int64_t nq = 0;
   int rc = charge_stats(c, n, s->q, st, &nq);
@@ -637,6 +1062,7 @@ extern "C" int rbe_step(rbe_ctx *c, rbe_state *s, int32_t nsteps, uint64_t first
   if (nsteps == 0) return RBE_OK;
   HIP_TRY(c, hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
+  if (c->batched()) return batch_step(c, s, nsteps, first_eval, st);
   const int64_t n = s->n;
   int64_t nq = 0;
   int rc = charge_stats(c, n, s->q, st, &nq);
@@ -707,6 +1133,7 @@ extern "C" int rbe_sync_check(rbe_ctx *c, void *stream) {
   if (flag & kErrBadId) return c->fail(RBE_ERANGE, "a particle id lies outside [0, n)");
   if (flag & kErrSampler) return c->fail(RBE_EINVAL, "mode sampler rejected every attempt");
   if (flag & kErrGhostOverflow) return c->fail(RBE_ERANGE, "the ghost shell exceeded its capacity");
+  if (flag & kErrBarrier) return c->fail(RBE_EDEVICE, "a grid barrier of the batched step timed out");
   return RBE_OK;
 }
 
@@ -738,6 +1165,7 @@ extern "C" int rbe_set_timing(rbe_ctx *c, int enable) {
     }
     t.used = 0;
     t.kind.clear();
+    t.count.clear();
     for (int k = 0; k < RBE_TIMING_KINDS; ++k) {
       t.ms[k] = 0.0;
       t.launches[k] = 0;

@@ -1,0 +1,485 @@
+// Batched form: many independent systems ("replicas") of uneven size advanced
+// together, one persistent fused launch per velocity-Verlet step.
+//
+// All replicas live in concatenated arrays; replica r owns particles
+// [p0, p0 + n) and binning keys [c0, c0 + 2 C_r) (its charged cells, then its
+// neutral cells). One kernel runs the whole step for every replica, phase by
+// phase, with a grid-wide barrier between phases:
+//
+//   P0  half-kick + drift + wrap; binning keys + histogram; mode sample of
+//       every replica (Eq. 9)
+//   P1  scan: tile sums of the concatenated histogram
+//   P2  scan: one block scans the tile sums
+//   P3  scan: cell starts (one exclusive scan serves every replica, because
+//       replica r's keys and particles both follow those of replicas < r)
+//   P4  provisional scatter (atomic slots)
+//   P5  stable placement (slot = bucket start + members with a smaller index)
+//   P6  reorder of the state and packing of the sorted records
+//   P7  near field of every particle; structure-factor partials (chunk x mode)
+//   P8  structure factors: fixed-order sum of the chunk partials per mode
+//   P9  Fourier gather + second half-kick
+//
+// The grid is sized to the kernel's resident capacity, so every block is
+// resident and the barrier cannot wait on a block that never starts; the
+// barrier's wait is still bounded in time and reports an error instead of
+// hanging. Data written inside the kernel is read only through vector loads
+// after an agent-scope fence.
+#include "fourier_device.h"
+#include "pair_device.h"
+#include "sampler_device.h"
+
+namespace rbe {
+
+constexpr int kBatchThreads = 256;
+constexpr int kScanTileB = kBatchThreads * 8;
+constexpr uint64_t kBarrierTimeoutTicks = 200000000ull;  // 2 s at the 100 MHz wall clock
+
+// Grid-wide barrier. A wait longer than the time limit flags kErrBarrier;
+// once that flag is up no block waits again, so a launch whose blocks were
+// not all resident still ends (with its result reported as failed).
+__device__ inline void grid_barrier(unsigned *bar, int *err) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
+    if (arrived == gridDim.x) {
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const uint64_t t0 = wall_clock64();
+      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrBarrier) break;
+        __builtin_amdgcn_s_sleep(4);
+        if (wall_clock64() - t0 > kBarrierTimeoutTicks) {
+          atomicOr(err, kErrBarrier);
+          break;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  __threadfence();
+}
+
+__device__ inline int block_scan_excl(int v, int *lds, int *total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) lds[wave] = incl;
+  __syncthreads();
+  int off = 0, tot = 0;
+  for (int w = 0; w < kBatchThreads / 64; ++w) {
+    const int s = lds[w];
+    if (w < wave) off += s;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + incl - v;
+}
+
+// Plain near-field sums of one particle (no random batch list, no ghosts).
+template <bool F32>
+__device__ inline void batch_pair(const BatchArgs &a, const RepDesc &R, int64_t i) {
+  const Grid &g = R.g;
+  const PairParams &pp = a.pp;
+  const double4 pi4 = a.xq[i];
+  const double xi = pi4.x, yi = pi4.y, zi = pi4.z, qi = pi4.w;
+  const int cx = cell_coord(xi, g.inv_h[0], g.nx);
+  const int cy = cell_coord(yi, g.inv_h[1], g.ny);
+  const int cz = cell_coord(zi, g.inv_h[2], g.nz);
+  ForceAcc<F32> acc;
+  auto visit_q = [&](int j, const double4 &pj, int, double shx, double shy, double shz) {
+    const double dx = (xi - pj.x) - shx, dy = (yi - pj.y) - shy, dz = (zi - pj.z) - shz;
+    const double r2 = sq_dist(dx, dy, dz);
+    if (r2 == 0.0 && j == (int)i) return;
+    if (r2 <= pp.rc2 || r2 <= pp.rlj2) acc.template add<true>(pp, a.pf, r2, qi, pj.w, dx, dy, dz);
+  };
+  auto visit_lj = [&](int j, const double4 &pj, int, double shx, double shy, double shz) {
+    const double dx = (xi - pj.x) - shx, dy = (yi - pj.y) - shy, dz = (zi - pj.z) - shz;
+    const double r2 = sq_dist(dx, dy, dz);
+    if (r2 == 0.0 && j == (int)i) return;
+    if (r2 <= pp.rlj2) acc.template add<false>(pp, a.pf, r2, qi, pj.w, dx, dy, dz);
+  };
+  if (qi != 0.0) {
+    if (pp.do_coul || pp.do_lj) for_stencil<false>(g, a.cell_start, a.xq, a.sid, 0, cx, cy, cz, R.s_coul, visit_q, R.c0);
+    if (pp.do_lj) for_stencil<false>(g, a.cell_start, a.xq, a.sid, 1, cx, cy, cz, R.s_lj, visit_lj, R.c0);
+  } else if (pp.do_lj) {
+    for_stencil<false>(g, a.cell_start, a.xq, a.sid, 0, cx, cy, cz, R.s_lj, visit_lj, R.c0);
+    for_stencil<false>(g, a.cell_start, a.xq, a.sid, 1, cx, cy, cz, R.s_lj, visit_lj, R.c0);
+  }
+  a.ofx[i] = acc.get(0);
+  a.ofy[i] = acc.get(1);
+  a.ofz[i] = acc.get(2);
+}
+
+template <bool F32>
+__global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchArgs a) {
+  __shared__ int lds[kBatchThreads / 64];
+  const int tid = threadIdx.x;
+  const int64_t gtid = (int64_t)blockIdx.x * kBatchThreads + tid;
+  const int64_t gstride = (int64_t)gridDim.x * kBatchThreads;
+  const int lane = tid & 63;
+  const int64_t gwave = (int64_t)blockIdx.x * (kBatchThreads / 64) + (tid >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * (kBatchThreads / 64);
+  const int P = a.P;
+  const bool do_near = (a.pp.do_coul || a.pp.do_lj);
+  const bool do_far = a.do_far != 0;
+  const uint64_t eval = *((volatile uint64_t *)a.eval);
+
+  // ---- P0: drift, keys + histogram, mode sample ----------------------------
+  for (int64_t i = gtid; i < a.ntot; i += gstride) {
+    const RepDesc &R = a.reps[a.rep_of[i]];
+    double x = a.ix[i], y = a.iy[i], z = a.iz[i];
+    if (a.mode == 0) {
+      const double u = a.ivx[i] + a.h * a.ifx[i], v = a.ivy[i] + a.h * a.ify[i], w = a.ivz[i] + a.h * a.ifz[i];
+      a.ivx[i] = u;
+      a.ivy[i] = v;
+      a.ivz[i] = w;
+      x = wrap_coord(x + a.dt * u, R.g.L[0]);
+      y = wrap_coord(y + a.dt * v, R.g.L[1]);
+      z = wrap_coord(z + a.dt * w, R.g.L[2]);
+      a.ix[i] = x;
+      a.iy[i] = y;
+      a.iz[i] = z;
+      if (!isfinite(u) || !isfinite(v) || !isfinite(w)) atomicOr(a.err, kErrNonFinite);
+    } else {
+      x = wrap_coord(x, R.g.L[0]);
+      y = wrap_coord(y, R.g.L[1]);
+      z = wrap_coord(z, R.g.L[2]);
+    }
+    const int cx = cell_coord(x, R.g.inv_h[0], R.g.nx);
+    const int cy = cell_coord(y, R.g.inv_h[1], R.g.ny);
+    const int cz = cell_coord(z, R.g.inv_h[2], R.g.nz);
+    const int64_t k = R.c0 + (a.iq[i] == 0.0 ? R.g.ncell : 0) + (cz * R.g.ny + cy) * R.g.nx + cx;
+    a.key[i] = (int32_t)k;
+    a.slot[i] = atomicAdd(&a.count[k], 1);
+  }
+  if (P > 0) {
+    for (int64_t it = gtid; it < (int64_t)a.nrep * P; it += gstride) {
+      const int r = (int)(it / P), l = (int)(it % P);
+      const RepDesc &R = a.reps[r];
+      const uint64_t ek = stream_out(R.seed ^ kTagModes, eval);
+      int mv[3];
+      if (!draw_mode(R.mt, a.cdf + R.cdf_off, ek, l, mv)) {
+        atomicOr(a.err, kErrSampler);
+        mv[0] = 1;
+        mv[1] = 0;
+        mv[2] = 0;
+      }
+      GatherMode gm;
+      gm.mx = (double)mv[0];
+      gm.my = (double)mv[1];
+      gm.mz = (double)mv[2];
+      gm.a = 0.0;
+      gm.b = 0.0;
+      gm.pad[0] = gm.pad[1] = gm.pad[2] = 0.0;
+      a.modes[it] = gm;
+      a.wk[it] = mode_weight(R.mt, P, mv[0], mv[1], mv[2]);
+    }
+  }
+  grid_barrier(a.bar, a.err);
+
+  // ---- P1: tile sums -------------------------------------------------------
+  for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+    const int64_t base = (int64_t)t * kScanTileB + (int64_t)tid * 8;
+    int s = 0;
+    for (int k = 0; k < 8; ++k)
+      if (base + k < a.nkeys) s += a.count[base + k];
+    int tot;
+    block_scan_excl(s, lds, &tot);
+    if (tid == 0) a.tile_sum[t] = tot;
+  }
+  grid_barrier(a.bar, a.err);
+
+  // ---- P2: scan of the tile sums (one block) --------------------------------
+  if (blockIdx.x == 0) {
+    int carry = 0;
+    for (int b = 0; b < a.ntiles; b += kBatchThreads) {
+      const int t = b + tid;
+      const int v = t < a.ntiles ? a.tile_sum[t] : 0;
+      int tot;
+      const int ex = block_scan_excl(v, lds, &tot);
+      if (t < a.ntiles) a.tile_sum[t] = carry + ex;
+      carry += tot;
+    }
+    if (tid == 0) a.cell_start[a.nkeys] = carry;
+  }
+  grid_barrier(a.bar, a.err);
+
+  // ---- P3: cell starts -------------------------------------------------------
+  for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+    const int64_t base = (int64_t)t * kScanTileB + (int64_t)tid * 8;
+    int v[8];
+    int s = 0;
+    for (int k = 0; k < 8; ++k) {
+      v[k] = base + k < a.nkeys ? a.count[base + k] : 0;
+      s += v[k];
+    }
+    int tot;
+    int run = a.tile_sum[t] + block_scan_excl(s, lds, &tot);
+    for (int k = 0; k < 8; ++k) {
+      if (base + k < a.nkeys) a.cell_start[base + k] = run;
+      run += v[k];
+    }
+  }
+  grid_barrier(a.bar, a.err);
+
+  // ---- P4: provisional scatter -----------------------------------------------
+  for (int64_t i = gtid; i < a.ntot; i += gstride) a.tmp[a.cell_start[a.key[i]] + a.slot[i]] = (int32_t)i;
+  grid_barrier(a.bar, a.err);
+
+  // ---- P5: stable placement; clear the histogram for the next step -----------
+  for (int64_t i = gtid; i < a.ntot; i += gstride) {
+    const int k = a.key[i];
+    const int lo = a.cell_start[k], hi = a.cell_start[k + 1];
+    int rank = 0;
+    for (int t = lo; t < hi; ++t) rank += a.tmp[t] < (int32_t)i;
+    a.perm[lo + rank] = (int32_t)i;
+  }
+  for (int64_t k = gtid; k < a.nkeys; k += gstride) a.count[k] = 0;
+  grid_barrier(a.bar, a.err);
+
+  // ---- P6: reorder + pack ------------------------------------------------------
+  for (int64_t k = gtid; k < a.ntot; k += gstride) {
+    const int j = a.perm[k];
+    const RepDesc &R = a.reps[a.rep_of[k]];
+    const double x = wrap_coord(a.ix[j], R.g.L[0]), y = wrap_coord(a.iy[j], R.g.L[1]),
+                 z = wrap_coord(a.iz[j], R.g.L[2]), q = a.iq[j];
+    const int32_t id = a.iid[j];
+    a.ox[k] = x;
+    a.oy[k] = y;
+    a.oz[k] = z;
+    a.oq[k] = q;
+    a.oid[k] = id;
+    if (a.mode == 0) {
+      a.ovx[k] = a.ivx[j];
+      a.ovy[k] = a.ivy[j];
+      a.ovz[k] = a.ivz[j];
+    }
+    a.xq[k] = make_double4(x, y, z, q);
+    if (q != 0.0) a.sq[k] = make_double4(x / R.g.L[0], y / R.g.L[1], z / R.g.L[2], q);
+    a.sid[k] = id;
+  }
+  grid_barrier(a.bar, a.err);
+
+  // ---- P7: near field; structure-factor partials ---------------------------------
+  for (int64_t i = gtid; i < a.ntot; i += gstride) {
+    const RepDesc &R = a.reps[a.rep_of[i]];
+    if (do_near) {
+      batch_pair<F32>(a, R, i);
+    } else {
+      a.ofx[i] = 0.0;
+      a.ofy[i] = 0.0;
+      a.ofz[i] = 0.0;
+    }
+  }
+  if (P > 0 && do_far) {
+    const int groups = (P + 63) / 64;
+    for (int64_t it = gwave; it < a.rho_items; it += nwaves) {
+      // replica of this item: last r with rho_item_off <= it
+      int lo = 0, hi = a.nrep - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.reps[mid].rho_item_off <= it) lo = mid;
+        else hi = mid - 1;
+      }
+      const RepDesc &R = a.reps[lo];
+      const int local = (int)(it - R.rho_item_off);
+      const int chunk = local / groups, grp = local % groups;
+      const int l = grp * 64 + lane;
+      const bool active = l < P;
+      const GatherMode gm = a.modes[(int64_t)lo * P + (active ? l : 0)];
+      const int64_t j0 = R.p0 + (int64_t)chunk * R.chunk_len;
+      const int64_t j1 = min(R.p0 + (int64_t)R.nq, j0 + R.chunk_len);
+      double2 out;
+      if (F32) {
+        float re = 0.f, rc = 0.f, im = 0.f, ic = 0.f;
+        for (int64_t j = j0; j < j1; ++j) {
+          const double4 s = a.sq[j];
+          const float t = (float)turn_fraction(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
+          const float q = (float)s.w;
+          kahan_add(re, rc, q * __builtin_amdgcn_cosf(t));
+          kahan_add(im, ic, q * __builtin_amdgcn_sinf(t));
+        }
+        out = make_double2((double)re - (double)rc, (double)im - (double)ic);
+      } else {
+        double re = 0.0, im = 0.0;
+        for (int64_t j = j0; j < j1; ++j) {
+          const double4 s = a.sq[j];
+          const double t = turn_fraction(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
+          double sn, cs;
+          sincospi(2.0 * t, &sn, &cs);
+          re = fma(s.w, cs, re);
+          im = fma(s.w, sn, im);
+        }
+        out = make_double2(re, im);
+      }
+      if (active) a.part[(int64_t)(R.chunk_off + chunk) * P + l] = out;
+    }
+  }
+  grid_barrier(a.bar, a.err);
+
+  // ---- P8: structure factors and gather coefficients --------------------------
+  if (P > 0 && do_far) {
+    for (int64_t it = gwave; it < (int64_t)a.nrep * P; it += nwaves) {
+      const int r = (int)(it / P), l = (int)(it % P);
+      const RepDesc &R = a.reps[r];
+      double re = 0.0, im = 0.0;
+      for (int c = lane; c < R.nchunks; c += 64) {
+        const double2 v = a.part[(int64_t)(R.chunk_off + c) * P + l];
+        re += v.x;
+        im += v.y;
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        re += __shfl_xor(re, o, 64);
+        im += __shfl_xor(im, o, 64);
+      }
+      if (lane == 0) {
+        const double w = a.wk[it];
+        a.modes[it].a = w * im;
+        a.modes[it].b = w * re;
+      }
+    }
+  }
+  grid_barrier(a.bar, a.err);
+
+  // ---- P9: Fourier gather + second half-kick -----------------------------------
+  for (int64_t i = gtid; i < a.ntot; i += gstride) {
+    const int r = a.rep_of[i];
+    const RepDesc &R = a.reps[r];
+    double fx = a.ofx[i], fy = a.ofy[i], fz = a.ofz[i];
+    if (P > 0 && do_far && i < R.p0 + R.nq) {
+      const double4 s = a.sq[i];
+      const GatherMode *md = a.modes + (int64_t)r * P;
+      if (F32) {
+        float gx = 0.f, gy = 0.f, gz = 0.f, ex = 0.f, ey = 0.f, ez = 0.f;
+        for (int l = 0; l < P; ++l) {
+          const GatherMode gm = md[l];
+          const float t = (float)turn_fraction(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
+          const float g = (float)gm.a * __builtin_amdgcn_cosf(t) - (float)gm.b * __builtin_amdgcn_sinf(t);
+          kahan_add(gx, ex, g * (float)gm.mx);
+          kahan_add(gy, ey, g * (float)gm.my);
+          kahan_add(gz, ez, g * (float)gm.mz);
+        }
+        fx -= s.w * (kTwoPi / R.g.L[0]) * ((double)gx - (double)ex);
+        fy -= s.w * (kTwoPi / R.g.L[1]) * ((double)gy - (double)ey);
+        fz -= s.w * (kTwoPi / R.g.L[2]) * ((double)gz - (double)ez);
+      } else {
+        double gx = 0.0, gy = 0.0, gz = 0.0;
+        for (int l = 0; l < P; ++l) {
+          const GatherMode gm = md[l];
+          const double t = turn_fraction(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
+          double sn, cs;
+          sincospi(2.0 * t, &sn, &cs);
+          const double g = gm.a * cs - gm.b * sn;
+          gx = fma(g, gm.mx, gx);
+          gy = fma(g, gm.my, gy);
+          gz = fma(g, gm.mz, gz);
+        }
+        fx -= s.w * (kTwoPi / R.g.L[0]) * gx;
+        fy -= s.w * (kTwoPi / R.g.L[1]) * gy;
+        fz -= s.w * (kTwoPi / R.g.L[2]) * gz;
+      }
+    }
+    a.ofx[i] = fx;
+    a.ofy[i] = fy;
+    a.ofz[i] = fz;
+    if (a.mode == 0) {
+      const double u = a.ovx[i] + a.h * fx, v = a.ovy[i] + a.h * fy, w = a.ovz[i] + a.h * fz;
+      a.ovx[i] = u;
+      a.ovy[i] = v;
+      a.ovz[i] = w;
+      if (!isfinite(u) || !isfinite(v) || !isfinite(w)) atomicOr(a.err, kErrNonFinite);
+    } else {
+      const int j = a.perm[i];
+      a.cfx[j] = fx;
+      a.cfy[j] = fy;
+      a.cfz[j] = fz;
+    }
+  }
+  if (a.mode == 0 && gtid == 0) *((volatile uint64_t *)a.eval) = eval + 1;
+}
+
+int batch_grid_blocks(int prec, int device) {
+  int per_cu = 0, cus = 0;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+  if (prec == RBE_FP32C)
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(k_batch_step<true>),
+                                                 kBatchThreads, 0);
+  else
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(k_batch_step<false>),
+                                                 kBatchThreads, 0);
+  if (per_cu < 1) per_cu = 1;
+  if (cus < 1) cus = 1;
+  return per_cu * cus;
+}
+
+void launch_batch_step(int prec, int blocks, const BatchArgs &a, hipStream_t st) {
+  if (prec == RBE_FP32C)
+    k_batch_step<true><<<blocks, kBatchThreads, 0, st>>>(a);
+  else
+    k_batch_step<false><<<blocks, kBatchThreads, 0, st>>>(a);
+}
+
+int batch_scan_tiles(int64_t nkeys) { return (int)((nkeys + kScanTileB - 1) / kScanTileB); }
+
+hipError_t add_batch_node(hipGraph_t graph, hipGraphNode_t *node, const hipGraphNode_t *deps, int ndeps, int prec,
+                          int blocks, BatchArgs *a) {
+  hipKernelNodeParams kp{};
+  kp.func = prec == RBE_FP32C ? reinterpret_cast<void *>(k_batch_step<true>)
+                              : reinterpret_cast<void *>(k_batch_step<false>);
+  kp.gridDim = dim3((unsigned)blocks);
+  kp.blockDim = dim3(kBatchThreads);
+  kp.sharedMemBytes = 0;
+  void *args[] = {a};
+  kp.kernelParams = args;
+  kp.extra = nullptr;
+  return hipGraphAddKernelNode(node, graph, deps, (size_t)ndeps, &kp);
+}
+
+__global__ void __launch_bounds__(256) k_qstats_rep(const int64_t *__restrict__ off, const double *__restrict__ q,
+                                                    int32_t *__restrict__ nq, double *__restrict__ qs) {
+  __shared__ int lc[4];
+  __shared__ double ls[4], la[4];
+  const int r = blockIdx.x;
+  const int64_t lo = off[r], hi = off[r + 1];
+  int c = 0;
+  double s = 0.0, a = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+    const double v = q[i];
+    c += v != 0.0;
+    s += v;
+    a += fabs(v);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    c += __shfl_xor(c, o, 64);
+    s += __shfl_xor(s, o, 64);
+    a += __shfl_xor(a, o, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    lc[w] = c;
+    ls[w] = s;
+    la[w] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    nq[r] = lc[0] + lc[1] + lc[2] + lc[3];
+    qs[2 * r] = (ls[0] + ls[1]) + (ls[2] + ls[3]);
+    qs[2 * r + 1] = (la[0] + la[1]) + (la[2] + la[3]);
+  }
+}
+
+void launch_qstats_rep(int nrep, const int64_t *off, const double *q, int32_t *nq, double *qs, hipStream_t st) {
+  k_qstats_rep<<<nrep, 256, 0, st>>>(off, q, nq, qs);
+}
+
+}  // namespace rbe

@@ -18,7 +18,7 @@
 // FP32C form: the turn reduction stays FP64; the hardware turn-argument
 // sine/cosine (v_sin_f32 / v_cos_f32 compute sin(2 pi x), cos(2 pi x)) run on
 // the FP32 fraction; sums are FP32 with Kahan compensation.
-#include "kernels.h"
+#include "fourier_device.h"
 
 namespace rbe {
 
@@ -45,12 +45,6 @@ void launch_modes_to_double(int P, const int32_t *m, double *mkd, hipStream_t st
   k_modes_to_double<<<(3 * P + 255) / 256, 256, 0, st>>>(P, m, mkd);
 }
 
-__device__ inline double turn_fraction(double mx, double my, double mz, double sx, double sy, double sz) {
-#pragma clang fp contract(off)
-  const double t = mx * sx + my * sy + mz * sz;
-  return t - rint(t);
-}
-
 // ---------------------------------------------------------------------------
 // structure factor partial sums
 // ---------------------------------------------------------------------------
@@ -73,14 +67,6 @@ __global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f64(int64_t nq, 
     im = fma(s.w, sn, im);
   }
   if (active) part[(int64_t)blockIdx.x * P + l] = make_double2(re, im);
-}
-
-__device__ inline void kahan_add(float &sum, float &comp, float v) {
-#pragma clang fp contract(off)
-  const float y = v - comp;
-  const float t = sum + y;
-  comp = (t - sum) - y;
-  sum = t;
 }
 
 __global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f32c(int64_t nq, int P, int chunk,

@@ -82,6 +82,11 @@ struct PairParams {
   int p_shell;
   uint64_t shell_key;    // stream key of the shell batches for this evaluation
 };
+// FP32 copies of the pair constants (FP32C form).
+struct PairF32 {
+  float sqrt_alpha, neg_alpha_log2e, two_sqrt_alpha_over_sqrt_pi, kc, eps24, sig2;
+};
+PairF32 make_pair_f32(const PairParams &pp);
 struct PairCounters {
   unsigned long long *c;  // [4] or nullptr
 };
@@ -141,5 +146,65 @@ struct StateArrays {
   int32_t *id;
 };
 void launch_reorder_state(int64_t n, const int32_t *perm, StateArrays in, StateArrays out, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// batched form (many replicas, one persistent launch per step)
+// ---------------------------------------------------------------------------
+struct RepDesc {
+  Grid g;
+  int64_t p0, n;       // particle range
+  int64_t c0;          // first key (2 * ncell keys per replica)
+  int s_coul, s_lj;    // stencil radii
+  ModeTable mt;        // mode table; its cdf starts at cdf_off
+  int cdf_off;
+  uint64_t seed;
+  int nq;              // charged particles (the first nq of the replica's sorted range)
+  int chunk_len;       // structure-factor chunk length
+  int nchunks;         // chunks of this replica
+  int chunk_off;       // first chunk of this replica in the partial array
+  int rho_item_off;    // first structure-factor item of this replica
+};
+
+struct BatchArgs {
+  int nrep;
+  const RepDesc *reps;
+  const int32_t *rep_of;  // replica of every particle slot
+  int64_t ntot;
+  int64_t nkeys;
+  int ntiles;
+  int P;
+  int mode;               // 0: step, 1: force evaluation only
+  int rho_items;          // total structure-factor items (chunk x 64-mode group)
+  int do_far;             // Fourier part on
+  PairParams pp;          // physics shared by all replicas (grid fields unused)
+  PairF32 pf;
+  double h, dt;           // dt / (2 m), dt
+  // state: in (read; advanced in place by the drift) and out (sorted)
+  double *ix, *iy, *iz, *ivx, *ivy, *ivz, *iq, *ifx, *ify, *ifz;
+  int32_t *iid;
+  double *ox, *oy, *oz, *ovx, *ovy, *ovz, *oq, *ofx, *ofy, *ofz;
+  int32_t *oid;
+  double *cfx, *cfy, *cfz;  // force-only mode: output in the caller's order
+  double4 *xq, *sq;
+  int32_t *sid;
+  int32_t *key, *slot, *tmp, *perm, *count, *cell_start, *tile_sum;
+  const double *cdf;
+  GatherMode *modes;      // [nrep * P]
+  double *wk;             // [nrep * P] mode weights
+  double2 *part;          // [total chunks * P]
+  int *err;
+  unsigned *bar;          // [2] arrival count, generation
+  uint64_t *eval;         // evaluation index of the step (advanced by the kernel)
+};
+
+// Resident capacity of the step kernel (blocks), the launch, and the scan tiling.
+int batch_grid_blocks(int prec, int device);
+void launch_batch_step(int prec, int blocks, const BatchArgs &a, hipStream_t st);
+int batch_scan_tiles(int64_t nkeys);
+// Adds one step launch to `graph` (the node copies *a).
+hipError_t add_batch_node(hipGraph_t graph, hipGraphNode_t *node, const hipGraphNode_t *deps, int ndeps, int prec,
+                          int blocks, BatchArgs *a);
+// Per-replica charge statistics: nq[r] charged count, qs[2r] = sum q, qs[2r+1] = sum |q|.
+void launch_qstats_rep(int nrep, const int64_t *off, const double *q, int32_t *nq, double *qs, hipStream_t st);
 
 }  // namespace rbe

@@ -24,265 +24,9 @@
 // Pair force on i: (kc q_i q_j G(r) + G_LJ(r)) d, d = r_i - r_j,
 //   G(r)    = erfc(sqrt(a) r)/r^3 + 2 sqrt(a) exp(-a r^2)/(sqrt(pi) r^2),
 //   G_LJ(r) = 24 eps (2 sigma^12/r^14 - sigma^6/r^8).
-#include "kernels.h"
+#include "pair_device.h"
 
 namespace rbe {
-
-// FP64 erfc(x) = exp(-x^2) R(x) with R(x) = erfc(x) e^{x^2} a degree-20
-// polynomial in s = 2/(1 + x/2) - 1 (fit over x in [0, 8] by fit_erfcx.py,
-// relative error below 7.2e-15); e = exp(-x^2) is passed in.
-__device__ inline double erfc_scaled_f64(double x) {
-  const double s = 2.0 / fma(0.5, x, 1.0) - 1.0;
-  double r = 1.63618628481317543e-08;
-  r = fma(r, s, -4.60928758649811430e-08);
-  r = fma(r, s, -6.88442333452307132e-08);
-  r = fma(r, s, 4.40190654889049080e-07);
-  r = fma(r, s, -4.46917185831068957e-07);
-  r = fma(r, s, -1.14063358111397811e-06);
-  r = fma(r, s, 3.75537844601685302e-06);
-  r = fma(r, s, -1.41703053499259700e-06);
-  r = fma(r, s, -1.39602653735770222e-05);
-  r = fma(r, s, 2.75867068654632672e-05);
-  r = fma(r, s, 2.75241444094816018e-05);
-  r = fma(r, s, -1.74362281120596591e-04);
-  r = fma(r, s, 4.35557661104548185e-05);
-  r = fma(r, s, 9.81977137355043118e-04);
-  r = fma(r, s, -8.47143262890503600e-04);
-  r = fma(r, s, -6.99746174546772310e-03);
-  r = fma(r, s, 3.73289240473987467e-03);
-  r = fma(r, s, 7.89785810158994406e-02);
-  r = fma(r, s, 2.41658194242463487e-01);
-  r = fma(r, s, 4.27185847413955655e-01);
-  r = fma(r, s, 2.55395676310504194e-01);
-  return r;
-}
-
-__device__ inline double pair_scalar_f64(const PairParams &pp, double r2, double qi, double qj) {
-  const double inv_r2 = 1.0 / r2;
-  double f = 0.0;
-  if (pp.do_coul && r2 <= pp.rc2 && qi != 0.0 && qj != 0.0) {
-    const double r = sqrt(r2);
-    const double e = exp(-pp.alpha * r2);
-    const double R = erfc_scaled_f64(pp.sqrt_alpha * r);
-    // G = erfc(x)/r^3 + 2 sqrt(a) e/(sqrt(pi) r^2) = e/r^2 (R/r + 2 sqrt(a)/sqrt(pi))
-    const double G = e * inv_r2 * (R / r + pp.two_sqrt_alpha_over_sqrt_pi);
-    f = pp.kc * qi * qj * G;
-  }
-  if (pp.do_lj && r2 <= pp.rlj2) {
-    const double s2 = pp.sig2 * inv_r2;
-    const double s6 = s2 * s2 * s2;
-    f = fma(pp.eps24 * (2.0 * s6 * s6 - s6), inv_r2, f);
-  }
-  return f;
-}
-
-// FP32 form of the pair scalar: erfc(x) = exp(-x^2) R(x), R(x) = erfc(x) e^{x^2}
-// as a degree-9 polynomial in t = 1/(1 + x/2) (fit over x in [0, 8] by
-// fit_erfcx.py; relative error of the FP32 evaluation below 3.3e-7). The
-// exponential exp(-alpha r^2) is shared with the second term of G.
-struct PairF32 {
-  float sqrt_alpha, neg_alpha_log2e, two_sqrt_alpha_over_sqrt_pi, kc, eps24, sig2;
-};
-
-__device__ inline float erfcx_poly(float t) {
-  float r = -5.023304369e-02f;
-  r = fmaf(r, t, 2.383836403e-01f);
-  r = fmaf(r, t, -3.831243495e-01f);
-  r = fmaf(r, t, 1.457629880e-01f);
-  r = fmaf(r, t, 7.766769416e-02f);
-  r = fmaf(r, t, 1.499599762e-01f);
-  r = fmaf(r, t, 2.601579210e-01f);
-  r = fmaf(r, t, 2.789792283e-01f);
-  r = fmaf(r, t, 2.824637353e-01f);
-  r = fmaf(r, t, -1.781403551e-05f);
-  return r;
-}
-
-__device__ inline float pair_scalar_f32(const PairParams &pp, const PairF32 &pf, double r2d, float qiqj) {
-  const float r2 = (float)r2d;
-  const float rinv = __builtin_amdgcn_rsqf(r2);
-  const float rinv2 = rinv * rinv;
-  float f = 0.f;
-  if (pp.do_coul && r2d <= pp.rc2 && qiqj != 0.f) {
-    const float r = r2 * rinv;
-    const float x = pf.sqrt_alpha * r;
-    const float e = __builtin_amdgcn_exp2f(pf.neg_alpha_log2e * r2);
-    const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, x, 1.0f));
-    const float erfc_x = e * erfcx_poly(t);
-    const float G = fmaf(erfc_x * rinv, rinv2, pf.two_sqrt_alpha_over_sqrt_pi * e * rinv2);
-    f = pf.kc * qiqj * G;
-  }
-  if (pp.do_lj && r2d <= pp.rlj2) {
-    const float s2 = pf.sig2 * rinv2;
-    const float s6 = s2 * s2 * s2;
-    f = fmaf(pf.eps24 * fmaf(2.0f, s6 * s6, -s6), rinv2, f);
-  }
-  return f;
-}
-
-__device__ inline double pair_scalar_lj_f64(const PairParams &pp, double r2) {
-  if (!(pp.do_lj && r2 <= pp.rlj2)) return 0.0;
-  const double inv_r2 = 1.0 / r2;
-  const double s2 = pp.sig2 * inv_r2;
-  const double s6 = s2 * s2 * s2;
-  return pp.eps24 * (2.0 * s6 * s6 - s6) * inv_r2;
-}
-
-__device__ inline float pair_scalar_lj_f32(const PairParams &pp, const PairF32 &pf, double r2d) {
-  if (!(pp.do_lj && r2d <= pp.rlj2)) return 0.f;
-  const float rinv2 = __builtin_amdgcn_rcpf((float)r2d);
-  const float s2 = pf.sig2 * rinv2;
-  const float s6 = s2 * s2 * s2;
-  return pf.eps24 * fmaf(2.0f, s6 * s6, -s6) * rinv2;
-}
-
-// Kahan-compensated FP32 accumulation of a 3-vector.
-struct Kahan3 {
-  float s[3] = {0.f, 0.f, 0.f}, c[3] = {0.f, 0.f, 0.f};
-  __device__ inline void add(int k, float v) {
-#pragma clang fp contract(off)
-    const float y = v - c[k];
-    const float t = s[k] + y;
-    c[k] = (t - s[k]) - y;
-    s[k] = t;
-  }
-  __device__ inline double get(int k) const { return (double)s[k] - (double)c[k]; }
-};
-
-__device__ inline double sq_dist(double dx, double dy, double dz) {
-#pragma clang fp contract(off)
-  return dx * dx + dy * dy + dz * dz;
-}
-
-__device__ inline double min_image(double a, double L) {
-#pragma clang fp contract(off)
-  return a - L * rint(a / L);
-}
-
-// Calls fn(j, p_j, id_j, shx, shy, shz) for the records j0..j1-1 of xq (and
-// ids when WITH_ID, else id_j = 0). Four fixed slots: slot k holds record
-// j + k and is reloaded with j + k + 4 right after use, so each load has
-// three candidates of work to complete behind it. Indices past the range are
-// clamped to its last record (always a valid address).
-template <bool WITH_ID, class Fn>
-__device__ inline void scan_range(const double4 *__restrict__ xq, const int32_t *__restrict__ ids, int j0, int j1,
-                                  double shx, double shy, double shz, Fn &&fn) {
-  if (j0 >= j1) return;
-  const int last = j1 - 1;
-  double4 r0 = xq[j0], r1 = xq[min(j0 + 1, last)], r2 = xq[min(j0 + 2, last)], r3 = xq[min(j0 + 3, last)];
-  int d0 = 0, d1 = 0, d2 = 0, d3 = 0;
-  if (WITH_ID) {
-    d0 = ids[j0];
-    d1 = ids[min(j0 + 1, last)];
-    d2 = ids[min(j0 + 2, last)];
-    d3 = ids[min(j0 + 3, last)];
-  }
-#pragma unroll 1
-  for (int j = j0; j < j1; j += 4) {
-    fn(j, r0, d0, shx, shy, shz);
-    r0 = xq[min(j + 4, last)];
-    if (WITH_ID) d0 = ids[min(j + 4, last)];
-    if (j + 1 < j1) fn(j + 1, r1, d1, shx, shy, shz);
-    r1 = xq[min(j + 5, last)];
-    if (WITH_ID) d1 = ids[min(j + 5, last)];
-    if (j + 2 < j1) fn(j + 2, r2, d2, shx, shy, shz);
-    r2 = xq[min(j + 6, last)];
-    if (WITH_ID) d2 = ids[min(j + 6, last)];
-    if (j + 3 < j1) fn(j + 3, r3, d3, shx, shy, shz);
-    r3 = xq[min(j + 7, last)];
-    if (WITH_ID) d3 = ids[min(j + 7, last)];
-  }
-}
-
-// Periodic traversal: every particle j of species block `blk` in the
-// (2s+1)^3 cells around (cx, cy, cz); (shx, shy, shz) is the image shift of j
-// (its image lies at r_j + shift).
-template <bool WITH_ID, class Fn>
-__device__ inline void for_stencil(const Grid &g, const int32_t *__restrict__ cell_start,
-                                   const double4 *__restrict__ xq, const int32_t *__restrict__ ids, int blk, int cx,
-                                   int cy, int cz, int s, Fn &&fn) {
-  const int base = blk * g.ncell;
-  for (int oz = -s; oz <= s; ++oz) {
-    const int az = cz + oz;
-    const int qz = floor_div(az, g.nz);
-    const int wz = az - qz * g.nz;
-    const double shz = (double)qz * g.L[2];
-    for (int oy = -s; oy <= s; ++oy) {
-      const int ay = cy + oy;
-      const int qy = floor_div(ay, g.ny);
-      const int wy = ay - qy * g.ny;
-      const double shy = (double)qy * g.L[1];
-      const int row = base + (wz * g.ny + wy) * g.nx;
-      int a = cx - s;
-      const int a_end = cx + s;
-      while (a <= a_end) {
-        const int qx = floor_div(a, g.nx);
-        const int b = min(a_end, (qx + 1) * g.nx - 1);
-        const int j0 = cell_start[row + (a - qx * g.nx)];
-        const int j1 = cell_start[row + (b - qx * g.nx) + 1];
-        scan_range<WITH_ID>(xq, ids, j0, j1, (double)qx * g.L[0], shy, shz, fn);
-        a = b + 1;
-      }
-    }
-  }
-}
-
-// Ghost-shell traversal (no periodic images): the natives of the stencil
-// rows that lie inside the native grid, then the ghosts of the same rows of
-// the padded grid. (cx, cy, cz) is a native cell.
-template <bool WITH_ID, class Fn>
-__device__ inline void for_stencil_ghost(const Grid &g, const int32_t *__restrict__ cell_start,
-                                         const double4 *__restrict__ xq, const int32_t *__restrict__ ids,
-                                         const int32_t *__restrict__ gcell_start, const double4 *__restrict__ gxq,
-                                         const int32_t *__restrict__ gid, int blk, int cx, int cy, int cz, int s,
-                                         Fn &&fn) {
-  const int base = blk * g.ncell;
-  const int pbase = blk * g.pncell;
-  const int xa = max(cx - s, 0), xb = min(cx + s, g.nx - 1);
-  for (int oz = -s; oz <= s; ++oz) {
-    const int z = cz + oz;
-    for (int oy = -s; oy <= s; ++oy) {
-      const int y = cy + oy;
-      if (z >= 0 && z < g.nz && y >= 0 && y < g.ny) {
-        const int row = base + (z * g.ny + y) * g.nx;
-        scan_range<WITH_ID>(xq, ids, cell_start[row + xa], cell_start[row + xb + 1], 0.0, 0.0, 0.0, fn);
-      }
-      const int prow = pbase + ((z + g.goff[2]) * g.pny + (y + g.goff[1])) * g.pnx + g.goff[0];
-      scan_range<WITH_ID>(gxq, gid, gcell_start[prow + cx - s], gcell_start[prow + cx + s + 1], 0.0, 0.0, 0.0, fn);
-    }
-  }
-}
-
-// Accumulator of the per-particle force in the two precision forms.
-// add<true> evaluates Coulomb + LJ, add<false> LJ only (j neutral).
-template <bool F32>
-struct ForceAcc;
-template <>
-struct ForceAcc<false> {
-  double v[3] = {0.0, 0.0, 0.0};
-  template <bool COUL>
-  __device__ inline void add(const PairParams &pp, const PairF32 &, double r2, double qi, double qj, double dx,
-                             double dy, double dz) {
-    const double sc = COUL ? pair_scalar_f64(pp, r2, qi, qj) : pair_scalar_lj_f64(pp, r2);
-    v[0] = fma(sc, dx, v[0]);
-    v[1] = fma(sc, dy, v[1]);
-    v[2] = fma(sc, dz, v[2]);
-  }
-  __device__ inline double get(int k) const { return v[k]; }
-};
-template <>
-struct ForceAcc<true> {
-  Kahan3 k;
-  template <bool COUL>
-  __device__ inline void add(const PairParams &pp, const PairF32 &pf, double r2, double qi, double qj, double dx,
-                             double dy, double dz) {
-    const float sc = COUL ? pair_scalar_f32(pp, pf, r2, (float)(qi * qj)) : pair_scalar_lj_f32(pp, pf, r2);
-    k.add(0, sc * (float)dx);
-    k.add(1, sc * (float)dy);
-    k.add(2, sc * (float)dz);
-  }
-  __device__ inline double get(int c) const { return k.get(c); }
-};
 
 struct PairCtx {
   PairParams pp;
@@ -565,7 +309,7 @@ __global__ void __launch_bounds__(kShellThreads) k_pair_shell(PairCtx c) {
   flush_counts<COUNT>(c, n_coul, n_lj, n_tested, (unsigned long long)ns);
 }
 
-static PairF32 make_f32(const PairParams &pp) {
+PairF32 make_pair_f32(const PairParams &pp) {
   PairF32 pf;
   pf.sqrt_alpha = (float)pp.sqrt_alpha;
   pf.neg_alpha_log2e = (float)(-pp.alpha * 1.4426950408889634074);
@@ -643,7 +387,7 @@ void launch_pair(int prec, int part, const PairParams &pp, int64_t n, int64_t nq
   if (n <= 0) return;
   PairCtx c;
   c.pp = pp;
-  c.pf = make_f32(pp);
+  c.pf = make_pair_f32(pp);
   c.xq = s.xq;
   c.ids = s.id;
   c.cell_start = cell_start;

@@ -148,6 +148,6 @@ void launch_sample_modes_dev_eval(const ModeTable &t, const double *cdf_dev, uin
 // ---------------------------------------------------------------------------
 // Error flag bits (device int)
 // ---------------------------------------------------------------------------
-enum : int { kErrNonFinite = 1, kErrBadId = 2, kErrSampler = 4, kErrGhostOverflow = 8 };
+enum : int { kErrNonFinite = 1, kErrBadId = 2, kErrSampler = 4, kErrGhostOverflow = 8, kErrBarrier = 16 };
 
 }  // namespace rbe

@@ -74,3 +74,33 @@ def test_null_arguments():
     assert lib.rbe_forces(None, None, None, None, 0, None, None) == rbe.RBE_EINVAL
     assert lib.rbe_step(None, None, 1, 0, None) == rbe.RBE_EINVAL
     assert lib.rbe_sync_check(None, None) == rbe.RBE_EINVAL
+
+
+def _create_batch(plist, offsets):
+    lib = rbe.load()
+    h = ctypes.c_void_p()
+    arr = (rbe.Params * len(plist))(*plist)
+    off = (ctypes.c_int64 * len(offsets))(*offsets)
+    rc = lib.rbe_create_batch(ctypes.byref(h), len(plist), arr, off, 0)
+    return rc, lib.rbe_last_error(None).decode()
+
+
+def test_create_batch_rejects_bad_layouts():
+    p = [rbe.make_params(12.6, 0.3, 6.0, 2.5, 100, seed=s) for s in range(3)]
+    assert _create_batch(p, [1, 10, 20, 30])[0] == rbe.RBE_EINVAL   # offset[0] != 0
+    assert _create_batch(p, [0, 10, 10, 30])[0] == rbe.RBE_EINVAL   # empty replica
+    assert _create_batch(p, [0, 10, 20, 2 ** 31])[0] == rbe.RBE_EINVAL
+
+
+def test_create_batch_requires_shared_physics():
+    p = [rbe.make_params(12.6 + r, 0.3, 6.0, 2.5, 100, seed=r) for r in range(3)]
+    p[2].alpha = 0.31
+    rc, msg = _create_batch(p, [0, 10, 20, 30])
+    assert rc == rbe.RBE_EINVAL and "replica 2" in msg
+    p = [rbe.make_params(12.6, 0.35, 6.0, 2.5, 100, r_core=3.0, p_shell=20) for _ in range(2)]
+    rc, msg = _create_batch(p, [0, 10, 20])
+    assert rc == rbe.RBE_EINVAL and "random batch list" in msg
+    # a replica whose box is too small for the cutoff is named
+    p = [rbe.make_params(12.6, 0.3, 6.0, 2.5, 100), rbe.make_params(11.0, 0.3, 6.0, 2.5, 100)]
+    rc, msg = _create_batch(p, [0, 10, 20])
+    assert rc == rbe.RBE_EBOX and "replica 1" in msg
