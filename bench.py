@@ -49,12 +49,33 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="electrolyte1m")
+    ap.add_argument("--workload", default="electrolyte1m",
+                    choices=["plain3k", "electrolyte1m", "ions8m", "subdomain64m", "replica256"])
+    ap.add_argument("--compare-steps", type=int, default=20,
+                    help="steps of each comparison form (replica256: FP64 and FP32C per-replica loops)")
+    ap.add_argument("--edge", type=float, default=None, help="cell edge (replica256)")
     ap.add_argument("--prec", default=None, choices=["fp64", "fp32c"])
     ap.add_argument("--n", type=int, default=None, help="override the particle count (same density)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel HIP event timing")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (scale of the HBM byte counters)")
     return ap.parse_args()
+
+
+def calibrate_copy(mib):
+    """Five plain device-to-device copies of `mib` MiB: the HBM byte counters of
+    one such copy should read `mib` MiB fetched and `mib` MiB written."""
+    import torch
+
+    n = mib * (1 << 20) // 8
+    src = torch.arange(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_mib": mib, "bytes_per_copy": 2 * n * 8}), flush=True)
 
 
 def main():
@@ -73,7 +94,11 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if a.calibrate_copy:
+        return calibrate_copy(a.calibrate_copy)
     rbe.load()
+    if a.workload == "replica256":
+        return bench_batch(a)
     p = gen.preset(a.workload, n=a.n)
     prec_name = a.prec or ("fp64" if a.workload in ("plain3k", "electrolyte1m") else "fp32c")
     prec = rbe.FP64 if prec_name == "fp64" else rbe.FP32C
@@ -151,6 +176,162 @@ def main():
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, s)
     print(json.dumps(out), flush=True)
+
+
+def bench_batch(a):
+    """256 replicas of uneven size advanced together by the batched form."""
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2609_02694_amd as rbe
+    from paper_2609_02694_amd import tune
+
+    prec_name = a.prec or "fp32c"
+    prec = rbe.FP64 if prec_name == "fp64" else rbe.FP32C
+    t0 = time.time()
+    sizes = gen.replica_sizes(256)
+    reps, cat, off = gen.replica_batch(sizes)
+    t_gen = time.time() - t0
+    ntot = int(off[-1])
+    edge = a.edge or DEFAULT_NCELL_H["replica"]
+    ctx = rbe.Context.batch(tune.batch_params(reps, edge, prec), off)
+    st = rbe.Particles.from_numpy(cat)
+    stream = torch.cuda.current_stream()
+    ctx.forces(st, None, None, 0)
+    K, W = a.steps, a.warmup
+    if W > 0:
+        ctx.step(st, W, 1)
+    torch.cuda.synchronize()
+    ctx.sync_check()
+    if not a.no_timing:
+        ctx.set_timing(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    ctx.step(st, K, 1 + W)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    w1 = time.perf_counter()
+    kt = ctx.timing() if not a.no_timing else {}
+    ctx.set_timing(False)
+    ctx.sync_check()
+    ctx.close()
+    wall_s = w1 - w0
+    value = ntot * K / wall_s
+    kernels = {k: {"total_ms": round(v[0], 4), "launches": v[1], "avg_us": round(1000 * v[0] / v[1], 3)}
+               for k, v in kt.items() if v[1] > 0}
+
+    # comparison forms (same replicas, same grids): per-replica loops of
+    # single-system contexts in FP64 and FP32C, and the batched form in FP64
+    def loop_rate(pr):
+        ctxs, sts = [], []
+        for (p, s) in reps:
+            n = max(1, int(p["L"] // edge))
+            ctxs.append(rbe.Context(rbe.params_from_preset(p, prec=pr, ncell=(n, n, n), seed=p["stream_seed"]),
+                                    p["n"]))
+            sts.append(rbe.Particles.from_numpy(s))
+        for c, s_ in zip(ctxs, sts):
+            c.forces(s_, None, None, 0)
+            c.step(s_, 2, 1)
+        torch.cuda.synchronize()
+        Kc = a.compare_steps
+        t = time.perf_counter()
+        for c, s_ in zip(ctxs, sts):
+            c.step(s_, Kc, 3)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        counts = None
+        if pr == rbe.FP64:
+            counts = [0, 0, 0, 0]
+            for c, s_ in zip(ctxs, sts):
+                c.set_counting(True)
+                c.forces(s_, None, None, 0)
+                for v in c.counters().values():
+                    for i in range(4):
+                        counts[i] += v[i]
+        for c in ctxs:
+            c.sync_check()
+            c.close()
+        return ntot * Kc / dt, counts
+
+    v64_loop, counts = loop_rate(rbe.FP64)
+    v32_loop, _ = loop_rate(rbe.FP32C)
+    other = rbe.FP64 if prec == rbe.FP32C else rbe.FP32C
+    ms_other = tune.time_batch(reps, cat, off, edge, other, steps=a.compare_steps)
+    forms = {
+        f"batched_{prec_name}": value,
+        f"batched_{'fp64' if other == rbe.FP64 else 'fp32c'}": ntot / (ms_other * 1e-3),
+        "loop_fp64": v64_loop,
+        "loop_fp32c": v32_loop,
+    }
+    nq = int(np.count_nonzero(cat["q"]))
+    P = reps[0][0]["P"]
+    roof = None
+    if "batch" in kernels:
+        work = FLOPS_COUL_PAIR * counts[0] + FLOPS_LJ_PAIR * counts[1] + (FLOPS_RHO_IK + FLOPS_GATHER_IK) * nq * P
+        avg_s = kernels["batch"]["avg_us"] * 1e-6
+        peak = PEAK_FP64_TFLOPS if prec == rbe.FP64 else PEAK_FP32_TFLOPS
+        ach = work / avg_s / 1e12
+        roof = dict(kernel="batch", bound="alu", achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak,
+                    traffic=None, work_per_launch=work)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": 1000.0 * wall_s / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == rbe.FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "replica256", "replicas": len(sizes), "n": ntot, "n_charged": nq,
+                   "n_min": min(sizes), "n_max": max(sizes), "density": 0.5, "alpha": reps[0][0]["alpha"],
+                   "r_coul": reps[0][0]["r_coul"], "r_lj": reps[0][0]["r_lj"], "P": P, "form": "batched " + prec_name,
+                   "cell_edge": edge, "parallelism": "single GPU"},
+        "event_ms_per_step": ev0.elapsed_time(ev1) / K,
+        "kernels": kernels,
+        "forms_particle_steps_per_s": forms,
+        "counts_per_eval": dict(zip(("coul_pairs", "lj_pairs", "candidates", "shell_members"), counts)),
+        "roofline": roof,
+        "gen_s": round(t_gen, 2),
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batch(reps)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_batch(reps, budget_s=15.0):
+    """The FP64 CPU oracle on one velocity-Verlet step of replicas taken in order until about budget_s."""
+    import numpy as np
+
+    import oracle
+
+    done = 0
+    t0 = time.perf_counter()
+    k = 0
+    for p, s in reps:
+        osys = oracle.sys_from_preset(p)
+        m, w = oracle.sample_k(p["stream_seed"], 1, p["L"], p["alpha"], p["P"])
+        r = np.stack([s["x"], s["y"], s["z"]], axis=1)
+        v = np.stack([s["vx"], s["vy"], s["vz"]], axis=1)
+        v = oracle.kick(np.zeros_like(r), v, p["dt"] / 2)
+        r = oracle.drift_wrap(r, v, p["dt"], p["L"])
+        F = oracle.total_force(r[:, 0], r[:, 1], r[:, 2], s["q"], s["id"], osys, m, w, ev=1, components=False)["F"]
+        v = oracle.kick(F, v, p["dt"] / 2)
+        done += p["n"]
+        k += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "particle-steps/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"one velocity-Verlet step of the first {k} replicas ({done} particles)",
+            "seconds": round(dt, 2)}
 
 
 def roofline(kernels, cnt, nq, p, prec, K):

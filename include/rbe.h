@@ -170,9 +170,10 @@ int rbe_step(rbe_ctx *ctx, rbe_state *s, int32_t nsteps, uint64_t first_eval, vo
 int rbe_sync_check(rbe_ctx *ctx, void *stream);
 
 /* Diagnostic counters of the last rbe_forces/rbe_step force evaluation
-   (host, 12 entries = 3 near-field launches x 4): launch k in {0: charged
-   particles (plain sums or core), 1: shell of the random batch list,
-   2: neutral particles}; entry [4k + 0] Coulomb pair terms evaluated (both
+   (host, 12 entries = 3 near-field parts x 4): part k in {0: charged
+   particles (plain sums, or core and shell of the random batch list),
+   1: reserved (zero), 2: neutral particles}; entry [4k + 0] Coulomb pair
+   terms evaluated (both
    charged, inside the cutoff), [4k + 1] LJ pair terms evaluated (inside
    r_lj), [4k + 2] candidate pairs tested, [4k + 3] shell members ranked
    (sum of #S_i, Eq. 10).
@@ -199,7 +200,8 @@ enum {
   RBE_TK_KICK_DRIFT = 8,  /* first half-kick + drift + wrap                 */
   RBE_TK_KICK = 9,        /* second half-kick (+ mean subtraction)          */
   RBE_TK_PAIR_CHARGED = 10, /* near field of the charged particles (core)   */
-  RBE_TK_PAIR_SHELL = 11, /* shell ranking and batch of Eq. 11              */
+  RBE_TK_PAIR_SHELL = 11, /* reserved: the shell of Eq. 11 is timed with
+                             RBE_TK_PAIR_CHARGED (one fused launch)          */
   RBE_TK_GHOST = 12,      /* ghost shell build and sort                     */
   RBE_TK_BATCH = 13,      /* persistent step of a batched context (one entry
                              per step; the phases are not timed apart)      */

@@ -321,6 +321,13 @@ extern "C" int rbe_create(rbe_ctx **out, const rbe_params *p, int64_t n_max, int
     g.goff[d] = p->ghost_width > 0 ? (int)std::ceil(p->ghost_width * g.inv_h[d] * (1.0 + 1e-12)) : 0;
   }
   g.ghost_width = p->ghost_width;
+  make_pair_params(c->p, g, &c->pp);
+  if (p->ghost_width > 0) {
+    // the ghost layers must also hold every stencil (radii are per grid, the
+    // same on all axes)
+    const int smax = std::max(c->pp.s_coul, std::max(c->pp.s_lj, c->pp.s_core));
+    for (int d = 0; d < 3; ++d) g.goff[d] = std::max(g.goff[d], smax);
+  }
   g.pnx = g.nx + 2 * g.goff[0];
   g.pny = g.ny + 2 * g.goff[1];
   g.pnz = g.nz + 2 * g.goff[2];
@@ -329,7 +336,7 @@ extern "C" int rbe_create(rbe_ctx **out, const rbe_params *p, int64_t n_max, int
     delete c;
     return create_fail(RBE_EINVAL, "padded cell grid too large");
   }
-  make_pair_params(c->p, g, &c->pp);
+  c->pp.g = g;
 
   // mode tables
   build_mode_table(p->L, p->alpha, &c->mt, nullptr);
@@ -658,6 +665,7 @@ static int eval_sorted(rbe_ctx *c, int64_t n, int64_t nq, const int32_t *m, cons
   if (terms & (RBE_TERM_LJ | RBE_TERM_COUL_REAL)) {
     PairParams pp = c->pp;
     pp.shell_key = shell_eval_key(c->p.seed, eval);
+    pp.shell_T0 = shell_first_threshold(pp, n);
     if (pp.rbl) {
       TScope ts(c, RBE_TK_REORDER, st);
       launch_inverse_ids(n, c->srt.id, c->inv_id, c->err, st);
@@ -674,11 +682,6 @@ static int eval_sorted(rbe_ctx *c, int64_t n, int64_t nq, const int32_t *m, cons
       TScope ts(c, RBE_TK_PAIR_CHARGED, st);
       launch_pair(c->p.prec, PAIR_PART_CHARGED, pp, n, nq, c->srt, c->cell_start, c->inv_id, gb, fx, fy, fz,
                   part_cnt(PAIR_PART_CHARGED), st);
-    }
-    if (pp.rbl) {
-      TScope ts(c, RBE_TK_PAIR_SHELL, st);
-      launch_pair(c->p.prec, PAIR_PART_SHELL, pp, n, nq, c->srt, c->cell_start, c->inv_id, gb, fx, fy, fz,
-                  part_cnt(PAIR_PART_SHELL), st);
     }
     {
       TScope ts(c, RBE_TK_PAIR, st);

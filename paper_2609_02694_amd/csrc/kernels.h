@@ -81,19 +81,25 @@ struct PairParams {
   int rbl;               // random batch list on
   int p_shell;
   uint64_t shell_key;    // stream key of the shell batches for this evaluation
+  uint64_t shell_T0;     // first key threshold of the shell selection (<= 2^32)
 };
 // FP32 copies of the pair constants (FP32C form).
 struct PairF32 {
   float sqrt_alpha, neg_alpha_log2e, two_sqrt_alpha_over_sqrt_pi, kc, eps24, sig2;
 };
 PairF32 make_pair_f32(const PairParams &pp);
+// Shell selection of the random batch list: keys collected per particle, and
+// the first threshold (about 3p keys below it for the mean shell of n
+// particles in the box; 2^32 = all keys when shells are small).
+constexpr int kShellCap = 128;
+uint64_t shell_first_threshold(const PairParams &pp, int64_t n);
 struct PairCounters {
   unsigned long long *c;  // [4] or nullptr
 };
 // Near-field force; charged particles are [0, nq) of the sorted order,
-// neutral ones [nq, n). Launched in three parts, in this order: charged
-// particles (plain sums, or the core of the random batch list), the shell of
-// the random batch list (adds to the charged forces), neutral particles.
+// neutral ones [nq, n). Launched in two parts: charged particles (plain
+// sums, or core and shell of the random batch list) and neutral particles.
+// PAIR_PART_SHELL launches nothing (kept for the counter layout).
 enum { PAIR_PART_CHARGED = 0, PAIR_PART_SHELL = 1, PAIR_PART_NEUTRAL = 2 };
 // gb: ghost shell of the natives (nullptr for the periodic traversal).
 void launch_pair(int prec, int part, const PairParams &pp, int64_t n, int64_t nq, const Sorted &s,

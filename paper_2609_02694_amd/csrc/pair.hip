@@ -1,25 +1,30 @@
 // Near-field force (Sec. 2.1, Eq. 7-8, 10-11): erfc-screened Coulomb plus
 // 12-6 Lennard-Jones over a cell list, with the core-shell random batch list.
 //
-// One thread per particle i (cell order), full neighbour sums, no atomics.
-// A thread walks the stencil of cells around its own cell; a stencil row is
-// a run of consecutive x-cells, contiguous in the sorted arrays, split only
-// where it crosses the periodic boundary (each piece carries the image shift
-// that the minimum-image convention assigns to it).
+// Full neighbour sums per particle i (cell order), no atomics. One wave per
+// cluster of 8 consecutive particles: lane l takes i = cluster[l / 8] and
+// every 8th record of one candidate sequence shared by the wave (the union
+// of the cluster's stencils), so the candidate loads are contiguous and the
+// loop is uniform (pair_device.h, cluster traversal). The 8 partial sums of
+// an i are added in a fixed order at the end.
 //
 // Species blocks: charged particles occupy keys [0, C), neutral ones
 // [C, 2C). Coulomb terms only involve charged pairs, so without the random
 // batch list a charged i walks the charged block out to r_coul and the
 // neutral block out to r_lj; a neutral i walks both blocks out to r_lj.
 //
-// Random batch list (Eq. 10-11), for particles whose shell terms can be
-// non-zero: every j within r_coul is classified with the squared distance
-// computed without contraction (the same IEEE expression as the CPU oracle):
-// core (r^2 <= r_core^2) terms are summed exactly; shell members are counted
-// and their ranking keys kept in a sorted register list of the 32 smallest.
-// The batch is the p smallest keys (all members if #S <= p); a key maps back
-// to the particle id (the key is a bijection of id_j), the id to its sorted
-// slot, and the batch terms are summed with the weight #S/|B|.
+// Random batch list (Eq. 10-11): every j within r_coul is classified with the
+// squared distance computed without contraction (the same IEEE expression as
+// the CPU oracle). Core terms (r^2 <= r_core^2) are summed exactly. Shell
+// members (r_core^2 < r^2 <= r_coul^2) are counted, #S_i, and ranked by the
+// 32-bit key of Eq. 11's batch: the batch B_i is the min(p, #S_i) members
+// with the smallest keys, summed with the weight #S_i/|B_i|. Selection in one
+// pass: keys below a threshold T are appended to the cluster's LDS buffer.
+// T is chosen so that about 3p keys fall below it for the mean shell size; if
+// the buffer ends with fewer than min(p, #S_i) keys or overflows, a pass that
+// only collects keys is repeated with T moved by bisection (keys are distinct,
+// so some T always works). The batch is read back through the key's inverse
+// (key -> id_j -> sorted slot) and its terms use the minimum image.
 //
 // Pair force on i: (kc q_i q_j G(r) + G_LJ(r)) d, d = r_i - r_j,
 //   G(r)    = erfc(sqrt(a) r)/r^3 + 2 sqrt(a) exp(-a r^2)/(sqrt(pi) r^2),
@@ -47,14 +52,14 @@ struct PairCtx {
   const int32_t *__restrict__ gcell_start;
 };
 
-// Stencil walk of the right kind for the kernel.
+// Walk of one species block for a row group.
 template <bool GHOST, bool WITH_ID, class Fn>
-__device__ inline void stencil(const PairCtx &c, int blk, int cx, int cy, int cz, int s, Fn &&fn) {
+__device__ inline void walk(const PairCtx &c, int blk, int xa, int xb, int cy, int cz, int s, int b, Fn &&fn) {
   if (GHOST)
-    for_stencil_ghost<WITH_ID>(c.pp.g, c.cell_start, c.xq, c.ids, c.gcell_start, c.gxq, c.gid, blk, cx, cy, cz, s,
-                               fn);
+    cluster_walk_ghost<WITH_ID>(c.pp.g, c.cell_start, c.xq, c.ids, c.gcell_start, c.gxq, c.gid, blk, xa, xb, cy, cz,
+                                s, b, fn);
   else
-    for_stencil<WITH_ID>(c.pp.g, c.cell_start, c.xq, c.ids, blk, cx, cy, cz, s, fn);
+    cluster_walk<WITH_ID>(c.pp.g, c.cell_start, c.xq, c.ids, (int64_t)blk * c.pp.g.ncell, xa, xb, cy, cz, s, b, fn);
 }
 
 template <bool COUNT>
@@ -68,245 +73,230 @@ __device__ inline void flush_counts(const PairCtx &c, unsigned long long n_coul,
   }
 }
 
-// Plain cutoff sums for particle i. MODE 0: neutral i (LJ over both species
-// blocks out to r_lj); MODE 1: charged i (charged block out to
-// max(r_coul, r_lj), neutral block out to r_lj).
+// i-side data of a cluster lane.
+struct ClusterI {
+  int a, b;
+  bool valid;
+  int64_t i;
+  double xi, yi, zi, qi;
+  int cx, cy, cz;
+};
+
+__device__ inline ClusterI load_cluster_i(const PairCtx &c) {
+  ClusterI r;
+  const int lane = threadIdx.x;
+  r.a = lane / kCJ;
+  r.b = lane % kCJ;
+  const int64_t i_raw = c.i0 + xcd_block(blockIdx.x, gridDim.x) * kCI + r.a;
+  r.valid = i_raw < c.i1;
+  r.i = r.valid ? i_raw : c.i1 - 1;
+  const double4 p = c.xq[r.i];
+  r.xi = p.x;
+  r.yi = p.y;
+  r.zi = p.z;
+  r.qi = p.w;
+  const Grid &g = c.pp.g;
+  r.cx = cell_coord(p.x, g.inv_h[0], g.nx);
+  r.cy = cell_coord(p.y, g.inv_h[1], g.ny);
+  r.cz = cell_coord(p.z, g.inv_h[2], g.nz);
+  return r;
+}
+
+// Plain cutoff sums. MODE 0: neutral i (LJ over both species blocks out to
+// r_lj); MODE 1: charged i (charged block out to max(r_coul, r_lj), neutral
+// block out to r_lj).
 template <bool F32, bool COUNT, int MODE, bool GHOST>
-__global__ void __launch_bounds__(256) k_pair_plain(PairCtx c) {
-  const int64_t i = c.i0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= c.i1) return;
+__global__ void __launch_bounds__(64) k_pair_plain(PairCtx c) {
+  const ClusterI I = load_cluster_i(c);
   const PairParams &pp = c.pp;
   const Grid &g = pp.g;
-  const double4 pi4 = c.xq[i];
-  const double xi = pi4.x, yi = pi4.y, zi = pi4.z, qi = pi4.w;
-  const int cx = cell_coord(xi, g.inv_h[0], g.nx);
-  const int cy = cell_coord(yi, g.inv_h[1], g.ny);
-  const int cz = cell_coord(zi, g.inv_h[2], g.nz);
   ForceAcc<F32> acc;
   unsigned long long n_coul = 0, n_lj = 0, n_tested = 0;
-  // Coulomb + LJ against charged j (block 0 of a charged i)
+  bool in_group = false;
   auto visit_q = [&](int j, const double4 &pj, int, double shx, double shy, double shz) {
-    const double dx = (xi - pj.x) - shx, dy = (yi - pj.y) - shy, dz = (zi - pj.z) - shz;
+    if (!in_group) return;
+    const double dx = (I.xi - pj.x) - shx, dy = (I.yi - pj.y) - shy, dz = (I.zi - pj.z) - shz;
     const double r2 = sq_dist(dx, dy, dz);
     if (COUNT) ++n_tested;
-    if (r2 == 0.0 && j == (int)i) return;
+    if (r2 == 0.0 && j == (int)I.i) return;
     if (r2 <= pp.rc2 || r2 <= pp.rlj2) {
-      acc.template add<true>(pp, c.pf, r2, qi, pj.w, dx, dy, dz);
+      acc.template add<true>(pp, c.pf, r2, I.qi, pj.w, dx, dy, dz);
       if (COUNT) {
         n_coul += (pp.do_coul && r2 <= pp.rc2);
         n_lj += (pp.do_lj && r2 <= pp.rlj2);
       }
     }
   };
-  // LJ only (every other species pairing)
   auto visit_lj = [&](int j, const double4 &pj, int, double shx, double shy, double shz) {
-    const double dx = (xi - pj.x) - shx, dy = (yi - pj.y) - shy, dz = (zi - pj.z) - shz;
+    if (!in_group) return;
+    const double dx = (I.xi - pj.x) - shx, dy = (I.yi - pj.y) - shy, dz = (I.zi - pj.z) - shz;
     const double r2 = sq_dist(dx, dy, dz);
     if (COUNT) ++n_tested;
-    if (r2 == 0.0 && j == (int)i) return;
+    if (r2 == 0.0 && j == (int)I.i) return;
     if (r2 <= pp.rlj2) {
-      acc.template add<false>(pp, c.pf, r2, qi, pj.w, dx, dy, dz);
+      acc.template add<false>(pp, c.pf, r2, I.qi, pj.w, dx, dy, dz);
       if (COUNT) n_lj += pp.do_lj;
     }
   };
-  if (MODE == 1) {
-    stencil<GHOST, false>(c, 0, cx, cy, cz, pp.s_coul, visit_q);
-    if (pp.do_lj) stencil<GHOST, false>(c, 1, cx, cy, cz, pp.s_lj, visit_lj);
-  } else if (pp.do_lj) {
-    stencil<GHOST, false>(c, 0, cx, cy, cz, pp.s_lj, visit_lj);
-    stencil<GHOST, false>(c, 1, cx, cy, cz, pp.s_lj, visit_lj);
+  const int64_t rowkey = (int64_t)I.cz * g.ny + I.cy;
+  for_each_row_group(I.valid, rowkey, I.cx, [&](bool in, int leader, int xa, int xb) {
+    in_group = in;
+    const int cy = __shfl(I.cy, leader, 64), cz = __shfl(I.cz, leader, 64);
+    if (MODE == 1) {
+      walk<GHOST, false>(c, 0, xa, xb, cy, cz, pp.s_coul, I.b, visit_q);
+      if (pp.do_lj) walk<GHOST, false>(c, 1, xa, xb, cy, cz, pp.s_lj, I.b, visit_lj);
+    } else if (pp.do_lj) {
+      walk<GHOST, false>(c, 0, xa, xb, cy, cz, pp.s_lj, I.b, visit_lj);
+      walk<GHOST, false>(c, 1, xa, xb, cy, cz, pp.s_lj, I.b, visit_lj);
+    }
+  });
+  const double f0 = sum_j_lanes(acc.get(0)), f1 = sum_j_lanes(acc.get(1)), f2 = sum_j_lanes(acc.get(2));
+  if (I.valid && I.b == 0) {
+    c.fx[I.i] = f0;
+    c.fy[I.i] = f1;
+    c.fz[I.i] = f2;
   }
-  c.fx[i] = acc.get(0);
-  c.fy[i] = acc.get(1);
-  c.fz[i] = acc.get(2);
   flush_counts<COUNT>(c, n_coul, n_lj, n_tested, 0);
 }
 
-// Sorted insertion of k into the ascending list L[0..CAP), dropping the
-// largest: the new L[t] is the (t+1)-th smallest of L and k, which is
-// min(L[t], max(L[t-1], k)); walking t downwards updates L in place.
-template <int CAP>
-__device__ inline void sorted_insert(uint32_t (&L)[CAP], uint32_t k) {
-#pragma unroll
-  for (int t = CAP - 1; t > 0; --t) L[t] = min(L[t], max(L[t - 1], k));
-  L[0] = min(L[0], k);
-}
-
-// Random batch list (Eq. 10-11) for particle i: exact core, ranked shell.
-// CAP >= p slots hold the smallest shell keys in ascending order.
-template <bool F32, bool COUNT, int CAP, bool GHOST>
-__global__ void __launch_bounds__(256) k_pair_rbl(PairCtx c) {
-  const int64_t i = c.i0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= c.i1) return;
+// Random batch list (Eq. 10-11) for the particles of the launch range: exact
+// core, counted and ranked shell, one walk of both species blocks out to
+// r_coul.
+template <bool F32, bool COUNT, bool GHOST>
+__global__ void __launch_bounds__(64) k_pair_rbl(PairCtx c) {
+  __shared__ uint32_t kbuf[kCI * kShellCap];
+  __shared__ uint32_t ksel[kCI * RBE_MAX_SHELL_BATCH];
+  __shared__ int kcnt[kCI];
+  const ClusterI I = load_cluster_i(c);
   const PairParams &pp = c.pp;
   const Grid &g = pp.g;
-  const double4 pi4 = c.xq[i];
-  const double xi = pi4.x, yi = pi4.y, zi = pi4.z, qi = pi4.w;
-  const int cx = cell_coord(xi, g.inv_h[0], g.nx);
-  const int cy = cell_coord(yi, g.inv_h[1], g.ny);
-  const int cz = cell_coord(zi, g.inv_h[2], g.nz);
+  const int p = pp.p_shell;
+  const ShellKey sk = shell_key_of(pp.shell_key, c.ids[I.i]);
   ForceAcc<F32> acc;
   unsigned long long n_coul = 0, n_lj = 0, n_tested = 0;
-  uint32_t keys[CAP];
-#pragma unroll
-  for (int t = 0; t < CAP; ++t) keys[t] = 0xFFFFFFFFu;
-  const ShellKey sk = shell_key_of(pp.shell_key, c.ids[i]);
-  int ns = 0;
+  int ns = 0;                // shell members seen by this lane
+  uint64_t T = pp.shell_T0;  // keys below T are collected
+  bool in_group = false;
+  if (I.b == 0) kcnt[I.a] = 0;
+  __syncthreads();
+  auto collect = [&](uint32_t k) {
+    if ((uint64_t)k < T) {
+      const int s = atomicAdd(&kcnt[I.a], 1);
+      if (s < kShellCap) kbuf[I.a * kShellCap + s] = k;
+    }
+  };
   auto visit = [&](int j, const double4 &pj, int idj, double shx, double shy, double shz) {
-    const double dx = (xi - pj.x) - shx, dy = (yi - pj.y) - shy, dz = (zi - pj.z) - shz;
+    if (!in_group) return;
+    const double dx = (I.xi - pj.x) - shx, dy = (I.yi - pj.y) - shy, dz = (I.zi - pj.z) - shz;
     const double r2 = sq_dist(dx, dy, dz);
     if (COUNT) ++n_tested;
-    if (r2 == 0.0 && j == (int)i) return;
+    if (r2 == 0.0 && j == (int)I.i) return;
     if (r2 <= pp.rcore2) {
-      acc.template add<true>(pp, c.pf, r2, qi, pj.w, dx, dy, dz);
+      acc.template add<true>(pp, c.pf, r2, I.qi, pj.w, dx, dy, dz);
       if (COUNT) {
-        n_coul += (pp.do_coul && qi != 0.0 && pj.w != 0.0);
+        n_coul += (pp.do_coul && I.qi != 0.0 && pj.w != 0.0);
         n_lj += (pp.do_lj && r2 <= pp.rlj2);
       }
     } else if (r2 <= pp.rc2) {
       ++ns;
-      const uint32_t k = shell_rank(sk, idj);
-      if (k < keys[CAP - 1]) sorted_insert<CAP>(keys, k);
+      collect(shell_rank(sk, idj));
     }
   };
-  stencil<GHOST, true>(c, 0, cx, cy, cz, pp.s_coul, visit);
-  stencil<GHOST, true>(c, 1, cx, cy, cz, pp.s_coul, visit);
-  double f0 = acc.get(0), f1 = acc.get(1), f2 = acc.get(2);
-  if (ns > 0) {
-    const int nb = ns < pp.p_shell ? ns : pp.p_shell;
-    ForceAcc<F32> sh;
-#pragma unroll
-    for (int t = 0; t < CAP; ++t) {
-      if (t < nb) {
-        const int32_t idj = shell_id_of(sk, keys[t]);
-        if ((uint32_t)idj >= (uint32_t)c.n) continue;  // bad ids (flagged by the inverse map)
-        const int j = c.inv_id[idj];
-        if ((uint32_t)j >= (uint32_t)c.n) continue;
-        const double4 pj = c.xq[j];
-        const double dx = min_image(xi - pj.x, g.L[0]);
-        const double dy = min_image(yi - pj.y, g.L[1]);
-        const double dz = min_image(zi - pj.z, g.L[2]);
-        const double r2 = sq_dist(dx, dy, dz);
-        sh.template add<true>(pp, c.pf, r2, qi, pj.w, dx, dy, dz);
-        if (COUNT) {
-          n_coul += (pp.do_coul && qi != 0.0 && pj.w != 0.0);
-          n_lj += (pp.do_lj && r2 <= pp.rlj2);
-        }
+  auto visit_collect = [&](int, const double4 &pj, int idj, double shx, double shy, double shz) {
+    if (!in_group) return;
+    const double dx = (I.xi - pj.x) - shx, dy = (I.yi - pj.y) - shy, dz = (I.zi - pj.z) - shz;
+    const double r2 = sq_dist(dx, dy, dz);
+    if (r2 > pp.rcore2 && r2 <= pp.rc2) collect(shell_rank(sk, idj));
+  };
+  const int64_t rowkey = (int64_t)I.cz * g.ny + I.cy;
+  auto walk_all = [&](bool active, auto &&fn) {
+    for_each_row_group(active, rowkey, I.cx, [&](bool in, int leader, int xa, int xb) {
+      in_group = in;
+      const int cy = __shfl(I.cy, leader, 64), cz = __shfl(I.cz, leader, 64);
+      walk<GHOST, true>(c, 0, xa, xb, cy, cz, pp.s_coul, I.b, fn);
+      walk<GHOST, true>(c, 1, xa, xb, cy, cz, pp.s_coul, I.b, fn);
+    });
+  };
+  walk_all(I.valid, visit);
+  __syncthreads();
+  const int m = sum_j_lanes(ns);  // #S_i
+  const int need = m < p ? m : p;
+  int got = kcnt[I.a];
+  // bisection on T when the buffer missed [need, cap] (rare; distinct keys
+  // end it within 33 rounds, the bound only guards against duplicate ids,
+  // which the inverse id map reports)
+  uint64_t lo = 0, hi = 1ull << 32;
+  bool pend = I.valid && need > 0 && (got < need || got > kShellCap);
+  for (int round = 0; __any(pend) && round < 40; ++round) {
+    if (pend) {
+      if (got < need) lo = T;
+      else hi = T;
+      T = (m <= kShellCap) ? (1ull << 32) : lo + (hi - lo) / 2;
+    }
+    __syncthreads();
+    if (pend && I.b == 0) kcnt[I.a] = 0;
+    __syncthreads();
+    walk_all(pend, visit_collect);
+    __syncthreads();
+    if (pend) got = kcnt[I.a];
+    pend = pend && (got < need || got > kShellCap);
+  }
+  got = min(got, kShellCap);
+  const int nb = min(need, got);  // = need unless ids repeat
+  // ranks of the collected keys (distinct); the first `need` form the batch
+  if (I.valid && nb > 0) {
+    const uint32_t *kb = kbuf + I.a * kShellCap;
+    for (int t = I.b; t < got; t += kCJ) {
+      const uint32_t k = kb[t];
+      int rank = 0;
+      for (int u = 0; u < got; ++u) rank += kb[u] < k;
+      if (rank < nb) ksel[I.a * RBE_MAX_SHELL_BATCH + rank] = k;
+    }
+  }
+  __syncthreads();
+  ForceAcc<F32> sh;
+  if (I.valid) {
+    for (int r = I.b; r < nb; r += kCJ) {
+      const int32_t idj = shell_id_of(sk, ksel[I.a * RBE_MAX_SHELL_BATCH + r]);
+      if ((uint32_t)idj >= (uint32_t)c.n) continue;  // bad ids (flagged by the inverse map)
+      const int j = c.inv_id[idj];
+      if ((uint32_t)j >= (uint32_t)c.n) continue;
+      const double4 pj = c.xq[j];
+      const double dx = min_image(I.xi - pj.x, g.L[0]);
+      const double dy = min_image(I.yi - pj.y, g.L[1]);
+      const double dz = min_image(I.zi - pj.z, g.L[2]);
+      const double r2 = sq_dist(dx, dy, dz);
+      sh.template add<true>(pp, c.pf, r2, I.qi, pj.w, dx, dy, dz);
+      if (COUNT) {
+        n_coul += (pp.do_coul && I.qi != 0.0 && pj.w != 0.0);
+        n_lj += (pp.do_lj && r2 <= pp.rlj2);
       }
     }
-    const double scale = (double)ns / (double)nb;
-    f0 = fma(scale, sh.get(0), f0);
-    f1 = fma(scale, sh.get(1), f1);
-    f2 = fma(scale, sh.get(2), f2);
   }
-  c.fx[i] = f0;
-  c.fy[i] = f1;
-  c.fz[i] = f2;
-  flush_counts<COUNT>(c, n_coul, n_lj, n_tested, (unsigned long long)ns);
+  double f0 = sum_j_lanes(acc.get(0)), f1 = sum_j_lanes(acc.get(1)), f2 = sum_j_lanes(acc.get(2));
+  const double s0 = sum_j_lanes(sh.get(0)), s1 = sum_j_lanes(sh.get(1)), s2 = sum_j_lanes(sh.get(2));
+  if (nb > 0) {
+    const double scale = (double)m / (double)nb;
+    f0 = fma(scale, s0, f0);
+    f1 = fma(scale, s1, f1);
+    f2 = fma(scale, s2, f2);
+  }
+  if (I.valid && I.b == 0) {
+    c.fx[I.i] = f0;
+    c.fy[I.i] = f1;
+    c.fz[I.i] = f2;
+  }
+  flush_counts<COUNT>(c, n_coul, n_lj, n_tested, I.b == 0 && I.valid ? (unsigned long long)m : 0ull);
 }
 
-constexpr int kShellThreads = 256;
-constexpr int kShellRoom = 16;  // buffer slots beyond the batch capacity
-
-// Shell part of the random batch list (Eq. 10-11) for a charged i whose core
-// terms were summed by the plain kernel with the Coulomb cutoff set to r_core:
-// every j with r_core^2 < r^2 <= r_coul^2 (same contraction-free r^2 as the
-// core test) is counted and ranked; the p smallest keys form the batch, whose
-// terms are added to f_i with the weight #S_i/|B_i|.
-//
-// Selection: each lane appends the keys below its threshold tau to its own
-// LDS buffer (CAP + kShellRoom slots). When a buffer fills, the buffers of the
-// wave are reduced to their p smallest keys and a full lane's tau becomes the
-// largest of them: any later key above tau has p smaller keys before it and
-// cannot be in the batch (keys are distinct). So a buffer always contains the
-// p smallest keys its lane has seen.
-template <bool F32, bool COUNT, int CAP, bool GHOST>
-__global__ void __launch_bounds__(kShellThreads) k_pair_shell(PairCtx c) {
-  constexpr int B = CAP + kShellRoom;
-  __shared__ uint32_t sbuf[B * kShellThreads];
-  const int tid = threadIdx.x;
-  const int64_t i = c.i0 + blockIdx.x * (int64_t)blockDim.x + tid;
-  if (i >= c.i1) return;
-  const PairParams &pp = c.pp;
-  const Grid &g = pp.g;
-  const int p = pp.p_shell;
-  const double4 pi4 = c.xq[i];
-  const double xi = pi4.x, yi = pi4.y, zi = pi4.z, qi = pi4.w;
-  const int cx = cell_coord(xi, g.inv_h[0], g.nx);
-  const int cy = cell_coord(yi, g.inv_h[1], g.ny);
-  const int cz = cell_coord(zi, g.inv_h[2], g.nz);
-  const ShellKey sk = shell_key_of(pp.shell_key, c.ids[i]);
-  int ns = 0, cnt = 0;
-  int sorted = 0;  // buf[0..sorted) is ascending (left by the last reduction)
-  uint32_t tau = 0xFFFFFFFFu;
-  bool have_tau = false;
-  unsigned long long n_tested = 0, n_coul = 0, n_lj = 0;
-  // reduce the buffer to its min(p, cnt) smallest keys, sorted; returns them in L
-  auto reduce = [&](uint32_t (&L)[CAP]) {
-#pragma unroll
-    for (int t = 0; t < CAP; ++t) L[t] = t < sorted ? sbuf[t * kShellThreads + tid] : 0xFFFFFFFFu;
-    for (int t = sorted; t < cnt; ++t) sorted_insert<CAP>(L, sbuf[t * kShellThreads + tid]);
-    const int keep = cnt < p ? cnt : p;
-#pragma unroll
-    for (int t = 0; t < CAP; ++t)
-      if (t < keep) sbuf[t * kShellThreads + tid] = L[t];
-    cnt = keep;
-    sorted = keep;
-  };
-  auto visit = [&](int, const double4 &pj, int idj, double shx, double shy, double shz) {
-    const double dx = (xi - pj.x) - shx, dy = (yi - pj.y) - shy, dz = (zi - pj.z) - shz;
-    const double r2 = sq_dist(dx, dy, dz);
-    if (COUNT) ++n_tested;
-    if (r2 > pp.rcore2 && r2 <= pp.rc2) {
-      ++ns;
-      const uint32_t k = shell_rank(sk, idj);
-      if (!have_tau || k < tau) sbuf[cnt++ * kShellThreads + tid] = k;
-    }
-    // every active lane reduces when one lane's buffer is full (one pass of
-    // the wave instead of one per lane)
-    if (__any(cnt == B)) {
-      uint32_t L[CAP];
-      reduce(L);
-      if (cnt == p) {
-#pragma unroll
-        for (int t = 0; t < CAP; ++t)
-          if (t == p - 1) tau = L[t];
-        have_tau = true;
-      }
-    }
-  };
-  stencil<GHOST, true>(c, 0, cx, cy, cz, pp.s_coul, visit);
-  stencil<GHOST, true>(c, 1, cx, cy, cz, pp.s_coul, visit);
-  if (ns > 0) {
-    uint32_t L[CAP];
-    reduce(L);
-    const int nb = cnt;  // = min(ns, p)
-    ForceAcc<F32> sh;
-#pragma unroll
-    for (int t = 0; t < CAP; ++t) {
-      if (t < nb) {
-        const int32_t idj = shell_id_of(sk, L[t]);
-        if ((uint32_t)idj >= (uint32_t)c.n) continue;  // bad ids (flagged by the inverse map)
-        const int j = c.inv_id[idj];
-        if ((uint32_t)j >= (uint32_t)c.n) continue;
-        const double4 pj = c.xq[j];
-        const double dx = min_image(xi - pj.x, g.L[0]);
-        const double dy = min_image(yi - pj.y, g.L[1]);
-        const double dz = min_image(zi - pj.z, g.L[2]);
-        const double r2 = sq_dist(dx, dy, dz);
-        sh.template add<true>(pp, c.pf, r2, qi, pj.w, dx, dy, dz);
-        if (COUNT) {
-          n_coul += (pp.do_coul && qi != 0.0 && pj.w != 0.0);
-          n_lj += (pp.do_lj && r2 <= pp.rlj2);
-        }
-      }
-    }
-    const double scale = (double)ns / (double)nb;
-    c.fx[i] = fma(scale, sh.get(0), c.fx[i]);
-    c.fy[i] = fma(scale, sh.get(1), c.fy[i]);
-    c.fz[i] = fma(scale, sh.get(2), c.fz[i]);
-  }
-  flush_counts<COUNT>(c, n_coul, n_lj, n_tested, (unsigned long long)ns);
+uint64_t shell_first_threshold(const PairParams &pp, int64_t n) {
+  const double V = pp.g.L[0] * pp.g.L[1] * pp.g.L[2];
+  const double rc = std::sqrt(pp.rc2), r0 = std::sqrt(pp.rcore2);
+  const double m_mean = (double)n / V * (4.0 / 3.0) * kPi * (rc * rc * rc - r0 * r0 * r0);
+  if (!(m_mean > 0.5 * kShellCap)) return 1ull << 32;
+  const double f = 3.0 * pp.p_shell / m_mean;
+  if (f >= 1.0) return 1ull << 32;
+  return (uint64_t)(f * 4294967296.0);
 }
 
 PairF32 make_pair_f32(const PairParams &pp) {
@@ -325,48 +315,25 @@ static void launch_range(K kernel, PairCtx c, int64_t i0, int64_t i1, hipStream_
   if (i1 <= i0) return;
   c.i0 = i0;
   c.i1 = i1;
-  const unsigned blocks = (unsigned)((i1 - i0 + 255) / 256);
-  kernel<<<blocks, 256, 0, st>>>(c);
-}
-
-template <bool F32, bool COUNT, bool GHOST>
-static void launch_rbl(PairCtx c, int64_t i0, int64_t i1, bool split, hipStream_t st) {
-  const int p = c.pp.p_shell;
-  if (split) {
-    if (p <= 8) launch_range(k_pair_shell<F32, COUNT, 8, GHOST>, c, i0, i1, st);
-    else if (p <= 16) launch_range(k_pair_shell<F32, COUNT, 16, GHOST>, c, i0, i1, st);
-    else if (p <= 24) launch_range(k_pair_shell<F32, COUNT, 24, GHOST>, c, i0, i1, st);
-    else launch_range(k_pair_shell<F32, COUNT, 32, GHOST>, c, i0, i1, st);
-    return;
-  }
-  if (p <= 16) launch_range(k_pair_rbl<F32, COUNT, 16, GHOST>, c, i0, i1, st);
-  else launch_range(k_pair_rbl<F32, COUNT, 32, GHOST>, c, i0, i1, st);
+  const unsigned blocks = (unsigned)((i1 - i0 + kCI - 1) / kCI);
+  kernel<<<blocks, 64, 0, st>>>(c);
 }
 
 // Charged particles occupy [0, nq) of the sorted order, neutral ones [nq, n).
-// With the random batch list and r_lj <= r_core, a charged particle's core is
-// the plain sum with the Coulomb cutoff set to r_core (same r^2 test), and its
-// shell is added by the shell kernel; otherwise one fused kernel does both.
-// part: PAIR_PART_CHARGED, PAIR_PART_SHELL (after CHARGED) or PAIR_PART_NEUTRAL.
+// With the random batch list the charged particles take the RBL kernel; the
+// neutral ones too when r_lj > r_core (their LJ terms then reach the shell),
+// else their sums are plain (every LJ term lies in the core).
+// part: PAIR_PART_CHARGED, PAIR_PART_SHELL (nothing left to do: the shell is
+// fused into the charged part) or PAIR_PART_NEUTRAL.
 template <bool F32, bool COUNT, bool GHOST>
 static void launch_part(PairCtx c, int64_t nq, int part, hipStream_t st) {
   const PairParams pp = c.pp;
-  const bool split = pp.rbl && pp.rlj2 <= pp.rcore2;
-  if (pp.rbl && !split) {
-    if (part == PAIR_PART_CHARGED) launch_rbl<F32, COUNT, GHOST>(c, 0, c.n, false, st);
-    return;
-  }
   if (part == PAIR_PART_CHARGED) {
-    PairCtx core = c;
-    if (split) {
-      core.pp.rc2 = pp.rcore2;
-      core.pp.s_coul = pp.s_core;
-    }
-    launch_range(k_pair_plain<F32, COUNT, 1, GHOST>, core, 0, nq, st);
-  } else if (part == PAIR_PART_SHELL) {
-    if (split) launch_rbl<F32, COUNT, GHOST>(c, 0, nq, true, st);
-  } else {
-    launch_range(k_pair_plain<F32, COUNT, 0, GHOST>, c, nq, c.n, st);
+    if (pp.rbl) launch_range(k_pair_rbl<F32, COUNT, GHOST>, c, 0, nq, st);
+    else launch_range(k_pair_plain<F32, COUNT, 1, GHOST>, c, 0, nq, st);
+  } else if (part == PAIR_PART_NEUTRAL) {
+    if (pp.rbl && pp.rlj2 > pp.rcore2 && pp.do_lj) launch_range(k_pair_rbl<F32, COUNT, GHOST>, c, nq, c.n, st);
+    else launch_range(k_pair_plain<F32, COUNT, 0, GHOST>, c, nq, c.n, st);
   }
 }
 

@@ -260,3 +260,142 @@ struct ForceAcc<true> {
 };
 
 }  // namespace rbe
+
+namespace rbe {
+
+// ---------------------------------------------------------------------------
+// Cluster traversal (8 x 8 lanes per wave)
+// ---------------------------------------------------------------------------
+// A wave computes the near field of a cluster of up to kCI consecutive
+// particles of the cell order. Lane l plays i = cluster[l / kCJ] against the
+// j-stream offset l % kCJ: the wave walks one shared sequence of candidate
+// records kCJ at a time, so a load instruction touches kCJ consecutive
+// records (two cache lines) and every lane runs the same loop. Particles of a
+// cluster that lie in different cell rows (or species blocks, or replicas)
+// are handled one row group after another; a group walks the union of its
+// particles' stencils: the stencil rows around (cy, cz) with x running from
+// min(cx) - s to max(cx) + s.
+constexpr int kCI = 8;
+constexpr int kCJ = 8;
+
+// fn(j, p_j, id_j, shx, shy, shz) for the records j0..j1-1 taken by this
+// lane (j = j0 + b, j0 + b + kCJ, ...), one record prefetched ahead. The
+// trip count depends only on j0, j1, so the loop is the same for the wave.
+template <bool WITH_ID, class Fn>
+__device__ inline void scan_cluster(const double4 *__restrict__ xq, const int32_t *__restrict__ ids, int j0, int j1,
+                                    int b, double shx, double shy, double shz, Fn &&fn) {
+  if (j0 >= j1) return;
+  const int last = j1 - 1;
+  int j = j0 + b;
+  double4 r = xq[min(j, last)];
+  int d = WITH_ID ? ids[min(j, last)] : 0;
+#pragma unroll 1
+  for (int base = j0; base < j1; base += kCJ) {
+    const int jn = j + kCJ;
+    const double4 rn = xq[min(jn, last)];
+    const int dn = WITH_ID ? ids[min(jn, last)] : 0;
+    if (j < j1) fn(j, r, d, shx, shy, shz);
+    r = rn;
+    d = dn;
+    j = jn;
+  }
+}
+
+// Periodic walk of species block `blk` (keys base + blk * C + cell) for a row
+// group: rows (cy + oy, cz + oz), |oy|, |oz| <= s, x from xa - s to xb + s,
+// each row split where it crosses the periodic boundary (a cell met twice is
+// met with two different image shifts, so no image is counted twice).
+template <bool WITH_ID, class Fn>
+__device__ inline void cluster_walk(const Grid &g, const int32_t *__restrict__ cell_start,
+                                    const double4 *__restrict__ xq, const int32_t *__restrict__ ids, int64_t base,
+                                    int xa, int xb, int cy, int cz, int s, int b, Fn &&fn) {
+  for (int oz = -s; oz <= s; ++oz) {
+    const int az = cz + oz;
+    const int qz = floor_div(az, g.nz);
+    const int wz = az - qz * g.nz;
+    const double shz = (double)qz * g.L[2];
+    for (int oy = -s; oy <= s; ++oy) {
+      const int ay = cy + oy;
+      const int qy = floor_div(ay, g.ny);
+      const int wy = ay - qy * g.ny;
+      const double shy = (double)qy * g.L[1];
+      const int64_t row = base + (int64_t)(wz * g.ny + wy) * g.nx;
+      int x = xa - s;
+      const int x_end = xb + s;
+      while (x <= x_end) {
+        const int qx = floor_div(x, g.nx);
+        const int xe = min(x_end, (qx + 1) * g.nx - 1);
+        const int j0 = cell_start[row + (x - qx * g.nx)];
+        const int j1 = cell_start[row + (xe - qx * g.nx) + 1];
+        scan_cluster<WITH_ID>(xq, ids, j0, j1, b, (double)qx * g.L[0], shy, shz, fn);
+        x = xe + 1;
+      }
+    }
+  }
+}
+
+// Ghost-shell walk (no periodic images): the native part of each stencil row
+// clipped to the native grid, then the same row of the padded ghost grid.
+template <bool WITH_ID, class Fn>
+__device__ inline void cluster_walk_ghost(const Grid &g, const int32_t *__restrict__ cell_start,
+                                          const double4 *__restrict__ xq, const int32_t *__restrict__ ids,
+                                          const int32_t *__restrict__ gcell_start, const double4 *__restrict__ gxq,
+                                          const int32_t *__restrict__ gid, int blk, int xa, int xb, int cy, int cz,
+                                          int s, int b, Fn &&fn) {
+  const int64_t base = (int64_t)blk * g.ncell;
+  const int64_t pbase = (int64_t)blk * g.pncell;
+  const int na = max(xa - s, 0), nb = min(xb + s, g.nx - 1);
+  for (int oz = -s; oz <= s; ++oz) {
+    const int z = cz + oz;
+    for (int oy = -s; oy <= s; ++oy) {
+      const int y = cy + oy;
+      if (z >= 0 && z < g.nz && y >= 0 && y < g.ny) {
+        const int64_t row = base + (int64_t)(z * g.ny + y) * g.nx;
+        scan_cluster<WITH_ID>(xq, ids, cell_start[row + na], cell_start[row + nb + 1], b, 0.0, 0.0, 0.0, fn);
+      }
+      const int64_t prow = pbase + (int64_t)((z + g.goff[2]) * g.pny + (y + g.goff[1])) * g.pnx + g.goff[0];
+      scan_cluster<WITH_ID>(gxq, gid, gcell_start[prow + xa - s], gcell_start[prow + xb + s + 1], b, 0.0, 0.0, 0.0,
+                            fn);
+    }
+  }
+}
+
+// Row groups of a cluster wave. `valid`: this lane's i exists; rowkey: a
+// value shared exactly by the particles of one cell row (and species block,
+// and replica). Calls gfn(in, leader, xa, xb) once per distinct row, where
+// `in` says whether this lane's i belongs to the group, `leader` is a lane of
+// the group and [xa, xb] the group's x-cell range (all wave-uniform).
+template <class GroupFn>
+__device__ inline void for_each_row_group(bool valid, int64_t rowkey, int cx, GroupFn &&gfn) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long todo = __ballot(valid && (lane % kCJ) == 0);
+  while (todo) {
+    const int leader = __builtin_amdgcn_readfirstlane(__ffsll((long long)todo) - 1);
+    const int64_t R = __shfl(rowkey, leader, 64);
+    const bool in = valid && rowkey == R;
+    int xa = in ? cx : 0x7FFFFFFF, xb = in ? cx : -0x7FFFFFFF;
+#pragma unroll
+    for (int o = kCJ; o < 64; o <<= 1) {
+      xa = min(xa, __shfl_xor(xa, o, 64));
+      xb = max(xb, __shfl_xor(xb, o, 64));
+    }
+    xa = __builtin_amdgcn_readfirstlane(xa);
+    xb = __builtin_amdgcn_readfirstlane(xb);
+    gfn(in, leader, xa, xb);
+    todo &= ~__ballot(in && (lane % kCJ) == 0);
+  }
+}
+
+// Sum over the kCJ lanes that share an i (fixed order: deterministic).
+__device__ inline double sum_j_lanes(double v) {
+#pragma unroll
+  for (int o = 1; o < kCJ; o <<= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline int sum_j_lanes(int v) {
+#pragma unroll
+  for (int o = 1; o < kCJ; o <<= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+}  // namespace rbe

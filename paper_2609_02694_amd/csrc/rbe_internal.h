@@ -120,6 +120,22 @@ __host__ __device__ inline int floor_div(int a, int n) {
 }
 
 // ---------------------------------------------------------------------------
+// XCD-aware workgroup order
+// ---------------------------------------------------------------------------
+// The dispatcher hands workgroups to the 8 XCDs round-robin (workgroup b runs
+// on XCD b mod 8), and each XCD has its own L2. xcd_block maps b to a
+// logical index under which every XCD's workgroups are consecutive, so each
+// L2 serves one contiguous range of the cell-ordered particles (a compact
+// region of the box and its stencil neighbourhood) instead of all of it.
+// A bijection of [0, nb) for any nb.
+constexpr int kNumXcd = 8;
+__host__ __device__ inline int64_t xcd_block(int64_t b, int64_t nb) {
+  const int64_t x = b % kNumXcd, local = b / kNumXcd;
+  const int64_t base = nb / kNumXcd, rem = nb % kNumXcd;
+  return x * base + (x < rem ? x : rem) + local;
+}
+
+// ---------------------------------------------------------------------------
 // Mode tables for the sampler (host-built, copied to the device)
 // ---------------------------------------------------------------------------
 struct ModeTable {

@@ -13,6 +13,8 @@ import math
 
 from . import Context, Particles, params_from_preset
 
+BATCH_EDGES = (2.0, 2.5, 3.0, 3.5, 4.0, 6.0)
+
 DEFAULT_EDGES = (1.25, 1.5, 1.75, 2.0, 2.25, 2.5, 3.0, 3.5, 4.0)
 
 
@@ -64,3 +66,45 @@ def default_ncell(preset: dict) -> int:
     """Grid used without tuning: edge about max(r_lj, r_coul / 3)."""
     h = max(preset["r_lj"] * 0.6, preset["r_coul"] / 3.0)
     return max(1, int(math.floor(preset["L"] / h)))
+
+
+def batch_params(reps, edge: float, prec: int):
+    """Per-replica params of a batch with cells of edge about `edge` (at least one per axis)."""
+    out = []
+    for p, _ in reps:
+        n = max(1, int(p["L"] // edge))
+        out.append(params_from_preset(p, prec=prec, ncell=(n, n, n), seed=p["stream_seed"]))
+    return out
+
+
+def time_batch(reps, cat_np: dict, offsets, edge: float, prec: int, steps: int = 10, warmup: int = 2) -> float:
+    """Milliseconds per batched step (all replicas) with cell edge about `edge`."""
+    import torch
+
+    ctx = Context.batch(batch_params(reps, edge, prec), offsets)
+    st = Particles.from_numpy(cat_np)
+    ctx.forces(st, None, None, 0)
+    ctx.step(st, warmup, 1)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ctx.step(st, steps, 1 + warmup)
+    e1.record()
+    torch.cuda.synchronize()
+    ctx.sync_check()
+    ctx.close()
+    return e0.elapsed_time(e1) / steps
+
+
+def tune_batch(reps, cat_np: dict, offsets, prec: int, steps: int = 10, edges=BATCH_EDGES, verbose=False):
+    """Returns (best edge, {edge: ms per step}) for the batched step."""
+    table = {}
+    for h in edges:
+        if min(p["L"] for p, _ in reps) < h:
+            continue
+        table[h] = time_batch(reps, cat_np, offsets, h, prec, steps)
+        if verbose:
+            print(f"tune: batch edge {h:.2f} -> {table[h]:.3f} ms/step", flush=True)
+    best = min(table, key=table.get)
+    return best, table
