@@ -249,6 +249,7 @@ static void make_pair_params(const rbe_params &p, const Grid &g, PairParams *out
   pp.rc2 = p.r_coul * p.r_coul;
   pp.rlj2 = p.r_lj * p.r_lj;
   pp.rcore2 = p.r_core * p.r_core;
+  pp.rq2 = std::fmax(pp.rc2, pp.rlj2);
   pp.alpha = p.alpha;
   pp.sqrt_alpha = std::sqrt(p.alpha);
   pp.two_sqrt_alpha_over_sqrt_pi = 2.0 * pp.sqrt_alpha / std::sqrt(kPi);

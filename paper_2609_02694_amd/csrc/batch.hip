@@ -83,64 +83,42 @@ __device__ inline int block_scan_excl(int v, int *lds, int *total) {
   return off + incl - v;
 }
 
-// Plain near-field sums (no random batch list, no ghosts) of the cluster of
-// particles [kCI cl, kCI cl + kCI), one wave (cluster traversal of
-// pair_device.h). A cluster may straddle rows, species blocks and replicas:
-// each row group walks with its own replica's grid.
+// Plain near-field sums of one particle (no random batch list, no ghosts),
+// one thread walking the stencil rows of its own cell in its replica.
 template <bool F32>
-__device__ inline void batch_cluster(const BatchArgs &a, int64_t cl) {
-  const int lane = threadIdx.x & 63, ai = lane / kCJ, b = lane % kCJ;
+__device__ inline void batch_pair(const BatchArgs &a, const RepDesc &R, int64_t i) {
+  const Grid &g = R.g;
   const PairParams &pp = a.pp;
-  const int64_t i_raw = cl * kCI + ai;
-  const bool valid = i_raw < a.ntot;
-  const int64_t i = valid ? i_raw : a.ntot - 1;
-  const int r = a.rep_of[i];
-  const Grid &g = a.reps[r].g;
   const double4 pi4 = a.xq[i];
   const double xi = pi4.x, yi = pi4.y, zi = pi4.z, qi = pi4.w;
   const int cx = cell_coord(xi, g.inv_h[0], g.nx);
   const int cy = cell_coord(yi, g.inv_h[1], g.ny);
   const int cz = cell_coord(zi, g.inv_h[2], g.nz);
-  const int charged = qi != 0.0;
-  const int64_t rowkey = a.reps[r].c0 + (charged ? 0 : g.ncell) + (int64_t)(cz * g.ny + cy) * g.nx;
   ForceAcc<F32> acc;
-  bool in_group = false;
   auto visit_q = [&](int j, const double4 &pj, int, double shx, double shy, double shz) {
-    if (!in_group) return;
     const double dx = (xi - pj.x) - shx, dy = (yi - pj.y) - shy, dz = (zi - pj.z) - shz;
     const double r2 = sq_dist(dx, dy, dz);
     if (r2 == 0.0 && j == (int)i) return;
-    if (r2 <= pp.rc2 || r2 <= pp.rlj2) acc.template add<true>(pp, a.pf, r2, qi, pj.w, dx, dy, dz);
+    if (r2 <= pp.rq2) acc.template add<true>(pp, a.pf, r2, qi, pj.w, dx, dy, dz);
   };
   auto visit_lj = [&](int j, const double4 &pj, int, double shx, double shy, double shz) {
-    if (!in_group) return;
     const double dx = (xi - pj.x) - shx, dy = (yi - pj.y) - shy, dz = (zi - pj.z) - shz;
     const double r2 = sq_dist(dx, dy, dz);
     if (r2 == 0.0 && j == (int)i) return;
     if (r2 <= pp.rlj2) acc.template add<false>(pp, a.pf, r2, qi, pj.w, dx, dy, dz);
   };
-  for_each_row_group(valid, rowkey, cx, [&](bool in, int leader, int xa, int xb) {
-    in_group = in;
-    const int rl = __builtin_amdgcn_readfirstlane(__shfl(r, leader, 64));
-    const RepDesc &R = a.reps[rl];
-    const int gcy = __shfl(cy, leader, 64), gcz = __shfl(cz, leader, 64);
-    const bool gq = __shfl(charged, leader, 64) != 0;
-    const int64_t b0 = R.c0, b1 = R.c0 + R.g.ncell;
-    if (gq) {
-      cluster_walk<false>(R.g, a.cell_start, a.xq, a.sid, b0, xa, xb, gcy, gcz, R.s_coul, b, visit_q);
-      if (pp.do_lj) cluster_walk<false>(R.g, a.cell_start, a.xq, a.sid, b1, xa, xb, gcy, gcz, R.s_lj, b, visit_lj);
-    } else if (pp.do_lj) {
-      cluster_walk<false>(R.g, a.cell_start, a.xq, a.sid, b0, xa, xb, gcy, gcz, R.s_lj, b, visit_lj);
-      cluster_walk<false>(R.g, a.cell_start, a.xq, a.sid, b1, xa, xb, gcy, gcz, R.s_lj, b, visit_lj);
-    }
-  });
-  const double f0 = sum_j_lanes(acc.get(0)), f1 = sum_j_lanes(acc.get(1)), f2 = sum_j_lanes(acc.get(2));
-  if (valid && b == 0) {
-    a.ofx[i] = f0;
-    a.ofy[i] = f1;
-    a.ofz[i] = f2;
+  if (qi != 0.0) {
+    if (pp.do_coul || pp.do_lj) for_stencil<false>(g, a.cell_start, a.xq, a.sid, 0, cx, cy, cz, R.s_coul, visit_q, R.c0);
+    if (pp.do_lj) for_stencil<false>(g, a.cell_start, a.xq, a.sid, 1, cx, cy, cz, R.s_lj, visit_lj, R.c0);
+  } else if (pp.do_lj) {
+    for_stencil<false>(g, a.cell_start, a.xq, a.sid, 0, cx, cy, cz, R.s_lj, visit_lj, R.c0);
+    for_stencil<false>(g, a.cell_start, a.xq, a.sid, 1, cx, cy, cz, R.s_lj, visit_lj, R.c0);
   }
+  a.ofx[i] = acc.get(0);
+  a.ofy[i] = acc.get(1);
+  a.ofz[i] = acc.get(2);
 }
+
 
 template <bool F32>
 __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchArgs a) {
@@ -293,11 +271,10 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchArgs a) {
   grid_barrier(a.bar, a.err);
 
   // ---- P7: near field; structure-factor partials ---------------------------------
-  if (do_near) {
-    const int64_t nclusters = (a.ntot + kCI - 1) / kCI;
-    for (int64_t cl = gwave; cl < nclusters; cl += nwaves) batch_cluster<F32>(a, cl);
-  } else {
-    for (int64_t i = gtid; i < a.ntot; i += gstride) {
+  for (int64_t i = gtid; i < a.ntot; i += gstride) {
+    if (do_near) {
+      batch_pair<F32>(a, a.reps[a.rep_of[i]], i);
+    } else {
       a.ofx[i] = 0.0;
       a.ofy[i] = 0.0;
       a.ofz[i] = 0.0;

@@ -75,6 +75,7 @@ struct PairParams {
   int s_lj;              // stencil radius covering r_lj
   int s_core;            // stencil radius covering max(r_core, r_lj)
   double rc2, rlj2, rcore2;
+  double rq2;            // max(rc2, rlj2): reach of a charged pair
   double alpha, sqrt_alpha, two_sqrt_alpha_over_sqrt_pi;
   double kc, eps24, sig2;
   int do_coul, do_lj;

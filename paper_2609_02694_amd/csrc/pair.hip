@@ -1,12 +1,14 @@
 // Near-field force (Sec. 2.1, Eq. 7-8, 10-11): erfc-screened Coulomb plus
 // 12-6 Lennard-Jones over a cell list, with the core-shell random batch list.
 //
-// Full neighbour sums per particle i (cell order), no atomics. One wave per
-// cluster of 8 consecutive particles: lane l takes i = cluster[l / 8] and
-// every 8th record of one candidate sequence shared by the wave (the union
-// of the cluster's stencils), so the candidate loads are contiguous and the
-// loop is uniform (pair_device.h, cluster traversal). The 8 partial sums of
-// an i are added in a fixed order at the end.
+// Full neighbour sums per particle i (cell order), no atomics. Two forms:
+// plain sums run one thread per particle, each walking the stencil rows of
+// its own cell; the random batch list runs one wave per cluster of 8
+// consecutive particles: lane l takes i = cluster[l / 8] and every 8th record
+// of one candidate sequence shared by the wave (the union of the cluster's
+// stencils), so the candidate loads are contiguous and the loop is uniform
+// (pair_device.h, cluster traversal); the 8 partial sums of an i are added
+// in a fixed order at the end.
 //
 // Species blocks: charged particles occupy keys [0, C), neutral ones
 // [C, 2C). Coulomb terms only involve charged pairs, so without the random
@@ -102,60 +104,69 @@ __device__ inline ClusterI load_cluster_i(const PairCtx &c) {
   return r;
 }
 
-// Plain cutoff sums. MODE 0: neutral i (LJ over both species blocks out to
-// r_lj); MODE 1: charged i (charged block out to max(r_coul, r_lj), neutral
-// block out to r_lj).
+// Periodic or ghost-shell stencil walk of one particle (thread form).
+template <bool GHOST, bool WITH_ID, class Fn>
+__device__ inline void stencil(const PairCtx &c, int blk, int cx, int cy, int cz, int s, Fn &&fn) {
+  if (GHOST)
+    for_stencil_ghost<WITH_ID>(c.pp.g, c.cell_start, c.xq, c.ids, c.gcell_start, c.gxq, c.gid, blk, cx, cy, cz, s,
+                               fn);
+  else
+    for_stencil<WITH_ID>(c.pp.g, c.cell_start, c.xq, c.ids, blk, cx, cy, cz, s, fn);
+}
+
+// Plain cutoff sums, one thread per particle i walking its own stencil (on
+// MI355X this beats the cluster form when most candidates within reach are
+// summed, i.e. without the shell test of the random batch list). MODE 0:
+// neutral i (LJ over both species blocks out to r_lj); MODE 1: charged i
+// (charged block out to max(r_coul, r_lj), neutral block out to r_lj).
 template <bool F32, bool COUNT, int MODE, bool GHOST>
-__global__ void __launch_bounds__(64) k_pair_plain(PairCtx c) {
-  const ClusterI I = load_cluster_i(c);
+__global__ void __launch_bounds__(256) k_pair_plain(PairCtx c) {
+  const int64_t i = c.i0 + xcd_block(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= c.i1) return;
   const PairParams &pp = c.pp;
   const Grid &g = pp.g;
+  const double4 pi4 = c.xq[i];
+  const double xi = pi4.x, yi = pi4.y, zi = pi4.z, qi = pi4.w;
+  const int cx = cell_coord(xi, g.inv_h[0], g.nx);
+  const int cy = cell_coord(yi, g.inv_h[1], g.ny);
+  const int cz = cell_coord(zi, g.inv_h[2], g.nz);
   ForceAcc<F32> acc;
   unsigned long long n_coul = 0, n_lj = 0, n_tested = 0;
-  bool in_group = false;
+  // Coulomb + LJ against charged j (block 0 of a charged i)
   auto visit_q = [&](int j, const double4 &pj, int, double shx, double shy, double shz) {
-    if (!in_group) return;
-    const double dx = (I.xi - pj.x) - shx, dy = (I.yi - pj.y) - shy, dz = (I.zi - pj.z) - shz;
+    const double dx = (xi - pj.x) - shx, dy = (yi - pj.y) - shy, dz = (zi - pj.z) - shz;
     const double r2 = sq_dist(dx, dy, dz);
     if (COUNT) ++n_tested;
-    if (r2 == 0.0 && j == (int)I.i) return;
-    if (r2 <= pp.rc2 || r2 <= pp.rlj2) {
-      acc.template add<true>(pp, c.pf, r2, I.qi, pj.w, dx, dy, dz);
+    if (r2 == 0.0 && j == (int)i) return;
+    if (r2 <= pp.rq2) {
+      acc.template add<true>(pp, c.pf, r2, qi, pj.w, dx, dy, dz);
       if (COUNT) {
         n_coul += (pp.do_coul && r2 <= pp.rc2);
         n_lj += (pp.do_lj && r2 <= pp.rlj2);
       }
     }
   };
+  // LJ only (every other species pairing)
   auto visit_lj = [&](int j, const double4 &pj, int, double shx, double shy, double shz) {
-    if (!in_group) return;
-    const double dx = (I.xi - pj.x) - shx, dy = (I.yi - pj.y) - shy, dz = (I.zi - pj.z) - shz;
+    const double dx = (xi - pj.x) - shx, dy = (yi - pj.y) - shy, dz = (zi - pj.z) - shz;
     const double r2 = sq_dist(dx, dy, dz);
     if (COUNT) ++n_tested;
-    if (r2 == 0.0 && j == (int)I.i) return;
+    if (r2 == 0.0 && j == (int)i) return;
     if (r2 <= pp.rlj2) {
-      acc.template add<false>(pp, c.pf, r2, I.qi, pj.w, dx, dy, dz);
+      acc.template add<false>(pp, c.pf, r2, qi, pj.w, dx, dy, dz);
       if (COUNT) n_lj += pp.do_lj;
     }
   };
-  const int64_t rowkey = (int64_t)I.cz * g.ny + I.cy;
-  for_each_row_group(I.valid, rowkey, I.cx, [&](bool in, int leader, int xa, int xb) {
-    in_group = in;
-    const int cy = __shfl(I.cy, leader, 64), cz = __shfl(I.cz, leader, 64);
-    if (MODE == 1) {
-      walk<GHOST, false>(c, 0, xa, xb, cy, cz, pp.s_coul, I.b, visit_q);
-      if (pp.do_lj) walk<GHOST, false>(c, 1, xa, xb, cy, cz, pp.s_lj, I.b, visit_lj);
-    } else if (pp.do_lj) {
-      walk<GHOST, false>(c, 0, xa, xb, cy, cz, pp.s_lj, I.b, visit_lj);
-      walk<GHOST, false>(c, 1, xa, xb, cy, cz, pp.s_lj, I.b, visit_lj);
-    }
-  });
-  const double f0 = sum_j_lanes(acc.get(0)), f1 = sum_j_lanes(acc.get(1)), f2 = sum_j_lanes(acc.get(2));
-  if (I.valid && I.b == 0) {
-    c.fx[I.i] = f0;
-    c.fy[I.i] = f1;
-    c.fz[I.i] = f2;
+  if (MODE == 1) {
+    stencil<GHOST, false>(c, 0, cx, cy, cz, pp.s_coul, visit_q);
+    if (pp.do_lj) stencil<GHOST, false>(c, 1, cx, cy, cz, pp.s_lj, visit_lj);
+  } else if (pp.do_lj) {
+    stencil<GHOST, false>(c, 0, cx, cy, cz, pp.s_lj, visit_lj);
+    stencil<GHOST, false>(c, 1, cx, cy, cz, pp.s_lj, visit_lj);
   }
+  c.fx[i] = acc.get(0);
+  c.fy[i] = acc.get(1);
+  c.fz[i] = acc.get(2);
   flush_counts<COUNT>(c, n_coul, n_lj, n_tested, 0);
 }
 
@@ -310,13 +321,21 @@ PairF32 make_pair_f32(const PairParams &pp) {
   return pf;
 }
 
+// Thread form: 256 particles per block. Cluster form: one wave of kCI
+// particles per block.
 template <class K>
-static void launch_range(K kernel, PairCtx c, int64_t i0, int64_t i1, hipStream_t st) {
+static void launch_threads(K kernel, PairCtx c, int64_t i0, int64_t i1, hipStream_t st) {
   if (i1 <= i0) return;
   c.i0 = i0;
   c.i1 = i1;
-  const unsigned blocks = (unsigned)((i1 - i0 + kCI - 1) / kCI);
-  kernel<<<blocks, 64, 0, st>>>(c);
+  kernel<<<(unsigned)((i1 - i0 + 255) / 256), 256, 0, st>>>(c);
+}
+template <class K>
+static void launch_clusters(K kernel, PairCtx c, int64_t i0, int64_t i1, hipStream_t st) {
+  if (i1 <= i0) return;
+  c.i0 = i0;
+  c.i1 = i1;
+  kernel<<<(unsigned)((i1 - i0 + kCI - 1) / kCI), 64, 0, st>>>(c);
 }
 
 // Charged particles occupy [0, nq) of the sorted order, neutral ones [nq, n).
@@ -329,11 +348,11 @@ template <bool F32, bool COUNT, bool GHOST>
 static void launch_part(PairCtx c, int64_t nq, int part, hipStream_t st) {
   const PairParams pp = c.pp;
   if (part == PAIR_PART_CHARGED) {
-    if (pp.rbl) launch_range(k_pair_rbl<F32, COUNT, GHOST>, c, 0, nq, st);
-    else launch_range(k_pair_plain<F32, COUNT, 1, GHOST>, c, 0, nq, st);
+    if (pp.rbl) launch_clusters(k_pair_rbl<F32, COUNT, GHOST>, c, 0, nq, st);
+    else launch_threads(k_pair_plain<F32, COUNT, 1, GHOST>, c, 0, nq, st);
   } else if (part == PAIR_PART_NEUTRAL) {
-    if (pp.rbl && pp.rlj2 > pp.rcore2 && pp.do_lj) launch_range(k_pair_rbl<F32, COUNT, GHOST>, c, nq, c.n, st);
-    else launch_range(k_pair_plain<F32, COUNT, 0, GHOST>, c, nq, c.n, st);
+    if (pp.rbl && pp.rlj2 > pp.rcore2 && pp.do_lj) launch_clusters(k_pair_rbl<F32, COUNT, GHOST>, c, nq, c.n, st);
+    else launch_threads(k_pair_plain<F32, COUNT, 0, GHOST>, c, nq, c.n, st);
   }
 }
 
