@@ -41,7 +41,7 @@ BYTES_KICK_DRIFT = 120   # read f (24) v (24) x (24), write v (24) x (24)
 BYTES_KICK = 96          # read f (24) v (24), write v (24) f (24)
 
 # cell edges picked by paper_2609_02694_amd.tune on MI355X
-DEFAULT_NCELL_H = {"plain3k": 4.29, "electrolyte1m": 3.078, "ions8m": 4.0, "subdomain64m": 2.5, "replica": 3.0}
+DEFAULT_NCELL_H = {"plain3k": 3.0, "electrolyte1m": 3.0, "ions8m": 4.0, "subdomain64m": 2.5, "replica": 3.0}
 
 
 def parse():
@@ -147,7 +147,7 @@ def main():
 
     kernels = {k: {"total_ms": round(v[0], 4), "launches": v[1], "avg_us": round(1000 * v[0] / v[1], 3)}
                for k, v in kt.items() if v[1] > 0}
-    roof = roofline(kernels, cnt, nq, p, prec, K)
+    roof, roofs = roofline(kernels, cnt, nq, p, prec, K, workload=a.workload)
 
     out = {
         "metric": METRIC,
@@ -170,6 +170,7 @@ def main():
         "counts_per_eval": {k: dict(zip(("coul_pairs", "lj_pairs", "candidates", "shell_members"), v))
                             for k, v in cnt.items()},
         "roofline": roof,
+        "rooflines": roofs,
         "gen_s": round(t_gen, 2),
     }
     ctx.close()
@@ -276,7 +277,7 @@ def bench_batch(a):
         peak = PEAK_FP64_TFLOPS if prec == rbe.FP64 else PEAK_FP32_TFLOPS
         ach = work / avg_s / 1e12
         roof = dict(kernel="batch", bound="alu", achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak,
-                    traffic=None, work_per_launch=work)
+                    traffic=measured_traffic("replica256", "batch"), work_per_launch=work)
     out = {
         "metric": METRIC,
         "value": value,
@@ -334,32 +335,76 @@ def cpu_baseline_batch(reps, budget_s=15.0):
             "seconds": round(dt, 2)}
 
 
-def roofline(kernels, cnt, nq, p, prec, K):
-    """Roofline figure of the dominant kernel (largest summed time)."""
-    if not kernels:
+# Fourier kernels, issue-slot model: per (charged particle, mode) two
+# transcendentals (sin, cos of the phase; quarter rate, 4 lane slots each)
+# plus 5 FP64 phase operations and 2 (structure factor) or 5 (gather) FMAs;
+# against 256 CU x 64 lanes x 2.4 GHz = 39.3 T lane-slots/s.
+PEAK_LANE_SLOTS_T = 256 * 64 * 2.4e9 / 1e12
+SLOTS_RHO_IK = 2 * 4 + 5 + 2
+SLOTS_GATHER_IK = 2 * 4 + 5 + 5
+
+
+def kernel_roofline(name, kernels, cnt, nq, p, prec):
+    """Roofline entry of one timed kernel kind (None if no model applies)."""
+    if name not in kernels:
         return None
-    name = max(kernels, key=lambda k: kernels[k]["total_ms"])
     avg_s = kernels[name]["avg_us"] * 1e-6
     peak_alu = PEAK_FP64_TFLOPS if prec == 0 else PEAK_FP32_TFLOPS
     n, P = p["n"], p["P"]
-    if name.startswith("pair"):
+    if name.startswith("pair") and cnt and name in cnt:
         c = cnt[name]
         work = FLOPS_COUL_PAIR * c[0] + FLOPS_LJ_PAIR * c[1] + OPS_SHELL_MEMBER * c[3]
         ach = work / avg_s / 1e12
         return dict(kernel=name, bound="alu", achieved=ach, peak=peak_alu, unit="TFLOP/s", frac=ach / peak_alu,
-                    traffic=None, work_per_launch=work)
+                    work_per_launch=work)
     if name in ("rho_partial", "gather"):
-        per = FLOPS_RHO_IK if name == "rho_partial" else FLOPS_GATHER_IK
+        per = SLOTS_RHO_IK if name == "rho_partial" else SLOTS_GATHER_IK
         work = per * nq * P
         ach = work / avg_s / 1e12
-        return dict(kernel=name, bound="alu", achieved=ach, peak=peak_alu, unit="TFLOP/s", frac=ach / peak_alu,
-                    traffic=None, work_per_launch=work)
+        return dict(kernel=name, bound="alu", achieved=ach, peak=PEAK_LANE_SLOTS_T, unit="Tslot/s",
+                    frac=ach / PEAK_LANE_SLOTS_T, work_per_launch=work)
     per_bytes = {"kick_drift": BYTES_KICK_DRIFT, "kick": BYTES_KICK}.get(name)
     if per_bytes is None:
-        return dict(kernel=name, bound="hbm", achieved=None, peak=PEAK_HBM_GBS, unit="GB/s", frac=None, traffic=None)
+        return None
     ach = per_bytes * n / avg_s / 1e9
     return dict(kernel=name, bound="hbm", achieved=ach, peak=PEAK_HBM_GBS, unit="GB/s", frac=ach / PEAK_HBM_GBS,
-                traffic=None)
+                work_per_launch=per_bytes * n)
+
+
+def measured_traffic(workload, name):
+    """HBM bytes per launch of a kernel kind from the committed rocprofv3 counter
+    runs (profiles/traffic.json), or None when the kernel sources changed since."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path)).get(workload)
+    if not d or name not in d.get("kinds", {}):
+        return None
+    h = hashlib.sha256()
+    for f in d["files"]:
+        fp = os.path.join(ROOT, f)
+        if not os.path.exists(fp):
+            return None
+        h.update(open(fp, "rb").read())
+    if h.hexdigest() != d["source_sha256"]:
+        return None
+    t = d["kinds"][name]
+    return t["read_bytes"] + t["write_bytes"]
+
+
+def roofline(kernels, cnt, nq, p, prec, K, workload=None):
+    """Roofline figure of the dominant kernel (largest summed time), and of every kind with a model."""
+    if not kernels:
+        return None, {}
+    every = {k: kernel_roofline(k, kernels, cnt, nq, p, prec) for k in kernels}
+    every = {k: v for k, v in every.items() if v}
+    name = max(kernels, key=lambda k: kernels[k]["total_ms"])
+    dom = every.get(name) or dict(kernel=name, bound="alu", achieved=None, peak=None, unit=None, frac=None)
+    dom = dict(dom)
+    dom["traffic"] = measured_traffic(workload, name) if workload else None
+    return dom, every
 
 
 def cpu_baseline(p, s):
