@@ -51,8 +51,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="electrolyte1m",
                     choices=["plain3k", "electrolyte1m", "ions8m", "subdomain64m", "replica256"])
-    ap.add_argument("--compare-steps", type=int, default=20,
-                    help="steps of each comparison form (replica256: FP64 and FP32C per-replica loops)")
+    ap.add_argument("--compare-steps", type=int, default=100,
+                    help="steps of each comparison form (the other precision; replica256: FP64 and FP32C "
+                         "per-replica loops and the other-precision batch); 0 skips them")
     ap.add_argument("--edge", type=float, default=None, help="cell edge (replica256)")
     ap.add_argument("--prec", default=None, choices=["fp64", "fp32c"])
     ap.add_argument("--n", type=int, default=None, help="override the particle count (same density)")
@@ -149,6 +150,23 @@ def main():
                for k, v in kt.items() if v[1] > 0}
     roof, roofs = roofline(kernels, cnt, nq, p, prec, K, workload=a.workload)
 
+    # the other precision form on the same system and grid (untimed in `value`)
+    forms = {prec_name: value}
+    if a.compare_steps > 0:
+        other = rbe.FP32C if prec == rbe.FP64 else rbe.FP64
+        oname = "fp32c" if other == rbe.FP32C else "fp64"
+        octx = rbe.Context(rbe.params_from_preset(p, prec=other, ncell=(nc, nc, nc)), n)
+        ost = rbe.Particles.from_numpy(s)
+        octx.forces(ost, None, None, 0)
+        octx.step(ost, 3, 1)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        octx.step(ost, a.compare_steps, 4)
+        torch.cuda.synchronize()
+        forms[oname] = n * a.compare_steps / (time.perf_counter() - t)
+        octx.sync_check()
+        octx.close()
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -171,6 +189,7 @@ def main():
                             for k, v in cnt.items()},
         "roofline": roof,
         "rooflines": roofs,
+        "forms_particle_steps_per_s": forms,
         "gen_s": round(t_gen, 2),
     }
     ctx.close()
@@ -238,7 +257,7 @@ def bench_batch(a):
             c.forces(s_, None, None, 0)
             c.step(s_, 2, 1)
         torch.cuda.synchronize()
-        Kc = a.compare_steps
+        Kc = max(2, a.compare_steps // 5)
         t = time.perf_counter()
         for c, s_ in zip(ctxs, sts):
             c.step(s_, Kc, 3)
