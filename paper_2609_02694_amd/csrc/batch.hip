@@ -107,12 +107,14 @@ __device__ inline void batch_pair(const BatchArgs &a, const RepDesc &R, int64_t 
     if (r2 == 0.0 && j == (int)i) return;
     if (r2 <= pp.rlj2) acc.template add<false>(pp, a.pf, r2, qi, pj.w, dx, dy, dz);
   };
+  const Reach rq{xi, yi, zi, pp.rq2}, rlj{xi, yi, zi, pp.rlj2};
   if (qi != 0.0) {
-    if (pp.do_coul || pp.do_lj) for_stencil<false>(g, a.cell_start, a.xq, a.sid, 0, cx, cy, cz, R.s_coul, visit_q, R.c0);
-    if (pp.do_lj) for_stencil<false>(g, a.cell_start, a.xq, a.sid, 1, cx, cy, cz, R.s_lj, visit_lj, R.c0);
+    if (pp.do_coul || pp.do_lj)
+      for_stencil<false>(g, a.cell_start, a.xq, a.sid, 0, cx, cy, cz, R.s_coul, rq, visit_q, R.c0);
+    if (pp.do_lj) for_stencil<false>(g, a.cell_start, a.xq, a.sid, 1, cx, cy, cz, R.s_lj, rlj, visit_lj, R.c0);
   } else if (pp.do_lj) {
-    for_stencil<false>(g, a.cell_start, a.xq, a.sid, 0, cx, cy, cz, R.s_lj, visit_lj, R.c0);
-    for_stencil<false>(g, a.cell_start, a.xq, a.sid, 1, cx, cy, cz, R.s_lj, visit_lj, R.c0);
+    for_stencil<false>(g, a.cell_start, a.xq, a.sid, 0, cx, cy, cz, R.s_lj, rlj, visit_lj, R.c0);
+    for_stencil<false>(g, a.cell_start, a.xq, a.sid, 1, cx, cy, cz, R.s_lj, rlj, visit_lj, R.c0);
   }
   a.ofx[i] = acc.get(0);
   a.ofy[i] = acc.get(1);

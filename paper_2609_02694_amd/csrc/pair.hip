@@ -106,12 +106,12 @@ __device__ inline ClusterI load_cluster_i(const PairCtx &c) {
 
 // Periodic or ghost-shell stencil walk of one particle (thread form).
 template <bool GHOST, bool WITH_ID, class Fn>
-__device__ inline void stencil(const PairCtx &c, int blk, int cx, int cy, int cz, int s, Fn &&fn) {
+__device__ inline void stencil(const PairCtx &c, int blk, int cx, int cy, int cz, int s, const Reach &R, Fn &&fn) {
   if (GHOST)
-    for_stencil_ghost<WITH_ID>(c.pp.g, c.cell_start, c.xq, c.ids, c.gcell_start, c.gxq, c.gid, blk, cx, cy, cz, s,
+    for_stencil_ghost<WITH_ID>(c.pp.g, c.cell_start, c.xq, c.ids, c.gcell_start, c.gxq, c.gid, blk, cx, cy, cz, s, R,
                                fn);
   else
-    for_stencil<WITH_ID>(c.pp.g, c.cell_start, c.xq, c.ids, blk, cx, cy, cz, s, fn);
+    for_stencil<WITH_ID>(c.pp.g, c.cell_start, c.xq, c.ids, blk, cx, cy, cz, s, R, fn);
 }
 
 // Plain cutoff sums, one thread per particle i walking its own stencil (on
@@ -157,12 +157,13 @@ __global__ void __launch_bounds__(256) k_pair_plain(PairCtx c) {
       if (COUNT) n_lj += pp.do_lj;
     }
   };
+  const Reach rq{xi, yi, zi, pp.rq2}, rlj{xi, yi, zi, pp.rlj2};
   if (MODE == 1) {
-    stencil<GHOST, false>(c, 0, cx, cy, cz, pp.s_coul, visit_q);
-    if (pp.do_lj) stencil<GHOST, false>(c, 1, cx, cy, cz, pp.s_lj, visit_lj);
+    stencil<GHOST, false>(c, 0, cx, cy, cz, pp.s_coul, rq, visit_q);
+    if (pp.do_lj) stencil<GHOST, false>(c, 1, cx, cy, cz, pp.s_lj, rlj, visit_lj);
   } else if (pp.do_lj) {
-    stencil<GHOST, false>(c, 0, cx, cy, cz, pp.s_lj, visit_lj);
-    stencil<GHOST, false>(c, 1, cx, cy, cz, pp.s_lj, visit_lj);
+    stencil<GHOST, false>(c, 0, cx, cy, cz, pp.s_lj, rlj, visit_lj);
+    stencil<GHOST, false>(c, 1, cx, cy, cz, pp.s_lj, rlj, visit_lj);
   }
   c.fx[i] = acc.get(0);
   c.fy[i] = acc.get(1);

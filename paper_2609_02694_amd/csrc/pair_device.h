@@ -169,27 +169,64 @@ __device__ inline void scan_range(const double4 *__restrict__ xq, const int32_t 
   }
 }
 
+// Walking particle of a thread-form traversal: position and the squared
+// reach of the walk. Each stencil row is trimmed to the x-cells the reach
+// sphere can touch: the gap g from (y, z) to the row's y/z cell slabs bounds
+// the x extent by sqrt(r^2 - g^2), and rows with g > r are skipped. The
+// gaps are shrunk and the extent grown by kTrimMargin, which covers the
+// rounding of the binning (a particle binned to cell c lies within a few ulp
+// of [c h, (c + 1) h]); every pair is still classified exactly afterwards.
+struct Reach {
+  double x, y, z, r2;
+};
+constexpr double kTrimMargin = 1e-9;
+// Distance from p to the cell slab [c h, (c + 1) h] (unwrapped cell index c),
+// minus the margin, at least 0.
+__device__ inline double slab_gap(double p, int c, double h) {
+#pragma clang fp contract(off)
+  const double lo = (double)c * h, hi = lo + h;
+  const double d = lo - p > 0.0 ? lo - p : (p - hi > 0.0 ? p - hi : 0.0);
+  return d > kTrimMargin ? d - kTrimMargin : 0.0;
+}
+// x-cell range [*xa, *xb] (unwrapped, inside [cx - s, cx + s]) of a row at
+// y/z gaps gy, gz; false if the row is out of reach.
+__device__ inline bool row_range(const Grid &g, const Reach &R, double gy, double gz, int cx, int s, int *xa,
+                                 int *xb) {
+#pragma clang fp contract(off)
+  const double rem = R.r2 - (gy * gy + gz * gz);
+  if (rem < 0.0) return false;
+  const double ext = sqrt(rem) + kTrimMargin;
+  const int lo = (int)floor((R.x - ext) * g.inv_h[0]);
+  const int hi = (int)floor((R.x + ext) * g.inv_h[0]);
+  *xa = max(cx - s, lo);
+  *xb = min(cx + s, hi);
+  return *xa <= *xb;
+}
+
 // Periodic traversal: every particle j of species block `blk` in the
-// (2s+1)^3 cells around (cx, cy, cz); (shx, shy, shz) is the image shift of j
-// (its image lies at r_j + shift).
+// (2s+1)^3 cells around (cx, cy, cz) that the reach of R can touch;
+// (shx, shy, shz) is the image shift of j (its image lies at r_j + shift).
 template <bool WITH_ID, class Fn>
 __device__ inline void for_stencil(const Grid &g, const int32_t *__restrict__ cell_start,
                                    const double4 *__restrict__ xq, const int32_t *__restrict__ ids, int blk, int cx,
-                                   int cy, int cz, int s, Fn &&fn, int64_t cell_base = 0) {
+                                   int cy, int cz, int s, const Reach &R, Fn &&fn, int64_t cell_base = 0) {
   const int64_t base = cell_base + (int64_t)blk * g.ncell;
+  const double hy = g.L[1] / g.ny, hz = g.L[2] / g.nz;
   for (int oz = -s; oz <= s; ++oz) {
     const int az = cz + oz;
+    const double gz = slab_gap(R.z, az, hz);
+    if (gz * gz > R.r2) continue;
     const int qz = floor_div(az, g.nz);
     const int wz = az - qz * g.nz;
     const double shz = (double)qz * g.L[2];
     for (int oy = -s; oy <= s; ++oy) {
       const int ay = cy + oy;
+      int a, a_end;
+      if (!row_range(g, R, slab_gap(R.y, ay, hy), gz, cx, s, &a, &a_end)) continue;
       const int qy = floor_div(ay, g.ny);
       const int wy = ay - qy * g.ny;
       const double shy = (double)qy * g.L[1];
-      const int64_t row = base + (wz * g.ny + wy) * g.nx;
-      int a = cx - s;
-      const int a_end = cx + s;
+      const int64_t row = base + (int64_t)(wz * g.ny + wy) * g.nx;
       while (a <= a_end) {
         const int qx = floor_div(a, g.nx);
         const int b = min(a_end, (qx + 1) * g.nx - 1);
@@ -204,26 +241,34 @@ __device__ inline void for_stencil(const Grid &g, const int32_t *__restrict__ ce
 
 // Ghost-shell traversal (no periodic images): the natives of the stencil
 // rows that lie inside the native grid, then the ghosts of the same rows of
-// the padded grid. (cx, cy, cz) is a native cell.
+// the padded grid, each row trimmed to the reach of R. (cx, cy, cz) is a
+// native cell.
 template <bool WITH_ID, class Fn>
 __device__ inline void for_stencil_ghost(const Grid &g, const int32_t *__restrict__ cell_start,
                                          const double4 *__restrict__ xq, const int32_t *__restrict__ ids,
                                          const int32_t *__restrict__ gcell_start, const double4 *__restrict__ gxq,
                                          const int32_t *__restrict__ gid, int blk, int cx, int cy, int cz, int s,
-                                         Fn &&fn) {
+                                         const Reach &R, Fn &&fn) {
   const int base = blk * g.ncell;
   const int pbase = blk * g.pncell;
-  const int xa = max(cx - s, 0), xb = min(cx + s, g.nx - 1);
+  const double hy = g.L[1] / g.ny, hz = g.L[2] / g.nz;
   for (int oz = -s; oz <= s; ++oz) {
     const int z = cz + oz;
+    const double gz = slab_gap(R.z, z, hz);
+    if (gz * gz > R.r2) continue;
     for (int oy = -s; oy <= s; ++oy) {
       const int y = cy + oy;
+      int xa, xb;
+      if (!row_range(g, R, slab_gap(R.y, y, hy), gz, cx, s, &xa, &xb)) continue;
       if (z >= 0 && z < g.nz && y >= 0 && y < g.ny) {
-        const int row = base + (z * g.ny + y) * g.nx;
-        scan_range<WITH_ID>(xq, ids, cell_start[row + xa], cell_start[row + xb + 1], 0.0, 0.0, 0.0, fn);
+        const int na = max(xa, 0), nb = min(xb, g.nx - 1);
+        if (na <= nb) {
+          const int row = base + (z * g.ny + y) * g.nx;
+          scan_range<WITH_ID>(xq, ids, cell_start[row + na], cell_start[row + nb + 1], 0.0, 0.0, 0.0, fn);
+        }
       }
       const int prow = pbase + ((z + g.goff[2]) * g.pny + (y + g.goff[1])) * g.pnx + g.goff[0];
-      scan_range<WITH_ID>(gxq, gid, gcell_start[prow + cx - s], gcell_start[prow + cx + s + 1], 0.0, 0.0, 0.0, fn);
+      scan_range<WITH_ID>(gxq, gid, gcell_start[prow + xa], gcell_start[prow + xb + 1], 0.0, 0.0, 0.0, fn);
     }
   }
 }
