@@ -9,8 +9,9 @@ namespace rbe {
 // FP64 erfc(x) = exp(-x^2) R(x) with R(x) = erfc(x) e^{x^2} a degree-20
 // polynomial in s = 2/(1 + x/2) - 1 (fit over x in [0, 8] by fit_erfcx.py,
 // relative error below 7.2e-15); e = exp(-x^2) is passed in.
+__device__ inline double rcp_f64(double a);
 __device__ inline double erfc_scaled_f64(double x) {
-  const double s = 2.0 / fma(0.5, x, 1.0) - 1.0;
+  const double s = fma(2.0, rcp_f64(fma(0.5, x, 1.0)), -1.0);
   double r = 1.63618628481317543e-08;
   r = fma(r, s, -4.60928758649811430e-08);
   r = fma(r, s, -6.88442333452307132e-08);
@@ -35,15 +36,59 @@ __device__ inline double erfc_scaled_f64(double x) {
   return r;
 }
 
+// FP64 building blocks of the pair scalar: hardware reciprocal and
+// reciprocal-square-root estimates refined by two Newton steps each (the
+// error of the estimate squares at every step: a few ulp after two), and
+// exp(x) for x <= 0 by x = k ln2 + t, |t| <= ln2/2 (ln2 split into a head
+// with 21 trailing zero bits, so k * head is exact, and a tail), the Taylor
+// series of e^t to degree 14 (remainder below 1e-17) and a scaling by 2^k.
+__device__ inline double rcp_f64(double a) {
+  double y = __builtin_amdgcn_rcp(a);
+  double e = fma(-a, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-a, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ inline double rsqrt_f64(double a) {
+  double y = __builtin_amdgcn_rsq(a);
+  // y <- y + y (1 - a y^2) / 2
+  double e = fma(-a * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-a * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+__device__ inline double exp_nonpos_f64(double x) {
+  const double k = rint(x * 1.4426950408889634);
+  double t = fma(-k, 0.6931471803691238, x);
+  t = fma(-k, 1.9082149292705877e-10, t);
+  double p = 1.1470745597729725e-11;
+  p = fma(p, t, 1.6059043836821613e-10);
+  p = fma(p, t, 2.08767569878681e-09);
+  p = fma(p, t, 2.505210838544172e-08);
+  p = fma(p, t, 2.755731922398589e-07);
+  p = fma(p, t, 2.7557319223985893e-06);
+  p = fma(p, t, 2.48015873015873e-05);
+  p = fma(p, t, 0.0001984126984126984);
+  p = fma(p, t, 0.001388888888888889);
+  p = fma(p, t, 0.008333333333333333);
+  p = fma(p, t, 0.041666666666666664);
+  p = fma(p, t, 0.16666666666666666);
+  p = fma(p, t, 0.5);
+  p = fma(p, t, 1.0);
+  p = fma(p, t, 1.0);
+  return ldexp(p, (int)k);
+}
+
 __device__ inline double pair_scalar_f64(const PairParams &pp, double r2, double qi, double qj) {
-  const double inv_r2 = 1.0 / r2;
+  const double rinv = rsqrt_f64(r2);
+  const double inv_r2 = rinv * rinv;
   double f = 0.0;
   if (pp.do_coul && r2 <= pp.rc2 && qi != 0.0 && qj != 0.0) {
-    const double r = sqrt(r2);
-    const double e = exp(-pp.alpha * r2);
+    const double r = r2 * rinv;
+    const double e = exp_nonpos_f64(-pp.alpha * r2);
     const double R = erfc_scaled_f64(pp.sqrt_alpha * r);
     // G = erfc(x)/r^3 + 2 sqrt(a) e/(sqrt(pi) r^2) = e/r^2 (R/r + 2 sqrt(a)/sqrt(pi))
-    const double G = e * inv_r2 * (R / r + pp.two_sqrt_alpha_over_sqrt_pi);
+    const double G = e * inv_r2 * fma(R, rinv, pp.two_sqrt_alpha_over_sqrt_pi);
     f = pp.kc * qi * qj * G;
   }
   if (pp.do_lj && r2 <= pp.rlj2) {
@@ -97,7 +142,7 @@ __device__ inline float pair_scalar_f32(const PairParams &pp, const PairF32 &pf,
 
 __device__ inline double pair_scalar_lj_f64(const PairParams &pp, double r2) {
   if (!(pp.do_lj && r2 <= pp.rlj2)) return 0.0;
-  const double inv_r2 = 1.0 / r2;
+  const double inv_r2 = rcp_f64(r2);
   const double s2 = pp.sig2 * inv_r2;
   const double s6 = s2 * s2 * s2;
   return pp.eps24 * (2.0 * s6 * s6 - s6) * inv_r2;

@@ -281,3 +281,51 @@ def test_step_ghost_shell_fp32c():
     F = np.stack([st.fx.cpu().numpy(), st.fy.cpu().numpy(), st.fz.cpu().numpy()], axis=1)
     assert rel_err(F, ref) < TOL32
     ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# exact boundaries: lattice distances equal to the cutoffs, particles on cell
+# faces (the trimmed stencil rows and the core/shell split must keep every
+# pair the oracle keeps)
+# ---------------------------------------------------------------------------
+def lattice_with_vacancies(seed=7, a=1.25, n=12, frac_removed=0.1):
+    """Rock-salt charges on a simple cubic lattice of spacing a (all
+    coordinates exact binary fractions), with an equal number of + and -
+    sites removed so that the forces do not cancel by symmetry."""
+    rng = np.random.default_rng(seed)
+    g = np.arange(n) * a
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    ijk = np.stack(np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij"), -1).reshape(-1, 3)
+    q = np.where(ijk.sum(1) % 2 == 0, 1.0, -1.0)
+    keep = np.ones(len(q), bool)
+    k = int(frac_removed * len(q) / 2)
+    keep[rng.choice(np.nonzero(q > 0)[0], k, replace=False)] = False
+    keep[rng.choice(np.nonzero(q < 0)[0], k, replace=False)] = False
+    s = dict(x=X.ravel()[keep].copy(), y=Y.ravel()[keep].copy(), z=Z.ravel()[keep].copy(), q=q[keep].copy())
+    s["id"] = np.arange(len(s["q"]), dtype=np.int32)
+    return s, n * a
+
+
+@pytest.mark.parametrize("ncell", [(6, 6, 6), (4, 4, 4), (12, 12, 12)])
+def test_forces_fp64_cutoffs_on_lattice_distances(ncell):
+    s, L = lattice_with_vacancies()
+    # r_lj = 2a, r_coul = 4a: many pairs exactly at each cutoff
+    p = dict(seed=77, n=len(s["q"]), L=L, alpha=0.3, r_coul=5.0, r_lj=2.5, r_core=0.0, p_shell=0, P=40, dt=0.002,
+             ghost=0.0)
+    m, w = oracle.sample_k(p["seed"], 0, L, p["alpha"], p["P"])
+    ref = oracle_forces(p, s, m, w, ev=0, cells=False)
+    for term, key in ((rbe.TERM_LJ, "lj"), (rbe.TERM_COUL_REAL, "coul"), (rbe.TERM_ALL, "F")):
+        F = gpu_forces(p, s, terms=term, m=m, w=w, ncell=ncell)
+        assert rel_err(F, ref[key]) < TOL64, (ncell, key)
+
+
+@pytest.mark.parametrize("ncell", [(6, 6, 6), (4, 4, 4)])
+def test_forces_fp64_rbl_core_on_lattice_distance(ncell):
+    s, L = lattice_with_vacancies(seed=8)
+    # r_core = 3a exactly, shell out to r_coul = 4a; p below the shell size
+    p = dict(seed=78, n=len(s["q"]), L=L, alpha=0.3, r_coul=5.0, r_lj=2.5, r_core=3.75, p_shell=8, P=40,
+             dt=0.002, ghost=0.0)
+    m, w = oracle.sample_k(p["seed"], 3, L, p["alpha"], p["P"])
+    ref = oracle_forces(p, s, m, w, ev=3, cells=False)
+    F = gpu_forces(p, s, m=m, w=w, ev=3, ncell=ncell)
+    assert rel_err(F, ref["F"]) < TOL64, ncell
