@@ -317,7 +317,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchArgs a) {
           const double4 s = a.sq[j];
           const double t = turn_fraction(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
           double sn, cs;
-          sincospi(2.0 * t, &sn, &cs);
+          sincos_turn_f64(t, &sn, &cs);
           re = fma(s.w, cs, re);
           im = fma(s.w, sn, im);
         }
@@ -380,7 +380,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchArgs a) {
           const GatherMode gm = md[l];
           const double t = turn_fraction(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
           double sn, cs;
-          sincospi(2.0 * t, &sn, &cs);
+          sincos_turn_f64(t, &sn, &cs);
           const double g = gm.a * cs - gm.b * sn;
           gx = fma(g, gm.mx, gx);
           gy = fma(g, gm.my, gy);

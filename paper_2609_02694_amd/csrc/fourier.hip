@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f64(int64_t nq, 
     const double4 s = sq[j];
     const double t = turn_fraction(mx, my, mz, s.x, s.y, s.z);
     double sn, cs;
-    sincospi(2.0 * t, &sn, &cs);
+    sincos_turn_f64(t, &sn, &cs);
     re = fma(s.w, cs, re);
     im = fma(s.w, sn, im);
   }
@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(256) k_gather_f64(int64_t nq, int P, const dou
     const GatherMode gm = modes[l];
     const double t = turn_fraction(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
     double sn, cs;
-    sincospi(2.0 * t, &sn, &cs);
+    sincos_turn_f64(t, &sn, &cs);
     const double g = gm.a * cs - gm.b * sn;  // w Im(exp(-i theta) rho)
     gx = fma(g, gm.mx, gx);
     gy = fma(g, gm.my, gy);

@@ -12,6 +12,38 @@ __device__ inline double turn_fraction(double mx, double my, double mz, double s
   return t - rint(t);
 }
 
+// sin and cos of 2 pi t for |t| <= 1/2 (FP64): u = 4t and f = u - rint(u)
+// are exact, theta = f pi/2 lies in [-pi/4, pi/4], sin theta and cos theta
+// come from their Taylor series to degrees 15 and 16 (truncation below
+// 5e-17), and the result is rotated by the rint(u) quarter turns.
+__device__ inline void sincos_turn_f64(double t, double *sn, double *cs) {
+  const double u = 4.0 * t;
+  const double q = rint(u);
+  const double th = (u - q) * 1.5707963267948966;
+  const double t2 = th * th;
+  double ps = -7.647163731819816e-13;
+  ps = fma(ps, t2, 1.6059043836821613e-10);
+  ps = fma(ps, t2, -2.505210838544172e-08);
+  ps = fma(ps, t2, 2.7557319223985893e-06);
+  ps = fma(ps, t2, -0.0001984126984126984);
+  ps = fma(ps, t2, 0.008333333333333333);
+  ps = fma(ps, t2, -0.16666666666666666);
+  ps = fma(ps * t2, th, th);
+  double pc = 4.779477332387385e-14;
+  pc = fma(pc, t2, -1.1470745597729725e-11);
+  pc = fma(pc, t2, 2.08767569878681e-09);
+  pc = fma(pc, t2, -2.755731922398589e-07);
+  pc = fma(pc, t2, 2.48015873015873e-05);
+  pc = fma(pc, t2, -0.001388888888888889);
+  pc = fma(pc, t2, 0.041666666666666664);
+  pc = fma(pc, t2, -0.5);
+  pc = fma(pc, t2, 1.0);
+  const int k = (int)q & 3;  // quarter turns, q in [-2, 2]
+  const double a = (k & 1) ? pc : ps, b = (k & 1) ? ps : pc;
+  *sn = (k & 2) ? -a : a;
+  *cs = (k == 1 || k == 2) ? -b : b;
+}
+
 // Kahan-compensated FP32 sum.
 __device__ inline void kahan_add(float &sum, float &comp, float v) {
 #pragma clang fp contract(off)
