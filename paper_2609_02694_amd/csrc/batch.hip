@@ -182,7 +182,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchArgs a) {
       gm.mz = (double)mv[2];
       gm.a = 0.0;
       gm.b = 0.0;
-      gm.pad[0] = gm.pad[1] = gm.pad[2] = 0.0;
+      gather_floats(gm);
       a.modes[it] = gm;
       a.wk[it] = mode_weight(R.mt, P, mv[0], mv[1], mv[2]);
     }
@@ -307,8 +307,8 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchArgs a) {
           const double4 s = a.sq[j];
           const float t = (float)turn_fraction(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
           const float q = (float)s.w;
-          kahan_add(re, rc, q * __builtin_amdgcn_cosf(t));
-          kahan_add(im, ic, q * __builtin_amdgcn_sinf(t));
+          kahan_fma(re, rc, q, __builtin_amdgcn_cosf(t));
+          kahan_fma(im, ic, q, __builtin_amdgcn_sinf(t));
         }
         out = make_double2((double)re - (double)rc, (double)im - (double)ic);
       } else {
@@ -348,6 +348,8 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchArgs a) {
         const double w = a.wk[it];
         a.modes[it].a = w * im;
         a.modes[it].b = w * re;
+        a.modes[it].af = (float)(w * im);
+        a.modes[it].bf = (float)(w * re);
       }
     }
   }
@@ -366,10 +368,10 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchArgs a) {
         for (int l = 0; l < P; ++l) {
           const GatherMode gm = md[l];
           const float t = (float)turn_fraction(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
-          const float g = (float)gm.a * __builtin_amdgcn_cosf(t) - (float)gm.b * __builtin_amdgcn_sinf(t);
-          kahan_add(gx, ex, g * (float)gm.mx);
-          kahan_add(gy, ey, g * (float)gm.my);
-          kahan_add(gz, ez, g * (float)gm.mz);
+          const float g = fmaf(gm.af, __builtin_amdgcn_cosf(t), -gm.bf * __builtin_amdgcn_sinf(t));
+          kahan_fma(gx, ex, g, gm.mxf);
+          kahan_fma(gy, ey, g, gm.myf);
+          kahan_fma(gz, ez, g, gm.mzf);
         }
         fx -= s.w * (kTwoPi / R.g.L[0]) * ((double)gx - (double)ex);
         fy -= s.w * (kTwoPi / R.g.L[1]) * ((double)gy - (double)ey);

@@ -85,8 +85,8 @@ __global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f32c(int64_t nq,
     const float q = (float)s.w;
     const float cs = __builtin_amdgcn_cosf(t);
     const float sn = __builtin_amdgcn_sinf(t);
-    kahan_add(re, re_c, q * cs);
-    kahan_add(im, im_c, q * sn);
+    kahan_fma(re, re_c, q, cs);
+    kahan_fma(im, im_c, q, sn);
   }
   if (active) part[(int64_t)blockIdx.x * P + l] = make_double2((double)re - (double)re_c, (double)im - (double)im_c);
 }
@@ -123,7 +123,7 @@ __global__ void __launch_bounds__(64) k_rho_final(int nchunks, int P, const doub
     gm.mz = mkd[2 * P + l];
     gm.a = w[l] * im;
     gm.b = w[l] * re;
-    gm.pad[0] = gm.pad[1] = gm.pad[2] = 0.0;
+    gather_floats(gm);
     modes[l] = gm;
   }
 }
@@ -184,10 +184,10 @@ __global__ void __launch_bounds__(256) k_gather_f32c(int64_t nq, int P, const do
     const float t = (float)turn_fraction(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
     const float cs = __builtin_amdgcn_cosf(t);
     const float sn = __builtin_amdgcn_sinf(t);
-    const float g = (float)gm.a * cs - (float)gm.b * sn;
-    kahan_add(gx, cx, g * (float)gm.mx);
-    kahan_add(gy, cy, g * (float)gm.my);
-    kahan_add(gz, cz, g * (float)gm.mz);
+    const float g = fmaf(gm.af, cs, -gm.bf * sn);
+    kahan_fma(gx, cx, g, gm.mxf);
+    kahan_fma(gy, cy, g, gm.myf);
+    kahan_fma(gz, cz, g, gm.mzf);
   }
   const double q = s.w;
   fx[i] -= q * kx * ((double)gx - (double)cx);

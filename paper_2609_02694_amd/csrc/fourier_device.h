@@ -5,10 +5,10 @@
 namespace rbe {
 
 // Phase of mode m at fractional coordinate s, in turns, reduced to
-// [-1/2, 1/2]: t = m . s - rint(m . s) (FP64, no contraction).
+// [-1/2, 1/2]: t = m . s - rint(m . s) (FP64, the dot product with fused
+// multiply-adds).
 __device__ inline double turn_fraction(double mx, double my, double mz, double sx, double sy, double sz) {
-#pragma clang fp contract(off)
-  const double t = mx * sx + my * sy + mz * sz;
+  const double t = fma(mx, sx, fma(my, sy, mz * sz));
   return t - rint(t);
 }
 
@@ -42,6 +42,26 @@ __device__ inline void sincos_turn_f64(double t, double *sn, double *cs) {
   const double a = (k & 1) ? pc : ps, b = (k & 1) ? ps : pc;
   *sn = (k & 2) ? -a : a;
   *cs = (k == 1 || k == 2) ? -b : b;
+}
+
+// Kahan-compensated FP32 sum of products: sum += a b, with the product
+// fused into the compensation step (one rounding instead of two).
+__device__ inline void kahan_fma(float &sum, float &comp, float a, float b) {
+#pragma clang fp contract(off)
+  const float y = fmaf(a, b, -comp);
+  const float t = sum + y;
+  comp = (t - sum) - y;
+  sum = t;
+}
+
+// FP32 copies of a mode's gather coefficients.
+__device__ inline void gather_floats(GatherMode &gm) {
+  gm.af = (float)gm.a;
+  gm.bf = (float)gm.b;
+  gm.mxf = (float)gm.mx;
+  gm.myf = (float)gm.my;
+  gm.mzf = (float)gm.mz;
+  gm.pad = 0.f;
 }
 
 // Kahan-compensated FP32 sum.

@@ -111,9 +111,9 @@ void launch_pair(int prec, int part, const PairParams &pp, int64_t n, int64_t nq
 // Fourier part
 // ---------------------------------------------------------------------------
 struct GatherMode {
-  double mx, my, mz;  // integer mode vector as doubles
-  double a, b;        // w Im rho, w Re rho
-  double pad[3];
+  double mx, my, mz;                // integer mode vector as doubles
+  double a, b;                      // w Im rho, w Re rho
+  float af, bf, mxf, myf, mzf, pad; // FP32 copies for the FP32C gather
 };
 struct FourierBuffers {
   double *mkd;           // [3][P] mode vectors as doubles
