@@ -166,6 +166,14 @@ struct Kahan3 {
     c[k] = (t - s[k]) - y;
     s[k] = t;
   }
+  // s += a b with the product fused into the compensation step
+  __device__ inline void add_prod(int k, float a, float b) {
+#pragma clang fp contract(off)
+    const float y = fmaf(a, b, -c[k]);
+    const float t = s[k] + y;
+    c[k] = (t - s[k]) - y;
+    s[k] = t;
+  }
   __device__ inline double get(int k) const { return (double)s[k] - (double)c[k]; }
 };
 
@@ -342,9 +350,9 @@ struct ForceAcc<true> {
   __device__ inline void add(const PairParams &pp, const PairF32 &pf, double r2, double qi, double qj, double dx,
                              double dy, double dz) {
     const float sc = COUL ? pair_scalar_f32(pp, pf, r2, (float)(qi * qj)) : pair_scalar_lj_f32(pp, pf, r2);
-    k.add(0, sc * (float)dx);
-    k.add(1, sc * (float)dy);
-    k.add(2, sc * (float)dz);
+    k.add_prod(0, sc, (float)dx);
+    k.add_prod(1, sc, (float)dy);
+    k.add_prod(2, sc, (float)dz);
   }
   __device__ inline double get(int c) const { return k.get(c); }
 };
