@@ -41,7 +41,7 @@ BYTES_KICK_DRIFT = 120   # read f (24) v (24) x (24), write v (24) x (24)
 BYTES_KICK = 96          # read f (24) v (24), write v (24) f (24)
 
 # cell edges picked by paper_2609_02694_amd.tune on MI355X
-DEFAULT_NCELL_H = {"plain3k": 3.0, "electrolyte1m": 3.0, "ions8m": 4.0, "subdomain64m": 2.5, "replica": 3.0}
+DEFAULT_NCELL_H = {"plain3k": 3.0, "electrolyte1m": 3.0, "ions8m": 4.0, "subdomain64m": 2.5, "replica": 2.0}
 
 
 def parse():

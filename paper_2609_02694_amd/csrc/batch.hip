@@ -13,7 +13,7 @@
 //   P3  scan: cell starts (one exclusive scan serves every replica, because
 //       replica r's keys and particles both follow those of replicas < r)
 //   P4  provisional scatter (atomic slots)
-//   P5  stable placement (slot = bucket start + members with a smaller index)
+//   P5  stable placement (each bucket's entries in increasing input order)
 //   P6  reorder of the state and packing of the sorted records
 //   P7  near field of every particle; structure-factor partials (chunk x mode)
 //   P8  structure factors: fixed-order sum of the chunk partials per mode
@@ -137,32 +137,38 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchArgs a) {
   const uint64_t eval = *((volatile uint64_t *)a.eval);
 
   // ---- P0: drift, keys + histogram, mode sample ----------------------------
-  for (int64_t i = gtid; i < a.ntot; i += gstride) {
-    const RepDesc &R = a.reps[a.rep_of[i]];
-    double x = a.ix[i], y = a.iy[i], z = a.iz[i];
-    if (a.mode == 0) {
-      const double u = a.ivx[i] + a.h * a.ifx[i], v = a.ivy[i] + a.h * a.ify[i], w = a.ivz[i] + a.h * a.ifz[i];
-      a.ivx[i] = u;
-      a.ivy[i] = v;
-      a.ivz[i] = w;
-      x = wrap_coord(x + a.dt * u, R.g.L[0]);
-      y = wrap_coord(y + a.dt * v, R.g.L[1]);
-      z = wrap_coord(z + a.dt * w, R.g.L[2]);
-      a.ix[i] = x;
-      a.iy[i] = y;
-      a.iz[i] = z;
-      if (!isfinite(u) || !isfinite(v) || !isfinite(w)) atomicOr(a.err, kErrNonFinite);
-    } else {
-      x = wrap_coord(x, R.g.L[0]);
-      y = wrap_coord(y, R.g.L[1]);
-      z = wrap_coord(z, R.g.L[2]);
+  // wave-uniform trip count (every lane takes part in the slot vote)
+  for (int64_t i = gtid; i - lane < a.ntot; i += gstride) {
+    const bool active = i < a.ntot;
+    int k = -1 - lane;  // lanes past the end: a key no other lane has
+    if (active) {
+      const RepDesc &R = a.reps[a.rep_of[i]];
+      double x = a.ix[i], y = a.iy[i], z = a.iz[i];
+      if (a.mode == 0) {
+        const double u = a.ivx[i] + a.h * a.ifx[i], v = a.ivy[i] + a.h * a.ify[i], w = a.ivz[i] + a.h * a.ifz[i];
+        a.ivx[i] = u;
+        a.ivy[i] = v;
+        a.ivz[i] = w;
+        x = wrap_coord(x + a.dt * u, R.g.L[0]);
+        y = wrap_coord(y + a.dt * v, R.g.L[1]);
+        z = wrap_coord(z + a.dt * w, R.g.L[2]);
+        a.ix[i] = x;
+        a.iy[i] = y;
+        a.iz[i] = z;
+        if (!isfinite(u) || !isfinite(v) || !isfinite(w)) atomicOr(a.err, kErrNonFinite);
+      } else {
+        x = wrap_coord(x, R.g.L[0]);
+        y = wrap_coord(y, R.g.L[1]);
+        z = wrap_coord(z, R.g.L[2]);
+      }
+      const int cx = cell_coord(x, R.g.inv_h[0], R.g.nx);
+      const int cy = cell_coord(y, R.g.inv_h[1], R.g.ny);
+      const int cz = cell_coord(z, R.g.inv_h[2], R.g.nz);
+      k = (int)(R.c0 + (a.iq[i] == 0.0 ? R.g.ncell : 0) + (cz * R.g.ny + cy) * R.g.nx + cx);
+      a.key[i] = k;
     }
-    const int cx = cell_coord(x, R.g.inv_h[0], R.g.nx);
-    const int cy = cell_coord(y, R.g.inv_h[1], R.g.ny);
-    const int cz = cell_coord(z, R.g.inv_h[2], R.g.nz);
-    const int64_t k = R.c0 + (a.iq[i] == 0.0 ? R.g.ncell : 0) + (cz * R.g.ny + cy) * R.g.nx + cx;
-    a.key[i] = (int32_t)k;
-    a.slot[i] = atomicAdd(&a.count[k], 1);
+    const int sl = run_slot(k, active, a.count);
+    if (active) a.slot[i] = sl;
   }
   if (P > 0) {
     for (int64_t it = gtid; it < (int64_t)a.nrep * P; it += gstride) {
@@ -239,13 +245,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchArgs a) {
   grid_barrier(a.bar, a.err);
 
   // ---- P5: stable placement; clear the histogram for the next step -----------
-  for (int64_t i = gtid; i < a.ntot; i += gstride) {
-    const int k = a.key[i];
-    const int lo = a.cell_start[k], hi = a.cell_start[k + 1];
-    int rank = 0;
-    for (int t = lo; t < hi; ++t) rank += a.tmp[t] < (int32_t)i;
-    a.perm[lo + rank] = (int32_t)i;
-  }
+  for (int64_t k = gtid; k < a.nkeys; k += gstride) place_bucket(a.cell_start[k], a.cell_start[k + 1], a.tmp, a.perm);
   for (int64_t k = gtid; k < a.nkeys; k += gstride) a.count[k] = 0;
   grid_barrier(a.bar, a.err);
 

@@ -8,9 +8,16 @@
 //
 // Steps: keys + histogram (integer atomics give exact counts) -> exclusive
 // scan -> provisional scatter (atomic slot order, not deterministic) ->
-// stable placement: a particle's final slot is start[key] + the number of
+// stable placement: each bucket's entries (input indices) are put in
+// increasing order, so a particle's final slot is start[key] + the number of
 // bucket members with a smaller input index. The output is a pure function
 // of the input, whatever order the atomics took.
+//
+// The input of a step is the previous step's cell order, so equal keys come
+// in runs. A wave takes one atomic per run (its length) and hands out the
+// slots of the run in input order; a bucket is then usually already in order
+// and its placement a copy (checked per bucket; out-of-order buckets are
+// sorted by insertion).
 #include "rbe_internal.h"
 #include "kernels.h"
 
@@ -48,13 +55,17 @@ __global__ void __launch_bounds__(256) k_bin_keys(int64_t n, const double *__res
                                                   int32_t *__restrict__ key, int32_t *__restrict__ slot,
                                                   int32_t *__restrict__ count) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int cx = cell_coord(wrap_coord(x[i], g.L[0]), g.inv_h[0], g.nx);
-  const int cy = cell_coord(wrap_coord(y[i], g.L[1]), g.inv_h[1], g.ny);
-  const int cz = cell_coord(wrap_coord(z[i], g.L[2]), g.inv_h[2], g.nz);
-  const int k = (q[i] == 0.0 ? g.ncell : 0) + (cz * g.ny + cy) * g.nx + cx;
-  key[i] = k;
-  slot[i] = atomicAdd(&count[k], 1);
+  const bool active = i < n;
+  int k = -1 - (int)(threadIdx.x & 63);  // lanes past the end: a key no other lane has
+  if (active) {
+    const int cx = cell_coord(wrap_coord(x[i], g.L[0]), g.inv_h[0], g.nx);
+    const int cy = cell_coord(wrap_coord(y[i], g.L[1]), g.inv_h[1], g.ny);
+    const int cz = cell_coord(wrap_coord(z[i], g.L[2]), g.inv_h[2], g.nz);
+    k = (q[i] == 0.0 ? g.ncell : 0) + (cz * g.ny + cy) * g.nx + cx;
+    key[i] = k;
+  }
+  const int sl = run_slot(k, active, count);  // every lane of the wave takes part in the vote
+  if (active) slot[i] = sl;
 }
 
 // ---------------------------------------------------------------------------
@@ -157,16 +168,11 @@ __global__ void __launch_bounds__(256) k_scatter_prov(int64_t n, const int32_t *
   tmp[start[key[i]] + slot[i]] = (int32_t)i;
 }
 
-__global__ void __launch_bounds__(256) k_stable_place(int64_t n, const int32_t *__restrict__ key,
-                                                      const int32_t *__restrict__ start,
-                                                      const int32_t *__restrict__ tmp, int32_t *__restrict__ perm) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int k = key[i];
-  const int lo = start[k], hi = start[k + 1];
-  int rank = 0;
-  for (int t = lo; t < hi; ++t) rank += tmp[t] < (int32_t)i;
-  perm[lo + rank] = (int32_t)i;
+__global__ void __launch_bounds__(256) k_place_buckets(int64_t nkeys, const int32_t *__restrict__ start,
+                                                       const int32_t *__restrict__ tmp, int32_t *__restrict__ perm) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= nkeys) return;
+  place_bucket(start[k], start[k + 1], tmp, perm);
 }
 
 void launch_bin(const BinBuffers &b, const Grid &g, int64_t n, const double *x, const double *y, const double *z,
@@ -181,7 +187,7 @@ void launch_bin(const BinBuffers &b, const Grid &g, int64_t n, const double *x, 
   if (n > 0) {
     const unsigned blocks = (unsigned)((n + 255) / 256);
     k_scatter_prov<<<blocks, 256, 0, st>>>(n, b.key, b.slot, cell_start, b.tmp);
-    k_stable_place<<<blocks, 256, 0, st>>>(n, b.key, cell_start, b.tmp, perm);
+    k_place_buckets<<<(unsigned)((nkeys + 255) / 256), 256, 0, st>>>(nkeys, cell_start, b.tmp, perm);
   }
 }
 

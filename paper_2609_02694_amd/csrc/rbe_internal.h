@@ -136,6 +136,50 @@ __host__ __device__ inline int64_t xcd_block(int64_t b, int64_t nb) {
 }
 
 // ---------------------------------------------------------------------------
+// Binning helpers (counting sort by cell key)
+// ---------------------------------------------------------------------------
+// Slot of this lane's particle in its key's bucket, one atomic per run of
+// equal keys in consecutive lanes (all lanes of the wave call it; lanes with
+// active = false take no slot and must carry a key no other lane has).
+__device__ inline int run_slot(int k, bool active, int32_t *count) {
+  const int lane = threadIdx.x & 63;
+  const int kp = __shfl_up(k, 1, 64);
+  const bool start = lane == 0 || kp != k;
+  const unsigned long long starts = __ballot(start);
+  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+  const int leader = 63 - __clzll((long long)(starts & upto));
+  const unsigned long long after = starts & ~upto;
+  const int next = after ? __ffsll((long long)after) - 1 : 64;
+  int base = 0;
+  if (start && active) base = atomicAdd(&count[k], next - lane);
+  base = __shfl(base, leader, 64);
+  return base + (lane - leader);
+}
+
+// One thread per bucket: copy its entries to perm, checking the order, and
+// sort them by insertion if they are out of order (entries are distinct).
+__device__ inline void place_bucket(int lo, int hi, const int32_t *__restrict__ tmp, int32_t *__restrict__ perm) {
+  bool sorted = true;
+  int32_t prev = -1;
+  for (int t = lo; t < hi; ++t) {
+    const int32_t v = tmp[t];
+    perm[t] = v;
+    sorted = sorted && v > prev;
+    prev = v;
+  }
+  if (sorted) return;
+  for (int t = lo + 1; t < hi; ++t) {
+    const int32_t v = perm[t];
+    int u = t;
+    while (u > lo && perm[u - 1] > v) {
+      perm[u] = perm[u - 1];
+      --u;
+    }
+    perm[u] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Mode tables for the sampler (host-built, copied to the device)
 // ---------------------------------------------------------------------------
 struct ModeTable {
