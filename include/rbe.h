@@ -100,7 +100,9 @@ typedef struct rbe_ctx rbe_ctx;
    `device` and allocate ALL its device scratch (cells, sorted copies, mode
    buffers, partial sums, flags). Validates *p (host): positive box, alpha,
    cutoffs <= L/2, 0 < P <= RBE_MAX_P, 1 <= p_shell <= 32 when r_core > 0,
-   r_core <= r_coul. On failure *out is NULL and the status says why. */
+   r_core <= r_coul, sqrt(alpha) r_coul <= 8, and with a ghost shell
+   max(r_coul, r_lj) <= ghost_width <= L/2 and n_max < 2^28. On failure *out
+   is NULL and the status says why. */
 int rbe_create(rbe_ctx **out, const rbe_params *p /* host */, int64_t n_max, int device);
 
 /* Batched form: n_sys independent systems ("replicas"), replica s owning

@@ -290,6 +290,8 @@ extern "C" int rbe_create(rbe_ctx **out, const rbe_params *p, int64_t n_max, int
   *out = nullptr;
   if (!p) return create_fail(RBE_EINVAL, "params is NULL");
   if (n_max < 1 || n_max > (int64_t)0x7FFFFFFF) return create_fail(RBE_EINVAL, "n_max must be in [1, 2^31)");
+  if (p && p->ghost_width > 0 && 8 * n_max >= (int64_t)0x7FFFFFFF)
+    return create_fail(RBE_EINVAL, "with a ghost shell n_max must be below 2^28 (image offsets are 32-bit)");
   std::string why;
   int rc = validate_params(p, &why);
   if (rc != RBE_OK) return create_fail(rc, why.c_str());

@@ -3,12 +3,14 @@
 // the near-field kernels can treat the box as a padded, non-periodic region
 // in which natives and ghosts share one traversal path.
 //
-// Copies are made direction by direction (x, then y, then z). Each stage
-// marks the sources near the two faces of its axis, scans the marks, and
-// appends the shifted copies; a stage's sources are the natives plus every
-// ghost made by the earlier stages, so edge and corner images arrive by
-// forwarding without diagonal copies. Only positions, charges and ids are
-// copied (the fields the near field reads); ghosts are never integrated.
+// The images are those of a staged exchange x, then y, then z in which each
+// stage also forwards the ghosts of the earlier stages (edge and corner
+// images arrive by forwarding). A native within w of a face on a set A of
+// axes (at most one face per axis, since w <= L/2) therefore has one image
+// per non-empty subset of A, shifted by one box edge along each axis of the
+// subset; they are made in one pass: count (2^|A| - 1) per native, scan,
+// write. Only positions, charges and ids are copied (the fields the near
+// field reads); ghosts are never integrated.
 //
 // The ghosts are then sorted by (species, padded cell) with the same stable
 // counting sort as the natives, on the padded grid.
@@ -16,52 +18,55 @@
 
 namespace rbe {
 
-__device__ inline double rec_coord(const double4 &r, int d) { return d == 0 ? r.x : (d == 1 ? r.y : r.z); }
-
-// flags[s] = 1 when source s lies within w of a face of axis d. Sources:
-// s < n are native records, n <= s < n + G the ghosts made so far.
-__global__ void __launch_bounds__(256) k_ghost_mark(int d, int64_t n, int64_t len, const double4 *__restrict__ xq,
-                                                    const double4 *__restrict__ graw,
-                                                    const int32_t *__restrict__ gcount, double L, double w,
-                                                    int32_t *__restrict__ flags) {
-  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (s >= len) return;
+// Face bits of a native: bit d set when coordinate d lies within w of a
+// face of axis d.
+__device__ inline int face_bits(const double4 &r, const Grid &g, double w) {
   int f = 0;
-  const int64_t G = *gcount;
-  if (s < n || s - n < G) {
-    const double c = rec_coord(s < n ? xq[s] : graw[s - n], d);
-    f = (c < w || c >= L - w) ? 1 : 0;
-  }
-  flags[s] = f;
+  if (r.x < w || r.x >= g.L[0] - w) f |= 1;
+  if (r.y < w || r.y >= g.L[1] - w) f |= 2;
+  if (r.z < w || r.z >= g.L[2] - w) f |= 4;
+  return f;
 }
 
-// Appends the shifted copy of every marked source at G + offs[s].
-__global__ void __launch_bounds__(256) k_ghost_copy(int d, int64_t n, int64_t len, int64_t cap,
-                                                    const double4 *__restrict__ xq, const int32_t *__restrict__ ids,
-                                                    double4 *__restrict__ graw, int32_t *__restrict__ gid,
-                                                    const int32_t *__restrict__ gcount,
-                                                    const int32_t *__restrict__ flags,
-                                                    const int32_t *__restrict__ offs, double L, double w, int *err) {
+// counts[s] = number of images of native s (2^|A| - 1).
+__global__ void __launch_bounds__(256) k_ghost_count(int64_t n, const double4 *__restrict__ xq, Grid g, double w,
+                                                     int32_t *__restrict__ counts) {
   const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (s >= len || !flags[s]) return;
-  const int64_t dst = (int64_t)*gcount + offs[s];
-  if (dst >= cap) {
-    atomicOr(err, kErrGhostOverflow);
-    return;
-  }
-  double4 r = s < n ? xq[s] : graw[s - n];
-  const int32_t id = s < n ? ids[s] : gid[s - n];
-  const double c = rec_coord(r, d);
-  const double shifted = c < w ? c + L : c - L;
-  if (d == 0) r.x = shifted;
-  else if (d == 1) r.y = shifted;
-  else r.z = shifted;
-  graw[dst] = r;
-  gid[dst] = id;
+  if (s >= n) return;
+  counts[s] = (1 << __popc(face_bits(xq[s], g, w))) - 1;
 }
 
-__global__ void k_ghost_count_add(int32_t *gcount, const int32_t *total, int64_t cap) {
-  const int64_t v = (int64_t)*gcount + *total;
+// Writes the images of native s at offs[s] onwards, subsets in increasing
+// bit order (x, y, xy, z, xz, yz, xyz).
+__global__ void __launch_bounds__(256) k_ghost_emit(int64_t n, int64_t cap, const double4 *__restrict__ xq,
+                                                    const int32_t *__restrict__ ids, Grid g, double w,
+                                                    const int32_t *__restrict__ offs, double4 *__restrict__ graw,
+                                                    int32_t *__restrict__ gid, int *err) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const double4 r = xq[s];
+  const int f = face_bits(r, g, w);
+  if (f == 0) return;
+  // shifted coordinate of each axis (low face: +L, high face: -L)
+  const double sx = r.x < w ? r.x + g.L[0] : r.x - g.L[0];
+  const double sy = r.y < w ? r.y + g.L[1] : r.y - g.L[1];
+  const double sz = r.z < w ? r.z + g.L[2] : r.z - g.L[2];
+  int64_t dst = offs[s];
+  for (int sub = 1; sub < 8; ++sub) {
+    if ((sub & f) != sub) continue;
+    if (dst < 0 || dst >= cap) {
+      atomicOr(err, kErrGhostOverflow);
+      return;
+    }
+    graw[dst] = make_double4((sub & 1) ? sx : r.x, (sub & 2) ? sy : r.y, (sub & 4) ? sz : r.z, r.w);
+    gid[dst] = ids[s];
+    ++dst;
+  }
+}
+
+// ghost count = min(total images, capacity)
+__global__ void k_ghost_total(int32_t *gcount, const int32_t *total, int64_t cap) {
+  const int64_t v = *total;
   *gcount = (int32_t)(v < cap ? v : cap);
 }
 
@@ -120,16 +125,12 @@ void launch_build_ghosts(const Grid &g, int64_t n, const Sorted &s, const GhostB
                          hipStream_t st) {
   launch_fill_i32(gb.count, 1, 0, st);
   const double w = g.ghost_width;
-  for (int d = 0; d < 3; ++d) {
-    // stage 0 reads the natives only; later stages also the ghosts made so far
-    const int64_t len = d == 0 ? n : n + gb.cap;
-    if (len <= 0) continue;
-    const unsigned blocks = (unsigned)((len + 255) / 256);
-    k_ghost_mark<<<blocks, 256, 0, st>>>(d, n, len, s.xq, gb.raw_xq, gb.count, g.L[d], w, gb.flags);
-    launch_exclusive_scan(gb.flags, len, gb.offs, gb.scan_tmp, st);
-    k_ghost_copy<<<blocks, 256, 0, st>>>(d, n, len, gb.cap, s.xq, s.id, gb.raw_xq, gb.raw_id, gb.count, gb.flags,
-                                         gb.offs, g.L[d], w, err);
-    k_ghost_count_add<<<1, 1, 0, st>>>(gb.count, gb.offs + len, gb.cap);
+  if (n > 0) {
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    k_ghost_count<<<blocks, 256, 0, st>>>(n, s.xq, g, w, gb.flags);
+    launch_exclusive_scan(gb.flags, n, gb.offs, gb.scan_tmp, st);
+    k_ghost_emit<<<blocks, 256, 0, st>>>(n, gb.cap, s.xq, s.id, g, w, gb.offs, gb.raw_xq, gb.raw_id, err);
+    k_ghost_total<<<1, 1, 0, st>>>(gb.count, gb.offs + n, gb.cap);
   }
   // sort by (species, padded cell)
   const int64_t nkeys = 2 * (int64_t)g.pncell;
