@@ -83,14 +83,20 @@ __global__ void __launch_bounds__(256) k_ghost_keys(int64_t cap, const int32_t *
                                                     int32_t *__restrict__ key, int32_t *__restrict__ slot,
                                                     int32_t *__restrict__ count) {
   const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (k >= cap || k >= *gcount) return;
-  const double4 r = graw[k];
-  const int cx = padded_coord(r.x, g.inv_h[0], g.goff[0], g.pnx);
-  const int cy = padded_coord(r.y, g.inv_h[1], g.goff[1], g.pny);
-  const int cz = padded_coord(r.z, g.inv_h[2], g.goff[2], g.pnz);
-  const int kk = (r.w == 0.0 ? g.pncell : 0) + (cz * g.pny + cy) * g.pnx + cx;
-  key[k] = kk;
-  slot[k] = atomicAdd(&count[kk], 1);
+  const int64_t n = min(cap, (int64_t)*gcount);
+  if (k - (threadIdx.x & 63) >= n) return;  // whole wave past the end
+  const bool active = k < n;
+  int kk = -1 - (int)(threadIdx.x & 63);  // lanes past the end: a key no other lane has
+  if (active) {
+    const double4 r = graw[k];
+    const int cx = padded_coord(r.x, g.inv_h[0], g.goff[0], g.pnx);
+    const int cy = padded_coord(r.y, g.inv_h[1], g.goff[1], g.pny);
+    const int cz = padded_coord(r.z, g.inv_h[2], g.goff[2], g.pnz);
+    kk = (r.w == 0.0 ? g.pncell : 0) + (cz * g.pny + cy) * g.pnx + cx;
+    key[k] = kk;
+  }
+  const int sl = run_slot(kk, active, count);  // every lane of the wave takes part
+  if (active) slot[k] = sl;
 }
 
 __global__ void __launch_bounds__(256) k_ghost_scatter(int64_t cap, const int32_t *__restrict__ gcount,
@@ -102,23 +108,25 @@ __global__ void __launch_bounds__(256) k_ghost_scatter(int64_t cap, const int32_
   tmp[start[key[k]] + slot[k]] = (int32_t)k;
 }
 
-// Stable placement and gather in one pass: slot = start[key] + number of
-// bucket members with a smaller ghost index.
-__global__ void __launch_bounds__(256) k_ghost_place(int64_t cap, const int32_t *__restrict__ gcount,
-                                                     const int32_t *__restrict__ key,
-                                                     const int32_t *__restrict__ start,
-                                                     const int32_t *__restrict__ tmp,
-                                                     const double4 *__restrict__ graw,
-                                                     const int32_t *__restrict__ gid_raw, double4 *__restrict__ gxq,
-                                                     int32_t *__restrict__ gid) {
-  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (k >= cap || k >= *gcount) return;
-  const int b = key[k];
-  const int lo = start[b], hi = start[b + 1];
-  int rank = 0;
-  for (int t = lo; t < hi; ++t) rank += tmp[t] < (int32_t)k;
-  gxq[lo + rank] = graw[k];
-  gid[lo + rank] = gid_raw[k];
+// Stable placement per bucket (entries in increasing creation order), then
+// the gather of the records into that order.
+__global__ void __launch_bounds__(256) k_ghost_buckets(int64_t nkeys, const int32_t *__restrict__ start,
+                                                       const int32_t *__restrict__ tmp, int32_t *__restrict__ perm) {
+  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (b >= nkeys) return;
+  place_bucket(start[b], start[b + 1], tmp, perm);
+}
+
+__global__ void __launch_bounds__(256) k_ghost_gather(int64_t cap, const int32_t *__restrict__ gcount,
+                                                      const int32_t *__restrict__ perm,
+                                                      const double4 *__restrict__ graw,
+                                                      const int32_t *__restrict__ gid_raw, double4 *__restrict__ gxq,
+                                                      int32_t *__restrict__ gid) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= cap || t >= *gcount) return;
+  const int k = perm[t];
+  gxq[t] = graw[k];
+  gid[t] = gid_raw[k];
 }
 
 void launch_build_ghosts(const Grid &g, int64_t n, const Sorted &s, const GhostBuffers &gb, int *err,
@@ -139,8 +147,9 @@ void launch_build_ghosts(const Grid &g, int64_t n, const Sorted &s, const GhostB
   k_ghost_keys<<<cblocks, 256, 0, st>>>(gb.cap, gb.count, gb.raw_xq, g, gb.key, gb.slot, gb.cell_count);
   launch_exclusive_scan(gb.cell_count, nkeys, gb.cell_start, gb.cell_scan_tmp, st);
   k_ghost_scatter<<<cblocks, 256, 0, st>>>(gb.cap, gb.count, gb.key, gb.slot, gb.cell_start, gb.tmp);
-  k_ghost_place<<<cblocks, 256, 0, st>>>(gb.cap, gb.count, gb.key, gb.cell_start, gb.tmp, gb.raw_xq, gb.raw_id,
-                                         gb.xq, gb.id);
+  // the keys are no longer needed: their array receives the placement
+  k_ghost_buckets<<<(unsigned)((nkeys + 255) / 256), 256, 0, st>>>(nkeys, gb.cell_start, gb.tmp, gb.key);
+  k_ghost_gather<<<cblocks, 256, 0, st>>>(gb.cap, gb.count, gb.key, gb.raw_xq, gb.raw_id, gb.xq, gb.id);
 }
 
 }  // namespace rbe
