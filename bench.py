@@ -246,23 +246,26 @@ def bench_batch(a):
 
     # comparison forms (same replicas, same grids): per-replica loops of
     # single-system contexts in FP64 and FP32C, and the batched form in FP64
-    def loop_rate(pr):
+    def loop_rate(pr, steps):
+        """particle-steps/s of a loop of single-system contexts (0 steps: only the
+        pair counts of one evaluation, FP64 contexts)."""
         ctxs, sts = [], []
         for (p, s) in reps:
             n = max(1, int(p["L"] // edge))
             ctxs.append(rbe.Context(rbe.params_from_preset(p, prec=pr, ncell=(n, n, n), seed=p["stream_seed"]),
                                     p["n"]))
             sts.append(rbe.Particles.from_numpy(s))
-        for c, s_ in zip(ctxs, sts):
-            c.forces(s_, None, None, 0)
-            c.step(s_, 2, 1)
-        torch.cuda.synchronize()
-        Kc = max(2, a.compare_steps // 5)
-        t = time.perf_counter()
-        for c, s_ in zip(ctxs, sts):
-            c.step(s_, Kc, 3)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t
+        rate = None
+        if steps > 0:
+            for c, s_ in zip(ctxs, sts):
+                c.forces(s_, None, None, 0)
+                c.step(s_, 2, 1)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for c, s_ in zip(ctxs, sts):
+                c.step(s_, steps, 3)
+            torch.cuda.synchronize()
+            rate = ntot * steps / (time.perf_counter() - t)
         counts = None
         if pr == rbe.FP64:
             counts = [0, 0, 0, 0]
@@ -275,18 +278,18 @@ def bench_batch(a):
         for c in ctxs:
             c.sync_check()
             c.close()
-        return ntot * Kc / dt, counts
+        return rate, counts
 
-    v64_loop, counts = loop_rate(rbe.FP64)
-    v32_loop, _ = loop_rate(rbe.FP32C)
-    other = rbe.FP64 if prec == rbe.FP32C else rbe.FP32C
-    ms_other = tune.time_batch(reps, cat, off, edge, other, steps=a.compare_steps)
-    forms = {
-        f"batched_{prec_name}": value,
-        f"batched_{'fp64' if other == rbe.FP64 else 'fp32c'}": ntot / (ms_other * 1e-3),
-        "loop_fp64": v64_loop,
-        "loop_fp32c": v32_loop,
-    }
+    Kc = max(2, a.compare_steps // 5) if a.compare_steps > 0 else 0
+    v64_loop, counts = loop_rate(rbe.FP64, Kc)
+    forms = {f"batched_{prec_name}": value}
+    if a.compare_steps > 0:
+        v32_loop, _ = loop_rate(rbe.FP32C, Kc)
+        other = rbe.FP64 if prec == rbe.FP32C else rbe.FP32C
+        ms_other = tune.time_batch(reps, cat, off, edge, other, steps=a.compare_steps)
+        forms[f"batched_{'fp64' if other == rbe.FP64 else 'fp32c'}"] = ntot / (ms_other * 1e-3)
+        forms["loop_fp64"] = v64_loop
+        forms["loop_fp32c"] = v32_loop
     nq = int(np.count_nonzero(cat["q"]))
     P = reps[0][0]["P"]
     roof = None
