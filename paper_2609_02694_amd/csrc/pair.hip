@@ -54,14 +54,16 @@ struct PairCtx {
   const int32_t *__restrict__ gcell_start;
 };
 
-// Walk of one species block for a row group.
+// Cluster walk of one species block for a row group.
 template <bool GHOST, bool WITH_ID, class Fn>
 __device__ inline void walk(const PairCtx &c, int blk, int xa, int xb, int cy, int cz, int s, int b, Fn &&fn) {
+  auto no_tick = []() {};
   if (GHOST)
     cluster_walk_ghost<WITH_ID>(c.pp.g, c.cell_start, c.xq, c.ids, c.gcell_start, c.gxq, c.gid, blk, xa, xb, cy, cz,
-                                s, b, fn);
+                                s, b, fn, no_tick);
   else
-    cluster_walk<WITH_ID>(c.pp.g, c.cell_start, c.xq, c.ids, (int64_t)blk * c.pp.g.ncell, xa, xb, cy, cz, s, b, fn);
+    cluster_walk<WITH_ID>(c.pp.g, c.cell_start, c.xq, c.ids, (int64_t)blk * c.pp.g.ncell, xa, xb, cy, cz, s, b, fn,
+                          no_tick);
 }
 
 template <bool COUNT>
@@ -197,28 +199,28 @@ __global__ void __launch_bounds__(64) k_pair_rbl(PairCtx c) {
       if (s < kShellCap) kbuf[I.a * kShellCap + s] = k;
     }
   };
-  auto visit = [&](int j, const double4 &pj, int idj, double shx, double shy, double shz) {
-    if (!in_group) return;
+  auto visit = [&](bool ok, int j, const double4 &pj, int idj, double shx, double shy, double shz) {
     const double dx = (I.xi - pj.x) - shx, dy = (I.yi - pj.y) - shy, dz = (I.zi - pj.z) - shz;
     const double r2 = sq_dist(dx, dy, dz);
-    if (COUNT) ++n_tested;
-    if (r2 == 0.0 && j == (int)I.i) return;
-    if (r2 <= pp.rcore2) {
-      acc.template add<true>(pp, c.pf, r2, I.qi, pj.w, dx, dy, dz);
+    // flat predicates (bitwise, so no branch per condition)
+    const bool live = ok & in_group & ((r2 != 0.0) | (j != (int)I.i));
+    const bool core = live & (r2 <= pp.rcore2);
+    const bool shell = live & (r2 > pp.rcore2) & (r2 <= pp.rc2);
+    if (COUNT) n_tested += ok & in_group;
+    if (core) {
+      acc.template add<true, true>(pp, c.pf, r2, I.qi, pj.w, dx, dy, dz);
       if (COUNT) {
         n_coul += (pp.do_coul && I.qi != 0.0 && pj.w != 0.0);
         n_lj += (pp.do_lj && r2 <= pp.rlj2);
       }
-    } else if (r2 <= pp.rc2) {
-      ++ns;
-      collect(shell_rank(sk, idj));
     }
+    ns += shell;
+    if (shell) collect(shell_rank(sk, idj));
   };
-  auto visit_collect = [&](int, const double4 &pj, int idj, double shx, double shy, double shz) {
-    if (!in_group) return;
+  auto visit_collect = [&](bool ok, int, const double4 &pj, int idj, double shx, double shy, double shz) {
     const double dx = (I.xi - pj.x) - shx, dy = (I.yi - pj.y) - shy, dz = (I.zi - pj.z) - shz;
     const double r2 = sq_dist(dx, dy, dz);
-    if (r2 > pp.rcore2 && r2 <= pp.rc2) collect(shell_rank(sk, idj));
+    if (ok & in_group & (r2 > pp.rcore2) & (r2 <= pp.rc2)) collect(shell_rank(sk, idj));
   };
   const int64_t rowkey = (int64_t)I.cz * g.ny + I.cy;
   auto walk_all = [&](bool active, auto &&fn) {

@@ -6,34 +6,77 @@
 
 namespace rbe {
 
+// Coefficients of the FP64 polynomials below, highest degree first.
+#define RBE_ERFCX_COEFS \
+    1.63618628481317543e-08, -4.60928758649811430e-08, -6.88442333452307132e-08, \
+    4.40190654889049080e-07, -4.46917185831068957e-07, -1.14063358111397811e-06, \
+    3.75537844601685302e-06, -1.41703053499259700e-06, -1.39602653735770222e-05, \
+    2.75867068654632672e-05, 2.75241444094816018e-05, -1.74362281120596591e-04, \
+    4.35557661104548185e-05, 9.81977137355043118e-04, -8.47143262890503600e-04, \
+    -6.99746174546772310e-03, 3.73289240473987467e-03, 7.89785810158994406e-02, \
+    2.41658194242463487e-01, 4.27185847413955655e-01, 2.55395676310504194e-01
+#define RBE_EXP_COEFS \
+    1.1470745597729725e-11, 1.6059043836821613e-10, 2.08767569878681e-09, 2.505210838544172e-08, \
+    2.755731922398589e-07, 2.7557319223985893e-06, 2.48015873015873e-05, 0.0001984126984126984, \
+    0.001388888888888889, 0.008333333333333333, 0.041666666666666664, 0.16666666666666666, 0.5, 1.0, \
+    1.0
+constexpr double kErfcxCoef[] = {RBE_ERFCX_COEFS};
+constexpr double kExpCoef[] = {RBE_EXP_COEFS};
+constexpr int kErfcxTerms = (int)(sizeof(kErfcxCoef) / sizeof(double));
+constexpr int kExpTerms = (int)(sizeof(kExpCoef) / sizeof(double));
+// The same coefficients in constant memory, for kernels that evaluate the
+// pair scalar in a branch most trips of a neighbour walk skip: read there
+// with scalar loads at an opaque offset, so the compiler cannot keep the
+// whole table in vector registers for the walk (it did, costing a wave of
+// occupancy).
+static __constant__ double kErfcxTable[kErfcxTerms] = {RBE_ERFCX_COEFS};
+static __constant__ double kExpTable[kExpTerms] = {RBE_EXP_COEFS};
+__device__ inline int opaque_zero() {
+  int z;
+  asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+  return z;
+}
+// d = a b + c as one v_fma_f64 with c in vector (fma_vv) or scalar (fma_vs)
+// registers; plain fma() here becomes v_fmac with the addend copied into the
+// destination first, two or three instructions per polynomial step.
+__device__ inline double fma_vv(double a, double b, double c) {
+  double d;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+  return d;
+}
+__device__ inline double fma_vs(double a, double b, double c) {
+  double d;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(c));
+  return d;
+}
+// Horner evaluation of a coefficient list at x (TABLE: from constant memory).
+template <bool TABLE, int N>
+__device__ inline double horner_f64(const double (&coef)[N], const double *table, double x) {
+  if constexpr (TABLE) {
+    const double *t = table + opaque_zero();
+    double c[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) c[k] = t[k];  // issued together, merged into wide scalar loads
+    double r = c[0];
+#pragma unroll
+    for (int k = 1; k < N; ++k) r = fma_vs(r, x, c[k]);
+    return r;
+  } else {
+    double r = coef[0];
+#pragma unroll
+    for (int k = 1; k < N; ++k) r = fma_vv(r, x, coef[k]);
+    return r;
+  }
+}
+
 // FP64 erfc(x) = exp(-x^2) R(x) with R(x) = erfc(x) e^{x^2} a degree-20
 // polynomial in s = 2/(1 + x/2) - 1 (fit over x in [0, 8] by fit_erfcx.py,
 // relative error below 7.2e-15); e = exp(-x^2) is passed in.
 __device__ inline double rcp_f64(double a);
+template <bool TABLE>
 __device__ inline double erfc_scaled_f64(double x) {
   const double s = fma(2.0, rcp_f64(fma(0.5, x, 1.0)), -1.0);
-  double r = 1.63618628481317543e-08;
-  r = fma(r, s, -4.60928758649811430e-08);
-  r = fma(r, s, -6.88442333452307132e-08);
-  r = fma(r, s, 4.40190654889049080e-07);
-  r = fma(r, s, -4.46917185831068957e-07);
-  r = fma(r, s, -1.14063358111397811e-06);
-  r = fma(r, s, 3.75537844601685302e-06);
-  r = fma(r, s, -1.41703053499259700e-06);
-  r = fma(r, s, -1.39602653735770222e-05);
-  r = fma(r, s, 2.75867068654632672e-05);
-  r = fma(r, s, 2.75241444094816018e-05);
-  r = fma(r, s, -1.74362281120596591e-04);
-  r = fma(r, s, 4.35557661104548185e-05);
-  r = fma(r, s, 9.81977137355043118e-04);
-  r = fma(r, s, -8.47143262890503600e-04);
-  r = fma(r, s, -6.99746174546772310e-03);
-  r = fma(r, s, 3.73289240473987467e-03);
-  r = fma(r, s, 7.89785810158994406e-02);
-  r = fma(r, s, 2.41658194242463487e-01);
-  r = fma(r, s, 4.27185847413955655e-01);
-  r = fma(r, s, 2.55395676310504194e-01);
-  return r;
+  return horner_f64<TABLE>(kErfcxCoef, kErfcxTable, s);
 }
 
 // FP64 building blocks of the pair scalar: hardware reciprocal and
@@ -57,36 +100,23 @@ __device__ inline double rsqrt_f64(double a) {
   e = fma(-a * y, y, 1.0);
   return fma(0.5 * y, e, y);
 }
+template <bool TABLE>
 __device__ inline double exp_nonpos_f64(double x) {
   const double k = rint(x * 1.4426950408889634);
   double t = fma(-k, 0.6931471803691238, x);
   t = fma(-k, 1.9082149292705877e-10, t);
-  double p = 1.1470745597729725e-11;
-  p = fma(p, t, 1.6059043836821613e-10);
-  p = fma(p, t, 2.08767569878681e-09);
-  p = fma(p, t, 2.505210838544172e-08);
-  p = fma(p, t, 2.755731922398589e-07);
-  p = fma(p, t, 2.7557319223985893e-06);
-  p = fma(p, t, 2.48015873015873e-05);
-  p = fma(p, t, 0.0001984126984126984);
-  p = fma(p, t, 0.001388888888888889);
-  p = fma(p, t, 0.008333333333333333);
-  p = fma(p, t, 0.041666666666666664);
-  p = fma(p, t, 0.16666666666666666);
-  p = fma(p, t, 0.5);
-  p = fma(p, t, 1.0);
-  p = fma(p, t, 1.0);
-  return ldexp(p, (int)k);
+  return ldexp(horner_f64<TABLE>(kExpCoef, kExpTable, t), (int)k);
 }
 
+template <bool TABLE = false>
 __device__ inline double pair_scalar_f64(const PairParams &pp, double r2, double qi, double qj) {
   const double rinv = rsqrt_f64(r2);
   const double inv_r2 = rinv * rinv;
   double f = 0.0;
   if (pp.do_coul && r2 <= pp.rc2 && qi != 0.0 && qj != 0.0) {
     const double r = r2 * rinv;
-    const double e = exp_nonpos_f64(-pp.alpha * r2);
-    const double R = erfc_scaled_f64(pp.sqrt_alpha * r);
+    const double e = exp_nonpos_f64<TABLE>(-pp.alpha * r2);
+    const double R = erfc_scaled_f64<TABLE>(pp.sqrt_alpha * r);
     // G = erfc(x)/r^3 + 2 sqrt(a) e/(sqrt(pi) r^2) = e/r^2 (R/r + 2 sqrt(a)/sqrt(pi))
     const double G = e * inv_r2 * fma(R, rinv, pp.two_sqrt_alpha_over_sqrt_pi);
     f = pp.kc * qi * qj * G;
@@ -327,16 +357,17 @@ __device__ inline void for_stencil_ghost(const Grid &g, const int32_t *__restric
 }
 
 // Accumulator of the per-particle force in the two precision forms.
-// add<true> evaluates Coulomb + LJ, add<false> LJ only (j neutral).
+// add<true> evaluates Coulomb + LJ, add<false> LJ only (j neutral); TABLE
+// selects the constant-memory polynomial coefficients (FP64 form).
 template <bool F32>
 struct ForceAcc;
 template <>
 struct ForceAcc<false> {
   double v[3] = {0.0, 0.0, 0.0};
-  template <bool COUL>
+  template <bool COUL, bool TABLE = false>
   __device__ inline void add(const PairParams &pp, const PairF32 &, double r2, double qi, double qj, double dx,
                              double dy, double dz) {
-    const double sc = COUL ? pair_scalar_f64(pp, r2, qi, qj) : pair_scalar_lj_f64(pp, r2);
+    const double sc = COUL ? pair_scalar_f64<TABLE>(pp, r2, qi, qj) : pair_scalar_lj_f64(pp, r2);
     v[0] = fma(sc, dx, v[0]);
     v[1] = fma(sc, dy, v[1]);
     v[2] = fma(sc, dz, v[2]);
@@ -346,7 +377,7 @@ struct ForceAcc<false> {
 template <>
 struct ForceAcc<true> {
   Kahan3 k;
-  template <bool COUL>
+  template <bool COUL, bool TABLE = false>
   __device__ inline void add(const PairParams &pp, const PairF32 &pf, double r2, double qi, double qj, double dx,
                              double dy, double dz) {
     const float sc = COUL ? pair_scalar_f32(pp, pf, r2, (float)(qi * qj)) : pair_scalar_lj_f32(pp, pf, r2);
@@ -376,26 +407,54 @@ namespace rbe {
 constexpr int kCI = 8;
 constexpr int kCJ = 8;
 
-// fn(j, p_j, id_j, shx, shy, shz) for the records j0..j1-1 taken by this
-// lane (j = j0 + b, j0 + b + kCJ, ...), one record prefetched ahead. The
-// trip count depends only on j0, j1, so the loop is the same for the wave.
-template <bool WITH_ID, class Fn>
+// Buffer resource over `bytes` bytes at p (gfx9 raw buffer, no stride):
+// loads that start past the end return zeros instead of touching memory.
+__device__ inline __amdgpu_buffer_rsrc_t bounded_rsrc(const void *p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, bytes, 0x00020000);
+}
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ inline double dword_pair(uint32_t lo, uint32_t hi) {
+  return __builtin_bit_cast(double, (uint64_t)lo | ((uint64_t)hi << 32));
+}
+// Record k of a segment (zeros past its end).
+__device__ inline double4 load_record(__amdgpu_buffer_rsrc_t r, int k) {
+  const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, k * 32, 0, 0);
+  const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(r, k * 32 + 16, 0, 0);
+  return make_double4(dword_pair(a.x, a.y), dword_pair(a.z, a.w), dword_pair(c.x, c.y), dword_pair(c.z, c.w));
+}
+
+// fn(ok, j, p_j, id_j, shx, shy, shz) for the records j0..j1-1 taken by this
+// lane (j = j0 + b, j0 + b + kCJ, ...; ok = false on trips where this lane's
+// j is past j1), one record prefetched ahead, then tick() once per trip with
+// the whole wave. The trip count depends only on j0, j1, so the loop is the
+// same for the wave; the segment is read through bounded buffer loads, so the
+// lookahead needs no clamping.
+template <bool WITH_ID, class Fn, class Tick>
 __device__ inline void scan_cluster(const double4 *__restrict__ xq, const int32_t *__restrict__ ids, int j0, int j1,
-                                    int b, double shx, double shy, double shz, Fn &&fn) {
+                                    int b, double shx, double shy, double shz, Fn &&fn, Tick &&tick) {
+  j0 = __builtin_amdgcn_readfirstlane(j0);  // uniform by construction; tell the compiler
+  j1 = __builtin_amdgcn_readfirstlane(j1);
   if (j0 >= j1) return;
-  const int last = j1 - 1;
-  int j = j0 + b;
-  double4 r = xq[min(j, last)];
-  int d = WITH_ID ? ids[min(j, last)] : 0;
+  const int cnt = j1 - j0;
+  const __amdgpu_buffer_rsrc_t rx = bounded_rsrc(xq + j0, cnt * (int)sizeof(double4));
+  const __amdgpu_buffer_rsrc_t ri = bounded_rsrc(WITH_ID ? ids + j0 : ids, WITH_ID ? cnt * 4 : 0);
+  auto load_id = [&](int k) { return WITH_ID ? (int)__builtin_amdgcn_raw_buffer_load_b32(ri, k * 4, 0, 0) : 0; };
+  int k = b;
+  double4 r0 = load_record(rx, k);
+  int d0 = load_id(k);
 #pragma unroll 1
-  for (int base = j0; base < j1; base += kCJ) {
-    const int jn = j + kCJ;
-    const double4 rn = xq[min(jn, last)];
-    const int dn = WITH_ID ? ids[min(jn, last)] : 0;
-    if (j < j1) fn(j, r, d, shx, shy, shz);
-    r = rn;
-    d = dn;
-    j = jn;
+  for (int base = 0;; base += 2 * kCJ) {
+    const double4 r1 = load_record(rx, k + kCJ);
+    const int d1 = load_id(k + kCJ);
+    fn(k < cnt, j0 + k, r0, d0, shx, shy, shz);
+    tick();
+    if (base + kCJ >= cnt) break;
+    r0 = load_record(rx, k + 2 * kCJ);
+    d0 = load_id(k + 2 * kCJ);
+    fn(k + kCJ < cnt, j0 + k + kCJ, r1, d1, shx, shy, shz);
+    tick();
+    if (base + 2 * kCJ >= cnt) break;
+    k += 2 * kCJ;
   }
 }
 
@@ -403,10 +462,10 @@ __device__ inline void scan_cluster(const double4 *__restrict__ xq, const int32_
 // group: rows (cy + oy, cz + oz), |oy|, |oz| <= s, x from xa - s to xb + s,
 // each row split where it crosses the periodic boundary (a cell met twice is
 // met with two different image shifts, so no image is counted twice).
-template <bool WITH_ID, class Fn>
+template <bool WITH_ID, class Fn, class Tick>
 __device__ inline void cluster_walk(const Grid &g, const int32_t *__restrict__ cell_start,
                                     const double4 *__restrict__ xq, const int32_t *__restrict__ ids, int64_t base,
-                                    int xa, int xb, int cy, int cz, int s, int b, Fn &&fn) {
+                                    int xa, int xb, int cy, int cz, int s, int b, Fn &&fn, Tick &&tick) {
   for (int oz = -s; oz <= s; ++oz) {
     const int az = cz + oz;
     const int qz = floor_div(az, g.nz);
@@ -425,7 +484,7 @@ __device__ inline void cluster_walk(const Grid &g, const int32_t *__restrict__ c
         const int xe = min(x_end, (qx + 1) * g.nx - 1);
         const int j0 = cell_start[row + (x - qx * g.nx)];
         const int j1 = cell_start[row + (xe - qx * g.nx) + 1];
-        scan_cluster<WITH_ID>(xq, ids, j0, j1, b, (double)qx * g.L[0], shy, shz, fn);
+        scan_cluster<WITH_ID>(xq, ids, j0, j1, b, (double)qx * g.L[0], shy, shz, fn, tick);
         x = xe + 1;
       }
     }
@@ -434,12 +493,12 @@ __device__ inline void cluster_walk(const Grid &g, const int32_t *__restrict__ c
 
 // Ghost-shell walk (no periodic images): the native part of each stencil row
 // clipped to the native grid, then the same row of the padded ghost grid.
-template <bool WITH_ID, class Fn>
+template <bool WITH_ID, class Fn, class Tick>
 __device__ inline void cluster_walk_ghost(const Grid &g, const int32_t *__restrict__ cell_start,
                                           const double4 *__restrict__ xq, const int32_t *__restrict__ ids,
                                           const int32_t *__restrict__ gcell_start, const double4 *__restrict__ gxq,
                                           const int32_t *__restrict__ gid, int blk, int xa, int xb, int cy, int cz,
-                                          int s, int b, Fn &&fn) {
+                                          int s, int b, Fn &&fn, Tick &&tick) {
   const int64_t base = (int64_t)blk * g.ncell;
   const int64_t pbase = (int64_t)blk * g.pncell;
   const int na = max(xa - s, 0), nb = min(xb + s, g.nx - 1);
@@ -449,11 +508,11 @@ __device__ inline void cluster_walk_ghost(const Grid &g, const int32_t *__restri
       const int y = cy + oy;
       if (z >= 0 && z < g.nz && y >= 0 && y < g.ny) {
         const int64_t row = base + (int64_t)(z * g.ny + y) * g.nx;
-        scan_cluster<WITH_ID>(xq, ids, cell_start[row + na], cell_start[row + nb + 1], b, 0.0, 0.0, 0.0, fn);
+        scan_cluster<WITH_ID>(xq, ids, cell_start[row + na], cell_start[row + nb + 1], b, 0.0, 0.0, 0.0, fn, tick);
       }
       const int64_t prow = pbase + (int64_t)((z + g.goff[2]) * g.pny + (y + g.goff[1])) * g.pnx + g.goff[0];
       scan_cluster<WITH_ID>(gxq, gid, gcell_start[prow + xa - s], gcell_start[prow + xb + s + 1], b, 0.0, 0.0, 0.0,
-                            fn);
+                            fn, tick);
     }
   }
 }
