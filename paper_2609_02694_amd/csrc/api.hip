@@ -358,9 +358,9 @@ extern "C" int rbe_create(rbe_ctx **out, const rbe_params *p, int64_t n_max, int
   c->cell_start = b.alloc<int32_t>(nkeys + 1);
   c->perm = b.alloc<int32_t>(n_max);
   c->inv_id = b.alloc<int32_t>(n_max);
-  c->srt.xq = b.alloc<double4>(n_max);
+  c->srt.xq = b.alloc<double4>(n_max + kScanPad);
   c->srt.sq = b.alloc<double4>(n_max);
-  c->srt.id = b.alloc<int32_t>(n_max);
+  c->srt.id = b.alloc<int32_t>(n_max + kScanPad);
   for (int s = 0; s < 2; ++s) {
     WorkSet &w = c->ws[s];
     w.x = b.alloc<double>(n_max);
@@ -404,8 +404,8 @@ extern "C" int rbe_create(rbe_ctx **out, const rbe_params *p, int64_t n_max, int
     const int64_t pkeys = 2 * (int64_t)g.pncell;
     gb.raw_xq = b.alloc<double4>(cap);
     gb.raw_id = b.alloc<int32_t>(cap);
-    gb.xq = b.alloc<double4>(cap);
-    gb.id = b.alloc<int32_t>(cap);
+    gb.xq = b.alloc<double4>(cap + kScanPad);
+    gb.id = b.alloc<int32_t>(cap + kScanPad);
     gb.cell_start = b.alloc<int32_t>(pkeys + 1);
     gb.cell_count = b.alloc<int32_t>(pkeys);
     gb.cell_scan_tmp = b.alloc<int32_t>(scan_tiles(pkeys));
@@ -548,9 +548,9 @@ extern "C" int rbe_create_batch(rbe_ctx **out, int32_t n_sys, const rbe_params *
     w.fz = b.alloc<double>(n);
     w.id = b.alloc<int32_t>(n);
   }
-  c->srt.xq = b.alloc<double4>(n);
+  c->srt.xq = b.alloc<double4>(n + kScanPad);
   c->srt.sq = b.alloc<double4>(n);
-  c->srt.id = b.alloc<int32_t>(n);
+  c->srt.id = b.alloc<int32_t>(n + kScanPad);
   c->perm = b.alloc<int32_t>(n);
   c->cell_start = b.alloc<int32_t>(B.nkeys + 1);
   c->cdf_dev = b.alloc<double>((int64_t)cdf_all.size());

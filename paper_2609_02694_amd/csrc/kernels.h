@@ -93,6 +93,10 @@ PairF32 make_pair_f32(const PairParams &pp);
 // the first threshold (about 3p keys below it for the mean shell of n
 // particles in the box; 2^32 = all keys when shells are small).
 constexpr int kShellCap = 128;
+// Records of padding after every particle array a thread-form neighbour
+// scan reads (sorted natives, ghosts, batch): its lookahead loads may run
+// up to this many records minus one past the end of a range.
+constexpr int kScanPad = 8;
 uint64_t shell_first_threshold(const PairParams &pp, int64_t n);
 struct PairCounters {
   unsigned long long *c;  // [4] or nullptr

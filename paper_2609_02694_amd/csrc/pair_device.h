@@ -220,35 +220,40 @@ __device__ inline double min_image(double a, double L) {
 // Calls fn(j, p_j, id_j, shx, shy, shz) for the records j0..j1-1 of xq (and
 // ids when WITH_ID, else id_j = 0). Four fixed slots: slot k holds record
 // j + k and is reloaded with j + k + 4 right after use, so each load has
-// three candidates of work to complete behind it. Indices past the range are
-// clamped to its last record (always a valid address).
+// three candidates of work to complete behind it. The lookahead reads up to
+// kScanPad - 1 records past j1: every array scanned here is allocated with
+// kScanPad records of padding, so those loads stay inside the allocation
+// (their values are never used), and the addresses are plain increments.
 template <bool WITH_ID, class Fn>
 __device__ inline void scan_range(const double4 *__restrict__ xq, const int32_t *__restrict__ ids, int j0, int j1,
                                   double shx, double shy, double shz, Fn &&fn) {
   if (j0 >= j1) return;
-  const int last = j1 - 1;
-  double4 r0 = xq[j0], r1 = xq[min(j0 + 1, last)], r2 = xq[min(j0 + 2, last)], r3 = xq[min(j0 + 3, last)];
+  const double4 *p = xq + j0;
+  const int32_t *q = WITH_ID ? ids + j0 : ids;
+  double4 r0 = p[0], r1 = p[1], r2 = p[2], r3 = p[3];
   int d0 = 0, d1 = 0, d2 = 0, d3 = 0;
   if (WITH_ID) {
-    d0 = ids[j0];
-    d1 = ids[min(j0 + 1, last)];
-    d2 = ids[min(j0 + 2, last)];
-    d3 = ids[min(j0 + 3, last)];
+    d0 = q[0];
+    d1 = q[1];
+    d2 = q[2];
+    d3 = q[3];
   }
 #pragma unroll 1
   for (int j = j0; j < j1; j += 4) {
     fn(j, r0, d0, shx, shy, shz);
-    r0 = xq[min(j + 4, last)];
-    if (WITH_ID) d0 = ids[min(j + 4, last)];
+    r0 = p[4];
+    if (WITH_ID) d0 = q[4];
     if (j + 1 < j1) fn(j + 1, r1, d1, shx, shy, shz);
-    r1 = xq[min(j + 5, last)];
-    if (WITH_ID) d1 = ids[min(j + 5, last)];
+    r1 = p[5];
+    if (WITH_ID) d1 = q[5];
     if (j + 2 < j1) fn(j + 2, r2, d2, shx, shy, shz);
-    r2 = xq[min(j + 6, last)];
-    if (WITH_ID) d2 = ids[min(j + 6, last)];
+    r2 = p[6];
+    if (WITH_ID) d2 = q[6];
     if (j + 3 < j1) fn(j + 3, r3, d3, shx, shy, shz);
-    r3 = xq[min(j + 7, last)];
-    if (WITH_ID) d3 = ids[min(j + 7, last)];
+    r3 = p[7];
+    if (WITH_ID) d3 = q[7];
+    p += 4;
+    if (WITH_ID) q += 4;
   }
 }
 
