@@ -40,8 +40,10 @@ FLOPS_GATHER_IK = 18
 BYTES_KICK_DRIFT = 120   # read f (24) v (24) x (24), write v (24) x (24)
 BYTES_KICK = 96          # read f (24) v (24), write v (24) f (24)
 
-# cell edges picked by paper_2609_02694_amd.tune on MI355X
+# cell edges picked by paper_2609_02694_amd.tune on MI355X: (edge along y and z,
+# x cells per y/z cell edge)
 DEFAULT_NCELL_H = {"plain3k": 3.0, "electrolyte1m": 3.0, "ions8m": 4.0, "subdomain64m": 2.5, "replica": 2.0}
+DEFAULT_XSPLIT = {"plain3k": 1, "electrolyte1m": 6, "ions8m": 6, "subdomain64m": 4, "replica": 3}
 
 
 def parse():
@@ -54,7 +56,8 @@ def parse():
     ap.add_argument("--compare-steps", type=int, default=100,
                     help="steps of each comparison form (the other precision; replica256: FP64 and FP32C "
                          "per-replica loops and the other-precision batch); 0 skips them")
-    ap.add_argument("--edge", type=float, default=None, help="cell edge (replica256)")
+    ap.add_argument("--edge", type=float, default=None, help="cell edge (along y and z; replica256: all axes)")
+    ap.add_argument("--xsplit", type=int, default=None, help="x cells per y/z cell edge")
     ap.add_argument("--prec", default=None, choices=["fp64", "fp32c"])
     ap.add_argument("--n", type=int, default=None, help="override the particle count (same density)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -103,13 +106,14 @@ def main():
     p = gen.preset(a.workload, n=a.n)
     prec_name = a.prec or ("fp64" if a.workload in ("plain3k", "electrolyte1m") else "fp32c")
     prec = rbe.FP64 if prec_name == "fp64" else rbe.FP32C
-    h = DEFAULT_NCELL_H.get(a.workload, 3.0)
+    h = a.edge or DEFAULT_NCELL_H.get(a.workload, 3.0)
     nc = max(1, int(p["L"] // h))
+    nx = nc * (a.xsplit or DEFAULT_XSPLIT.get(a.workload, 1))
     t0 = time.time()
     s = gen.make_system(p)
     t_gen = time.time() - t0
     n = p["n"]
-    params = rbe.params_from_preset(p, prec=prec, ncell=(nc, nc, nc))
+    params = rbe.params_from_preset(p, prec=prec, ncell=(nx, nc, nc))
     ctx = rbe.Context(params, n)
     st = rbe.Particles.from_numpy(s)
     stream = torch.cuda.current_stream()
@@ -155,7 +159,7 @@ def main():
     if a.compare_steps > 0:
         other = rbe.FP32C if prec == rbe.FP64 else rbe.FP64
         oname = "fp32c" if other == rbe.FP32C else "fp64"
-        octx = rbe.Context(rbe.params_from_preset(p, prec=other, ncell=(nc, nc, nc)), n)
+        octx = rbe.Context(rbe.params_from_preset(p, prec=other, ncell=(nx, nc, nc)), n)
         ost = rbe.Particles.from_numpy(s)
         octx.forces(ost, None, None, 0)
         octx.step(ost, 3, 1)
@@ -182,7 +186,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": a.workload, "n": n, "n_charged": nq, "L": round(p["L"], 4), "alpha": p["alpha"],
                    "r_coul": p["r_coul"], "r_lj": p["r_lj"], "r_core": p["r_core"], "p_shell": p["p_shell"],
-                   "P": p["P"], "dt": p["dt"], "form": prec_name, "ncell": nc, "parallelism": "single GPU"},
+                   "P": p["P"], "dt": p["dt"], "form": prec_name, "ncell": [nx, nc, nc], "parallelism": "single GPU"},
         "event_ms_per_step": ev_ms / K,
         "kernels": kernels,
         "counts_per_eval": {k: dict(zip(("coul_pairs", "lj_pairs", "candidates", "shell_members"), v))
@@ -215,7 +219,8 @@ def bench_batch(a):
     t_gen = time.time() - t0
     ntot = int(off[-1])
     edge = a.edge or DEFAULT_NCELL_H["replica"]
-    ctx = rbe.Context.batch(tune.batch_params(reps, edge, prec), off)
+    xsplit = a.xsplit or DEFAULT_XSPLIT["replica"]
+    ctx = rbe.Context.batch(tune.batch_params(reps, edge, prec, xsplit), off)
     st = rbe.Particles.from_numpy(cat)
     stream = torch.cuda.current_stream()
     ctx.forces(st, None, None, 0)
@@ -252,7 +257,7 @@ def bench_batch(a):
         ctxs, sts = [], []
         for (p, s) in reps:
             n = max(1, int(p["L"] // edge))
-            ctxs.append(rbe.Context(rbe.params_from_preset(p, prec=pr, ncell=(n, n, n), seed=p["stream_seed"]),
+            ctxs.append(rbe.Context(rbe.params_from_preset(p, prec=pr, ncell=(xsplit * n, n, n), seed=p["stream_seed"]),
                                     p["n"]))
             sts.append(rbe.Particles.from_numpy(s))
         rate = None
@@ -286,7 +291,7 @@ def bench_batch(a):
     if a.compare_steps > 0:
         v32_loop, _ = loop_rate(rbe.FP32C, Kc)
         other = rbe.FP64 if prec == rbe.FP32C else rbe.FP32C
-        ms_other = tune.time_batch(reps, cat, off, edge, other, steps=a.compare_steps)
+        ms_other = tune.time_batch(reps, cat, off, edge, other, steps=a.compare_steps, xsplit=xsplit)
         forms[f"batched_{'fp64' if other == rbe.FP64 else 'fp32c'}"] = ntot / (ms_other * 1e-3)
         forms["loop_fp64"] = v64_loop
         forms["loop_fp32c"] = v32_loop
@@ -316,7 +321,7 @@ def bench_batch(a):
         "config": {"workload": "replica256", "replicas": len(sizes), "n": ntot, "n_charged": nq,
                    "n_min": min(sizes), "n_max": max(sizes), "density": 0.5, "alpha": reps[0][0]["alpha"],
                    "r_coul": reps[0][0]["r_coul"], "r_lj": reps[0][0]["r_lj"], "P": P, "form": "batched " + prec_name,
-                   "cell_edge": edge, "parallelism": "single GPU"},
+                   "cell_edge": edge, "xsplit": xsplit, "parallelism": "single GPU"},
         "event_ms_per_step": ev0.elapsed_time(ev1) / K,
         "kernels": kernels,
         "forms_particle_steps_per_s": forms,

@@ -241,11 +241,12 @@ static void make_pair_params(const rbe_params &p, const Grid &g, PairParams *out
   pp.g = g;
   const int nc[3] = {g.nx, g.ny, g.nz};
   const double rq = std::fmax(p.r_coul, p.r_lj);
-  for (int d = 0; d < 3; ++d) {
-    pp.s_coul = std::max(pp.s_coul, stencil_radius(rq, p.L[d], nc[d]));
-    pp.s_lj = std::max(pp.s_lj, stencil_radius(p.r_lj, p.L[d], nc[d]));
-    pp.s_core = std::max(pp.s_core, stencil_radius(std::fmax(p.r_core, p.r_lj), p.L[d], nc[d]));
-  }
+  auto radii = [&](double r) {
+    return Sten{stencil_radius(r, p.L[0], nc[0]), stencil_radius(r, p.L[1], nc[1]), stencil_radius(r, p.L[2], nc[2])};
+  };
+  pp.s_coul = radii(rq);
+  pp.s_lj = radii(p.r_lj);
+  pp.s_core = radii(std::fmax(p.r_core, p.r_lj));
   pp.rc2 = p.r_coul * p.r_coul;
   pp.rlj2 = p.r_lj * p.r_lj;
   pp.rcore2 = p.r_core * p.r_core;
@@ -326,10 +327,11 @@ extern "C" int rbe_create(rbe_ctx **out, const rbe_params *p, int64_t n_max, int
   g.ghost_width = p->ghost_width;
   make_pair_params(c->p, g, &c->pp);
   if (p->ghost_width > 0) {
-    // the ghost layers must also hold every stencil (radii are per grid, the
-    // same on all axes)
-    const int smax = std::max(c->pp.s_coul, std::max(c->pp.s_lj, c->pp.s_core));
-    for (int d = 0; d < 3; ++d) g.goff[d] = std::max(g.goff[d], smax);
+    // the ghost layers must also hold every stencil
+    const PairParams &q = c->pp;
+    g.goff[0] = std::max(g.goff[0], std::max(q.s_coul.x, std::max(q.s_lj.x, q.s_core.x)));
+    g.goff[1] = std::max(g.goff[1], std::max(q.s_coul.y, std::max(q.s_lj.y, q.s_core.y)));
+    g.goff[2] = std::max(g.goff[2], std::max(q.s_coul.z, std::max(q.s_lj.z, q.s_core.z)));
   }
   g.pnx = g.nx + 2 * g.goff[0];
   g.pny = g.ny + 2 * g.goff[1];

@@ -69,11 +69,16 @@ void launch_build_ghosts(const Grid &g, int64_t n, const Sorted &s, const GhostB
 // ---------------------------------------------------------------------------
 // near field
 // ---------------------------------------------------------------------------
+// Stencil radius in cells along each axis (grids may be finer along x, where
+// each stencil row is trimmed per particle, than along y and z).
+struct Sten {
+  int x, y, z;
+};
 struct PairParams {
   Grid g;
-  int s_coul;            // stencil radius (cells) covering max(r_coul, r_lj)
-  int s_lj;              // stencil radius covering r_lj
-  int s_core;            // stencil radius covering max(r_core, r_lj)
+  Sten s_coul;           // stencil radii covering max(r_coul, r_lj)
+  Sten s_lj;             // stencil radii covering r_lj
+  Sten s_core;           // stencil radii covering max(r_core, r_lj)
   double rc2, rlj2, rcore2;
   double rq2;            // max(rc2, rlj2): reach of a charged pair
   double alpha, sqrt_alpha, two_sqrt_alpha_over_sqrt_pi;
@@ -165,7 +170,7 @@ struct RepDesc {
   Grid g;
   int64_t p0, n;       // particle range
   int64_t c0;          // first key (2 * ncell keys per replica)
-  int s_coul, s_lj;    // stencil radii
+  Sten s_coul, s_lj;   // stencil radii
   ModeTable mt;        // mode table; its cdf starts at cdf_off
   int cdf_off;
   uint64_t seed;

@@ -56,7 +56,8 @@ struct PairCtx {
 
 // Cluster walk of one species block for a row group.
 template <bool GHOST, bool WITH_ID, class Fn>
-__device__ inline void walk(const PairCtx &c, int blk, int xa, int xb, int cy, int cz, int s, int b, Fn &&fn) {
+__device__ inline void walk(const PairCtx &c, int blk, int xa, int xb, int cy, int cz, const Sten &s, int b,
+                            Fn &&fn) {
   auto no_tick = []() {};
   if (GHOST)
     cluster_walk_ghost<WITH_ID>(c.pp.g, c.cell_start, c.xq, c.ids, c.gcell_start, c.gxq, c.gid, blk, xa, xb, cy, cz,
@@ -108,7 +109,8 @@ __device__ inline ClusterI load_cluster_i(const PairCtx &c) {
 
 // Periodic or ghost-shell stencil walk of one particle (thread form).
 template <bool GHOST, bool WITH_ID, class Fn>
-__device__ inline void stencil(const PairCtx &c, int blk, int cx, int cy, int cz, int s, const Reach &R, Fn &&fn) {
+__device__ inline void stencil(const PairCtx &c, int blk, int cx, int cy, int cz, const Sten &s, const Reach &R,
+                               Fn &&fn) {
   if (GHOST)
     for_stencil_ghost<WITH_ID>(c.pp.g, c.cell_start, c.xq, c.ids, c.gcell_start, c.gxq, c.gid, blk, cx, cy, cz, s, R,
                                fn);

@@ -292,25 +292,26 @@ __device__ inline bool row_range(const Grid &g, const Reach &R, double gy, doubl
 }
 
 // Periodic traversal: every particle j of species block `blk` in the
-// (2s+1)^3 cells around (cx, cy, cz) that the reach of R can touch;
+// (2 s.x + 1)(2 s.y + 1)(2 s.z + 1) cells around (cx, cy, cz) that the reach
+// of R can touch;
 // (shx, shy, shz) is the image shift of j (its image lies at r_j + shift).
 template <bool WITH_ID, class Fn>
 __device__ inline void for_stencil(const Grid &g, const int32_t *__restrict__ cell_start,
                                    const double4 *__restrict__ xq, const int32_t *__restrict__ ids, int blk, int cx,
-                                   int cy, int cz, int s, const Reach &R, Fn &&fn, int64_t cell_base = 0) {
+                                   int cy, int cz, const Sten &s, const Reach &R, Fn &&fn, int64_t cell_base = 0) {
   const int64_t base = cell_base + (int64_t)blk * g.ncell;
   const double hy = g.L[1] / g.ny, hz = g.L[2] / g.nz;
-  for (int oz = -s; oz <= s; ++oz) {
+  for (int oz = -s.z; oz <= s.z; ++oz) {
     const int az = cz + oz;
     const double gz = slab_gap(R.z, az, hz);
     if (gz * gz > R.r2) continue;
     const int qz = floor_div(az, g.nz);
     const int wz = az - qz * g.nz;
     const double shz = (double)qz * g.L[2];
-    for (int oy = -s; oy <= s; ++oy) {
+    for (int oy = -s.y; oy <= s.y; ++oy) {
       const int ay = cy + oy;
       int a, a_end;
-      if (!row_range(g, R, slab_gap(R.y, ay, hy), gz, cx, s, &a, &a_end)) continue;
+      if (!row_range(g, R, slab_gap(R.y, ay, hy), gz, cx, s.x, &a, &a_end)) continue;
       const int qy = floor_div(ay, g.ny);
       const int wy = ay - qy * g.ny;
       const double shy = (double)qy * g.L[1];
@@ -335,19 +336,19 @@ template <bool WITH_ID, class Fn>
 __device__ inline void for_stencil_ghost(const Grid &g, const int32_t *__restrict__ cell_start,
                                          const double4 *__restrict__ xq, const int32_t *__restrict__ ids,
                                          const int32_t *__restrict__ gcell_start, const double4 *__restrict__ gxq,
-                                         const int32_t *__restrict__ gid, int blk, int cx, int cy, int cz, int s,
-                                         const Reach &R, Fn &&fn) {
+                                         const int32_t *__restrict__ gid, int blk, int cx, int cy, int cz,
+                                         const Sten &s, const Reach &R, Fn &&fn) {
   const int base = blk * g.ncell;
   const int pbase = blk * g.pncell;
   const double hy = g.L[1] / g.ny, hz = g.L[2] / g.nz;
-  for (int oz = -s; oz <= s; ++oz) {
+  for (int oz = -s.z; oz <= s.z; ++oz) {
     const int z = cz + oz;
     const double gz = slab_gap(R.z, z, hz);
     if (gz * gz > R.r2) continue;
-    for (int oy = -s; oy <= s; ++oy) {
+    for (int oy = -s.y; oy <= s.y; ++oy) {
       const int y = cy + oy;
       int xa, xb;
-      if (!row_range(g, R, slab_gap(R.y, y, hy), gz, cx, s, &xa, &xb)) continue;
+      if (!row_range(g, R, slab_gap(R.y, y, hy), gz, cx, s.x, &xa, &xb)) continue;
       if (z >= 0 && z < g.nz && y >= 0 && y < g.ny) {
         const int na = max(xa, 0), nb = min(xb, g.nx - 1);
         if (na <= nb) {
@@ -464,26 +465,28 @@ __device__ inline void scan_cluster(const double4 *__restrict__ xq, const int32_
 }
 
 // Periodic walk of species block `blk` (keys base + blk * C + cell) for a row
-// group: rows (cy + oy, cz + oz), |oy|, |oz| <= s, x from xa - s to xb + s,
+// group: rows (cy + oy, cz + oz), |oy| <= s.y, |oz| <= s.z, x from xa - s.x
+// to xb + s.x,
 // each row split where it crosses the periodic boundary (a cell met twice is
 // met with two different image shifts, so no image is counted twice).
 template <bool WITH_ID, class Fn, class Tick>
 __device__ inline void cluster_walk(const Grid &g, const int32_t *__restrict__ cell_start,
                                     const double4 *__restrict__ xq, const int32_t *__restrict__ ids, int64_t base,
-                                    int xa, int xb, int cy, int cz, int s, int b, Fn &&fn, Tick &&tick) {
-  for (int oz = -s; oz <= s; ++oz) {
+                                    int xa, int xb, int cy, int cz, const Sten &s, int b, Fn &&fn,
+                                    Tick &&tick) {
+  for (int oz = -s.z; oz <= s.z; ++oz) {
     const int az = cz + oz;
     const int qz = floor_div(az, g.nz);
     const int wz = az - qz * g.nz;
     const double shz = (double)qz * g.L[2];
-    for (int oy = -s; oy <= s; ++oy) {
+    for (int oy = -s.y; oy <= s.y; ++oy) {
       const int ay = cy + oy;
       const int qy = floor_div(ay, g.ny);
       const int wy = ay - qy * g.ny;
       const double shy = (double)qy * g.L[1];
       const int64_t row = base + (int64_t)(wz * g.ny + wy) * g.nx;
-      int x = xa - s;
-      const int x_end = xb + s;
+      int x = xa - s.x;
+      const int x_end = xb + s.x;
       while (x <= x_end) {
         const int qx = floor_div(x, g.nx);
         const int xe = min(x_end, (qx + 1) * g.nx - 1);
@@ -503,21 +506,21 @@ __device__ inline void cluster_walk_ghost(const Grid &g, const int32_t *__restri
                                           const double4 *__restrict__ xq, const int32_t *__restrict__ ids,
                                           const int32_t *__restrict__ gcell_start, const double4 *__restrict__ gxq,
                                           const int32_t *__restrict__ gid, int blk, int xa, int xb, int cy, int cz,
-                                          int s, int b, Fn &&fn, Tick &&tick) {
+                                          const Sten &s, int b, Fn &&fn, Tick &&tick) {
   const int64_t base = (int64_t)blk * g.ncell;
   const int64_t pbase = (int64_t)blk * g.pncell;
-  const int na = max(xa - s, 0), nb = min(xb + s, g.nx - 1);
-  for (int oz = -s; oz <= s; ++oz) {
+  const int na = max(xa - s.x, 0), nb = min(xb + s.x, g.nx - 1);
+  for (int oz = -s.z; oz <= s.z; ++oz) {
     const int z = cz + oz;
-    for (int oy = -s; oy <= s; ++oy) {
+    for (int oy = -s.y; oy <= s.y; ++oy) {
       const int y = cy + oy;
       if (z >= 0 && z < g.nz && y >= 0 && y < g.ny) {
         const int64_t row = base + (int64_t)(z * g.ny + y) * g.nx;
         scan_cluster<WITH_ID>(xq, ids, cell_start[row + na], cell_start[row + nb + 1], b, 0.0, 0.0, 0.0, fn, tick);
       }
       const int64_t prow = pbase + (int64_t)((z + g.goff[2]) * g.pny + (y + g.goff[1])) * g.pnx + g.goff[0];
-      scan_cluster<WITH_ID>(gxq, gid, gcell_start[prow + xa - s], gcell_start[prow + xb + s + 1], b, 0.0, 0.0, 0.0,
-                            fn, tick);
+      scan_cluster<WITH_ID>(gxq, gid, gcell_start[prow + xa - s.x], gcell_start[prow + xb + s.x + 1], b, 0.0, 0.0,
+                            0.0, fn, tick);
     }
   }
 }

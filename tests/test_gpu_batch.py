@@ -62,6 +62,23 @@ def test_batched_forces_per_replica(prec, tol):
     ctx.close()
 
 
+@pytest.mark.parametrize("prec,tol", [(rbe.FP64, TOL64), (rbe.FP32C, TOL32)])
+def test_batched_forces_split_x_grids(prec, tol):
+    """Per-replica grids with x cells finer than y/z cells (per-axis stencil radii)."""
+    from paper_2609_02694_amd import tune
+    reps, cat, off = gen.replica_batch(SMALL)
+    ctx = rbe.Context.batch(tune.batch_params(reps, 2.0, prec, xsplit=3), off)
+    st = rbe.Particles.from_numpy(cat)
+    ctx.forces(st, None, None, 4)
+    torch.cuda.synchronize()
+    ctx.sync_check()
+    F = host(st)["F"]
+    for r, (p, s) in enumerate(reps):
+        e = rel_err(F[off[r]:off[r + 1]], replica_oracle(p, s, 4))
+        assert e < tol, (r, p["n"], e)
+    ctx.close()
+
+
 @pytest.mark.parametrize("terms", [rbe.TERM_FOURIER, rbe.TERM_COUL_REAL, rbe.TERM_LJ])
 def test_batched_terms(terms):
     reps, cat, off = gen.replica_batch(SMALL[:3])

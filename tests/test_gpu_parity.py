@@ -138,6 +138,20 @@ def test_forces_fp64_rbl_small_box_wrapping_stencil():
         assert rel_err(F, ref["F"]) < TOL64, ncell
 
 
+@pytest.mark.parametrize("prec,tol", [(rbe.FP64, TOL64), (rbe.FP32C, TOL32)])
+@pytest.mark.parametrize("xsplit", [3, 6])
+def test_forces_rbl_electrolyte_20k_split_x(prec, tol, xsplit):
+    """Cells split along x only (stencil radii differ per axis): same forces."""
+    p, s = system("electrolyte1m", n=20000)
+    m, w = oracle.sample_k(p["seed"], 5, p["L"], p["alpha"], p["P"])
+    ref = oracle_forces(p, s, m, w, ev=5, cells=False)
+    nc = int(p["L"] // 3.0)
+    F = gpu_forces(p, s, prec=prec, m=m, w=w, ev=5, ncell=(xsplit * nc, nc, nc))
+    e = rel_err(F, ref["F"])
+    print(f"electrolyte20k split x{xsplit} prec={prec} rel err {e:.3e}")
+    assert e < tol
+
+
 # ---------------------------------------------------------------------------
 # FP32-compensated form
 # ---------------------------------------------------------------------------
@@ -253,6 +267,19 @@ def test_forces_ghost_shell_matches_periodic(prec, tol):
     assert rel_err(F, F2) < (1e-13 if prec == rbe.FP64 else 1e-6)
 
 
+@pytest.mark.parametrize("prec,tol", [(rbe.FP64, TOL64), (rbe.FP32C, TOL32)])
+def test_forces_ghost_shell_split_x(prec, tol):
+    """Ghost layers per axis sized for per-axis stencil radii (x cells 4x finer)."""
+    p, s = system("subdomain64m", n=40000)
+    m, w = oracle.sample_k(p["seed"], 2, p["L"], p["alpha"], p["P"])
+    ref = oracle_forces(p, s, m, w, ev=2, cells=True)
+    nc = int(p["L"] // 2.5)
+    F = gpu_forces(p, s, prec=prec, m=m, w=w, ev=2, ncell=(4 * nc, nc, nc))
+    e = rel_err(F, ref["F"])
+    print(f"ghost shell split x prec={prec} rel err {e:.3e}")
+    assert e < tol
+
+
 def test_forces_ghost_shell_with_random_batch_list():
     p, s = system("electrolyte1m", n=20000, ghost=6.0)
     m, w = oracle.sample_k(p["seed"], 4, p["L"], p["alpha"], p["P"])
@@ -306,7 +333,7 @@ def lattice_with_vacancies(seed=7, a=1.25, n=12, frac_removed=0.1):
     return s, n * a
 
 
-@pytest.mark.parametrize("ncell", [(6, 6, 6), (4, 4, 4), (12, 12, 12)])
+@pytest.mark.parametrize("ncell", [(6, 6, 6), (4, 4, 4), (12, 12, 12), (24, 6, 6), (18, 4, 4)])
 def test_forces_fp64_cutoffs_on_lattice_distances(ncell):
     s, L = lattice_with_vacancies()
     # r_lj = 2a, r_coul = 4a: many pairs exactly at each cutoff
@@ -319,7 +346,7 @@ def test_forces_fp64_cutoffs_on_lattice_distances(ncell):
         assert rel_err(F, ref[key]) < TOL64, (ncell, key)
 
 
-@pytest.mark.parametrize("ncell", [(6, 6, 6), (4, 4, 4)])
+@pytest.mark.parametrize("ncell", [(6, 6, 6), (4, 4, 4), (24, 6, 6)])
 def test_forces_fp64_rbl_core_on_lattice_distance(ncell):
     s, L = lattice_with_vacancies(seed=8)
     # r_core = 3a exactly, shell out to r_coul = 4a; p below the shell size
