@@ -152,7 +152,7 @@ def main():
 
     kernels = {k: {"total_ms": round(v[0], 4), "launches": v[1], "avg_us": round(1000 * v[0] / v[1], 3)}
                for k, v in kt.items() if v[1] > 0}
-    roof, roofs = roofline(kernels, cnt, nq, p, prec, K, workload=a.workload)
+    roof, roofs = roofline(kernels, cnt, nq, p, prec, K, workload=a.workload, grid=[nx, nc, nc])
 
     # the other precision form on the same system and grid (untimed in `value`)
     forms = {prec_name: value}
@@ -304,7 +304,7 @@ def bench_batch(a):
         peak = PEAK_FP64_TFLOPS if prec == rbe.FP64 else PEAK_FP32_TFLOPS
         ach = work / avg_s / 1e12
         roof = dict(kernel="batch", bound="alu", achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak,
-                    traffic=measured_traffic("replica256", "batch"), work_per_launch=work)
+                    traffic=measured_traffic("replica256", "batch", [edge, xsplit]), work_per_launch=work)
     out = {
         "metric": METRIC,
         "value": value,
@@ -398,9 +398,10 @@ def kernel_roofline(name, kernels, cnt, nq, p, prec):
                 work_per_launch=per_bytes * n)
 
 
-def measured_traffic(workload, name):
+def measured_traffic(workload, name, grid=None):
     """HBM bytes per launch of a kernel kind from the committed rocprofv3 counter
-    runs (profiles/traffic.json), or None when the kernel sources changed since."""
+    runs (profiles/traffic.json), or None when the kernel sources or the cell
+    grid differ from the counted run."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -417,11 +418,13 @@ def measured_traffic(workload, name):
         h.update(open(fp, "rb").read())
     if h.hexdigest() != d["source_sha256"]:
         return None
+    if grid is not None and d.get("grid") != grid:
+        return None
     t = d["kinds"][name]
     return t["read_bytes"] + t["write_bytes"]
 
 
-def roofline(kernels, cnt, nq, p, prec, K, workload=None):
+def roofline(kernels, cnt, nq, p, prec, K, workload=None, grid=None):
     """Roofline figure of the dominant kernel (largest summed time), and of every kind with a model."""
     if not kernels:
         return None, {}
@@ -430,7 +433,7 @@ def roofline(kernels, cnt, nq, p, prec, K, workload=None):
     name = max(kernels, key=lambda k: kernels[k]["total_ms"])
     dom = every.get(name) or dict(kernel=name, bound="alu", achieved=None, peak=None, unit=None, frac=None)
     dom = dict(dom)
-    dom["traffic"] = measured_traffic(workload, name) if workload else None
+    dom["traffic"] = measured_traffic(workload, name, grid) if workload else None
     return dom, every
 
 
