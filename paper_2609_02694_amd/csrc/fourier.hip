@@ -58,6 +58,7 @@ __global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f64(int64_t nq, 
   const int64_t j0 = (int64_t)blockIdx.x * chunk;
   const int64_t j1 = min(nq, j0 + chunk);
   double re = 0.0, im = 0.0;
+#pragma unroll 4
   for (int64_t j = j0; j < j1; ++j) {
     const double4 s = sq[j];
     const double t = turn_fraction(mx, my, mz, s.x, s.y, s.z);
@@ -79,6 +80,7 @@ __global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f32c(int64_t nq,
   const int64_t j0 = (int64_t)blockIdx.x * chunk;
   const int64_t j1 = min(nq, j0 + chunk);
   float re = 0.f, re_c = 0.f, im = 0.f, im_c = 0.f;
+#pragma unroll 4
   for (int64_t j = j0; j < j1; ++j) {
     const double4 s = sq[j];
     const float t = (float)turn_fraction(mx, my, mz, s.x, s.y, s.z);
@@ -155,6 +157,7 @@ __global__ void __launch_bounds__(256) k_gather_f64(int64_t nq, int P, const dou
   if (i >= nq) return;
   const double4 s = sq[i];
   double gx = 0.0, gy = 0.0, gz = 0.0;
+#pragma unroll 4
   for (int l = 0; l < P; ++l) {
     const GatherMode gm = modes[l];
     const double t = turn_fraction(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
@@ -179,6 +182,7 @@ __global__ void __launch_bounds__(256) k_gather_f32c(int64_t nq, int P, const do
   if (i >= nq) return;
   const double4 s = sq[i];
   float gx = 0.f, gy = 0.f, gz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
+#pragma unroll 4
   for (int l = 0; l < P; ++l) {
     const GatherMode gm = modes[l];
     const float t = (float)turn_fraction(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
