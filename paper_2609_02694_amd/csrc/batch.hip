@@ -303,6 +303,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchArgs a) {
       double2 out;
       if (F32) {
         float re = 0.f, rc = 0.f, im = 0.f, ic = 0.f;
+#pragma unroll 4
         for (int64_t j = j0; j < j1; ++j) {
           const double4 s = a.sq[j];
           const float t = (float)turn_fraction(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
@@ -313,6 +314,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchArgs a) {
         out = make_double2((double)re - (double)rc, (double)im - (double)ic);
       } else {
         double re = 0.0, im = 0.0;
+#pragma unroll 4
         for (int64_t j = j0; j < j1; ++j) {
           const double4 s = a.sq[j];
           const double t = turn_fraction(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
@@ -365,6 +367,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchArgs a) {
       const GatherMode *md = a.modes + (int64_t)r * P;
       if (F32) {
         float gx = 0.f, gy = 0.f, gz = 0.f, ex = 0.f, ey = 0.f, ez = 0.f;
+#pragma unroll 4
         for (int l = 0; l < P; ++l) {
           const GatherMode gm = md[l];
           const float t = (float)turn_fraction(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
@@ -378,6 +381,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchArgs a) {
         fz -= s.w * (kTwoPi / R.g.L[2]) * ((double)gz - (double)ez);
       } else {
         double gx = 0.0, gy = 0.0, gz = 0.0;
+#pragma unroll 4
         for (int l = 0; l < P; ++l) {
           const GatherMode gm = md[l];
           const double t = turn_fraction(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
