@@ -70,7 +70,9 @@ typedef struct {
   int32_t kdist;      /* rbe_kdist                                                     */
   int32_t prec;       /* rbe_precision                                                 */
   int32_t terms;      /* RBE_TERM_* mask; 0 means RBE_TERM_ALL                         */
-  int32_t ncell[3];   /* cell grid over the box; 0 lets the library choose            */
+  int32_t ncell[3];   /* cell grid over the box (may differ per axis); 0 lets the
+                         library choose: edge about max(r_lj, r_coul / 2) along y
+                         and z, x cells four times finer                           */
   double lj_eps, lj_sigma; /* LJ parameters of Eq. 2                                   */
   double coulomb_k;   /* Coulomb prefactor (1 in reduced units)                        */
   double mass, dt;    /* particle mass and velocity-Verlet time step                   */

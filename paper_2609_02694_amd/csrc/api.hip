@@ -214,6 +214,11 @@ static int validate_params(const rbe_params *p, std::string *why) {
   return RBE_OK;
 }
 
+// Default grid: cell edge about max(r_lj, r_coul / 2) along y and z, and x
+// cells kDefaultXSplit times finer (stencil rows are trimmed per particle
+// along x, so finer x cells remove candidates without adding rows), as far
+// as the cell table allows.
+constexpr int kDefaultXSplit = 4;
 static void choose_grid(const rbe_params *p, int nc[3]) {
   const bool user = p->ncell[0] > 0 && p->ncell[1] > 0 && p->ncell[2] > 0;
   const double h = std::fmax(p->r_lj, 0.5 * p->r_coul);
@@ -224,6 +229,11 @@ static void choose_grid(const rbe_params *p, int nc[3]) {
       int c = (int)std::floor(p->L[d] / h);
       nc[d] = c < 1 ? 1 : c;
     }
+  }
+  if (!user) {
+    int k = kDefaultXSplit;
+    while (k > 1 && (int64_t)k * nc[0] * nc[1] * nc[2] * 2 >= (1LL << 29)) --k;
+    nc[0] *= k;
   }
 }
 
