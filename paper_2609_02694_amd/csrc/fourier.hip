@@ -93,16 +93,22 @@ __global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f32c(int64_t nq,
   if (active) part[(int64_t)blockIdx.x * P + l] = make_double2((double)re - (double)re_c, (double)im - (double)im_c);
 }
 
-// rho_l = sum over chunks (fixed order: lane-strided FP64 sums, then a fixed
-// butterfly). Also forms the gather coefficients of each mode.
-__global__ void __launch_bounds__(64) k_rho_final(int nchunks, int P, const double2 *__restrict__ part,
-                                                  const double *__restrict__ mkd, const double *__restrict__ w,
-                                                  double *__restrict__ rho, GatherMode *__restrict__ modes,
-                                                  double *__restrict__ rho_out) {
+// rho_l = sum over chunks (fixed order: thread-strided FP64 sums, a fixed
+// butterfly in each wave, then the waves in index order). Also forms the
+// gather coefficients of each mode.
+constexpr int kRhoFinalThreads = 256;
+__global__ void __launch_bounds__(kRhoFinalThreads) k_rho_final(int nchunks, int P, const double2 *__restrict__ part,
+                                                                const double *__restrict__ mkd,
+                                                                const double *__restrict__ w,
+                                                                double *__restrict__ rho,
+                                                                GatherMode *__restrict__ modes,
+                                                                double *__restrict__ rho_out) {
+  __shared__ double2 wsum[kRhoFinalThreads / 64];
   const int l = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double re = 0.0, im = 0.0;
-  for (int c = lane; c < nchunks; c += 64) {
+#pragma unroll 4
+  for (int c = threadIdx.x; c < nchunks; c += kRhoFinalThreads) {
     const double2 v = part[(int64_t)c * P + l];
     re += v.x;
     im += v.y;
@@ -112,7 +118,15 @@ __global__ void __launch_bounds__(64) k_rho_final(int nchunks, int P, const doub
     re += __shfl_xor(re, o, 64);
     im += __shfl_xor(im, o, 64);
   }
-  if (lane == 0) {
+  if (lane == 0) wsum[wave] = make_double2(re, im);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    re = 0.0;
+    im = 0.0;
+    for (int k = 0; k < kRhoFinalThreads / 64; ++k) {
+      re += wsum[k].x;
+      im += wsum[k].y;
+    }
     rho[l] = re;
     rho[P + l] = im;
     if (rho_out) {
@@ -143,7 +157,7 @@ int launch_rho_partial(int prec, int64_t nq, int P, const double4 *sq, const Fou
 }
 
 void launch_rho_final(int nchunks, int P, const FourierBuffers &fb, const double *w, double *rho_out, hipStream_t st) {
-  k_rho_final<<<P, 64, 0, st>>>(nchunks, P, fb.part, fb.mkd, w, fb.rho, fb.modes, rho_out);
+  k_rho_final<<<P, kRhoFinalThreads, 0, st>>>(nchunks, P, fb.part, fb.mkd, w, fb.rho, fb.modes, rho_out);
 }
 
 // ---------------------------------------------------------------------------

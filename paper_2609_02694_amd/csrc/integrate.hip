@@ -85,7 +85,7 @@ void launch_count_charged(int64_t n, const double *q, int32_t *out, hipStream_t 
 // fixed-order mean (Eq. 12)
 // ---------------------------------------------------------------------------
 constexpr int kMeanThreads = 256;
-constexpr int64_t kMeanPerBlock = 8192;
+constexpr int64_t kMeanPerBlock = 2048;
 
 int mean_blocks(int64_t n) { return (int)((n + kMeanPerBlock - 1) / kMeanPerBlock); }
 
@@ -111,6 +111,7 @@ __global__ void __launch_bounds__(kMeanThreads) k_mean_partial(int64_t n, const 
   const int64_t b0 = (int64_t)blockIdx.x * kMeanPerBlock;
   const int64_t b1 = min(n, b0 + kMeanPerBlock);
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll 4
   for (int64_t i = b0 + threadIdx.x; i < b1; i += kMeanThreads) {
     s0 += fx[i];
     s1 += fy[i];
@@ -130,6 +131,7 @@ __global__ void __launch_bounds__(kMeanThreads) k_mean_final(int nblk, int64_t n
                                                              double *__restrict__ mean) {
   __shared__ double lds[kMeanThreads / 64];
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll 4
   for (int b = threadIdx.x; b < nblk; b += kMeanThreads) {
     s0 += partials[3 * b];
     s1 += partials[3 * b + 1];
