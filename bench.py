@@ -42,7 +42,7 @@ BYTES_KICK = 96          # read f (24) v (24), write v (24) f (24)
 
 # cell edges picked by paper_2609_02694_amd.tune on MI355X: (edge along y and z,
 # x cells per y/z cell edge)
-DEFAULT_NCELL_H = {"plain3k": 3.0, "electrolyte1m": 3.0, "ions8m": 4.0, "subdomain64m": 2.5, "replica": 2.0}
+DEFAULT_NCELL_H = {"plain3k": 3.0, "electrolyte1m": 3.0, "ions8m": 4.0, "subdomain64m": 2.5, "replica": 2.5}
 DEFAULT_XSPLIT = {"plain3k": 1, "electrolyte1m": 6, "ions8m": 6, "subdomain64m": 4, "replica": 3}
 
 
@@ -58,6 +58,9 @@ def parse():
                          "per-replica loops and the other-precision batch); 0 skips them")
     ap.add_argument("--edge", type=float, default=None, help="cell edge (along y and z; replica256: all axes)")
     ap.add_argument("--xsplit", type=int, default=None, help="x cells per y/z cell edge")
+    ap.add_argument("--tune", action="store_true",
+                    help="pick the grid with the autotuner (cached in --tune-cache) instead of the defaults")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "tune_cache.json"))
     ap.add_argument("--prec", default=None, choices=["fp64", "fp32c"])
     ap.add_argument("--n", type=int, default=None, help="override the particle count (same density)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -113,6 +116,12 @@ def main():
     s = gen.make_system(p)
     t_gen = time.time() - t0
     n = p["n"]
+    tuned = None
+    if a.tune:
+        from paper_2609_02694_amd import tune
+        t1 = time.time()
+        (nx, nc, _), hit = tune.tune_grid_cached(p, s, prec, a.tune_cache, steps=10)
+        tuned = dict(cache_hit=hit, seconds=round(time.time() - t1, 1))
     params = rbe.params_from_preset(p, prec=prec, ncell=(nx, nc, nc))
     ctx = rbe.Context(params, n)
     st = rbe.Particles.from_numpy(s)
@@ -186,7 +195,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": a.workload, "n": n, "n_charged": nq, "L": round(p["L"], 4), "alpha": p["alpha"],
                    "r_coul": p["r_coul"], "r_lj": p["r_lj"], "r_core": p["r_core"], "p_shell": p["p_shell"],
-                   "P": p["P"], "dt": p["dt"], "form": prec_name, "ncell": [nx, nc, nc], "parallelism": "single GPU"},
+                   "P": p["P"], "dt": p["dt"], "form": prec_name, "ncell": [nx, nc, nc], "tuned": tuned,
+                   "parallelism": "single GPU"},
         "event_ms_per_step": ev_ms / K,
         "kernels": kernels,
         "counts_per_eval": {k: dict(zip(("coul_pairs", "lj_pairs", "candidates", "shell_members"), v))
@@ -220,6 +230,11 @@ def bench_batch(a):
     ntot = int(off[-1])
     edge = a.edge or DEFAULT_NCELL_H["replica"]
     xsplit = a.xsplit or DEFAULT_XSPLIT["replica"]
+    tuned = None
+    if a.tune:
+        t1 = time.time()
+        (edge, xsplit), hit = tune.tune_batch_cached(reps, cat, off, prec, a.tune_cache, steps=5)
+        tuned = dict(cache_hit=hit, seconds=round(time.time() - t1, 1))
     ctx = rbe.Context.batch(tune.batch_params(reps, edge, prec, xsplit), off)
     st = rbe.Particles.from_numpy(cat)
     stream = torch.cuda.current_stream()
@@ -321,7 +336,7 @@ def bench_batch(a):
         "config": {"workload": "replica256", "replicas": len(sizes), "n": ntot, "n_charged": nq,
                    "n_min": min(sizes), "n_max": max(sizes), "density": 0.5, "alpha": reps[0][0]["alpha"],
                    "r_coul": reps[0][0]["r_coul"], "r_lj": reps[0][0]["r_lj"], "P": P, "form": "batched " + prec_name,
-                   "cell_edge": edge, "xsplit": xsplit, "parallelism": "single GPU"},
+                   "cell_edge": edge, "xsplit": xsplit, "tuned": tuned, "parallelism": "single GPU"},
         "event_ms_per_step": ev0.elapsed_time(ev1) / K,
         "kernels": kernels,
         "forms_particle_steps_per_s": forms,

@@ -12,7 +12,10 @@ real system and returns the fastest grid.
 """
 from __future__ import annotations
 
+import hashlib
+import json
 import math
+import os
 
 from . import Context, Particles, params_from_preset
 
@@ -124,3 +127,86 @@ def tune_batch(reps, cat_np: dict, offsets, prec: int, steps: int = 10, edges=BA
                 print(f"tune: batch edge {h:.2f} xsplit {k} -> {table[(h, k)]:.3f} ms/step", flush=True)
     best = min(table, key=table.get)
     return best, table
+
+
+# ---------------------------------------------------------------------------
+# cache of tuned grids
+# ---------------------------------------------------------------------------
+_KEY_FIELDS = ("n", "L", "alpha", "r_coul", "r_lj", "r_core", "p_shell", "P", "ghost")
+
+
+def tune_key(preset: dict, prec: int, kind: str = "grid", extra=None) -> str:
+    """Cache key of a tuning problem: the physics and sizes that decide the
+    best grid, the precision form, and the GPU it was timed on."""
+    dev = "cpu"
+    try:
+        import torch
+
+        if torch.cuda.is_available():
+            dev = torch.cuda.get_device_name(0)
+    except Exception:
+        pass
+    d = {k: preset.get(k) for k in _KEY_FIELDS}
+    d.update(kind=kind, prec=int(prec), device=dev, extra=extra)
+    return hashlib.sha256(json.dumps(d, sort_keys=True, default=str).encode()).hexdigest()[:24]
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path, key, value):
+    data = _load(path)
+    data[key] = value
+    d = os.path.dirname(os.path.abspath(path))
+    os.makedirs(d, exist_ok=True)
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def tune_grid_cached(preset: dict, state_np: dict, prec: int, cache_path: str, steps: int = 20,
+                     edges=DEFAULT_EDGES, xsplits=DEFAULT_XSPLITS, verbose=False, timer=None):
+    """tune_grid with a JSON cache at cache_path: returns (grid, hit). `timer`
+    replaces the step timing (same signature as time_steps), for tests."""
+    key = tune_key(preset, prec, "grid", [list(edges), list(xsplits)])
+    hit = _load(cache_path).get(key)
+    if hit is not None:
+        return tuple(hit["grid"]), True
+    r_max = max(preset["r_coul"], preset["r_lj"])
+    t = timer or time_steps
+    table = {g: t(preset, state_np, g, prec, steps) for g in candidate_grids(preset["L"], r_max, edges, xsplits)}
+    best = min(table, key=table.get)
+    if verbose:
+        for g, ms in table.items():
+            print(f"tune: ncell={g} -> {ms:.3f} ms/step", flush=True)
+    _store(cache_path, key, {"grid": list(best), "ms": {"x".join(map(str, g)): v for g, v in table.items()}})
+    return best, False
+
+
+def tune_batch_cached(reps, cat_np: dict, offsets, prec: int, cache_path: str, steps: int = 10,
+                      edges=BATCH_EDGES, xsplits=(1, 2, 3), verbose=False, timer=None):
+    """tune_batch with a JSON cache: returns ((edge, xsplit), hit)."""
+    sizes = [int(p["n"]) for p, _ in reps]
+    key = tune_key(reps[0][0], prec, "batch", [sizes, list(edges), list(xsplits)])
+    hit = _load(cache_path).get(key)
+    if hit is not None:
+        return (hit["edge"], hit["xsplit"]), True
+    t = timer or time_batch
+    table = {}
+    for h in edges:
+        if min(p["L"] for p, _ in reps) < h:
+            continue
+        for k in xsplits:
+            table[(h, k)] = t(reps, cat_np, offsets, h, prec, steps, xsplit=k)
+            if verbose:
+                print(f"tune: batch edge {h:.2f} xsplit {k} -> {table[(h, k)]:.3f} ms/step", flush=True)
+    best = min(table, key=table.get)
+    _store(cache_path, key, {"edge": best[0], "xsplit": best[1],
+                             "ms": {f"{h}/{k}": v for (h, k), v in table.items()}})
+    return best, False

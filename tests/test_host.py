@@ -104,3 +104,37 @@ def test_batch_params_split_x():
                   P=10, dt=0.002, ghost=0.0), None)]
     (pr,) = tune.batch_params(reps, 2.0, 1, xsplit=3)
     assert tuple(pr.ncell) == (18, 6, 6)
+
+
+def test_tuner_cache_picks_fastest_and_reuses(tmp_path):
+    from paper_2609_02694_amd import tune
+    preset = dict(n=1000, L=30.0, alpha=0.3, r_coul=6.0, r_lj=2.5, r_core=0.0, p_shell=0, P=10, ghost=0.0)
+    calls = []
+
+    def fake_timer(p, s, grid, prec, steps):
+        calls.append(grid)
+        return abs(grid[0] - 20) + abs(grid[1] - 10)  # fastest at (20, 10, 10)
+
+    path = str(tmp_path / "cache.json")
+    g, hit = tune.tune_grid_cached(preset, None, 0, path, edges=(3.0, 5.0), xsplits=(1, 2), timer=fake_timer)
+    assert g == (20, 10, 10) and not hit and len(calls) == 4
+    g2, hit2 = tune.tune_grid_cached(preset, None, 0, path, edges=(3.0, 5.0), xsplits=(1, 2), timer=fake_timer)
+    assert g2 == g and hit2 and len(calls) == 4  # served from the cache, nothing timed
+    # another precision is another problem
+    _, hit3 = tune.tune_grid_cached(preset, None, 1, path, edges=(3.0, 5.0), xsplits=(1, 2), timer=fake_timer)
+    assert not hit3
+
+
+def test_batch_tuner_cache(tmp_path):
+    from paper_2609_02694_amd import tune
+    reps = [(dict(n=100, L=12.5, alpha=0.3, r_coul=6.0, r_lj=2.5, r_core=0.0, p_shell=0, P=10, ghost=0.0), None),
+            (dict(n=300, L=18.0, alpha=0.3, r_coul=6.0, r_lj=2.5, r_core=0.0, p_shell=0, P=10, ghost=0.0), None)]
+
+    def fake(reps_, cat, off, h, prec, steps, xsplit=1):
+        return h + 1.0 / xsplit
+
+    path = str(tmp_path / "c.json")
+    best, hit = tune.tune_batch_cached(reps, None, None, 1, path, edges=(2.0, 3.0), xsplits=(1, 3), timer=fake)
+    assert best == (2.0, 3) and not hit
+    assert tune.tune_batch_cached(reps, None, None, 1, path, edges=(2.0, 3.0), xsplits=(1, 3), timer=fake) == (
+        (2.0, 3), True)
