@@ -464,43 +464,96 @@ __device__ inline void scan_cluster(const double4 *__restrict__ xq, const int32_
   }
 }
 
+// Row tables of a cluster walk: lane t of the wave resolves stencil row
+// r0 + t (rows ordered z-major) into the cell-table bounds of its segments,
+// so the cell-table loads of up to 64 rows are in flight together instead of
+// one dependent pair per row; the walk then takes each row's bounds from its
+// lane (wave-uniform reads).
+struct RowSegs {
+  int j0a, j1a, j0b, j1b;  // up to two segments of the row
+  int qxa, qxb, qy, qz;    // their image shifts in boxes
+};
+__device__ inline RowSegs row_segs_at(const RowSegs &v, int k) {
+  RowSegs u;
+  u.j0a = __builtin_amdgcn_readlane(v.j0a, k);
+  u.j1a = __builtin_amdgcn_readlane(v.j1a, k);
+  u.j0b = __builtin_amdgcn_readlane(v.j0b, k);
+  u.j1b = __builtin_amdgcn_readlane(v.j1b, k);
+  u.qxa = __builtin_amdgcn_readlane(v.qxa, k);
+  u.qxb = __builtin_amdgcn_readlane(v.qxb, k);
+  u.qy = __builtin_amdgcn_readlane(v.qy, k);
+  u.qz = __builtin_amdgcn_readlane(v.qz, k);
+  return u;
+}
+
 // Periodic walk of species block `blk` (keys base + blk * C + cell) for a row
 // group: rows (cy + oy, cz + oz), |oy| <= s.y, |oz| <= s.z, x from xa - s.x
-// to xb + s.x,
-// each row split where it crosses the periodic boundary (a cell met twice is
-// met with two different image shifts, so no image is counted twice).
+// to xb + s.x, each row split where it crosses the periodic boundary (a cell
+// met twice is met with two different image shifts, so no image is counted
+// twice).
 template <bool WITH_ID, class Fn, class Tick>
 __device__ inline void cluster_walk(const Grid &g, const int32_t *__restrict__ cell_start,
                                     const double4 *__restrict__ xq, const int32_t *__restrict__ ids, int64_t base,
                                     int xa, int xb, int cy, int cz, const Sten &s, int b, Fn &&fn,
                                     Tick &&tick) {
-  for (int oz = -s.z; oz <= s.z; ++oz) {
-    const int az = cz + oz;
-    const int qz = floor_div(az, g.nz);
-    const int wz = az - qz * g.nz;
-    const double shz = (double)qz * g.L[2];
-    for (int oy = -s.y; oy <= s.y; ++oy) {
-      const int ay = cy + oy;
-      const int qy = floor_div(ay, g.ny);
-      const int wy = ay - qy * g.ny;
-      const double shy = (double)qy * g.L[1];
-      const int64_t row = base + (int64_t)(wz * g.ny + wy) * g.nx;
-      int x = xa - s.x;
-      const int x_end = xb + s.x;
-      while (x <= x_end) {
-        const int qx = floor_div(x, g.nx);
-        const int xe = min(x_end, (qx + 1) * g.nx - 1);
-        const int j0 = cell_start[row + (x - qx * g.nx)];
-        const int j1 = cell_start[row + (xe - qx * g.nx) + 1];
-        scan_cluster<WITH_ID>(xq, ids, j0, j1, b, (double)qx * g.L[0], shy, shz, fn, tick);
-        x = xe + 1;
+  const int x0 = xa - s.x, x1 = xb + s.x;
+  if (x1 - x0 + 1 > g.nx) {
+    // the range wraps more than once (boxes of few cells): row by row
+    for (int oz = -s.z; oz <= s.z; ++oz) {
+      const int az = cz + oz;
+      const int qz = floor_div(az, g.nz);
+      const double shz = (double)qz * g.L[2];
+      for (int oy = -s.y; oy <= s.y; ++oy) {
+        const int ay = cy + oy;
+        const int qy = floor_div(ay, g.ny);
+        const double shy = (double)qy * g.L[1];
+        const int64_t row = base + (int64_t)((az - qz * g.nz) * g.ny + (ay - qy * g.ny)) * g.nx;
+        int x = x0;
+        while (x <= x1) {
+          const int qx = floor_div(x, g.nx);
+          const int xe = min(x1, (qx + 1) * g.nx - 1);
+          const int j0 = cell_start[row + (x - qx * g.nx)];
+          const int j1 = cell_start[row + (xe - qx * g.nx) + 1];
+          scan_cluster<WITH_ID>(xq, ids, j0, j1, b, (double)qx * g.L[0], shy, shz, fn, tick);
+          x = xe + 1;
+        }
       }
+    }
+    return;
+  }
+  const int lane = threadIdx.x & 63;
+  const int nyr = 2 * s.y + 1, nrows = nyr * (2 * s.z + 1);
+  for (int r0 = 0; r0 < nrows; r0 += 64) {
+    RowSegs v{0, 0, 0, 0, 0, 0, 0, 0};
+    const int r = r0 + lane;
+    if (r < nrows) {
+      const int az = cz + r / nyr - s.z, ay = cy + r % nyr - s.y;
+      v.qz = floor_div(az, g.nz);
+      v.qy = floor_div(ay, g.ny);
+      const int64_t row = base + (int64_t)((az - v.qz * g.nz) * g.ny + (ay - v.qy * g.ny)) * g.nx;
+      v.qxa = floor_div(x0, g.nx);
+      const int ea = min(x1, (v.qxa + 1) * g.nx - 1);
+      v.j0a = cell_start[row + (x0 - v.qxa * g.nx)];
+      v.j1a = cell_start[row + (ea - v.qxa * g.nx) + 1];
+      if (ea < x1) {  // wraps once: the rest lies in the next image
+        v.qxb = v.qxa + 1;
+        v.j0b = cell_start[row];
+        v.j1b = cell_start[row + (x1 - v.qxb * g.nx) + 1];
+      }
+    }
+    const int nr = min(64, nrows - r0);
+    for (int k = 0; k < nr; ++k) {
+      const RowSegs u = row_segs_at(v, k);
+      const double shy = (double)u.qy * g.L[1], shz = (double)u.qz * g.L[2];
+      scan_cluster<WITH_ID>(xq, ids, u.j0a, u.j1a, b, (double)u.qxa * g.L[0], shy, shz, fn, tick);
+      scan_cluster<WITH_ID>(xq, ids, u.j0b, u.j1b, b, (double)u.qxb * g.L[0], shy, shz, fn, tick);
     }
   }
 }
 
 // Ghost-shell walk (no periodic images): the native part of each stencil row
-// clipped to the native grid, then the same row of the padded ghost grid.
+// clipped to the native grid, then the same row of the padded ghost grid
+// (row tables as in the periodic walk: segment a native, segment b ghost).
 template <bool WITH_ID, class Fn, class Tick>
 __device__ inline void cluster_walk_ghost(const Grid &g, const int32_t *__restrict__ cell_start,
                                           const double4 *__restrict__ xq, const int32_t *__restrict__ ids,
@@ -510,17 +563,27 @@ __device__ inline void cluster_walk_ghost(const Grid &g, const int32_t *__restri
   const int64_t base = (int64_t)blk * g.ncell;
   const int64_t pbase = (int64_t)blk * g.pncell;
   const int na = max(xa - s.x, 0), nb = min(xb + s.x, g.nx - 1);
-  for (int oz = -s.z; oz <= s.z; ++oz) {
-    const int z = cz + oz;
-    for (int oy = -s.y; oy <= s.y; ++oy) {
-      const int y = cy + oy;
+  const int lane = threadIdx.x & 63;
+  const int nyr = 2 * s.y + 1, nrows = nyr * (2 * s.z + 1);
+  for (int r0 = 0; r0 < nrows; r0 += 64) {
+    RowSegs v{0, 0, 0, 0, 0, 0, 0, 0};
+    const int r = r0 + lane;
+    if (r < nrows) {
+      const int z = cz + r / nyr - s.z, y = cy + r % nyr - s.y;
       if (z >= 0 && z < g.nz && y >= 0 && y < g.ny) {
         const int64_t row = base + (int64_t)(z * g.ny + y) * g.nx;
-        scan_cluster<WITH_ID>(xq, ids, cell_start[row + na], cell_start[row + nb + 1], b, 0.0, 0.0, 0.0, fn, tick);
+        v.j0a = cell_start[row + na];
+        v.j1a = cell_start[row + nb + 1];
       }
       const int64_t prow = pbase + (int64_t)((z + g.goff[2]) * g.pny + (y + g.goff[1])) * g.pnx + g.goff[0];
-      scan_cluster<WITH_ID>(gxq, gid, gcell_start[prow + xa - s.x], gcell_start[prow + xb + s.x + 1], b, 0.0, 0.0,
-                            0.0, fn, tick);
+      v.j0b = gcell_start[prow + xa - s.x];
+      v.j1b = gcell_start[prow + xb + s.x + 1];
+    }
+    const int nr = min(64, nrows - r0);
+    for (int k = 0; k < nr; ++k) {
+      const RowSegs u = row_segs_at(v, k);
+      scan_cluster<WITH_ID>(xq, ids, u.j0a, u.j1a, b, 0.0, 0.0, 0.0, fn, tick);
+      scan_cluster<WITH_ID>(gxq, gid, u.j0b, u.j1b, b, 0.0, 0.0, 0.0, fn, tick);
     }
   }
 }
