@@ -64,23 +64,6 @@ void launch_scatter_forces(int64_t n, const int32_t *perm, const double *fx, con
   k_scatter_forces<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, perm, fx, fy, fz, ox, oy, oz);
 }
 
-__global__ void k_count_charged(int64_t n, const double *__restrict__ q, int32_t *out) {
-  int c = 0;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    c += q[i] != 0.0;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-  if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
-}
-
-void launch_count_charged(int64_t n, const double *q, int32_t *out, hipStream_t st) {
-  launch_fill_i32(out, 1, 0, st);
-  if (n <= 0) return;
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 2048) blocks = 2048;
-  k_count_charged<<<(unsigned)blocks, 256, 0, st>>>(n, q, out);
-}
-
 // ---------------------------------------------------------------------------
 // fixed-order mean (Eq. 12)
 // ---------------------------------------------------------------------------
@@ -226,26 +209,6 @@ void launch_kick_drift(int64_t n, double h, double dt, const Grid &g, const doub
                        hipStream_t st) {
   if (n <= 0) return;
   k_kick_drift<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, h, dt, g, fx, fy, fz, vx, vy, vz, x, y, z, err);
-}
-
-__global__ void __launch_bounds__(256) k_reorder_state(int64_t n, const int32_t *__restrict__ perm, StateArrays in,
-                                                       StateArrays out) {
-  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  const int j = perm[k];
-  out.x[k] = in.x[j];
-  out.y[k] = in.y[j];
-  out.z[k] = in.z[j];
-  out.vx[k] = in.vx[j];
-  out.vy[k] = in.vy[j];
-  out.vz[k] = in.vz[j];
-  out.q[k] = in.q[j];
-  out.id[k] = in.id[j];
-}
-
-void launch_reorder_state(int64_t n, const int32_t *perm, StateArrays in, StateArrays out, hipStream_t st) {
-  if (n <= 0) return;
-  k_reorder_state<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, perm, in, out);
 }
 
 }  // namespace rbe

@@ -41,8 +41,6 @@ void launch_inverse_ids(int64_t n, const int32_t *id_sorted, int32_t *inv, int *
 // out[perm[k]] = in[k] for the three force components.
 void launch_scatter_forces(int64_t n, const int32_t *perm, const double *fx, const double *fy, const double *fz,
                            double *ox, double *oy, double *oz, hipStream_t st);
-// Count the charged particles (q != 0) into *out (device int).
-void launch_count_charged(int64_t n, const double *q, int32_t *out, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // ghost shell (ghost_width > 0)
@@ -161,7 +159,6 @@ struct StateArrays {
   double *x, *y, *z, *vx, *vy, *vz, *q;
   int32_t *id;
 };
-void launch_reorder_state(int64_t n, const int32_t *perm, StateArrays in, StateArrays out, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // batched form (many replicas, one persistent launch per step)

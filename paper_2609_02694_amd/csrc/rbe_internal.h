@@ -200,10 +200,6 @@ int sample_modes_host(const ModeTable &t, const double *cdf, uint64_t seed, uint
 // Device sampler launch (cdf is a device copy of the host table).
 void launch_sample_modes(const ModeTable &t, const double *cdf_dev, uint64_t seed, uint64_t eval, int P,
                          int32_t *m, double *w, int *err_flag, hipStream_t st);
-// Variant that reads eval from device memory (for a captured step loop).
-void launch_sample_modes_dev_eval(const ModeTable &t, const double *cdf_dev, uint64_t seed,
-                                  const uint64_t *eval_dev, int P, int32_t *m, double *w, int *err_flag,
-                                  hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Error flag bits (device int)

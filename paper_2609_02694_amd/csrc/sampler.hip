@@ -60,13 +60,11 @@ int sample_modes_host(const ModeTable &t, const double *cdf, uint64_t seed, uint
 }
 
 __global__ void __launch_bounds__(256) k_sample_modes(ModeTable t, const double *__restrict__ cdf, uint64_t seed,
-                                                      const uint64_t *eval_dev, uint64_t eval, int P,
-                                                      int32_t *__restrict__ m, double *__restrict__ w,
-                                                      int *err) {
+                                                      uint64_t eval, int P, int32_t *__restrict__ m,
+                                                      double *__restrict__ w, int *err) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= P) return;
-  const uint64_t ev = eval_dev ? *eval_dev : eval;
-  const uint64_t ek = stream_out(seed ^ kTagModes, ev);
+  const uint64_t ek = stream_out(seed ^ kTagModes, eval);
   int mv[3];
   if (!draw_mode(t, cdf, ek, l, mv)) {
     atomicOr(err, kErrSampler);
@@ -80,12 +78,7 @@ __global__ void __launch_bounds__(256) k_sample_modes(ModeTable t, const double 
 
 void launch_sample_modes(const ModeTable &t, const double *cdf_dev, uint64_t seed, uint64_t eval, int P, int32_t *m,
                          double *w, int *err_flag, hipStream_t st) {
-  k_sample_modes<<<(P + 255) / 256, 256, 0, st>>>(t, cdf_dev, seed, nullptr, eval, P, m, w, err_flag);
-}
-
-void launch_sample_modes_dev_eval(const ModeTable &t, const double *cdf_dev, uint64_t seed, const uint64_t *eval_dev,
-                                  int P, int32_t *m, double *w, int *err_flag, hipStream_t st) {
-  k_sample_modes<<<(P + 255) / 256, 256, 0, st>>>(t, cdf_dev, seed, eval_dev, 0, P, m, w, err_flag);
+  k_sample_modes<<<(P + 255) / 256, 256, 0, st>>>(t, cdf_dev, seed, eval, P, m, w, err_flag);
 }
 
 }  // namespace rbe
