@@ -6,18 +6,32 @@ structure factors; the structure factors themselves are checked at sampled
 modes. Properties that hold at any size (zero net force, Eq. 12) cover what a
 sample cannot.
 """
+import importlib.util
+import os
+
 import numpy as np
 import pytest
 
+import gen
 import oracle
-from gpu_common import rel_err, system, to_device
+from gpu_common import oracle_forces, rel_err, system, to_device
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 import paper_2609_02694_amd as rbe  # noqa: E402
 
-NCELL_EDGE = {"electrolyte1m": 3.078, "ions8m": 4.0, "subdomain64m": 2.5}
+
+def bench_grids():
+    """The cell-grid defaults bench.py times (y/z edge, x split per workload)."""
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "bench.py")
+    spec = importlib.util.spec_from_file_location("bench_grids", path)
+    b = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(b)
+    return b.DEFAULT_NCELL_H, b.DEFAULT_XSPLIT
+
+
+EDGE, XSPLIT = bench_grids()
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -30,8 +44,9 @@ def _need_gpu():
 def run_full(name, prec, ev=0, nsample=64, nmodes=8):
     p, s = system(name)
     n = p["n"]
-    nc = int(p["L"] // NCELL_EDGE[name])
-    params = rbe.params_from_preset(p, prec=prec, ncell=(nc, nc, nc))
+    nc = int(p["L"] // EDGE[name])
+    params = rbe.params_from_preset(p, prec=prec, ncell=(XSPLIT[name] * nc, nc, nc))
+    print(f"{name}: grid {(XSPLIT[name] * nc, nc, nc)}", flush=True)
     ctx = rbe.Context(params, n)
     st = to_device(s)
     m, w = oracle.sample_k(p["seed"], ev, p["L"], p["alpha"], p["P"])
@@ -98,3 +113,32 @@ def test_full_subdomain64m_fp32c():
     e = rel_err(F[idx], FN + FF)
     print(f"subdomain64m FP32C sampled rel err {e:.3e}")
     assert e < 1e-5
+
+
+def test_full_replica256_batched_fp32c():
+    """All 256 replicas (1,000 to 60,000 particles) in one batched context on
+    the bench's grids; the smallest, a middle and the largest replica are
+    checked whole against the oracle, and every replica's net force is ~0."""
+    from paper_2609_02694_amd import tune
+    sizes = gen.replica_sizes(256)
+    reps, cat, off = gen.replica_batch(sizes)
+    print(f"replica256: {int(off[-1])} particles, edge {EDGE['replica']}, x split {XSPLIT['replica']}", flush=True)
+    ctx = rbe.Context.batch(tune.batch_params(reps, EDGE["replica"], rbe.FP32C, XSPLIT["replica"]), off)
+    st = rbe.Particles.from_numpy(cat)
+    ctx.forces(st, None, None, 3)
+    torch.cuda.synchronize()
+    ctx.sync_check()
+    F = np.stack([st.fx.cpu().numpy(), st.fy.cpu().numpy(), st.fz.cpu().numpy()], axis=1)
+    ctx.close()
+    order = np.argsort(sizes)
+    for r in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
+        p, s = reps[r]
+        m, w = oracle.sample_k(p["stream_seed"], 3, p["L"], p["alpha"], p["P"])
+        ref = oracle_forces(p, s, m, w, ev=3)["F"]
+        e = rel_err(F[off[r]:off[r + 1]], ref)
+        print(f"replica {r} (n={p['n']}) rel err {e:.3e}", flush=True)
+        assert e < 1e-5
+    for r in range(len(reps)):
+        Fr = F[off[r]:off[r + 1]]
+        rms = np.sqrt((Fr ** 2).sum() / len(Fr))
+        assert np.abs(Fr.sum(axis=0)).max() < 1e-5 * np.sqrt(len(Fr)) * rms, r
