@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(256) k_pair_plain(PairCtx c) {
 // core, counted and ranked shell, one walk of both species blocks out to
 // r_coul.
 template <bool F32, bool COUNT, bool GHOST>
-__global__ void __launch_bounds__(64) k_pair_rbl(PairCtx c) {
+__global__ void __launch_bounds__(64, 5) k_pair_rbl(PairCtx c) {
   __shared__ uint32_t kbuf[kCI * kShellCap];
   __shared__ uint32_t ksel[kCI * RBE_MAX_SHELL_BATCH];
   __shared__ int kcnt[kCI];
