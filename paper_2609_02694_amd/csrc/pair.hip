@@ -123,8 +123,12 @@ __device__ inline void stencil(const PairCtx &c, int blk, int cx, int cy, int cz
 // summed, i.e. without the shell test of the random batch list). MODE 0:
 // neutral i (LJ over both species blocks out to r_lj); MODE 1: charged i
 // (charged block out to max(r_coul, r_lj), neutral block out to r_lj).
+// Occupancy asked of the compiler: FP32 forms six (charged) or seven
+// (neutral) waves per SIMD, FP64 forms three or seven (measured best; the
+// FP64 charged form spills at four).
 template <bool F32, bool COUNT, int MODE, bool GHOST>
-__global__ void __launch_bounds__(256) k_pair_plain(PairCtx c) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F32 ? (MODE ? 6 : 7) : (MODE ? 3 : 7))))
+k_pair_plain(PairCtx c) {
   const int64_t i = c.i0 + xcd_block(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
   if (i >= c.i1) return;
   const PairParams &pp = c.pp;
