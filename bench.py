@@ -26,7 +26,7 @@ PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic work per unit ("Roofline accounting"):
+# Algorithmic work per unit (FMA = 2 flops; a special function counts 1):
 #   near field: per Coulomb pair term 27 flops, per LJ pair term 22 flops,
 #               per ranked shell member 20 ops
 #   structure factor: 13 flops per (charged particle, mode)
@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--xsplit", type=int, default=None, help="x cells per y/z cell edge")
     ap.add_argument("--tune", action="store_true",
                     help="pick the grid with the autotuner (cached in --tune-cache) instead of the defaults")
-    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "tune_cache.json"))
+    ap.add_argument("--tune-cache", default=os.environ.get("RBE_TUNE_CACHE", os.path.join(ROOT, ".tune_cache.json")))
     ap.add_argument("--prec", default=None, choices=["fp64", "fp32c"])
     ap.add_argument("--n", type=int, default=None, help="override the particle count (same density)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -88,8 +88,8 @@ def calibrate_copy(mib):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {a.gpus} is not supported "
-              "(the multi-GPU sharding is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: the path runs on one GPU only; --gpus {a.gpus} is not supported "
+              "(sharding across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
