@@ -356,3 +356,40 @@ def test_forces_fp64_rbl_core_on_lattice_distance(ncell):
     ref = oracle_forces(p, s, m, w, ev=3, cells=False)
     F = gpu_forces(p, s, m=m, w=w, ev=3, ncell=ncell)
     assert rel_err(F, ref["F"]) < TOL64, ncell
+
+
+# ---------------------------------------------------------------------------
+# degenerate sizes: two particles, almost no charges, one mode, ragged counts
+# ---------------------------------------------------------------------------
+def small_system(n, n_charged, L, seed):
+    rng = np.random.default_rng(seed)
+    s = dict(x=rng.uniform(0, L, n), y=rng.uniform(0, L, n), z=rng.uniform(0, L, n), q=np.zeros(n))
+    s["q"][: n_charged // 2] = 1.0
+    s["q"][n_charged // 2: n_charged] = -1.0
+    s["id"] = rng.permutation(n).astype(np.int32)
+    return s
+
+
+@pytest.mark.parametrize("prec,tol", [(rbe.FP64, TOL64), (rbe.FP32C, TOL32)])
+@pytest.mark.parametrize("n,n_charged,r_core,p_shell,P", [
+    (2, 2, 0.0, 0, 1),        # one ion pair, one mode
+    (2, 2, 1.5, 4, 3),        # random batch list with at most one shell member
+    (67, 2, 1.5, 4, 5),       # ragged count, two charges among neutrals
+    (300, 0, 0.0, 0, 4),      # no charges at all: LJ only, Fourier part empty
+    (301, 300, 2.0, 8, 7),    # ragged, one neutral
+])
+def test_forces_degenerate_sizes(prec, tol, n, n_charged, r_core, p_shell, P):
+    L = 12.0
+    s = small_system(n, n_charged, L, seed=n + P)
+    # keep particles apart so LJ stays finite
+    s["x"] = (np.arange(n) % 7) * (L / 7) + 0.3 * (s["x"] / L)
+    s["y"] = ((np.arange(n) // 7) % 7) * (L / 7) + 0.3 * (s["y"] / L)
+    s["z"] = (np.arange(n) // 49) * (L / 7) + 0.3 * (s["z"] / L)
+    p = dict(seed=91 + n, n=n, L=L, alpha=0.4, r_coul=5.0, r_lj=2.5, r_core=r_core, p_shell=p_shell, P=P,
+             dt=0.002, ghost=0.0)
+    print(f"degenerate n={n} nq={n_charged} r_core={r_core} P={P} prec={prec}", flush=True)
+    m, w = oracle.sample_k(p["seed"], 2, L, p["alpha"], P)
+    ref = oracle_forces(p, s, m, w, ev=2, cells=False)
+    F = gpu_forces(p, s, prec=prec, m=m, w=w, ev=2)
+    assert np.all(np.isfinite(F))
+    assert rel_err(F, ref["F"]) < tol
