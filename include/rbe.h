@@ -201,8 +201,11 @@ enum {
   RBE_TK_RHO_PARTIAL = 5, /* structure-factor chunk partials                */
   RBE_TK_RHO_FINAL = 6,   /* fixed-order final sum                          */
   RBE_TK_GATHER = 7,      /* Fourier force gather                           */
-  RBE_TK_KICK_DRIFT = 8,  /* first half-kick + drift + wrap                 */
-  RBE_TK_KICK = 9,        /* second half-kick (+ mean subtraction)          */
+  RBE_TK_KICK_DRIFT = 8,  /* first half-kick + drift + wrap (from a call's
+                             second step on, fused with the previous step's
+                             second half-kick)                              */
+  RBE_TK_KICK = 9,        /* second half-kick (+ mean subtraction) of a
+                             call's last step                               */
   RBE_TK_PAIR_CHARGED = 10, /* near field of the charged particles (core)   */
   RBE_TK_PAIR_SHELL = 11, /* reserved: the shell of Eq. 11 is timed with
                              RBE_TK_PAIR_CHARGED (one fused launch)          */

@@ -1100,10 +1100,18 @@ extern "C" int rbe_step(rbe_ctx *c, rbe_state *s, int32_t nsteps, uint64_t first
   HIP_TRY(c, hipMemcpyAsync(A->id, s->id, bi, hipMemcpyDeviceToDevice, st));
   const double h = 0.5 * c->p.dt / c->p.mass;
   const bool near = (c->p.terms & (RBE_TERM_LJ | RBE_TERM_COUL_REAL)) != 0;
+  const double *mean = (c->pp.rbl && near) ? c->mean : nullptr;
   for (int32_t k = 0; k < nsteps; ++k) {
     {
+      // step 0 starts from the caller's forces; later steps fuse the previous
+      // step's second half-kick into this one's first half-kick and drift
       TScope ts(c, RBE_TK_KICK_DRIFT, st);
-      launch_kick_drift(n, h, c->p.dt, c->g, A->fx, A->fy, A->fz, A->vx, A->vy, A->vz, A->x, A->y, A->z, c->err, st);
+      if (k == 0)
+        launch_kick_drift(n, h, c->p.dt, c->g, A->fx, A->fy, A->fz, A->vx, A->vy, A->vz, A->x, A->y, A->z, c->err,
+                          st);
+      else
+        launch_kick_kick_drift(n, h, c->p.dt, c->g, mean, A->fx, A->fy, A->fz, A->vx, A->vy, A->vz, A->x, A->y,
+                               A->z, c->err, st);
     }
     {
       TScope ts(c, RBE_TK_BIN, st);
@@ -1116,10 +1124,9 @@ extern "C" int rbe_step(rbe_ctx *c, rbe_state *s, int32_t nsteps, uint64_t first
     }
     rc = eval_sorted(c, n, nq, nullptr, nullptr, first_eval + (uint64_t)k, nullptr, B->fx, B->fy, B->fz, st);
     if (rc != RBE_OK) return rc;
-    {
+    if (k == nsteps - 1) {
       TScope ts(c, RBE_TK_KICK, st);
-      launch_kick(n, h, (c->pp.rbl && near) ? c->mean : nullptr, B->fx, B->fy, B->fz, B->vx, B->vy, B->vz, c->err,
-                  st);
+      launch_kick(n, h, mean, B->fx, B->fy, B->fz, B->vx, B->vy, B->vz, c->err, st);
     }
     std::swap(A, B);
   }

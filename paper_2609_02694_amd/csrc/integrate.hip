@@ -204,6 +204,46 @@ __global__ void __launch_bounds__(256) k_kick_drift(int64_t n, double h, double 
   if (!isfinite(u) || !isfinite(v) || !isfinite(w)) atomicOr(err, kErrNonFinite);
 }
 
+// The second half-kick of one step followed by the first half-kick and drift
+// of the next (both half-kicks with the same force, mean-corrected when
+// `mean` is given), in one pass: the same two roundings of v as the separate
+// kernels, without writing the corrected force back (the next evaluation
+// overwrites it).
+__global__ void __launch_bounds__(256) k_kick_kick_drift(int64_t n, double h, double dt, Grid g,
+                                                         const double *__restrict__ mean,
+                                                         const double *__restrict__ fx,
+                                                         const double *__restrict__ fy,
+                                                         const double *__restrict__ fz, double *__restrict__ vx,
+                                                         double *__restrict__ vy, double *__restrict__ vz,
+                                                         double *__restrict__ x, double *__restrict__ y,
+                                                         double *__restrict__ z, int *err) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double a = fx[i], b = fy[i], c = fz[i];
+  if (mean) {
+    a -= mean[0];
+    b -= mean[1];
+    c -= mean[2];
+  }
+  const double u1 = vx[i] + h * a, v1 = vy[i] + h * b, w1 = vz[i] + h * c;
+  const double u = u1 + h * a, v = v1 + h * b, w = w1 + h * c;
+  vx[i] = u;
+  vy[i] = v;
+  vz[i] = w;
+  x[i] = wrap_coord(x[i] + dt * u, g.L[0]);
+  y[i] = wrap_coord(y[i] + dt * v, g.L[1]);
+  z[i] = wrap_coord(z[i] + dt * w, g.L[2]);
+  if (!isfinite(u1) || !isfinite(v1) || !isfinite(w1) || !isfinite(u) || !isfinite(v) || !isfinite(w))
+    atomicOr(err, kErrNonFinite);
+}
+void launch_kick_kick_drift(int64_t n, double h, double dt, const Grid &g, const double *mean, const double *fx,
+                            const double *fy, const double *fz, double *vx, double *vy, double *vz, double *x,
+                            double *y, double *z, int *err, hipStream_t st) {
+  if (n <= 0) return;
+  k_kick_kick_drift<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, h, dt, g, mean, fx, fy, fz, vx, vy, vz, x, y, z,
+                                                                 err);
+}
+
 void launch_kick_drift(int64_t n, double h, double dt, const Grid &g, const double *fx, const double *fy,
                        const double *fz, double *vx, double *vy, double *vz, double *x, double *y, double *z, int *err,
                        hipStream_t st) {

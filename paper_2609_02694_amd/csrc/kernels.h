@@ -151,6 +151,9 @@ void launch_kick(int64_t n, double h, const double *mean, double *fx, double *fy
 // f -= mean in place.
 void launch_sub_mean(int64_t n, const double *mean, double *fx, double *fy, double *fz, hipStream_t st);
 // v += h f; x <- wrap(x + dt v).
+void launch_kick_kick_drift(int64_t n, double h, double dt, const Grid &g, const double *mean, const double *fx,
+                            const double *fy, const double *fz, double *vx, double *vy, double *vz, double *x,
+                            double *y, double *z, int *err, hipStream_t st);
 void launch_kick_drift(int64_t n, double h, double dt, const Grid &g, const double *fx, const double *fy,
                        const double *fz, double *vx, double *vy, double *vz, double *x, double *y, double *z,
                        int *err, hipStream_t st);
