@@ -673,15 +673,17 @@ static int charge_stats(rbe_ctx *c, int64_t n, const double *q, hipStream_t st, 
 // one force evaluation on sorted data (ws[1] receives the sorted force)
 // ---------------------------------------------------------------------------
 // Inputs in c->srt (xq, sq, id) and c->cell_start; output in fx/fy/fz (sorted).
+// inv_ready: the id -> slot map was already written (by the step's reorder)
+// and the ids were validated earlier in the same call.
 static int eval_sorted(rbe_ctx *c, int64_t n, int64_t nq, const int32_t *m, const double *w, uint64_t eval,
-                       double *rho_out, double *fx, double *fy, double *fz, hipStream_t st) {
+                       double *rho_out, double *fx, double *fy, double *fz, hipStream_t st, bool inv_ready = false) {
   const int P = c->p.P;
   const int terms = c->p.terms;
   if (terms & (RBE_TERM_LJ | RBE_TERM_COUL_REAL)) {
     PairParams pp = c->pp;
     pp.shell_key = shell_eval_key(c->p.seed, eval);
     pp.shell_T0 = shell_first_threshold(pp, n);
-    if (pp.rbl) {
+    if (pp.rbl && !inv_ready) {
       TScope ts(c, RBE_TK_REORDER, st);
       launch_inverse_ids(n, c->srt.id, c->inv_id, c->err, st);
     }
@@ -1050,14 +1052,18 @@ extern "C" int rbe_forces(rbe_ctx *c, const rbe_state *s, const int32_t *m, cons
 }
 
 // Reorder the working set through perm and pack the sorted records in one pass.
+// With inv (random batch list), also the id -> slot map: inv[id] = k for ids
+// inside [0, n) (the ids were validated by the call's first evaluation).
 __global__ void __launch_bounds__(256) k_reorder_pack(int64_t n, const int32_t *__restrict__ perm, StateArrays in,
                                                       StateArrays out, Grid g, double4 *__restrict__ xq,
-                                                      double4 *__restrict__ sq, int32_t *__restrict__ ids) {
+                                                      double4 *__restrict__ sq, int32_t *__restrict__ ids,
+                                                      int32_t *__restrict__ inv) {
   const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (k >= n) return;
   const int j = perm[k];
   const double x = in.x[j], y = in.y[j], z = in.z[j], q = in.q[j];
   const int32_t id = in.id[j];
+  if (inv && (uint32_t)id < (uint32_t)n) inv[id] = (int32_t)k;
   out.x[k] = x;
   out.y[k] = y;
   out.z[k] = z;
@@ -1119,10 +1125,13 @@ extern "C" int rbe_step(rbe_ctx *c, rbe_state *s, int32_t nsteps, uint64_t first
     }
     {
       TScope ts(c, RBE_TK_REORDER, st);
+      // from the second step on, the reorder also writes the id -> slot map
+      // of the random batch list (the first step's evaluation validates ids)
+      int32_t *inv = (k > 0 && c->pp.rbl && near) ? c->inv_id : nullptr;
       k_reorder_pack<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, c->perm, A->arrays(), B->arrays(), c->g,
-                                                                   c->srt.xq, c->srt.sq, c->srt.id);
+                                                                   c->srt.xq, c->srt.sq, c->srt.id, inv);
     }
-    rc = eval_sorted(c, n, nq, nullptr, nullptr, first_eval + (uint64_t)k, nullptr, B->fx, B->fy, B->fz, st);
+    rc = eval_sorted(c, n, nq, nullptr, nullptr, first_eval + (uint64_t)k, nullptr, B->fx, B->fy, B->fz, st, k > 0);
     if (rc != RBE_OK) return rc;
     if (k == nsteps - 1) {
       TScope ts(c, RBE_TK_KICK, st);

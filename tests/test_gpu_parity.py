@@ -290,6 +290,31 @@ def test_forces_ghost_shell_with_random_batch_list():
     assert e < TOL64
 
 
+@pytest.mark.parametrize("ghost", [0.0, 6.0])
+def test_step_random_batch_list_fp64(ghost):
+    """Several steps with the random batch list: after the first step the id
+    -> slot map of the batch members comes from the reorder; the final forces
+    must equal a fresh oracle evaluation at the final positions."""
+    p, s = system("electrolyte1m", n=20000, ghost=ghost)
+    params = rbe.params_from_preset(p, prec=rbe.FP64)
+    ctx = rbe.Context(params, p["n"])
+    st = to_device(s)
+    ctx.forces(st, None, None, 0)
+    ctx.step(st, 4, 1)
+    torch.cuda.synchronize()
+    ctx.sync_check()
+    x = st.x.cpu().numpy(); y = st.y.cpu().numpy(); z = st.z.cpu().numpy()
+    q = st.q.cpu().numpy(); ids = st.id.cpu().numpy()
+    m, w = oracle.sample_k(p["seed"], 4, p["L"], p["alpha"], p["P"])
+    ref = oracle.total_force(x, y, z, q, ids, oracle.sys_from_preset(p), m, w, seed=p["seed"], ev=4, cells=False,
+                             components=False)["F"]
+    F = np.stack([st.fx.cpu().numpy(), st.fy.cpu().numpy(), st.fz.cpu().numpy()], axis=1)
+    e = rel_err(F, ref)
+    print(f"RBL 4 steps ghost={ghost} final-force rel err {e:.3e}")
+    assert e < TOL64
+    ctx.close()
+
+
 def test_step_ghost_shell_fp32c():
     p, s = system("subdomain64m", n=30000)
     params = rbe.params_from_preset(p, prec=rbe.FP32C)
