@@ -286,7 +286,7 @@ __global__ void __launch_bounds__(64, 5) k_pair_rbl(PairCtx c) {
       const double dy = min_image(I.yi - pj.y, g.L[1]);
       const double dz = min_image(I.zi - pj.z, g.L[2]);
       const double r2 = sq_dist(dx, dy, dz);
-      sh.template add<true>(pp, c.pf, r2, I.qi, pj.w, dx, dy, dz);
+      sh.template add<true, true>(pp, c.pf, r2, I.qi, pj.w, dx, dy, dz);
       if (COUNT) {
         n_coul += (pp.do_coul && I.qi != 0.0 && pj.w != 0.0);
         n_lj += (pp.do_lj && r2 <= pp.rlj2);
