@@ -71,8 +71,9 @@ struct rbe_ctx {
   FourierBuffers fb{};
   GhostBuffers gb{};
   bool ghosts = false;
-  int32_t *m_dev = nullptr;
-  double *w_dev = nullptr;
+  int32_t *m_dev = nullptr;  // [kSampleSteps][3][P] mode samples (rbe_step draws them ahead)
+  double *w_dev = nullptr;   // [kSampleSteps][P]
+  double *mkd_dev = nullptr; // [kSampleSteps][3][P] the same modes as doubles
   double *mean_part = nullptr, *mean = nullptr;
   int *err = nullptr;
   int32_t *nq_dev = nullptr;
@@ -150,6 +151,9 @@ static void timer_flush(rbe_ctx *c, hipStream_t st) {
   t.kind.clear();
   t.count.clear();
 }
+
+// Evaluations whose mode samples rbe_step draws in one launch.
+constexpr int kSampleSteps = 32;
 
 struct TScope {
   rbe_ctx *c;
@@ -395,8 +399,9 @@ extern "C" int rbe_create(rbe_ctx **out, const rbe_params *p, int64_t n_max, int
   c->fb.part = b.alloc<double2>(nchunk * P);
   c->fb.rho = b.alloc<double>(2 * P);
   c->fb.modes = b.alloc<GatherMode>(P);
-  c->m_dev = b.alloc<int32_t>(3 * P);
-  c->w_dev = b.alloc<double>(P);
+  c->m_dev = b.alloc<int32_t>((int64_t)kSampleSteps * 3 * P);
+  c->w_dev = b.alloc<double>((int64_t)kSampleSteps * P);
+  c->mkd_dev = b.alloc<double>((int64_t)kSampleSteps * 3 * P);
   c->mean_part = b.alloc<double>(3 * (int64_t)mean_blocks(n_max) + 3);
   c->mean = b.alloc<double>(3);
   c->err = b.alloc<int>(1);
@@ -674,9 +679,11 @@ static int charge_stats(rbe_ctx *c, int64_t n, const double *q, hipStream_t st, 
 // ---------------------------------------------------------------------------
 // Inputs in c->srt (xq, sq, id) and c->cell_start; output in fx/fy/fz (sorted).
 // inv_ready: the id -> slot map was already written (by the step's reorder)
-// and the ids were validated earlier in the same call.
+// and the ids were validated earlier in the same call. mkd_pre: the modes m
+// as doubles, drawn ahead by rbe_step (then m and w are that draw).
 static int eval_sorted(rbe_ctx *c, int64_t n, int64_t nq, const int32_t *m, const double *w, uint64_t eval,
-                       double *rho_out, double *fx, double *fy, double *fz, hipStream_t st, bool inv_ready = false) {
+                       double *rho_out, double *fx, double *fy, double *fz, hipStream_t st, bool inv_ready = false,
+                       const double *mkd_pre = nullptr) {
   const int P = c->p.P;
   const int terms = c->p.terms;
   if (terms & (RBE_TERM_LJ | RBE_TERM_COUL_REAL)) {
@@ -715,27 +722,30 @@ static int eval_sorted(rbe_ctx *c, int64_t n, int64_t nq, const int32_t *m, cons
     launch_fill_f64(fz, n, 0.0, st);
   }
   if (terms & RBE_TERM_FOURIER) {
-    {
+    FourierBuffers fb = c->fb;
+    if (mkd_pre) {
+      fb.mkd = const_cast<double *>(mkd_pre);  // drawn ahead with the modes
+    } else {
       TScope ts(c, RBE_TK_SAMPLE, st);
       if (!m) {
         launch_sample_modes(c->mt, c->cdf_dev, c->p.seed, eval, P, c->m_dev, c->w_dev, c->err, st);
         m = c->m_dev;
         w = c->w_dev;
       }
-      launch_modes_to_double(P, m, c->fb.mkd, st);
+      launch_modes_to_double(P, m, fb.mkd, st);
     }
     int nchunks;
     {
       TScope ts(c, RBE_TK_RHO_PARTIAL, st);
-      nchunks = launch_rho_partial(c->p.prec, nq, P, c->srt.sq, c->fb, st);
+      nchunks = launch_rho_partial(c->p.prec, nq, P, c->srt.sq, fb, st);
     }
     {
       TScope ts(c, RBE_TK_RHO_FINAL, st);
-      launch_rho_final(nchunks, P, c->fb, w, rho_out, st);
+      launch_rho_final(nchunks, P, fb, w, rho_out, st);
     }
     {
       TScope ts(c, RBE_TK_GATHER, st);
-      launch_fourier_gather(c->p.prec, nq, P, c->srt.sq, c->fb, c->g, fx, fy, fz, st);
+      launch_fourier_gather(c->p.prec, nq, P, c->srt.sq, fb, c->g, fx, fy, fz, st);
     }
   }
   return RBE_OK;
@@ -1106,6 +1116,7 @@ extern "C" int rbe_step(rbe_ctx *c, rbe_state *s, int32_t nsteps, uint64_t first
   HIP_TRY(c, hipMemcpyAsync(A->id, s->id, bi, hipMemcpyDeviceToDevice, st));
   const double h = 0.5 * c->p.dt / c->p.mass;
   const bool near = (c->p.terms & (RBE_TERM_LJ | RBE_TERM_COUL_REAL)) != 0;
+  const bool fourier = (c->p.terms & RBE_TERM_FOURIER) != 0;
   const double *mean = (c->pp.rbl && near) ? c->mean : nullptr;
   for (int32_t k = 0; k < nsteps; ++k) {
     {
@@ -1131,7 +1142,17 @@ extern "C" int rbe_step(rbe_ctx *c, rbe_state *s, int32_t nsteps, uint64_t first
       k_reorder_pack<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, c->perm, A->arrays(), B->arrays(), c->g,
                                                                    c->srt.xq, c->srt.sq, c->srt.id, inv);
     }
-    rc = eval_sorted(c, n, nq, nullptr, nullptr, first_eval + (uint64_t)k, nullptr, B->fx, B->fy, B->fz, st, k > 0);
+    const int64_t P = c->p.P;
+    const int ks = k % kSampleSteps;
+    if (fourier && ks == 0) {
+      // the mode samples of the next kSampleSteps evaluations in one launch
+      TScope ts(c, RBE_TK_SAMPLE, st);
+      launch_sample_modes(c->mt, c->cdf_dev, c->p.seed, first_eval + (uint64_t)k, (int)P, c->m_dev, c->w_dev, c->err,
+                          st, std::min(kSampleSteps, nsteps - k), c->mkd_dev);
+    }
+    rc = eval_sorted(c, n, nq, fourier ? c->m_dev + 3 * P * ks : nullptr, fourier ? c->w_dev + P * ks : nullptr,
+                     first_eval + (uint64_t)k, nullptr, B->fx, B->fy, B->fz, st, k > 0,
+                     fourier ? c->mkd_dev + 3 * P * ks : nullptr);
     if (rc != RBE_OK) return rc;
     if (k == nsteps - 1) {
       TScope ts(c, RBE_TK_KICK, st);

@@ -198,8 +198,10 @@ void build_mode_table(const double L[3], double alpha, ModeTable *t, double *cdf
 int sample_modes_host(const ModeTable &t, const double *cdf, uint64_t seed, uint64_t eval, int P, int32_t *m,
                       double *w);
 // Device sampler launch (cdf is a device copy of the host table).
+// nev consecutive evaluations from eval (sample y at m + 3P y, w + P y, and
+// the mode vectors as doubles at mkd + 3P y when mkd is given).
 void launch_sample_modes(const ModeTable &t, const double *cdf_dev, uint64_t seed, uint64_t eval, int P,
-                         int32_t *m, double *w, int *err_flag, hipStream_t st);
+                         int32_t *m, double *w, int *err_flag, hipStream_t st, int nev = 1, double *mkd = nullptr);
 
 // ---------------------------------------------------------------------------
 // Error flag bits (device int)

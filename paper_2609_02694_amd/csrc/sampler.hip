@@ -59,26 +59,38 @@ int sample_modes_host(const ModeTable &t, const double *cdf, uint64_t seed, uint
   return 0;
 }
 
+// Evaluation eval + blockIdx.y writes its sample at m + 3P y, w + P y (and
+// the mode vectors as doubles at mkd + 3P y when mkd is given).
 __global__ void __launch_bounds__(256) k_sample_modes(ModeTable t, const double *__restrict__ cdf, uint64_t seed,
                                                       uint64_t eval, int P, int32_t *__restrict__ m,
-                                                      double *__restrict__ w, int *err) {
+                                                      double *__restrict__ w, double *__restrict__ mkd, int *err) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= P) return;
-  const uint64_t ek = stream_out(seed ^ kTagModes, eval);
+  const int y = blockIdx.y;
+  const uint64_t ek = stream_out(seed ^ kTagModes, eval + (uint64_t)y);
   int mv[3];
   if (!draw_mode(t, cdf, ek, l, mv)) {
     atomicOr(err, kErrSampler);
     mv[0] = 1; mv[1] = 0; mv[2] = 0;
   }
-  m[l] = mv[0];
-  m[P + l] = mv[1];
-  m[2 * P + l] = mv[2];
-  w[l] = mode_weight(t, P, mv[0], mv[1], mv[2]);
+  int32_t *my = m + (int64_t)3 * P * y;
+  my[l] = mv[0];
+  my[P + l] = mv[1];
+  my[2 * P + l] = mv[2];
+  w[(int64_t)P * y + l] = mode_weight(t, P, mv[0], mv[1], mv[2]);
+  if (mkd) {
+    double *dy = mkd + (int64_t)3 * P * y;
+    dy[l] = (double)mv[0];
+    dy[P + l] = (double)mv[1];
+    dy[2 * P + l] = (double)mv[2];
+  }
 }
 
 void launch_sample_modes(const ModeTable &t, const double *cdf_dev, uint64_t seed, uint64_t eval, int P, int32_t *m,
-                         double *w, int *err_flag, hipStream_t st) {
-  k_sample_modes<<<(P + 255) / 256, 256, 0, st>>>(t, cdf_dev, seed, eval, P, m, w, err_flag);
+                         double *w, int *err_flag, hipStream_t st, int nev, double *mkd) {
+  if (nev < 1) return;
+  k_sample_modes<<<dim3((unsigned)((P + 255) / 256), (unsigned)nev), 256, 0, st>>>(t, cdf_dev, seed, eval, P, m, w,
+                                                                                   mkd, err_flag);
 }
 
 }  // namespace rbe
