@@ -14,7 +14,7 @@
  *   F_i^F  Fourier part by importance sampling (Eq. 9): P modes k_l drawn from
  *          P(k) ~ exp(-k^2/(4 alpha)) on the reciprocal lattice without k = 0,
  *          structure factors rho(k_l) = sum_j q_j exp(i k_l . r_j) (Eq. 5) and
- *          F_i^F = -q_i sum_l w_l k_l Im(exp(-i k_l . r_i) rho(k_l)),
+ *          F_i^F = -kc q_i sum_l w_l k_l Im(exp(-i k_l . r_i) rho(k_l)),
  *          w_l = (S/P) 4 pi / (V k_l^2), S = sum_{k != 0} exp(-k^2/(4 alpha)).
  *
  * alpha is the paper's alpha: the real-space kernel is erfc(sqrt(alpha) r)/r
@@ -74,7 +74,8 @@ typedef struct {
                          library choose: edge about max(r_lj, r_coul / 2) along y
                          and z, x cells four times finer                           */
   double lj_eps, lj_sigma; /* LJ parameters of Eq. 2                                   */
-  double coulomb_k;   /* Coulomb prefactor (1 in reduced units)                        */
+  double coulomb_k;   /* Coulomb prefactor kc (1 in reduced units); scales every
+                         Coulomb term: real space, Fourier part and the energies      */
   double mass, dt;    /* particle mass and velocity-Verlet time step                   */
   double ghost_width; /* 0: periodic traversal; > 0: near field over a locally built
                          shell of periodic ghost copies of this width (>= r_coul)       */
@@ -160,6 +161,34 @@ int rbe_sample_k(const rbe_params *p /* host */, uint64_t eval, int32_t *m, doub
    rho_out, if not NULL, receives Re rho | Im rho (2*P doubles, device). */
 int rbe_forces(rbe_ctx *ctx, const rbe_state *s, const int32_t *m, const double *w, uint64_t eval,
                double *rho_out, void *stream);
+
+/* Energy terms of Sec. 2.1 for the state as given (diagnostics: energy
+   conservation, thermodynamics), computed in FP64 whatever the context's
+   precision, into u_out[0..RBE_ENERGY_TERMS) (device doubles):
+     [RBE_U_COUL_REAL] kc sum_{i<j} q_i q_j erfc(sqrt(alpha) r)/r over every
+                       pair with r <= r_coul (minimum image): the screened
+                       part of Eq. 4, the energy whose gradient is the near
+                       field of Eq. 7-8. The random batch list of Eq. 10-11
+                       is a force estimator only: every pair inside the
+                       cutoff is counted here;
+     [RBE_U_LJ]        sum_{i<j} 4 eps ((sigma/r)^12 - (sigma/r)^6) over
+                       r <= r_lj (Eq. 2, plain truncation, no shift);
+     [RBE_U_FOURIER]   kc (1/2) sum_l w_l |rho(k_l)|^2 = kc (S/P)(2 pi/V)
+                       sum_l |rho(k_l)|^2 / k_l^2: the importance-sampling
+                       estimate of Eq. 5 with the modes of Eq. 9. (m, w) is
+                       the mode sample (device); m NULL draws the one of
+                       `eval`, the same as rbe_forces and rbe_sample_k;
+     [RBE_U_SELF]      kc sqrt(alpha/pi) sum_i q_i^2 (Eq. 6);
+     [RBE_U_KINETIC]   (mass/2) sum_i |v_i|^2, 0 when s->vx..vz are NULL.
+   The potential energy is U_COUL_REAL + U_LJ + U_FOURIER - U_SELF. Terms
+   left out of the context's `terms` mask are 0 (U_SELF goes with the
+   Fourier term). Only s->x, y, z, q (and v when given) are read; f and id
+   may be NULL. rho_out as in rbe_forces. Not available on a batched
+   context. */
+enum { RBE_U_COUL_REAL = 0, RBE_U_LJ = 1, RBE_U_FOURIER = 2, RBE_U_SELF = 3, RBE_U_KINETIC = 4,
+       RBE_ENERGY_TERMS = 5 };
+int rbe_energy(rbe_ctx *ctx, const rbe_state *s, const int32_t *m, const double *w, uint64_t eval,
+               double *u_out, double *rho_out, void *stream);
 
 /* nsteps velocity-Verlet steps:
      v += dt/(2m) F;  x <- wrap(x + dt v);  F <- force(x, eval = first_eval + k);

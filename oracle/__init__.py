@@ -68,6 +68,8 @@ def _load():
         "orc_real_energy": (None, [i64, _D, _D, _D, _D, S, _D, _D]),
         "orc_ewald_exact": (None, [i64, _D, _D, _D, _D, _D, d, d, _D, _D, _D, _D, _D, _D]),
         "orc_full_lattice": (i64, [_D, d, _I32, _I32, _D]),
+        "orc_self_energy": (d, [i64, _D, d]),
+        "orc_kinetic_energy": (d, [i64, _D, _D, _D, d]),
         "orc_bin": (ctypes.c_int, [i64, _D, _D, _D, _D, _D, _I32, _I32, _I32]),
         "orc_kick": (None, [i64, d, _D, _D, _D, _D, _D, _D]),
         "orc_drift_wrap": (None, [i64, d, _D, _D, _D, _D, _D, _D, _D]),
@@ -106,7 +108,8 @@ def make_sys(L, alpha, r_coul, r_lj, r_core=0.0, p_shell=0, eps=1.0, sigma=1.0, 
 
 
 def sys_from_preset(p: dict) -> OrcSys:
-    return make_sys(p["L"], p["alpha"], p["r_coul"], p["r_lj"], p.get("r_core", 0.0), p.get("p_shell", 0))
+    return make_sys(p["L"], p["alpha"], p["r_coul"], p["r_lj"], p.get("r_core", 0.0), p.get("p_shell", 0),
+                    kc=p.get("kc", 1.0))
 
 
 # --------------------------------------------------------------------------
@@ -232,6 +235,17 @@ def real_energy(x, y, z, q, sys: OrcSys):
     return uc.value, ul.value
 
 
+def self_energy(q, alpha) -> float:
+    (q, pq) = _d(q)
+    return _load().orc_self_energy(len(q), pq, alpha)
+
+
+def kinetic_energy(v, mass) -> float:
+    v = np.asarray(v, np.float64)
+    cols = [_d(v[:, d]) for d in range(3)]
+    return _load().orc_kinetic_energy(v.shape[0], *[c[1] for c in cols], mass)
+
+
 def ewald_exact(x, y, z, q, L, alpha, tol=1e-17):
     """Exact Ewald energy parts (real, recip, self) and total force."""
     (x, px), (y, py), (z, pz), (q, pq) = _d(x), _d(y), _d(z), _d(q)
@@ -304,8 +318,28 @@ def total_force(x, y, z, q, ids, sys: OrcSys, m, w, seed=0, ev=0, terms=LJ | COU
     FF = np.zeros((n, 3))
     if terms & FOURIER:
         FF, re, im = fourier_force(x, y, z, q, sys.L, m, w)
+        FF = sys.kc * FF  # the Coulomb prefactor scales the Fourier part too
         out["rho_re"], out["rho_im"] = re, im
     out["fourier"] = FF
     out["near"] = FN
     out["F"] = FN + FF
+    return out
+
+
+def energy_terms(x, y, z, q, sys: OrcSys, m, w, v=None, mass=1.0, terms=LJ | COUL_REAL | FOURIER):
+    """Energy terms of Sec. 2.1 for a fixed mode sample (m, w):
+    coul_real = kc sum_{i<j} q_i q_j erfc(sqrt(a) r)/r within r_coul (Eq. 4),
+    lj = sum_{i<j} 4 eps ((sigma/r)^12 - (sigma/r)^6) within r_lj (Eq. 2),
+    fourier = kc (1/2) sum_l w_l |rho_l|^2 (Eq. 5 sampled as in Eq. 9),
+    self = kc sqrt(a/pi) sum q^2 (Eq. 6), kinetic = (m/2) sum |v|^2.
+    The potential is coul_real + lj + fourier - self; its negative gradient
+    at fixed modes is total_force without the random batch list."""
+    uc, ul = real_energy(x, y, z, q, sys)
+    out = dict(coul_real=uc if terms & COUL_REAL else 0.0, lj=ul if terms & LJ else 0.0, fourier=0.0, self=0.0)
+    if terms & FOURIER:
+        re, im = rho(x, y, z, q, sys.L, m)
+        out["fourier"] = sys.kc * fourier_energy(w, re, im)
+        out["self"] = sys.kc * self_energy(q, sys.alpha)
+    out["kinetic"] = kinetic_energy(v, mass) if v is not None else 0.0
+    out["potential"] = out["coul_real"] + out["lj"] + out["fourier"] - out["self"]
     return out

@@ -564,12 +564,23 @@ void orc_ewald_exact(int64_t n, const double *x, const double *y, const double *
       }
   for (int64_t i = 0; i < n; ++i) { fx[i] += gx[i]; fy[i] += gy[i]; fz[i] += gz[i]; }
   free(gx); free(gy); free(gz);
-  double us = 0.0;
-  for (int64_t i = 0; i < n; ++i) us += q[i] * q[i];
-  us *= sqrt(alpha / PI);
   *u_real = ur;
   *u_recip = uk;
-  *u_self = us;
+  *u_self = orc_self_energy(n, q, alpha);
+}
+
+/* Self energy (Eq. 6): sqrt(a/pi) sum_i q_i^2. */
+double orc_self_energy(int64_t n, const double *q, double alpha) {
+  double us = 0.0;
+  for (int64_t i = 0; i < n; ++i) us += q[i] * q[i];
+  return us * sqrt(alpha / PI);
+}
+
+/* Kinetic energy (m/2) sum_i |v_i|^2. */
+double orc_kinetic_energy(int64_t n, const double *vx, const double *vy, const double *vz, double mass) {
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i) s += vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i];
+  return 0.5 * mass * s;
 }
 
 int64_t orc_full_lattice(const double L[3], double alpha, const int32_t mmax[3], int32_t *m, double *w) {

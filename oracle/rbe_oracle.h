@@ -73,6 +73,9 @@ void orc_real_energy(int64_t n, const double *x, const double *y, const double *
 void orc_ewald_exact(int64_t n, const double *x, const double *y, const double *z, const double *q,
                      const double L[3], double alpha, double tol, double *u_real, double *u_recip, double *u_self,
                      double *fx, double *fy, double *fz);
+/* Self energy of Eq. 6 (without a Coulomb prefactor) and the kinetic energy. */
+double orc_self_energy(int64_t n, const double *q, double alpha);
+double orc_kinetic_energy(int64_t n, const double *vx, const double *vy, const double *vz, double mass);
 /* Deterministic full-lattice mode set with weights 4 pi exp(-k^2/4a)/(V k^2),
    all m != 0 with |m_d| <= mmax[d]. Returns the mode count (m, w may be NULL
    to query it). */

@@ -23,8 +23,9 @@ MAX_P = 4096
 MAX_SHELL_BATCH = 32
 
 EXPORTED = ["rbe_create", "rbe_create_batch", "rbe_destroy", "rbe_last_error", "rbe_build_cells", "rbe_sample_k",
-            "rbe_forces", "rbe_step", "rbe_sync_check", "rbe_set_counting", "rbe_get_counters", "rbe_set_timing",
+            "rbe_forces", "rbe_energy", "rbe_step", "rbe_sync_check", "rbe_set_counting", "rbe_get_counters", "rbe_set_timing",
             "rbe_get_timing"]
+ENERGY_NAMES = ["coul_real", "lj", "fourier", "self", "kinetic"]
 TIMING_KINDS = ["bin", "reorder", "pair_neutral", "mean", "sample", "rho_partial", "rho_final", "gather",
                 "kick_drift", "kick", "pair_charged", "pair_shell", "ghost", "batch"]
 
@@ -80,6 +81,7 @@ def load():
         "rbe_build_cells": [vp, vp, vp, vp, vp, i64, vp, vp, vp],
         "rbe_sample_k": [P, u64, vp, vp, ctypes.c_int, vp],
         "rbe_forces": [vp, ctypes.POINTER(State), vp, vp, u64, vp, vp],
+        "rbe_energy": [vp, ctypes.POINTER(State), vp, vp, u64, vp, vp, vp],
         "rbe_step": [vp, ctypes.POINTER(State), i32, u64, vp],
         "rbe_sync_check": [vp, vp],
         "rbe_set_counting": [vp, ctypes.c_int],
@@ -115,7 +117,7 @@ def make_params(L, alpha, r_coul, r_lj, P, r_core=0.0, p_shell=0, prec=FP64, ter
 
 def params_from_preset(pr: dict, prec=FP64, terms=TERM_ALL, ncell=(0, 0, 0), seed=None) -> Params:
     return make_params(pr["L"], pr["alpha"], pr["r_coul"], pr["r_lj"], pr["P"], pr.get("r_core", 0.0),
-                       pr.get("p_shell", 0), prec, terms, ncell, dt=pr.get("dt", 0.002),
+                       pr.get("p_shell", 0), prec, terms, ncell, kc=pr.get("kc", 1.0), dt=pr.get("dt", 0.002),
                        ghost_width=pr.get("ghost", 0.0), seed=pr["seed"] if seed is None else seed)
 
 
@@ -261,6 +263,18 @@ class Context:
         s = st.as_struct()
         self._ok(self.lib.rbe_forces(self.h, ctypes.byref(s), _ptr(m), _ptr(w), ev, _ptr(rho_out),
                                      _stream(stream)))
+
+    def energy(self, st: Particles, m=None, w=None, ev: int = 0, with_kinetic: bool = True, rho_out=None,
+               stream=None):
+        """Energy terms (device float64 tensor of ENERGY_TERMS entries, see ENERGY_NAMES)."""
+        import torch
+        s = st.as_struct()
+        if not with_kinetic:
+            s.vx = s.vy = s.vz = None
+        u = torch.empty(len(ENERGY_NAMES), dtype=torch.float64, device=st.x.device)
+        self._ok(self.lib.rbe_energy(self.h, ctypes.byref(s), _ptr(m), _ptr(w), ev, _ptr(u), _ptr(rho_out),
+                                     _stream(stream)))
+        return u
 
     def step(self, st: Particles, nsteps: int, first_eval: int, stream=None):
         s = st.as_struct()

@@ -75,6 +75,7 @@ struct rbe_ctx {
   double *w_dev = nullptr;   // [kSampleSteps][P]
   double *mkd_dev = nullptr; // [kSampleSteps][3][P] the same modes as doubles
   double *mean_part = nullptr, *mean = nullptr;
+  double *epart = nullptr;   // energy partial sums
   int *err = nullptr;
   int32_t *nq_dev = nullptr;
   double *qstats = nullptr;  // [sum q, sum |q|]
@@ -404,6 +405,7 @@ extern "C" int rbe_create(rbe_ctx **out, const rbe_params *p, int64_t n_max, int
   c->mkd_dev = b.alloc<double>((int64_t)kSampleSteps * 3 * P);
   c->mean_part = b.alloc<double>(3 * (int64_t)mean_blocks(n_max) + 3);
   c->mean = b.alloc<double>(3);
+  c->epart = b.alloc<double>(energy_part_len(n_max));
   c->err = b.alloc<int>(1);
   c->nq_dev = b.alloc<int32_t>(1);
   c->qstats = b.alloc<double>(2);
@@ -741,7 +743,7 @@ static int eval_sorted(rbe_ctx *c, int64_t n, int64_t nq, const int32_t *m, cons
     }
     {
       TScope ts(c, RBE_TK_RHO_FINAL, st);
-      launch_rho_final(nchunks, P, fb, w, rho_out, st);
+      launch_rho_final(nchunks, P, fb, w, c->p.coulomb_k, rho_out, st);
     }
     {
       TScope ts(c, RBE_TK_GATHER, st);
@@ -1057,6 +1059,53 @@ extern "C" int rbe_forces(rbe_ctx *c, const rbe_state *s, const int32_t *m, cons
   if (rc != RBE_OK) return rc;
   if (c->pp.rbl && (c->p.terms & (RBE_TERM_LJ | RBE_TERM_COUL_REAL))) launch_sub_mean(n, c->mean, o.fx, o.fy, o.fz, st);
   launch_scatter_forces(n, c->perm, o.fx, o.fy, o.fz, s->fx, s->fy, s->fz, st);
+  HIP_TRY(c, hipGetLastError());
+  return RBE_OK;
+}
+
+extern "C" int rbe_energy(rbe_ctx *c, const rbe_state *s, const int32_t *m, const double *w, uint64_t eval,
+                          double *u_out, double *rho_out, void *stream) {
+  if (!c) return RBE_EINVAL;
+  if (!s || !s->x || !s->y || !s->z || !s->q) return c->fail(RBE_EINVAL, "state has a null position or charge array");
+  if (!u_out) return c->fail(RBE_EINVAL, "u_out is NULL");
+  if ((s->vx == nullptr) != (s->vy == nullptr) || (s->vx == nullptr) != (s->vz == nullptr))
+    return c->fail(RBE_EINVAL, "give all three velocity arrays or none");
+  if (s->n < 1 || s->n > c->n_max)
+    return c->fail(RBE_ERANGE, "n = %lld outside [1, n_max = %lld]", (long long)s->n, (long long)c->n_max);
+  if ((m == nullptr) != (w == nullptr)) return c->fail(RBE_EINVAL, "m and w must both be given or both be NULL");
+  if (c->batched()) return c->fail(RBE_EINVAL, "rbe_energy is not available on a batched context");
+  HIP_TRY(c, hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t n = s->n;
+  int64_t nq = 0;
+  int rc = charge_stats(c, n, s->q, st, &nq);
+  if (rc != RBE_OK) return rc;
+  const bool near = (c->p.terms & (RBE_TERM_LJ | RBE_TERM_COUL_REAL)) != 0;
+  const bool fourier = (c->p.terms & RBE_TERM_FOURIER) != 0;
+  launch_bin(c->bb, c->g, n, s->x, s->y, s->z, s->q, c->cell_start, c->perm, st);
+  launch_gather_sorted(n, c->perm, s->x, s->y, s->z, s->q, s->id, c->g, c->srt, st);
+  const int P = c->p.P;
+  EnergyFinal fin{};
+  if (fourier) {
+    if (!m) {
+      launch_sample_modes(c->mt, c->cdf_dev, c->p.seed, eval, P, c->m_dev, c->w_dev, c->err, st);
+      m = c->m_dev;
+      w = c->w_dev;
+    }
+    launch_modes_to_double(P, m, c->fb.mkd, st);
+    // structure factors always in FP64 here, whatever the context's precision
+    const int nchunks = launch_rho_partial(RBE_FP64, nq, P, c->srt.sq, c->fb, st);
+    launch_rho_final(nchunks, P, c->fb, w, c->p.coulomb_k, rho_out, st);
+    fin.w = w;
+    fin.rho = c->fb.rho;
+  }
+  fin.P = P;
+  fin.kc = c->p.coulomb_k;
+  fin.self_coef = c->p.coulomb_k * std::sqrt(c->p.alpha / kPi);
+  fin.half_mass = 0.5 * c->p.mass;
+  fin.out = u_out;
+  launch_energy(c->pp, 4.0 * c->p.lj_eps, n, nq, c->srt, c->cell_start, near, s->q, s->vx, s->vy, s->vz, c->epart,
+                fin, st);
   HIP_TRY(c, hipGetLastError());
   return RBE_OK;
 }

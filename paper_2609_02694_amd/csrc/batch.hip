@@ -347,7 +347,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchArgs a) {
         im += __shfl_xor(im, o, 64);
       }
       if (lane == 0) {
-        const double w = a.wk[it];
+        const double w = a.pp.kc * a.wk[it];
         a.modes[it].a = w * im;
         a.modes[it].b = w * re;
         a.modes[it].af = (float)(w * im);

@@ -1,6 +1,7 @@
 // Fourier part of the RBE force (Sec. 2.1, Eq. 5, 7, 9; Sec. 2.3.1):
 // structure factors rho(k_l) = sum_j q_j exp(i k_l . r_j) over the charged
-// particles, then F_i = -q_i sum_l w_l k_l Im(exp(-i k_l . r_i) rho_l).
+// particles, then F_i = -kc q_i sum_l w_l k_l Im(exp(-i k_l . r_i) rho_l)
+// (kc the Coulomb prefactor, 1 in reduced units).
 //
 // Phase: k_l . r_j = 2 pi t with t = m_l . s_j (s = r/L, the fractional
 // coordinate). Whole turns are removed in FP64 (t - rint(t), exact for the
@@ -99,7 +100,7 @@ __global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f32c(int64_t nq,
 constexpr int kRhoFinalThreads = 256;
 __global__ void __launch_bounds__(kRhoFinalThreads) k_rho_final(int nchunks, int P, const double2 *__restrict__ part,
                                                                 const double *__restrict__ mkd,
-                                                                const double *__restrict__ w,
+                                                                const double *__restrict__ w, double kc,
                                                                 double *__restrict__ rho,
                                                                 GatherMode *__restrict__ modes,
                                                                 double *__restrict__ rho_out) {
@@ -137,8 +138,9 @@ __global__ void __launch_bounds__(kRhoFinalThreads) k_rho_final(int nchunks, int
     gm.mx = mkd[l];
     gm.my = mkd[P + l];
     gm.mz = mkd[2 * P + l];
-    gm.a = w[l] * im;
-    gm.b = w[l] * re;
+    const double wl = kc * w[l];
+    gm.a = wl * im;
+    gm.b = wl * re;
     gather_floats(gm);
     modes[l] = gm;
   }
@@ -156,8 +158,9 @@ int launch_rho_partial(int prec, int64_t nq, int P, const double4 *sq, const Fou
   return nchunks;
 }
 
-void launch_rho_final(int nchunks, int P, const FourierBuffers &fb, const double *w, double *rho_out, hipStream_t st) {
-  k_rho_final<<<P, kRhoFinalThreads, 0, st>>>(nchunks, P, fb.part, fb.mkd, w, fb.rho, fb.modes, rho_out);
+void launch_rho_final(int nchunks, int P, const FourierBuffers &fb, const double *w, double kc, double *rho_out,
+                      hipStream_t st) {
+  k_rho_final<<<P, kRhoFinalThreads, 0, st>>>(nchunks, P, fb.part, fb.mkd, w, kc, fb.rho, fb.modes, rho_out);
 }
 
 // ---------------------------------------------------------------------------

@@ -18,7 +18,7 @@ __global__ void __launch_bounds__(256) k_gather_sorted(int64_t n, const int32_t 
   const double qq = q[j];
   xq[k] = make_double4(wx, wy, wz, qq);
   if (qq != 0.0) sq[k] = make_double4(wx / g.L[0], wy / g.L[1], wz / g.L[2], qq);
-  ids[k] = id[j];
+  if (id) ids[k] = id[j];
 }
 
 void launch_gather_sorted(int64_t n, const int32_t *perm, const double *x, const double *y, const double *z,

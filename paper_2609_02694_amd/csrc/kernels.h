@@ -33,7 +33,8 @@ struct Sorted {
   double4 *sq;
   int32_t *id;
 };
-// Gather the caller's arrays through perm into the packed sorted records.
+// Gather the caller's arrays through perm into the packed sorted records
+// (id may be nullptr: then s.id is left as it is).
 void launch_gather_sorted(int64_t n, const int32_t *perm, const double *x, const double *y, const double *z,
                           const double *q, const int32_t *id, const Grid &g, Sorted s, hipStream_t st);
 // Build the inverse id map inv[id[k]] = k (flags ids outside [0, n)).
@@ -134,9 +135,34 @@ int rho_chunk(int64_t nq, int P, int prec, int nchunk_max);
 void launch_modes_to_double(int P, const int32_t *m, double *mkd, hipStream_t st);
 // Returns the number of chunk partials written.
 int launch_rho_partial(int prec, int64_t nq, int P, const double4 *sq, const FourierBuffers &fb, hipStream_t st);
-void launch_rho_final(int nchunks, int P, const FourierBuffers &fb, const double *w, double *rho_out, hipStream_t st);
+// The gather coefficients take the weights times kc (the Coulomb prefactor
+// scales the Fourier force like every other Coulomb term).
+void launch_rho_final(int nchunks, int P, const FourierBuffers &fb, const double *w, double kc, double *rho_out,
+                      hipStream_t st);
 void launch_fourier_gather(int prec, int64_t nq, int P, const double4 *sq, const FourierBuffers &fb, const Grid &g,
                            double *fx, double *fy, double *fz, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// energy terms (diagnostics, FP64)
+// ---------------------------------------------------------------------------
+struct EnergyFinal {
+  const double *near_part;  // [2 nb_near] block partials (Coulomb, LJ); set by launch_energy
+  int64_t nb_near;
+  const double *sq_part;    // [2 nb_sq] block partials (q^2, |v|^2); set by launch_energy
+  int64_t nb_sq;
+  const double *w, *rho;    // mode weights [P] and Re | Im rho [2 P]; rho nullptr: no Fourier term
+  int P;
+  double kc, self_coef, half_mass;  // kc, kc sqrt(alpha/pi), mass/2
+  double *out;              // [5] device
+};
+// Length of the partial-sum scratch launch_energy needs for n_max particles.
+int energy_part_len(int64_t n_max);
+// Near-field energies of the sorted particles (when near), the q^2 and v^2
+// sums of the caller's arrays (vx may be nullptr), and the final fixed-order
+// combination into fin.out.
+void launch_energy(const PairParams &pp, double lj4, int64_t n, int64_t nq, const Sorted &s,
+                   const int32_t *cell_start, bool near, const double *q, const double *vx, const double *vy,
+                   const double *vz, double *part, EnergyFinal fin, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // reductions and integration

@@ -1,0 +1,164 @@
+"""GPU parity of the energy terms (rbe_energy) and of the Coulomb prefactor.
+
+The energy terms are computed in FP64 in every context precision. Bound:
+relative error 1e-11 per term against the oracle. The real-space Coulomb sum
+of random ions cancels about a thousandfold (|U| against the sum of |terms|),
+so rounding of 1e-14 relative to the terms' magnitudes can reach 1e-11 of the
+result; the other terms are sums of one sign and sit near 1e-14.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import gpu_forces, oracle_forces, rel_err, system, to_device
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2609_02694_amd as rbe  # noqa: E402
+
+TOL_E = 1e-11
+TOL64 = 1e-12
+NAMES = rbe.ENERGY_NAMES
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rbe.load()
+
+
+def gpu_energy(p, s, prec=rbe.FP64, terms=rbe.TERM_ALL, m=None, w=None, ev=0, ncell=(0, 0, 0), kinetic=True):
+    params = rbe.params_from_preset(p, prec=prec, terms=terms, ncell=ncell)
+    ctx = rbe.Context(params, len(s["x"]))
+    st = to_device(s)
+    md = wd = None
+    if m is not None:
+        md = torch.as_tensor(np.ascontiguousarray(m, np.int32).ravel()).cuda()
+        wd = torch.as_tensor(np.ascontiguousarray(w, np.float64)).cuda()
+    u = ctx.energy(st, md, wd, ev, with_kinetic=kinetic)
+    torch.cuda.synchronize()
+    ctx.sync_check()
+    ctx.close()
+    return dict(zip(NAMES, u.cpu().numpy().tolist()))
+
+
+def oracle_energy(p, s, m, w, terms=oracle.LJ | oracle.COUL_REAL | oracle.FOURIER, kinetic=True):
+    v = np.stack([s["vx"], s["vy"], s["vz"]], axis=1) if kinetic else None
+    return oracle.energy_terms(s["x"], s["y"], s["z"], s["q"], oracle.sys_from_preset(p), m, w, v=v,
+                               terms=terms)
+
+
+def assert_terms_close(got, ref, tol=TOL_E):
+    for k in NAMES:
+        if ref[k] == 0.0:
+            assert got[k] == 0.0, k
+        else:
+            e = abs(got[k] - ref[k]) / abs(ref[k])
+            print(f"  {k}: gpu {got[k]:.15e} oracle {ref[k]:.15e} rel {e:.2e}")
+            assert e < tol, k
+
+
+@pytest.fixture(scope="module")
+def plain3k():
+    p, s = system("plain3k")
+    m, w = oracle.sample_k(p["seed"], 0, p["L"], p["alpha"], p["P"])
+    return p, s, m, w
+
+
+@pytest.mark.parametrize("prec", [rbe.FP64, rbe.FP32C])
+def test_energy_plain3k_matches_oracle(plain3k, prec):
+    p, s, m, w = plain3k
+    got = gpu_energy(p, s, prec=prec, m=m, w=w)
+    assert_terms_close(got, oracle_energy(p, s, m, w))
+
+
+def test_energy_device_drawn_modes_match(plain3k):
+    p, s, m, w = plain3k
+    got = gpu_energy(p, s, m=None, w=None, ev=0)  # the library draws the sample of eval 0
+    assert_terms_close(got, oracle_energy(p, s, m, w))
+
+
+@pytest.mark.parametrize("ncell", [(3, 3, 3), (16, 5, 5)])
+def test_energy_independent_of_cell_grid(plain3k, ncell):
+    p, s, m, w = plain3k
+    assert_terms_close(gpu_energy(p, s, m=m, w=w, ncell=ncell), oracle_energy(p, s, m, w))
+
+
+@pytest.mark.parametrize("terms", [rbe.TERM_LJ, rbe.TERM_COUL_REAL, rbe.TERM_FOURIER])
+def test_energy_terms_mask(plain3k, terms):
+    p, s, m, w = plain3k
+    got = gpu_energy(p, s, terms=terms, m=m, w=w, kinetic=False)
+    assert got["kinetic"] == 0.0
+    assert_terms_close(got, oracle_energy(p, s, m, w, terms=terms, kinetic=False))
+
+
+def test_energy_random_batch_list_context_counts_every_pair():
+    """The random batch list changes forces only: the energy of an RBL
+    context is the full sum inside the cutoffs (20k particles, 25 % ions)."""
+    p, s = system("electrolyte1m", n=20000)
+    m, w = oracle.sample_k(p["seed"], 3, p["L"], p["alpha"], p["P"])
+    got = gpu_energy(p, s, m=m, w=w)
+    assert_terms_close(got, oracle_energy(p, s, m, w))
+
+
+def test_energy_ghost_shell_context():
+    p, s = system("subdomain64m", n=30000)
+    m, w = oracle.sample_k(p["seed"], 0, p["L"], p["alpha"], p["P"])
+    assert p["ghost"] > 0
+    assert_terms_close(gpu_energy(p, s, m=m, w=w), oracle_energy(p, s, m, w))
+
+
+def test_coulomb_prefactor_scales_forces_and_energies():
+    p, s = system("plain3k", n=2000, L=26.2, kc=2.5)
+    m, w = oracle.sample_k(p["seed"], 0, p["L"], p["alpha"], p["P"])
+    ref = oracle_forces(p, s, m, w)
+    F = gpu_forces(p, s, m=m, w=w)
+    assert rel_err(F, ref["F"]) < TOL64
+    Ff = gpu_forces(p, s, terms=rbe.TERM_FOURIER, m=m, w=w)
+    assert rel_err(Ff, ref["fourier"]) < TOL64
+    assert_terms_close(gpu_energy(p, s, m=m, w=w), oracle_energy(p, s, m, w))
+
+
+def test_gpu_force_is_minus_gradient_of_gpu_energy():
+    """Both library entry points on the same fixed modes, no random batch
+    list: central differences of the potential match the force."""
+    p, sub = system("plain3k", n=400, L=16.0)
+    m, w = oracle.sample_k(p["seed"], 0, p["L"], p["alpha"], p["P"])
+    F = gpu_forces(p, sub, m=m, w=w)
+    h = 1e-5
+    for i in (0, 57, 131):
+        for d, key in enumerate("xyz"):
+            sp = dict(sub)
+            sm = dict(sub)
+            sp[key] = sub[key].copy()
+            sm[key] = sub[key].copy()
+            sp[key][i] += h
+            sm[key][i] -= h
+            ep = gpu_energy(p, sp, m=m, w=w, kinetic=False)
+            em = gpu_energy(p, sm, m=m, w=w, kinetic=False)
+            up = ep["coul_real"] + ep["lj"] + ep["fourier"] - ep["self"]
+            um = em["coul_real"] + em["lj"] + em["fourier"] - em["self"]
+            fd = -(up - um) / (2 * h)
+            assert abs(fd - F[i, d]) < 1e-5 * max(1.0, np.abs(F[i]).max()), (i, d, fd, F[i, d])
+
+
+def test_energy_rejected_on_batched_context():
+    p, s = system("replica", n=2000)
+    params = rbe.params_from_preset(p)
+    ctx = rbe.Context.batch([params, params], [0, 2000, 4000])
+    two = {k: np.concatenate([s[k], s[k]]) for k in ("x", "y", "z", "vx", "vy", "vz", "q")}
+    two["id"] = np.arange(4000, dtype=np.int32)
+    with pytest.raises(rbe.RbeError):
+        ctx.energy(to_device(two))
+    ctx.close()
+
+
+def test_energy_self_term_closed_form(plain3k):
+    p, s, m, w = plain3k
+    got = gpu_energy(p, s, m=m, w=w)
+    expect = math.sqrt(p["alpha"] / math.pi) * float(np.sum(np.asarray(s["q"]) ** 2))
+    assert got["self"] == pytest.approx(expect, rel=1e-14)

@@ -422,3 +422,41 @@ def test_vv_energy_error_scales_as_dt_squared():
 
     d1, d2 = energy_dev(0.02), energy_dev(0.01)
     assert 2.5 < d1 / d2 < 6.0, (d1, d2)
+
+
+def test_total_force_is_minus_gradient_of_energy_terms_with_prefactor():
+    """With a Coulomb prefactor kc != 1 and a fixed mode sample, the total
+    force without the random batch list (Eq. 7-9) is minus the gradient of
+    coul_real + lj + fourier - self: kc must scale the real-space, Fourier
+    and self terms alike (the self term is constant in the positions)."""
+    x, y, z, q, ids = _lj_ions(40, 6.0, 31)
+    kc = 2.5
+    s = oracle.make_sys(6.0, 0.5, 2.9, 2.5, kc=kc)
+    m, w = _random_modes(24, 4, 9)
+    F = oracle.total_force(x, y, z, q, ids, s, m, w, components=False)["F"]
+    h = 1e-6
+    coords = [x, y, z]
+    for i in (0, 11, 33):
+        for d in range(3):
+            cp = [c.copy() for c in coords]
+            cm = [c.copy() for c in coords]
+            cp[d][i] += h
+            cm[d][i] -= h
+            up = oracle.energy_terms(*cp, q, s, m, w)["potential"]
+            um = oracle.energy_terms(*cm, q, s, m, w)["potential"]
+            fd = -(up - um) / (2 * h)
+            assert abs(fd - F[i, d]) < 1e-5 * max(1.0, np.abs(F[i]).max())
+    # the prefactor is linear in every Coulomb term
+    e1 = oracle.energy_terms(x, y, z, q, oracle.make_sys(6.0, 0.5, 2.9, 2.5), m, w)
+    e2 = oracle.energy_terms(x, y, z, q, s, m, w)
+    for k in ("coul_real", "fourier", "self"):
+        assert e2[k] == pytest.approx(kc * e1[k], rel=1e-14)
+    assert e2["lj"] == e1["lj"]
+
+
+def test_self_and_kinetic_energy_closed_forms():
+    """Eq. 6 for a +-q pair is 2 q^2 sqrt(a/pi); (m/2)|v|^2 for one particle."""
+    a = 0.37
+    assert oracle.self_energy(np.array([1.5, -1.5]), a) == pytest.approx(2 * 2.25 * math.sqrt(a / math.pi),
+                                                                         rel=1e-15)
+    assert oracle.kinetic_energy(np.array([[1.0, 2.0, -2.0]]), 3.0) == pytest.approx(13.5, rel=1e-15)
