@@ -162,8 +162,8 @@ int rbe_sample_k(const rbe_params *p /* host */, uint64_t eval, int32_t *m, doub
 int rbe_forces(rbe_ctx *ctx, const rbe_state *s, const int32_t *m, const double *w, uint64_t eval,
                double *rho_out, void *stream);
 
-/* Energy terms of Sec. 2.1 for the state as given (diagnostics: energy
-   conservation, thermodynamics), computed in FP64 whatever the context's
+/* Energy and virial terms of Sec. 2.1 for the state as given (diagnostics:
+   energy conservation, pressure), computed in FP64 whatever the context's
    precision, into u_out[0..RBE_ENERGY_TERMS) (device doubles):
      [RBE_U_COUL_REAL] kc sum_{i<j} q_i q_j erfc(sqrt(alpha) r)/r over every
                        pair with r <= r_coul (minimum image): the screened
@@ -179,14 +179,21 @@ int rbe_forces(rbe_ctx *ctx, const rbe_state *s, const int32_t *m, const double 
                        the mode sample (device); m NULL draws the one of
                        `eval`, the same as rbe_forces and rbe_sample_k;
      [RBE_U_SELF]      kc sqrt(alpha/pi) sum_i q_i^2 (Eq. 6);
-     [RBE_U_KINETIC]   (mass/2) sum_i |v_i|^2, 0 when s->vx..vz are NULL.
-   The potential energy is U_COUL_REAL + U_LJ + U_FOURIER - U_SELF. Terms
-   left out of the context's `terms` mask are 0 (U_SELF goes with the
-   Fourier term). Only s->x, y, z, q (and v when given) are read; f and id
+     [RBE_U_KINETIC]   (mass/2) sum_i |v_i|^2, 0 when s->vx..vz are NULL;
+     [RBE_W_COUL_REAL] sum_{i<j} d_ij . F_ij of the screened Coulomb pairs:
+                       kc q_i q_j r^2 G(r) with G of Eq. 8;
+     [RBE_W_LJ]        sum_{i<j} r^2 G_LJ(r) (Eq. 8);
+     [RBE_W_FOURIER]   kc (1/2) sum_l w_l |rho(k_l)|^2 (1 - k_l^2/(2 alpha)):
+                       minus the derivative of U_FOURIER under a uniform
+                       dilation of positions and box.
+   The potential energy is U_COUL_REAL + U_LJ + U_FOURIER - U_SELF, and the
+   pressure (2 U_KINETIC + W_COUL_REAL + W_LJ + W_FOURIER) / (3 V) (the self
+   energy does not depend on the volume). Terms left out of the context's
+   `terms` mask are 0 (U_SELF goes with the Fourier term). Only s->x, y, z, q (and v when given) are read; f and id
    may be NULL. rho_out as in rbe_forces. Not available on a batched
    context. */
 enum { RBE_U_COUL_REAL = 0, RBE_U_LJ = 1, RBE_U_FOURIER = 2, RBE_U_SELF = 3, RBE_U_KINETIC = 4,
-       RBE_ENERGY_TERMS = 5 };
+       RBE_W_COUL_REAL = 5, RBE_W_LJ = 6, RBE_W_FOURIER = 7, RBE_ENERGY_TERMS = 8 };
 int rbe_energy(rbe_ctx *ctx, const rbe_state *s, const int32_t *m, const double *w, uint64_t eval,
                double *u_out, double *rho_out, void *stream);
 

@@ -69,6 +69,8 @@ def _load():
         "orc_ewald_exact": (None, [i64, _D, _D, _D, _D, _D, d, d, _D, _D, _D, _D, _D, _D]),
         "orc_full_lattice": (i64, [_D, d, _I32, _I32, _D]),
         "orc_self_energy": (d, [i64, _D, d]),
+        "orc_fourier_virial": (d, [i32, _I32, _D, d, _D, _D, _D]),
+        "orc_real_virial": (None, [i64, _D, _D, _D, _D, S, _D, _D]),
         "orc_kinetic_energy": (d, [i64, _D, _D, _D, d]),
         "orc_bin": (ctypes.c_int, [i64, _D, _D, _D, _D, _D, _I32, _I32, _I32]),
         "orc_kick": (None, [i64, d, _D, _D, _D, _D, _D, _D]),
@@ -235,6 +237,20 @@ def real_energy(x, y, z, q, sys: OrcSys):
     return uc.value, ul.value
 
 
+def fourier_virial(m, L, alpha, w, rho_re, rho_im) -> float:
+    m = np.ascontiguousarray(m, np.int32)
+    Lv, pL = _d(np.broadcast_to(np.asarray(L, np.float64), (3,)))
+    (w, pw), (re, pre), (im, pim) = _d(w), _d(rho_re), _d(rho_im)
+    return _load().orc_fourier_virial(len(w), m.ctypes.data_as(_I32), pL, alpha, pw, pre, pim)
+
+
+def real_virial(x, y, z, q, sys: OrcSys):
+    (x, px), (y, py), (z, pz), (q, pq) = _d(x), _d(y), _d(z), _d(q)
+    wc, wl = ctypes.c_double(), ctypes.c_double()
+    _load().orc_real_virial(len(x), px, py, pz, pq, ctypes.byref(sys), ctypes.byref(wc), ctypes.byref(wl))
+    return wc.value, wl.value
+
+
 def self_energy(q, alpha) -> float:
     (q, pq) = _d(q)
     return _load().orc_self_energy(len(q), pq, alpha)
@@ -327,19 +343,26 @@ def total_force(x, y, z, q, ids, sys: OrcSys, m, w, seed=0, ev=0, terms=LJ | COU
 
 
 def energy_terms(x, y, z, q, sys: OrcSys, m, w, v=None, mass=1.0, terms=LJ | COUL_REAL | FOURIER):
-    """Energy terms of Sec. 2.1 for a fixed mode sample (m, w):
+    """Energy and virial terms of Sec. 2.1 for a fixed mode sample (m, w):
     coul_real = kc sum_{i<j} q_i q_j erfc(sqrt(a) r)/r within r_coul (Eq. 4),
     lj = sum_{i<j} 4 eps ((sigma/r)^12 - (sigma/r)^6) within r_lj (Eq. 2),
     fourier = kc (1/2) sum_l w_l |rho_l|^2 (Eq. 5 sampled as in Eq. 9),
-    self = kc sqrt(a/pi) sum q^2 (Eq. 6), kinetic = (m/2) sum |v|^2.
-    The potential is coul_real + lj + fourier - self; its negative gradient
-    at fixed modes is total_force without the random batch list."""
+    self = kc sqrt(a/pi) sum q^2 (Eq. 6), kinetic = (m/2) sum |v|^2, and the
+    virials w_coul_real, w_lj (sum_{i<j} d_ij . F_ij) and w_fourier
+    (kc (1/2) sum_l w_l |rho_l|^2 (1 - k_l^2/(2a))). The potential is
+    coul_real + lj + fourier - self; its negative gradient at fixed modes is
+    total_force without the random batch list; the pressure is
+    (2 kinetic + w_coul_real + w_lj + w_fourier) / (3 V)."""
     uc, ul = real_energy(x, y, z, q, sys)
+    wc, wl = real_virial(x, y, z, q, sys)
     out = dict(coul_real=uc if terms & COUL_REAL else 0.0, lj=ul if terms & LJ else 0.0, fourier=0.0, self=0.0)
     if terms & FOURIER:
         re, im = rho(x, y, z, q, sys.L, m)
         out["fourier"] = sys.kc * fourier_energy(w, re, im)
         out["self"] = sys.kc * self_energy(q, sys.alpha)
     out["kinetic"] = kinetic_energy(v, mass) if v is not None else 0.0
+    out["w_coul_real"] = wc if terms & COUL_REAL else 0.0
+    out["w_lj"] = wl if terms & LJ else 0.0
+    out["w_fourier"] = sys.kc * fourier_virial(m, sys.L, sys.alpha, w, re, im) if terms & FOURIER else 0.0
     out["potential"] = out["coul_real"] + out["lj"] + out["fourier"] - out["self"]
     return out

@@ -237,6 +237,21 @@ double orc_fourier_energy(int32_t P, const double *w, const double *rho_re, cons
   return u;
 }
 
+/* Virial of the fixed-mode energy U* under a uniform dilation of positions
+   and box (k_l -> k_l/s, V -> s^3 V, rho_l unchanged), with the sampling
+   weights read as the importance-sampled sum of Eq. 5:
+   W = -dU/ds = (1/2) sum_l w_l |rho_l|^2 (1 - k_l^2/(2 alpha)). */
+double orc_fourier_virial(int32_t P, const int32_t *m, const double L[3], double alpha, const double *w,
+                          const double *rho_re, const double *rho_im) {
+  double v = 0.0;
+  for (int32_t l = 0; l < P; ++l) {
+    double kx = TWO_PI * m[l] / L[0], ky = TWO_PI * m[P + l] / L[1], kz = TWO_PI * m[2 * P + l] / L[2];
+    double k2 = kx * kx + ky * ky + kz * kz;
+    v += 0.5 * w[l] * (rho_re[l] * rho_re[l] + rho_im[l] * rho_im[l]) * (1.0 - k2 / (2.0 * alpha));
+  }
+  return v;
+}
+
 /* ===================================================================== */
 /* Real space: erfc-Coulomb + LJ with the random batch list              */
 /* ===================================================================== */
@@ -486,6 +501,35 @@ void orc_real_energy(int64_t n, const double *x, const double *y, const double *
   }
   *u_coul = uc;
   *u_lj = ul;
+}
+
+/* Pair virials W = sum_{i<j} d_ij . F_ij (d = r_i - r_j, minimum image):
+   Coulomb: kc q_i q_j r^2 G(r) (r <= r_coul), LJ: r^2 G_LJ(r) (r <= r_lj),
+   with G and G_LJ of Eq. 8. */
+void orc_real_virial(int64_t n, const double *x, const double *y, const double *z, const double *q,
+                     const orc_sys *s, double *w_coul, double *w_lj) {
+  double wc = 0.0, wl = 0.0;
+  const double rc2 = s->r_coul * s->r_coul, rl2 = s->r_lj * s->r_lj, sa = sqrt(s->alpha);
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : wc, wl)
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t j = i + 1; j < n; ++j) {
+      double dx, dy, dz;
+      min_image(s->L, x[i], y[i], z[i], x[j], y[j], z[j], &dx, &dy, &dz);
+      double r2 = dx * dx + dy * dy + dz * dz;
+      if (r2 <= rc2) {
+        double r = sqrt(r2);
+        double G = erfc(sa * r) / (r2 * r) + 2.0 * sa * exp(-s->alpha * r2) / (sqrt(PI) * r2);
+        wc += s->kc * q[i] * q[j] * G * r2;
+      }
+      if (r2 <= rl2) {
+        double s2 = s->sigma * s->sigma / r2, s6 = s2 * s2 * s2;
+        double GL = 24.0 * s->eps * (2.0 * s6 * s6 - s6) / r2;
+        wl += GL * r2;
+      }
+    }
+  }
+  *w_coul = wc;
+  *w_lj = wl;
 }
 
 /* ===================================================================== */

@@ -51,6 +51,9 @@ void orc_fourier_force(int64_t n, const double *x, const double *y, const double
                        const double *rho_im, double *fx, double *fy, double *fz);
 /* U* = 1/2 sum_l w_l |rho_l|^2 : the energy whose exact gradient is the fixed-mode force */
 double orc_fourier_energy(int32_t P, const double *w, const double *rho_re, const double *rho_im);
+/* W* = 1/2 sum_l w_l |rho_l|^2 (1 - k_l^2/(2 alpha)) : minus the dilation derivative of U* */
+double orc_fourier_virial(int32_t P, const int32_t *m, const double L[3], double alpha, const double *w,
+                          const double *rho_re, const double *rho_im);
 
 /* --- real space (Eq. 2, 7, 8, 10-12) --- */
 /* Full-list near-field force on the particles listed in idx[0..nidx) (all if
@@ -68,6 +71,10 @@ void orc_mean_correct(int64_t n, double *fx, double *fy, double *fz, double mean
 /* real-space energies (i<j) over minimum images within the cutoffs */
 void orc_real_energy(int64_t n, const double *x, const double *y, const double *z, const double *q,
                      const orc_sys *s, double *u_coul, double *u_lj);
+
+/* real-space pair virials sum_{i<j} d_ij . F_ij within the cutoffs */
+void orc_real_virial(int64_t n, const double *x, const double *y, const double *z, const double *q,
+                     const orc_sys *s, double *w_coul, double *w_lj);
 
 /* --- exact Ewald sum for tiny boxes (Eq. 3-8) --- */
 void orc_ewald_exact(int64_t n, const double *x, const double *y, const double *z, const double *q,

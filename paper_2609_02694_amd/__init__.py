@@ -25,7 +25,7 @@ MAX_SHELL_BATCH = 32
 EXPORTED = ["rbe_create", "rbe_create_batch", "rbe_destroy", "rbe_last_error", "rbe_build_cells", "rbe_sample_k",
             "rbe_forces", "rbe_energy", "rbe_step", "rbe_sync_check", "rbe_set_counting", "rbe_get_counters", "rbe_set_timing",
             "rbe_get_timing"]
-ENERGY_NAMES = ["coul_real", "lj", "fourier", "self", "kinetic"]
+ENERGY_NAMES = ["coul_real", "lj", "fourier", "self", "kinetic", "w_coul_real", "w_lj", "w_fourier"]
 TIMING_KINDS = ["bin", "reorder", "pair_neutral", "mean", "sample", "rho_partial", "rho_final", "gather",
                 "kick_drift", "kick", "pair_charged", "pair_shell", "ghost", "batch"]
 
@@ -266,7 +266,7 @@ class Context:
 
     def energy(self, st: Particles, m=None, w=None, ev: int = 0, with_kinetic: bool = True, rho_out=None,
                stream=None):
-        """Energy terms (device float64 tensor of ENERGY_TERMS entries, see ENERGY_NAMES)."""
+        """Energy and virial terms (device float64 tensor, one entry per ENERGY_NAMES name)."""
         import torch
         s = st.as_struct()
         if not with_kinetic:

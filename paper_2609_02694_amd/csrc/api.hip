@@ -1098,8 +1098,11 @@ extern "C" int rbe_energy(rbe_ctx *c, const rbe_state *s, const int32_t *m, cons
     launch_rho_final(nchunks, P, c->fb, w, c->p.coulomb_k, rho_out, st);
     fin.w = w;
     fin.rho = c->fb.rho;
+    fin.mkd = c->fb.mkd;
   }
   fin.P = P;
+  for (int d = 0; d < 3; ++d) fin.L[d] = c->p.L[d];
+  fin.alpha = c->p.alpha;
   fin.kc = c->p.coulomb_k;
   fin.self_coef = c->p.coulomb_k * std::sqrt(c->p.alpha / kPi);
   fin.half_mass = 0.5 * c->p.mass;

@@ -146,14 +146,17 @@ void launch_fourier_gather(int prec, int64_t nq, int P, const double4 *sq, const
 // energy terms (diagnostics, FP64)
 // ---------------------------------------------------------------------------
 struct EnergyFinal {
-  const double *near_part;  // [2 nb_near] block partials (Coulomb, LJ); set by launch_energy
+  const double *near_part;  // [4 nb_near] block partials (Coulomb and LJ energy, Coulomb and LJ
+                            // virial); set by launch_energy
   int64_t nb_near;
   const double *sq_part;    // [2 nb_sq] block partials (q^2, |v|^2); set by launch_energy
   int64_t nb_sq;
   const double *w, *rho;    // mode weights [P] and Re | Im rho [2 P]; rho nullptr: no Fourier term
+  const double *mkd;        // [3][P] mode vectors as doubles
   int P;
+  double L[3], alpha;
   double kc, self_coef, half_mass;  // kc, kc sqrt(alpha/pi), mass/2
-  double *out;              // [5] device
+  double *out;              // [8] device
 };
 // Length of the partial-sum scratch launch_energy needs for n_max particles.
 int energy_part_len(int64_t n_max);

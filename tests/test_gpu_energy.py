@@ -1,7 +1,8 @@
-"""GPU parity of the energy terms (rbe_energy) and of the Coulomb prefactor.
+"""GPU parity of the energy and virial terms (rbe_energy) and of the Coulomb
+prefactor.
 
-The energy terms are computed in FP64 in every context precision. Bound:
-relative error 1e-11 per term against the oracle. The real-space Coulomb sum
+The terms are computed in FP64 in every context precision. Bound: relative
+error 1e-11 per term against the oracle. The real-space Coulomb sum
 of random ions cancels about a thousandfold (|U| against the sum of |terms|),
 so rounding of 1e-14 relative to the terms' magnitudes can reach 1e-11 of the
 result; the other terms are sums of one sign and sit near 1e-14.
@@ -162,3 +163,20 @@ def test_energy_self_term_closed_form(plain3k):
     got = gpu_energy(p, s, m=m, w=w)
     expect = math.sqrt(p["alpha"] / math.pi) * float(np.sum(np.asarray(s["q"]) ** 2))
     assert got["self"] == pytest.approx(expect, rel=1e-14)
+
+
+def test_virial_is_minus_dilation_derivative_of_gpu_energy():
+    """Real-space terms of the GPU energy under a uniform dilation of
+    positions and box (cutoffs fixed): W = -dU/ds, for the GPU's own virials."""
+    p, s = system("plain3k", n=1500, L=24.0)
+    m, w = oracle.sample_k(p["seed"], 0, p["L"], p["alpha"], p["P"])
+    e0 = gpu_energy(p, s, terms=rbe.TERM_LJ | rbe.TERM_COUL_REAL, m=m, w=w, kinetic=False)
+    h = 1e-7
+    u = []
+    for f in (1 + h, 1 - h):
+        ps = dict(p, L=p["L"] * f)
+        ss = dict(s, x=s["x"] * f, y=s["y"] * f, z=s["z"] * f)
+        e = gpu_energy(ps, ss, terms=rbe.TERM_LJ | rbe.TERM_COUL_REAL, m=m, w=w, kinetic=False)
+        u.append(e["coul_real"] + e["lj"])
+    fd = -(u[0] - u[1]) / (2 * h)
+    assert fd == pytest.approx(e0["w_coul_real"] + e0["w_lj"], rel=1e-6)

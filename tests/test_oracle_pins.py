@@ -460,3 +460,60 @@ def test_self_and_kinetic_energy_closed_forms():
     assert oracle.self_energy(np.array([1.5, -1.5]), a) == pytest.approx(2 * 2.25 * math.sqrt(a / math.pi),
                                                                          rel=1e-15)
     assert oracle.kinetic_energy(np.array([[1.0, 2.0, -2.0]]), 3.0) == pytest.approx(13.5, rel=1e-15)
+
+
+def _dilated_real_energy(x, y, z, q, L, s, alpha, r_coul, r_lj):
+    sys_s = oracle.make_sys(L * s, alpha, r_coul, r_lj)
+    return sum(oracle.real_energy(x * s, y * s, z * s, q, sys_s))
+
+
+def test_real_virial_is_minus_dilation_derivative():
+    """W = sum d.F = -dU/ds for positions and box scaled by s (cutoffs fixed;
+    no pair sits within the step of a cutoff)."""
+    x, y, z, q, ids = _lj_ions(60, 7.0, 41)
+    sys = oracle.make_sys(7.0, 0.5, 3.2, 2.5)
+    wc, wl = oracle.real_virial(x, y, z, q, sys)
+    h = 1e-7
+    up = _dilated_real_energy(x, y, z, q, 7.0, 1 + h, 0.5, 3.2, 2.5)
+    um = _dilated_real_energy(x, y, z, q, 7.0, 1 - h, 0.5, 3.2, 2.5)
+    fd = -(up - um) / (2 * h)
+    assert fd == pytest.approx(wc + wl, rel=1e-6, abs=1e-6)
+
+
+def test_fourier_virial_is_minus_dilation_derivative_of_exact_reciprocal_energy():
+    """With the deterministic full-lattice weights 4 pi exp(-k^2/4a)/(V k^2)
+    the fixed-mode energy is the exact reciprocal energy of Eq. 5; its
+    dilation derivative (weights recomputed at the scaled box, rho unchanged)
+    is minus the virial formula."""
+    x, y, z, q = random_ions(30, 6.0, 42)
+    alpha, L, mmax = 0.6, 6.0, (6, 6, 6)
+    m, w = oracle.full_lattice(L, alpha, mmax)
+    re, im = oracle.rho(x, y, z, q, L, m)
+    W = oracle.fourier_virial(m, L, alpha, w, re, im)
+    h = 1e-6
+    u = []
+    for s in (1 + h, 1 - h):
+        _, ws = oracle.full_lattice(L * s, alpha, mmax)
+        u.append(oracle.fourier_energy(ws, re, im))  # rho is dilation invariant (k.r fixed)
+    fd = -(u[0] - u[1]) / (2 * h)
+    assert fd == pytest.approx(W, rel=1e-7)
+
+
+def test_coulomb_virial_theorem_for_the_full_ewald_sum():
+    """The Ewald energy of a neutral periodic system is homogeneous of degree
+    -1 under dilation, so the Coulomb virial equals the total Coulomb energy:
+    W_real + W_recip = U_real + U_recip - U_self (real space converged inside
+    L/2, reciprocal sum over the full lattice)."""
+    x, y, z, q = random_ions(40, 10.0, 43)
+    L, alpha, rc = 10.0, 1.39, 5.0  # erfc(sqrt(a) rc) ~ 1e-16
+    sys = oracle.make_sys(L, alpha, rc, 2.5)
+    uc, _ = oracle.real_energy(x, y, z, q, sys)
+    wc, _ = oracle.real_virial(x, y, z, q, sys)
+    m, w = oracle.full_lattice(L, alpha, (24, 24, 24))
+    re, im = oracle.rho(x, y, z, q, L, m)
+    uk = oracle.fourier_energy(w, re, im)
+    wk = oracle.fourier_virial(m, L, alpha, w, re, im)
+    us = oracle.self_energy(q, alpha)
+    ex = oracle.ewald_exact(x, y, z, q, L, alpha)
+    assert uc + uk - us == pytest.approx(ex["u"], rel=1e-12)
+    assert wc + wk == pytest.approx(uc + uk - us, rel=1e-11)
