@@ -79,6 +79,10 @@ typedef struct {
   double mass, dt;    /* particle mass and velocity-Verlet time step                   */
   double ghost_width; /* 0: periodic traversal; > 0: near field over a locally built
                          shell of periodic ghost copies of this width (>= r_coul)       */
+  double nvt_kT;      /* Nose-Hoover target temperature k_B T (energy units)           */
+  double nvt_tau;     /* Nose-Hoover relaxation time; 0: plain velocity Verlet (NVE).
+                         > 0: rbe_step runs the NVT step below with thermostat mass
+                         Q = N_f nvt_kT nvt_tau^2, N_f = 3N - 3                     */
   uint64_t seed;      /* stream seed of the mode sample and of the shell batches       */
 } rbe_params;
 
@@ -94,6 +98,9 @@ typedef struct {
   double *fx, *fy, *fz;
   double *q;
   int32_t *id; /* unique, 0..n-1 (the shell batches of Eq. 11 are keyed by id) */
+  double *nh;  /* NVT (nvt_tau > 0) only: device [2] = {xi, eta}, the thermostat's
+                  friction variable and its time integral, advanced by rbe_step;
+                  K + U + Q xi^2/2 + N_f kT eta is the conserved quantity */
   int64_t n;
 } rbe_state;
 
@@ -202,7 +209,15 @@ int rbe_energy(rbe_ctx *ctx, const rbe_state *s, const int32_t *m, const double 
      v += dt/(2m) F
    for k = 0..nsteps-1. On entry s->f* must hold the force of the current
    positions. Positions, velocities, forces, charges and ids are returned in
-   cell order (the particles are reordered; id[] maps them back). */
+   cell order (the particles are reordered; id[] maps them back).
+   NVT (nvt_tau > 0; the paper runs every experiment in the Nose-Hoover
+   canonical ensemble, Sec. 3): each step is wrapped in two half-steps of a
+   single Nose-Hoover thermostat (symmetric Trotter split), with
+   K = (m/2) sum |v|^2 and G(K) = (2K - N_f kT)/Q:
+     half: xi += dt/4 G(K); v *= exp(-xi dt/2); eta += xi dt/2; xi += dt/4 G(K)
+     step: half; v += dt/(2m) F; x <- wrap(x + dt v); F <- force; v += dt/(2m) F; half
+   s->nh must then point to {xi, eta} on the device; n >= 2. Not available on
+   a batched context. */
 int rbe_step(rbe_ctx *ctx, rbe_state *s, int32_t nsteps, uint64_t first_eval, void *stream);
 
 /* Synchronize `stream` and report device-side errors recorded since the last
@@ -241,7 +256,9 @@ enum {
                              second step on, fused with the previous step's
                              second half-kick)                              */
   RBE_TK_KICK = 9,        /* second half-kick (+ mean subtraction) of a
-                             call's last step                               */
+                             call's last step; with NVT, every step's second
+                             half-kick with the kinetic-energy sum and the
+                             thermostat half-steps                          */
   RBE_TK_PAIR_CHARGED = 10, /* near field of the charged particles (core)   */
   RBE_TK_PAIR_SHELL = 11, /* reserved: the shell of Eq. 11 is timed with
                              RBE_TK_PAIR_CHARGED (one fused launch)          */

@@ -8,6 +8,7 @@ GPU library.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -340,6 +341,35 @@ def total_force(x, y, z, q, ids, sys: OrcSys, m, w, seed=0, ev=0, terms=LJ | COU
     out["near"] = FN
     out["F"] = FN + FF
     return out
+
+
+def nh_half(K, xi, eta, dt, nf, kT, Q):
+    """One half-step of a single Nose-Hoover thermostat (Hoover 1985, the
+    thermostat of the paper's NVT runs), symmetric Trotter split:
+    xi += dt/4 G(K); s = exp(-xi dt/2); eta += xi dt/2; K <- s^2 K;
+    xi += dt/4 G(K), with G(K) = (2K - nf kT)/Q. Returns (s, K, xi, eta);
+    the velocities are to be multiplied by s."""
+    xi = xi + 0.25 * dt * ((2.0 * K - nf * kT) / Q)
+    s = math.exp(-0.5 * dt * xi)
+    eta = eta + 0.5 * dt * xi
+    K = K * s * s
+    xi = xi + 0.25 * dt * ((2.0 * K - nf * kT) / Q)
+    return s, K, xi, eta
+
+
+def nvt_step(r, v, F, xi, eta, force, dt, L, mass, kT, tau):
+    """One NVT step: thermostat half, velocity-Verlet step with force(r),
+    thermostat half. Q = nf kT tau^2 with nf = 3N - 3. Returns (r, v, F, xi, eta)."""
+    nf = 3.0 * len(r) - 3.0
+    Q = nf * kT * tau * tau
+    s, _, xi, eta = nh_half(kinetic_energy(v, mass), xi, eta, dt, nf, kT, Q)
+    v = v * s
+    v = kick(F, v, 0.5 * dt / mass)
+    r = drift_wrap(r, v, dt, L)
+    F = force(r)
+    v = kick(F, v, 0.5 * dt / mass)
+    s, _, xi, eta = nh_half(kinetic_energy(v, mass), xi, eta, dt, nf, kT, Q)
+    return r, v * s, F, xi, eta
 
 
 def energy_terms(x, y, z, q, sys: OrcSys, m, w, v=None, mass=1.0, terms=LJ | COUL_REAL | FOURIER):

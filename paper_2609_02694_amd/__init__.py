@@ -55,12 +55,14 @@ class Params(ctypes.Structure):
         ("mass", ctypes.c_double),
         ("dt", ctypes.c_double),
         ("ghost_width", ctypes.c_double),
+        ("nvt_kT", ctypes.c_double),
+        ("nvt_tau", ctypes.c_double),
         ("seed", ctypes.c_uint64),
     ]
 
 
 class State(ctypes.Structure):
-    _fields_ = [(k, ctypes.c_void_p) for k in ("x", "y", "z", "vx", "vy", "vz", "fx", "fy", "fz", "q", "id")] + [
+    _fields_ = [(k, ctypes.c_void_p) for k in ("x", "y", "z", "vx", "vy", "vz", "fx", "fy", "fz", "q", "id", "nh")] + [
         ("n", ctypes.c_int64)]
 
 
@@ -102,7 +104,8 @@ def load():
 
 
 def make_params(L, alpha, r_coul, r_lj, P, r_core=0.0, p_shell=0, prec=FP64, terms=TERM_ALL, ncell=(0, 0, 0),
-                eps=1.0, sigma=1.0, kc=1.0, mass=1.0, dt=0.002, ghost_width=0.0, seed=0) -> Params:
+                eps=1.0, sigma=1.0, kc=1.0, mass=1.0, dt=0.002, ghost_width=0.0, seed=0, nvt_kT=0.0,
+                nvt_tau=0.0) -> Params:
     p = Params()
     Lv = L if hasattr(L, "__len__") else (L, L, L)
     for d in range(3):
@@ -112,13 +115,15 @@ def make_params(L, alpha, r_coul, r_lj, P, r_core=0.0, p_shell=0, prec=FP64, ter
     p.p_shell, p.P, p.kdist, p.prec, p.terms = p_shell, P, 0, prec, terms
     p.lj_eps, p.lj_sigma, p.coulomb_k, p.mass, p.dt = eps, sigma, kc, mass, dt
     p.ghost_width, p.seed = ghost_width, seed
+    p.nvt_kT, p.nvt_tau = nvt_kT, nvt_tau
     return p
 
 
 def params_from_preset(pr: dict, prec=FP64, terms=TERM_ALL, ncell=(0, 0, 0), seed=None) -> Params:
     return make_params(pr["L"], pr["alpha"], pr["r_coul"], pr["r_lj"], pr["P"], pr.get("r_core", 0.0),
                        pr.get("p_shell", 0), prec, terms, ncell, kc=pr.get("kc", 1.0), dt=pr.get("dt", 0.002),
-                       ghost_width=pr.get("ghost", 0.0), seed=pr["seed"] if seed is None else seed)
+                       ghost_width=pr.get("ghost", 0.0), seed=pr["seed"] if seed is None else seed,
+                       nvt_kT=pr.get("nvt_kT", 0.0), nvt_tau=pr.get("nvt_tau", 0.0))
 
 
 def _stream(stream):
@@ -145,6 +150,7 @@ class Particles:
     fz: object
     q: object
     id: object
+    nh: object = None  # NVT thermostat state {xi, eta}: float64 CUDA tensor of 2 entries
 
     @property
     def n(self) -> int:
@@ -161,6 +167,10 @@ class Particles:
         s = State()
         for k in ("x", "y", "z", "vx", "vy", "vz", "fx", "fy", "fz", "q", "id"):
             setattr(s, k, getattr(self, k).data_ptr())
+        if self.nh is not None:
+            if self.nh.dtype != torch.float64 or not self.nh.is_cuda or self.nh.numel() < 2:
+                raise ValueError("nh must be a float64 CUDA tensor of 2 entries")
+            s.nh = self.nh.data_ptr()
         s.n = self.n
         return s
 

@@ -76,6 +76,7 @@ struct rbe_ctx {
   double *mkd_dev = nullptr; // [kSampleSteps][3][P] the same modes as doubles
   double *mean_part = nullptr, *mean = nullptr;
   double *epart = nullptr;   // energy partial sums
+  double *nh_part = nullptr, *nh_scale = nullptr;  // thermostat: |v|^2 partials, pending velocity scaling
   int *err = nullptr;
   int32_t *nq_dev = nullptr;
   double *qstats = nullptr;  // [sum q, sum |q|]
@@ -201,6 +202,9 @@ static int validate_params(const rbe_params *p, std::string *why) {
   if (!(p->mass > 0) || !(p->dt >= 0)) return bad(RBE_EINVAL, "mass must be positive and dt non-negative");
   if (!(p->lj_sigma > 0) || !(p->lj_eps >= 0)) return bad(RBE_EINVAL, "bad LJ parameters");
   const double rmax = std::fmax(p->r_coul, p->r_lj);
+  if (!(p->nvt_tau >= 0.0) || !std::isfinite(p->nvt_tau)) return bad(RBE_EINVAL, "nvt_tau must be >= 0 and finite");
+  if (p->nvt_tau > 0.0 && (!(p->nvt_kT > 0.0) || !std::isfinite(p->nvt_kT)))
+    return bad(RBE_EINVAL, "NVT needs a positive finite nvt_kT");
   if (!(p->ghost_width >= 0.0)) return bad(RBE_EINVAL, "ghost_width must be >= 0");
   if (p->ghost_width > 0.0) {
     if (p->ghost_width < rmax) return bad(RBE_EINVAL, "ghost_width must cover the largest cutoff");
@@ -406,6 +410,8 @@ extern "C" int rbe_create(rbe_ctx **out, const rbe_params *p, int64_t n_max, int
   c->mean_part = b.alloc<double>(3 * (int64_t)mean_blocks(n_max) + 3);
   c->mean = b.alloc<double>(3);
   c->epart = b.alloc<double>(energy_part_len(n_max));
+  c->nh_part = b.alloc<double>(nh_part_len());
+  c->nh_scale = b.alloc<double>(1);
   c->err = b.alloc<int>(1);
   c->nq_dev = b.alloc<int32_t>(1);
   c->qstats = b.alloc<double>(2);
@@ -462,7 +468,7 @@ static bool same_shared_physics(const rbe_params &a, const rbe_params &b) {
   return a.alpha == b.alpha && a.r_coul == b.r_coul && a.r_lj == b.r_lj && a.r_core == b.r_core &&
          a.p_shell == b.p_shell && a.P == b.P && a.kdist == b.kdist && a.prec == b.prec && t(a.terms) == t(b.terms) &&
          a.lj_eps == b.lj_eps && a.lj_sigma == b.lj_sigma && a.coulomb_k == b.coulomb_k && a.mass == b.mass &&
-         a.dt == b.dt && a.ghost_width == b.ghost_width;
+         a.dt == b.dt && a.ghost_width == b.ghost_width && a.nvt_kT == b.nvt_kT && a.nvt_tau == b.nvt_tau;
 }
 
 extern "C" int rbe_create_batch(rbe_ctx **out, int32_t n_sys, const rbe_params *params, const int64_t *offset,
@@ -493,6 +499,8 @@ extern "C" int rbe_create_batch(rbe_ctx **out, int32_t n_sys, const rbe_params *
     return create_fail(RBE_EINVAL, "the random batch list (r_core > 0) is not available in the batched form");
   if (params[0].ghost_width > 0)
     return create_fail(RBE_EINVAL, "the ghost shell (ghost_width > 0) is not available in the batched form");
+  if (params[0].nvt_tau > 0)
+    return create_fail(RBE_EINVAL, "the NVT thermostat (nvt_tau > 0) is not available in the batched form");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
     return create_fail(RBE_EDEVICE, "no such HIP device");
@@ -1145,6 +1153,9 @@ extern "C" int rbe_step(rbe_ctx *c, rbe_state *s, int32_t nsteps, uint64_t first
   if (s->n < 1 || s->n > c->n_max)
     return c->fail(RBE_ERANGE, "n = %lld outside [1, n_max = %lld]", (long long)s->n, (long long)c->n_max);
   if (nsteps < 0) return c->fail(RBE_EINVAL, "nsteps < 0");
+  const bool nvt = c->p.nvt_tau > 0.0;
+  if (nvt && !s->nh) return c->fail(RBE_EINVAL, "NVT needs the thermostat state s->nh");
+  if (nvt && s->n < 2) return c->fail(RBE_EINVAL, "NVT needs at least two particles");
   if (nsteps == 0) return RBE_OK;
   HIP_TRY(c, hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
@@ -1170,14 +1181,28 @@ extern "C" int rbe_step(rbe_ctx *c, rbe_state *s, int32_t nsteps, uint64_t first
   const bool near = (c->p.terms & (RBE_TERM_LJ | RBE_TERM_COUL_REAL)) != 0;
   const bool fourier = (c->p.terms & RBE_TERM_FOURIER) != 0;
   const double *mean = (c->pp.rbl && near) ? c->mean : nullptr;
+  NhParams nhp{};
+  if (nvt) {
+    nhp.dt = c->p.dt;
+    nhp.nf = 3.0 * (double)n - 3.0;
+    nhp.kT = c->p.nvt_kT;
+    nhp.Q = nhp.nf * c->p.nvt_kT * c->p.nvt_tau * c->p.nvt_tau;
+    nhp.mass = c->p.mass;
+    // the first step's opening thermostat half on the caller's velocities
+    TScope ts(c, RBE_TK_KICK, st);
+    launch_nh(n, 0.0, nullptr, A->fx, A->fy, A->fz, A->vx, A->vy, A->vz, nhp, kNhStart, c->nh_part, s->nh,
+              c->nh_scale, c->err, st);
+  }
   for (int32_t k = 0; k < nsteps; ++k) {
     {
-      // step 0 starts from the caller's forces; later steps fuse the previous
-      // step's second half-kick into this one's first half-kick and drift
+      // step 0 starts from the caller's forces; later NVE steps fuse the
+      // previous step's second half-kick into this one's first half-kick and
+      // drift (NVT steps cannot: the thermostat needs the kinetic energy
+      // between the two half-kicks)
       TScope ts(c, RBE_TK_KICK_DRIFT, st);
-      if (k == 0)
-        launch_kick_drift(n, h, c->p.dt, c->g, A->fx, A->fy, A->fz, A->vx, A->vy, A->vz, A->x, A->y, A->z, c->err,
-                          st);
+      if (k == 0 || nvt)
+        launch_kick_drift(n, h, c->p.dt, c->g, nvt ? c->nh_scale : nullptr, A->fx, A->fy, A->fz, A->vx, A->vy, A->vz,
+                          A->x, A->y, A->z, c->err, st);
       else
         launch_kick_kick_drift(n, h, c->p.dt, c->g, mean, A->fx, A->fy, A->fz, A->vx, A->vy, A->vz, A->x, A->y,
                                A->z, c->err, st);
@@ -1206,7 +1231,15 @@ extern "C" int rbe_step(rbe_ctx *c, rbe_state *s, int32_t nsteps, uint64_t first
                      first_eval + (uint64_t)k, nullptr, B->fx, B->fy, B->fz, st, k > 0,
                      fourier ? c->mkd_dev + 3 * P * ks : nullptr);
     if (rc != RBE_OK) return rc;
-    if (k == nsteps - 1) {
+    if (nvt) {
+      // second half-kick, the closing thermostat half of this step and, unless
+      // this is the call's last step, the opening half of the next one
+      TScope ts(c, RBE_TK_KICK, st);
+      const bool last = k == nsteps - 1;
+      launch_nh(n, h, mean, B->fx, B->fy, B->fz, B->vx, B->vy, B->vz, nhp, last ? kNhEnd : (kNhEnd | kNhStart),
+                c->nh_part, s->nh, c->nh_scale, c->err, st);
+      if (last) launch_scale_v(n, c->nh_scale, B->vx, B->vy, B->vz, st);
+    } else if (k == nsteps - 1) {
       TScope ts(c, RBE_TK_KICK, st);
       launch_kick(n, h, mean, B->fx, B->fy, B->fz, B->vx, B->vy, B->vz, c->err, st);
     }

@@ -183,7 +183,10 @@ void launch_sub_mean(int64_t n, const double *mean, double *fx, double *fy, doub
   k_sub_mean<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, mean, fx, fy, fz);
 }
 
+// v <- s v + h f (s = *scale when given: the thermostat's velocity scaling
+// of the NVT step; the NVE step passes no scale); x <- wrap(x + dt v).
 __global__ void __launch_bounds__(256) k_kick_drift(int64_t n, double h, double dt, Grid g,
+                                                    const double *__restrict__ scale,
                                                     const double *__restrict__ fx, const double *__restrict__ fy,
                                                     const double *__restrict__ fz, double *__restrict__ vx,
                                                     double *__restrict__ vy, double *__restrict__ vz,
@@ -191,7 +194,14 @@ __global__ void __launch_bounds__(256) k_kick_drift(int64_t n, double h, double 
                                                     double *__restrict__ z, int *err) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double u = vx[i] + h * fx[i], v = vy[i] + h * fy[i], w = vz[i] + h * fz[i];
+  double v0x = vx[i], v0y = vy[i], v0z = vz[i];
+  if (scale) {
+    const double sc = *scale;
+    v0x *= sc;
+    v0y *= sc;
+    v0z *= sc;
+  }
+  const double u = v0x + h * fx[i], v = v0y + h * fy[i], w = v0z + h * fz[i];
   vx[i] = u;
   vy[i] = v;
   vz[i] = w;
@@ -244,11 +254,112 @@ void launch_kick_kick_drift(int64_t n, double h, double dt, const Grid &g, const
                                                                  err);
 }
 
-void launch_kick_drift(int64_t n, double h, double dt, const Grid &g, const double *fx, const double *fy,
-                       const double *fz, double *vx, double *vy, double *vz, double *x, double *y, double *z, int *err,
-                       hipStream_t st) {
+void launch_kick_drift(int64_t n, double h, double dt, const Grid &g, const double *scale, const double *fx,
+                       const double *fy, const double *fz, double *vx, double *vy, double *vz, double *x, double *y,
+                       double *z, int *err, hipStream_t st) {
   if (n <= 0) return;
-  k_kick_drift<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, h, dt, g, fx, fy, fz, vx, vy, vz, x, y, z, err);
+  k_kick_drift<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, h, dt, g, scale, fx, fy, fz, vx, vy, vz, x, y, z,
+                                                            err);
+}
+
+// ---------------------------------------------------------------------------
+// Nose-Hoover thermostat (NVT)
+// ---------------------------------------------------------------------------
+// Grid-stride partial sums of |v|^2 (fixed block count, fixed order), with
+// the second half-kick v += h (f - mean) applied first when h != 0 (the
+// corrected force is written back, as k_kick does).
+constexpr int kNhBlocks = 1024;
+int nh_part_len() { return kNhBlocks; }
+
+__global__ void __launch_bounds__(kMeanThreads) k_kick_vsq(int64_t n, double h, const double *__restrict__ mean,
+                                                           double *__restrict__ fx, double *__restrict__ fy,
+                                                           double *__restrict__ fz, double *__restrict__ vx,
+                                                           double *__restrict__ vy, double *__restrict__ vz,
+                                                           double *__restrict__ part, int *err) {
+  __shared__ double lds[kMeanThreads / 64];
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kMeanThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kMeanThreads) {
+    double u = vx[i], v = vy[i], w = vz[i];
+    if (h != 0.0) {
+      double a = fx[i], b = fy[i], c = fz[i];
+      if (mean) {
+        a -= mean[0];
+        b -= mean[1];
+        c -= mean[2];
+        fx[i] = a;
+        fy[i] = b;
+        fz[i] = c;
+      }
+      u += h * a;
+      v += h * b;
+      w += h * c;
+      vx[i] = u;
+      vy[i] = v;
+      vz[i] = w;
+      if (!isfinite(u) || !isfinite(v) || !isfinite(w)) atomicOr(err, kErrNonFinite);
+    }
+    s += u * u + v * v + w * w;
+  }
+  s = block_sum_fixed(s, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// One half-step of the thermostat on the kinetic energy K:
+//   xi += (dt/4) G(K);  s = exp(-xi dt/2);  eta += xi dt/2;  K <- s^2 K;
+//   xi += (dt/4) G(K),  G(K) = (2K - N_f kT)/Q.
+__device__ inline double nh_half(const NhParams &q, double *K, double *xi, double *eta) {
+  *xi += 0.25 * q.dt * ((2.0 * *K - q.nf * q.kT) / q.Q);
+  const double s = exp(-0.5 * q.dt * *xi);
+  *eta += 0.5 * q.dt * *xi;
+  *K *= s * s;
+  *xi += 0.25 * q.dt * ((2.0 * *K - q.nf * q.kT) / q.Q);
+  return s;
+}
+
+// K = (m/2) sum |v|^2 from the partials; then the end half of one step
+// (END) and/or the start half of the next (START). nh = {xi, eta} is
+// advanced in place; *scale receives the product of the velocity scalings,
+// applied by the next k_kick_drift (or k_scale_v after a call's last step).
+__global__ void __launch_bounds__(kMeanThreads) k_nh_thermo(int nb, const double *__restrict__ part, NhParams q,
+                                                            int mode, double *__restrict__ nh,
+                                                            double *__restrict__ scale) {
+  __shared__ double lds[kMeanThreads / 64];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kMeanThreads) s += part[b];
+  s = block_sum_fixed(s, lds);
+  if (threadIdx.x == 0) {
+    double K = 0.5 * q.mass * s, xi = nh[0], eta = nh[1], sc = 1.0;
+    if (mode & kNhEnd) sc *= nh_half(q, &K, &xi, &eta);
+    if (mode & kNhStart) sc *= nh_half(q, &K, &xi, &eta);
+    nh[0] = xi;
+    nh[1] = eta;
+    *scale = sc;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_scale_v(int64_t n, const double *__restrict__ scale, double *__restrict__ vx,
+                                                 double *__restrict__ vy, double *__restrict__ vz) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double sc = *scale;
+  vx[i] *= sc;
+  vy[i] *= sc;
+  vz[i] *= sc;
+}
+
+void launch_nh(int64_t n, double h, const double *mean, double *fx, double *fy, double *fz, double *vx, double *vy,
+               double *vz, const NhParams &q, int mode, double *part, double *nh, double *scale, int *err,
+               hipStream_t st) {
+  int64_t nb = (n + kMeanThreads - 1) / kMeanThreads;
+  if (nb > kNhBlocks) nb = kNhBlocks;
+  if (nb < 1) nb = 1;
+  k_kick_vsq<<<(unsigned)nb, kMeanThreads, 0, st>>>(n, h, mean, fx, fy, fz, vx, vy, vz, part, err);
+  k_nh_thermo<<<1, kMeanThreads, 0, st>>>((int)nb, part, q, mode, nh, scale);
+}
+
+void launch_scale_v(int64_t n, const double *scale, double *vx, double *vy, double *vz, hipStream_t st) {
+  if (n <= 0) return;
+  k_scale_v<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, scale, vx, vy, vz);
 }
 
 }  // namespace rbe

@@ -183,9 +183,24 @@ void launch_sub_mean(int64_t n, const double *mean, double *fx, double *fy, doub
 void launch_kick_kick_drift(int64_t n, double h, double dt, const Grid &g, const double *mean, const double *fx,
                             const double *fy, const double *fz, double *vx, double *vy, double *vz, double *x,
                             double *y, double *z, int *err, hipStream_t st);
-void launch_kick_drift(int64_t n, double h, double dt, const Grid &g, const double *fx, const double *fy,
-                       const double *fz, double *vx, double *vy, double *vz, double *x, double *y, double *z,
-                       int *err, hipStream_t st);
+// v <- s v + h f with s = *scale (nullptr: s = 1); x <- wrap(x + dt v).
+void launch_kick_drift(int64_t n, double h, double dt, const Grid &g, const double *scale, const double *fx,
+                       const double *fy, const double *fz, double *vx, double *vy, double *vz, double *x, double *y,
+                       double *z, int *err, hipStream_t st);
+// Nose-Hoover thermostat: constants of the half-steps.
+struct NhParams {
+  double dt, nf, kT, Q, mass;  // time step, degrees of freedom 3N - 3, target kT, thermostat mass, particle mass
+};
+enum { kNhStart = 1, kNhEnd = 2 };
+int nh_part_len();
+// Second half-kick (when h != 0; f -= mean written back when mean is given),
+// K = (m/2) sum |v|^2, then the thermostat half-steps of `mode` on nh = {xi,
+// eta} (device); *scale receives the velocity scaling still to apply.
+void launch_nh(int64_t n, double h, const double *mean, double *fx, double *fy, double *fz, double *vx, double *vy,
+               double *vz, const NhParams &q, int mode, double *part, double *nh, double *scale, int *err,
+               hipStream_t st);
+// v *= *scale.
+void launch_scale_v(int64_t n, const double *scale, double *vx, double *vy, double *vz, hipStream_t st);
 // Reorder the integrator state through perm (out[k] = in[perm[k]]).
 struct StateArrays {
   double *x, *y, *z, *vx, *vy, *vz, *q;

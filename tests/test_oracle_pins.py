@@ -517,3 +517,80 @@ def test_coulomb_virial_theorem_for_the_full_ewald_sum():
     ex = oracle.ewald_exact(x, y, z, q, L, alpha)
     assert uc + uk - us == pytest.approx(ex["u"], rel=1e-12)
     assert wc + wk == pytest.approx(uc + uk - us, rel=1e-11)
+
+
+def _nvt(r, v, xi, eta, q, L, s, m, w, dt, steps, kT, tau):
+    ids = np.arange(len(q), dtype=np.int32)
+
+    def force(r):
+        return oracle.total_force(r[:, 0], r[:, 1], r[:, 2], q, ids, s, m, w)["F"]
+    F = force(r)
+    for _ in range(steps):
+        r, v, F, xi, eta = oracle.nvt_step(r, v, F, xi, eta, force, dt, L, 1.0, kT, tau)
+    return r, v, xi, eta
+
+
+def test_nvt_time_reversible_with_fixed_modes():
+    """The Nose-Hoover equations are reversible under (v, xi) -> (-v, -xi);
+    the symmetric split keeps that exactly, up to rounding."""
+    n, L = 40, 8.0
+    x, y, z, q = random_ions(n, L, 44)
+    s = oracle.make_sys(L, 0.6, 3.9, 2.5)
+    m, w = oracle.sample_k(1, 0, L, 0.6, 20)
+    r0 = np.stack([x, y, z], axis=1)
+    v0 = np.stack(gen.velocities(44, 0, n), axis=1)
+    r1, v1, xi1, eta1 = _nvt(r0, v0, 0.3, 0.0, q, L, s, m, w, 0.002, 25, 0.5, 0.05)
+    assert abs(xi1 - 0.3) > 1e-3  # the thermostat did act
+    r2, v2, xi2, eta2 = _nvt(r1, -v1, -xi1, eta1, q, L, s, m, w, 0.002, 25, 0.5, 0.05)
+    d = (r2 - r0 + L / 2) % L - L / 2
+    assert np.abs(d).max() < 1e-9
+    assert np.abs(v2 + v0).max() < 1e-8
+    assert abs(xi2 + 0.3) < 1e-9 and abs(eta2) < 1e-9
+
+
+def test_nvt_with_infinite_thermostat_mass_is_nve():
+    """Q -> infinity leaves xi at 0, so every scaling is exactly 1."""
+    n, L = 40, 8.0
+    x, y, z, q = random_ions(n, L, 45)
+    s = oracle.make_sys(L, 0.6, 3.9, 2.5)
+    m, w = oracle.sample_k(1, 0, L, 0.6, 20)
+    r0 = np.stack([x, y, z], axis=1)
+    v0 = np.stack(gen.velocities(45, 0, n), axis=1)
+    r1, v1 = _vv(r0, v0, q, L, s, m, w, 0.002, 10)
+    r2, v2, xi, _ = _nvt(r0, v0, 0.0, 0.0, q, L, s, m, w, 0.002, 10, 0.5, 1e12)
+    assert np.array_equal(r1, r2) and np.array_equal(v1, v2) and abs(xi) < 1e-20
+
+
+@pytest.mark.slow
+def test_nvt_conserved_quantity_error_scales_as_dt_squared():
+    """With the exact Ewald force, K + U + Q xi^2/2 + N_f kT eta is conserved
+    by the Nose-Hoover dynamics; the integrator's error in it is O(dt^2)."""
+    n, L, a, kT, tau = 8, 5.0, 1.0, 0.5, 0.05
+    x, y, z, q = random_ions(n, L, 46)
+    r0 = np.stack([x, y, z], axis=1)
+    v0 = 0.5 * np.stack(gen.velocities(46, 0, n), axis=1)
+    nf = 3.0 * n - 3.0
+    Q = nf * kT * tau * tau
+
+    def force(r):
+        return oracle.ewald_exact(r[:, 0], r[:, 1], r[:, 2], q, L, a, tol=1e-14)
+
+    def h_dev(dt, T=0.2):
+        r, v, xi, eta = r0.copy(), v0.copy(), 0.0, 0.0
+        ex = force(r)
+        F = ex["F"]
+        h0 = ex["u"] + oracle.kinetic_energy(v, 1.0)
+        dev, last = 0.0, {}
+
+        def fwrap(rr):
+            last["ex"] = force(rr)
+            return last["ex"]["F"]
+        for _ in range(int(round(T / dt))):
+            r, v, F, xi, eta = oracle.nvt_step(r, v, F, xi, eta, fwrap, dt, L, 1.0, kT, tau)
+            h = last["ex"]["u"] + oracle.kinetic_energy(v, 1.0) + 0.5 * Q * xi * xi + nf * kT * eta
+            dev = max(dev, abs(h - h0))
+        return dev, xi
+
+    (d1, xi1), (d2, _) = h_dev(0.02), h_dev(0.01)
+    assert abs(xi1) > 1e-2  # the thermostat is active over the run
+    assert 2.5 < d1 / d2 < 6.0, (d1, d2)
