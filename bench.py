@@ -42,8 +42,10 @@ BYTES_KICK = 96          # read f (24) v (24), write v (24) f (24)
 
 # cell edges picked by paper_2609_02694_amd.tune on MI355X: (edge along y and z,
 # x cells per y/z cell edge)
-DEFAULT_NCELL_H = {"plain3k": 3.0, "electrolyte1m": 3.0, "ions8m": 4.0, "subdomain64m": 2.5, "replica": 2.5}
-DEFAULT_XSPLIT = {"plain3k": 1, "electrolyte1m": 6, "ions8m": 6, "subdomain64m": 4, "replica": 3}
+DEFAULT_NCELL_H = {"plain3k": 3.0, "electrolyte1m": 3.0, "ions8m": 4.0, "subdomain64m": 2.5, "replica": 2.5,
+                   "ljelectrolyte": 8.2}
+DEFAULT_XSPLIT = {"plain3k": 1, "electrolyte1m": 6, "ions8m": 6, "subdomain64m": 4, "replica": 3,
+                  "ljelectrolyte": 4}
 
 
 def parse():
@@ -52,7 +54,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="electrolyte1m",
-                    choices=["plain3k", "electrolyte1m", "ions8m", "subdomain64m", "replica256"])
+                    choices=["plain3k", "electrolyte1m", "ions8m", "subdomain64m", "replica256",
+                             "ljelectrolyte"])
     ap.add_argument("--compare-steps", type=int, default=100,
                     help="steps of each comparison form (the other precision; replica256: FP64 and FP32C "
                          "per-replica loops and the other-precision batch); 0 skips them")
@@ -107,7 +110,7 @@ def main():
     if a.workload == "replica256":
         return bench_batch(a)
     p = gen.preset(a.workload, n=a.n)
-    prec_name = a.prec or ("fp64" if a.workload in ("plain3k", "electrolyte1m") else "fp32c")
+    prec_name = a.prec or ("fp64" if a.workload in ("plain3k", "electrolyte1m", "ljelectrolyte") else "fp32c")
     prec = rbe.FP64 if prec_name == "fp64" else rbe.FP32C
     h = a.edge or DEFAULT_NCELL_H.get(a.workload, 3.0)
     nc = max(1, int(p["L"] // h))
@@ -125,6 +128,8 @@ def main():
     params = rbe.params_from_preset(p, prec=prec, ncell=(nx, nc, nc))
     ctx = rbe.Context(params, n)
     st = rbe.Particles.from_numpy(s)
+    if p.get("nvt_tau", 0.0) > 0:
+        st.nh = torch.zeros(2, dtype=torch.float64, device="cuda")  # Nose-Hoover {xi, eta}
     stream = torch.cuda.current_stream()
 
     # algorithmic counts of one force evaluation (counting pass, untimed)
@@ -170,6 +175,8 @@ def main():
         oname = "fp32c" if other == rbe.FP32C else "fp64"
         octx = rbe.Context(rbe.params_from_preset(p, prec=other, ncell=(nx, nc, nc)), n)
         ost = rbe.Particles.from_numpy(s)
+        if p.get("nvt_tau", 0.0) > 0:
+            ost.nh = torch.zeros(2, dtype=torch.float64, device="cuda")
         octx.forces(ost, None, None, 0)
         octx.step(ost, 3, 1)
         torch.cuda.synchronize()
@@ -196,6 +203,7 @@ def main():
         "config": {"workload": a.workload, "n": n, "n_charged": nq, "L": round(p["L"], 4), "alpha": p["alpha"],
                    "r_coul": p["r_coul"], "r_lj": p["r_lj"], "r_core": p["r_core"], "p_shell": p["p_shell"],
                    "P": p["P"], "dt": p["dt"], "form": prec_name, "ncell": [nx, nc, nc], "tuned": tuned,
+                   "ensemble": "NVT" if p.get("nvt_tau", 0.0) > 0 else "NVE",
                    "parallelism": "single GPU"},
         "event_ms_per_step": ev_ms / K,
         "kernels": kernels,

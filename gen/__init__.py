@@ -118,6 +118,13 @@ PRESETS = {
     # N = 64,000,000 at density 0.8, 10 % ions, 6-sigma ghost shell built locally, P = 1000.
     "subdomain64m": dict(seed=1005, n=64_000_000, density=0.8, L=None, frac_charged=0.10, alpha=0.35,
                          r_coul=6.0, r_lj=2.5, r_core=0.0, p_shell=0, P=1000, dt=0.002, ghost=6.0),
+    # The paper's implicit-solvent LJ electrolyte (Sec. 3.1 and its parameter table): N = 200,000
+    # monovalent ions, L = 271, one short-range cutoff r_s = 8 for LJ and Coulomb, core r_c = 4,
+    # batch p = 30, P = 200, dt = 0.001, Nose-Hoover at kT = 1 (relaxation time 100 dt). alpha is
+    # not printed: sqrt(alpha) r_s = 3 (erfc(3) = 2.2e-5, below the 1e-4 the paper asks of PPPM).
+    "ljelectrolyte": dict(seed=1006, n=200_000, density=200_000 / 271.0 ** 3, L=271.0, frac_charged=1.0,
+                              alpha=(3.0 / 8.0) ** 2, r_coul=8.0, r_lj=8.0, r_core=4.0, p_shell=30, P=200,
+                              dt=0.001, ghost=0.0, nvt_kT=1.0, nvt_tau=0.1),
 }
 
 

@@ -1301,7 +1301,9 @@ extern "C" int rbe_set_timing(rbe_ctx *c, int enable) {
   if (enable) {
     if (t.ev.empty()) {
       t.ev.resize(16384);
-      for (auto &e : t.ev) HIP_TRY(c, hipEventCreate(&e));
+      // timing only: no system-scope release at each record (that release
+      // writes back and invalidates the caches between the timed kernels)
+      for (auto &e : t.ev) HIP_TRY(c, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     }
     t.used = 0;
     t.kind.clear();

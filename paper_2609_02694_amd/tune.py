@@ -44,12 +44,15 @@ def _grid(ncell):
 
 
 def time_steps(preset: dict, state_np: dict, ncell, prec: int, steps: int = 20, warmup: int = 3) -> float:
-    """Milliseconds per step of `steps` velocity-Verlet steps on grid ncell ((nx, ny, nz) or n for n^3)."""
+    """Milliseconds per step of `steps` steps (velocity Verlet, NVT when the preset asks for it) on grid
+    ncell ((nx, ny, nz) or n for n^3)."""
     import torch
 
     params = params_from_preset(preset, prec=prec, ncell=_grid(ncell))
     ctx = Context(params, preset["n"])
     st = Particles.from_numpy(state_np)
+    if preset.get("nvt_tau", 0.0) > 0:
+        st.nh = torch.zeros(2, dtype=torch.float64, device="cuda")  # Nose-Hoover {xi, eta}
     ctx.forces(st, None, None, 0)
     ctx.step(st, warmup, 1)
     torch.cuda.synchronize()
@@ -132,7 +135,7 @@ def tune_batch(reps, cat_np: dict, offsets, prec: int, steps: int = 10, edges=BA
 # ---------------------------------------------------------------------------
 # cache of tuned grids
 # ---------------------------------------------------------------------------
-_KEY_FIELDS = ("n", "L", "alpha", "r_coul", "r_lj", "r_core", "p_shell", "P", "ghost")
+_KEY_FIELDS = ("n", "L", "alpha", "r_coul", "r_lj", "r_core", "p_shell", "P", "ghost", "nvt_tau")
 
 
 def tune_key(preset: dict, prec: int, kind: str = "grid", extra=None) -> str:

@@ -98,6 +98,18 @@ def test_full_electrolyte1m_fp64():
     assert np.abs(mean_est).max() < 1.0
 
 
+def test_full_ljelectrolyte_fp64():
+    """The paper's LJ electrolyte at its full size (200,000 ions, L = 271,
+    one cutoff r_s = 8, core 4, p = 30), FP64, as for the 1M electrolyte."""
+    p, s, F, idx, FN, FF = run_full("ljelectrolyte", rbe.FP64)
+    assert np.abs(F.sum(axis=0)).max() < 1e-9 * np.abs(F).sum() / len(F)
+    ref = FN + FF
+    mean_est = (ref - F[idx]).mean(axis=0)
+    e = rel_err(F[idx] + mean_est, ref)
+    print(f"ljelectrolyte FP64 sampled rel err {e:.3e}, mean {mean_est}")
+    assert e < 1e-12
+
+
 def test_full_ions8m_fp32c():
     p, s, F, idx, FN, FF = run_full("ions8m", rbe.FP32C)
     e = rel_err(F[idx], FN + FF)

@@ -133,3 +133,51 @@ def test_nvt_errors():
     pr = rbe.params_from_preset(dict(p, n=2000, L=26.0))
     with pytest.raises(rbe.RbeError):
         rbe.Context.batch([pr, pr], [0, 2000, 4000])
+
+
+@pytest.fixture(scope="module")
+def ljel20k():
+    """The paper's LJ electrolyte (one short-range cutoff r_s = 8 for LJ and
+    Coulomb, core 4, p = 30, P = 200, dt = 0.001, Nose-Hoover at kT = 1) at
+    20,000 ions and the paper's density."""
+    p, s = system("ljelectrolyte", n=20000)
+    m, w = oracle.sample_k(p["seed"], 0, p["L"], p["alpha"], p["P"])
+    ref = oracle.total_force(s["x"], s["y"], s["z"], s["q"], s["id"], oracle.sys_from_preset(p), m, w,
+                             seed=p["seed"], ev=0, components=False)
+    return p, s, m, w, ref
+
+
+@pytest.mark.parametrize("prec,tol", [(rbe.FP64, TOL64), (rbe.FP32C, 1e-5)])
+def test_forces_ljelectrolyte_20k(ljel20k, prec, tol):
+    from gpu_common import gpu_forces
+    p, s, m, w, ref = ljel20k
+    F = gpu_forces(p, s, prec=prec, m=m, w=w)
+    e = rel_err(F, ref["F"])
+    print(f"LJ electrolyte 20k prec={prec} rel err {e:.3e}")
+    assert e < tol
+
+
+def test_step_nvt_ljelectrolyte_20k_trajectory(ljel20k):
+    p, s, _, _, _ = ljel20k
+    nsteps = 3
+    g = _run_gpu(p, s, nsteps)
+    osys = oracle.sys_from_preset(p)
+
+    def force(r, ev):
+        m, w = oracle.sample_k(p["seed"], ev, p["L"], p["alpha"], p["P"])
+        return oracle.total_force(r[:, 0], r[:, 1], r[:, 2], s["q"], s["id"], osys, m, w, seed=p["seed"], ev=ev,
+                                  components=False)["F"]
+
+    r = np.stack([s["x"], s["y"], s["z"]], axis=1)
+    v = np.stack([s["vx"], s["vy"], s["vz"]], axis=1)
+    F = force(r, 0)
+    xi, eta = 0.0, 0.0
+    for k in range(nsteps):
+        r, v, F, xi, eta = oracle.nvt_step(r, v, F, xi, eta, lambda rr: force(rr, k + 1), p["dt"], p["L"], 1.0,
+                                           p["nvt_kT"], p["nvt_tau"])
+    d = (g["x"] - r + p["L"] / 2) % p["L"] - p["L"] / 2
+    print(f"LJ electrolyte NVT: xi {g['nh'][0]:.12e} (oracle {xi:.12e}), v rel {rel_err(g['v'], v):.2e}")
+    assert np.abs(d).max() < 1e-12 * p["L"]
+    assert rel_err(g["v"], v) < TOL64
+    assert rel_err(g["f"], F) < TOL64
+    assert abs(g["nh"][0] - xi) <= TOL64 * abs(xi) + 1e-15 and abs(g["nh"][1] - eta) <= TOL64 * abs(eta) + 1e-18
