@@ -48,6 +48,8 @@ def _create(p, n=100):
     ("kdist", 1, rbe.RBE_EINVAL),
     ("mass", 0.0, rbe.RBE_EINVAL),
     ("ghost_width", 1e-3, rbe.RBE_EINVAL),
+    ("nvt_tau", -0.1, rbe.RBE_EINVAL),
+    ("nvt_tau", float("inf"), rbe.RBE_EINVAL),
 ])
 def test_create_rejects_bad_params(field, value, code):
     p = rbe.make_params(30.0, 0.3, 8.0, 2.5, 100)
@@ -63,6 +65,18 @@ def test_create_rejects_bad_shell_batch():
     assert _create(p)[0] == rbe.RBE_EINVAL
 
 
+def test_create_rejects_thermostat_without_temperature():
+    p = rbe.make_params(30.0, 0.3, 8.0, 2.5, 100, nvt_tau=0.1, nvt_kT=0.0)
+    rc, msg = _create(p)
+    assert rc == rbe.RBE_EINVAL and "nvt_kT" in msg
+
+
+def test_create_batch_rejects_thermostat():
+    p = [rbe.make_params(12.6, 0.3, 6.0, 2.5, 100, seed=r, nvt_tau=0.1, nvt_kT=1.0) for r in range(2)]
+    rc, msg = _create_batch(p, [0, 10, 20])
+    assert rc == rbe.RBE_EINVAL and "NVT" in msg
+
+
 def test_create_rejects_bad_capacity():
     p = rbe.make_params(30.0, 0.3, 8.0, 2.5, 100)
     assert _create(p, n=0)[0] == rbe.RBE_EINVAL
@@ -73,6 +87,7 @@ def test_null_arguments():
     assert lib.rbe_create(None, None, 10, 0) == rbe.RBE_EINVAL
     assert lib.rbe_forces(None, None, None, None, 0, None, None) == rbe.RBE_EINVAL
     assert lib.rbe_step(None, None, 1, 0, None) == rbe.RBE_EINVAL
+    assert lib.rbe_energy(None, None, None, None, 0, None, None, None) == rbe.RBE_EINVAL
     assert lib.rbe_sync_check(None, None) == rbe.RBE_EINVAL
 
 
