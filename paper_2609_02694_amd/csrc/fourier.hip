@@ -10,8 +10,10 @@
 //
 // Structure factor: thread = mode, particles walked in a wave-uniform loop
 // (scalar loads of the packed (s, q) records), one partial sum per particle
-// chunk and mode; no cross-lane reduction. The chunk partials are summed in
-// FP64 in a fixed order by a second kernel.
+// chunk and mode. A wave left with fewer than 64 modes (P not a multiple of
+// 64) spreads each mode over several lanes that split the chunk's particles
+// and adds their sums with a fixed butterfly. The chunk partials are summed
+// in FP64 in a fixed order by a second kernel.
 //
 // Gather: thread = particle, modes walked in a wave-uniform loop with the
 // per-mode coefficients (m, w Im rho, w Re rho) in scalar registers.
@@ -49,18 +51,50 @@ void launch_modes_to_double(int P, const int32_t *m, double *mkd, hipStream_t st
 // ---------------------------------------------------------------------------
 // structure factor partial sums
 // ---------------------------------------------------------------------------
+// A wave holds 64 consecutive modes. The last wave of a mode set whose size
+// is not a multiple of 64 holds a < 64: its lanes then split as rep lanes per
+// mode (rep the largest power of two with rep a <= 64), each taking every
+// rep-th particle of the chunk, and the rep partial sums of a mode are added
+// by a fixed butterfly, so that wave does 1/rep of the trips instead of all.
+__device__ inline int wave_rep(int a) {
+  int rep = 1;
+  while (2 * rep * a <= 64) rep *= 2;
+  return rep;
+}
+
 __global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f64(int64_t nq, int P, int chunk,
                                                                      const double4 *__restrict__ sq,
                                                                      const double *__restrict__ mkd,
                                                                      double2 *__restrict__ part) {
-  const int l = blockIdx.y * kModesPerBlock + threadIdx.x;
-  const bool active = l < P;
-  const double mx = active ? mkd[l] : 0.0, my = active ? mkd[P + l] : 0.0, mz = active ? mkd[2 * P + l] : 0.0;
+  const int lane = threadIdx.x & 63;
+  const int l0 = blockIdx.y * kModesPerBlock + (threadIdx.x & ~63);  // first mode of this wave
+  const int a = min(64, P - l0);                                      // modes of this wave
+  if (a <= 0) return;
   const int64_t j0 = (int64_t)blockIdx.x * chunk;
   const int64_t j1 = min(nq, j0 + chunk);
-  double re = 0.0, im = 0.0;
+  if (a == 64) {
+    const int l = l0 + lane;
+    const double mx = mkd[l], my = mkd[P + l], mz = mkd[2 * P + l];
+    double re = 0.0, im = 0.0;
 #pragma unroll 4
-  for (int64_t j = j0; j < j1; ++j) {
+    for (int64_t j = j0; j < j1; ++j) {
+      const double4 s = sq[j];
+      const double t = turn_fraction(mx, my, mz, s.x, s.y, s.z);
+      double sn, cs;
+      sincos_turn_f64(t, &sn, &cs);
+      re = fma(s.w, cs, re);
+      im = fma(s.w, sn, im);
+    }
+    part[(int64_t)blockIdx.x * P + l] = make_double2(re, im);
+    return;
+  }
+  const int rep = wave_rep(a);
+  const int mi = lane / rep, ph = lane % rep;
+  const bool active = mi < a;
+  const int l = l0 + (active ? mi : 0);
+  const double mx = mkd[l], my = mkd[P + l], mz = mkd[2 * P + l];
+  double re = 0.0, im = 0.0;
+  for (int64_t j = j0 + ph; j < j1; j += rep) {
     const double4 s = sq[j];
     const double t = turn_fraction(mx, my, mz, s.x, s.y, s.z);
     double sn, cs;
@@ -68,30 +102,53 @@ __global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f64(int64_t nq, 
     re = fma(s.w, cs, re);
     im = fma(s.w, sn, im);
   }
-  if (active) part[(int64_t)blockIdx.x * P + l] = make_double2(re, im);
+  for (int o = rep >> 1; o > 0; o >>= 1) {
+    re += __shfl_xor(re, o, 64);
+    im += __shfl_xor(im, o, 64);
+  }
+  if (active && ph == 0) part[(int64_t)blockIdx.x * P + l] = make_double2(re, im);
 }
 
 __global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f32c(int64_t nq, int P, int chunk,
                                                                       const double4 *__restrict__ sq,
                                                                       const double *__restrict__ mkd,
                                                                       double2 *__restrict__ part) {
-  const int l = blockIdx.y * kModesPerBlock + threadIdx.x;
-  const bool active = l < P;
-  const double mx = active ? mkd[l] : 0.0, my = active ? mkd[P + l] : 0.0, mz = active ? mkd[2 * P + l] : 0.0;
+  const int lane = threadIdx.x & 63;
+  const int l0 = blockIdx.y * kModesPerBlock + (threadIdx.x & ~63);
+  const int a = min(64, P - l0);
+  if (a <= 0) return;
   const int64_t j0 = (int64_t)blockIdx.x * chunk;
   const int64_t j1 = min(nq, j0 + chunk);
+  const int rep = a == 64 ? 1 : wave_rep(a);
+  const int mi = lane / rep, ph = lane % rep;
+  const bool active = mi < a;
+  const int l = l0 + (active ? mi : 0);
+  const double mx = mkd[l], my = mkd[P + l], mz = mkd[2 * P + l];
   float re = 0.f, re_c = 0.f, im = 0.f, im_c = 0.f;
+  if (rep == 1) {
 #pragma unroll 4
-  for (int64_t j = j0; j < j1; ++j) {
-    const double4 s = sq[j];
-    const float t = (float)turn_fraction(mx, my, mz, s.x, s.y, s.z);
-    const float q = (float)s.w;
-    const float cs = __builtin_amdgcn_cosf(t);
-    const float sn = __builtin_amdgcn_sinf(t);
-    kahan_fma(re, re_c, q, cs);
-    kahan_fma(im, im_c, q, sn);
+    for (int64_t j = j0; j < j1; ++j) {
+      const double4 s = sq[j];
+      const float t = (float)turn_fraction(mx, my, mz, s.x, s.y, s.z);
+      const float q = (float)s.w;
+      kahan_fma(re, re_c, q, __builtin_amdgcn_cosf(t));
+      kahan_fma(im, im_c, q, __builtin_amdgcn_sinf(t));
+    }
+  } else {
+    for (int64_t j = j0 + ph; j < j1; j += rep) {
+      const double4 s = sq[j];
+      const float t = (float)turn_fraction(mx, my, mz, s.x, s.y, s.z);
+      const float q = (float)s.w;
+      kahan_fma(re, re_c, q, __builtin_amdgcn_cosf(t));
+      kahan_fma(im, im_c, q, __builtin_amdgcn_sinf(t));
+    }
   }
-  if (active) part[(int64_t)blockIdx.x * P + l] = make_double2((double)re - (double)re_c, (double)im - (double)im_c);
+  double dre = (double)re - (double)re_c, dim = (double)im - (double)im_c;
+  for (int o = rep >> 1; o > 0; o >>= 1) {
+    dre += __shfl_xor(dre, o, 64);
+    dim += __shfl_xor(dim, o, 64);
+  }
+  if (active && ph == 0) part[(int64_t)blockIdx.x * P + l] = make_double2(dre, dim);
 }
 
 // rho_l = sum over chunks (fixed order: thread-strided FP64 sums, a fixed

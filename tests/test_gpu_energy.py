@@ -180,3 +180,21 @@ def test_virial_is_minus_dilation_derivative_of_gpu_energy():
         u.append(e["coul_real"] + e["lj"])
     fd = -(u[0] - u[1]) / (2 * h)
     assert fd == pytest.approx(e0["w_coul_real"] + e0["w_lj"], rel=1e-6)
+
+
+def test_energy_without_charges_and_single_particle():
+    """Degenerate cases: a pure LJ fluid (no charged particle: the Coulomb,
+    Fourier and self terms vanish) and a single neutral particle."""
+    p, s = system("plain3k", n=800, L=20.0, frac_charged=0.0)
+    assert not np.any(s["q"])
+    m, w = oracle.sample_k(p["seed"], 0, p["L"], p["alpha"], p["P"])
+    got = gpu_energy(p, s, m=m, w=w)
+    for k in ("coul_real", "fourier", "self", "w_coul_real", "w_fourier"):
+        assert got[k] == 0.0, k
+    assert_terms_close(got, oracle_energy(p, s, m, w))
+    one = {k: np.array(v[:1]) for k, v in s.items() if k != "L"}
+    one["id"] = np.zeros(1, np.int32)
+    got1 = gpu_energy(dict(p, n=1), one, m=m, w=w)
+    assert got1["lj"] == 0.0 and got1["coul_real"] == 0.0 and got1["fourier"] == 0.0
+    assert got1["kinetic"] == pytest.approx(0.5 * float(one["vx"][0] ** 2 + one["vy"][0] ** 2 + one["vz"][0] ** 2),
+                                            rel=1e-15)

@@ -181,3 +181,31 @@ def test_step_nvt_ljelectrolyte_20k_trajectory(ljel20k):
     assert rel_err(g["v"], v) < TOL64
     assert rel_err(g["f"], F) < TOL64
     assert abs(g["nh"][0] - xi) <= TOL64 * abs(xi) + 1e-15 and abs(g["nh"][1] - eta) <= TOL64 * abs(eta) + 1e-18
+
+
+def test_step_nvt_ghost_shell_fp32c_tracks_fp64():
+    """NVT on a ghost-shell context in FP32C: after 4 steps the forces match a
+    fresh oracle evaluation to the FP32C bound and the thermostat variable
+    follows the FP64 run to the size of the FP32C force error."""
+    p, s = system("subdomain64m", n=30000, nvt_kT=0.8, nvt_tau=0.05)
+    out = {}
+    for prec in (rbe.FP64, rbe.FP32C):
+        ctx = rbe.Context(rbe.params_from_preset(p, prec=prec), p["n"])
+        st = to_device(s)
+        st.nh = torch.zeros(2, dtype=torch.float64, device="cuda")
+        ctx.forces(st, None, None, 0)
+        ctx.step(st, 4, 1)
+        torch.cuda.synchronize()
+        ctx.sync_check()
+        out[prec] = (st, float(st.nh[0].cpu()))
+        ctx.close()
+    st, xi32 = out[rbe.FP32C]
+    xi64 = out[rbe.FP64][1]
+    x = st.x.cpu().numpy(); y = st.y.cpu().numpy(); z = st.z.cpu().numpy()
+    q = st.q.cpu().numpy(); ids = st.id.cpu().numpy()
+    m, w = oracle.sample_k(p["seed"], 4, p["L"], p["alpha"], p["P"])
+    ref = oracle.total_force(x, y, z, q, ids, oracle.sys_from_preset(p), m, w, seed=p["seed"], ev=4, cells=True,
+                             components=False)["F"]
+    F = np.stack([st.fx.cpu().numpy(), st.fy.cpu().numpy(), st.fz.cpu().numpy()], axis=1)
+    assert rel_err(F, ref) < 1e-5
+    assert xi64 != 0.0 and abs(xi32 - xi64) < 1e-6 * abs(xi64)
