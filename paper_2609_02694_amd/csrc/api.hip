@@ -404,6 +404,7 @@ extern "C" int rbe_create(rbe_ctx **out, const rbe_params *p, int64_t n_max, int
   c->fb.part = b.alloc<double2>(nchunk * P);
   c->fb.rho = b.alloc<double>(2 * P);
   c->fb.modes = b.alloc<GatherMode>(P);
+  c->fb.turn_tab = b.alloc<double2>(kTurnTableEntries);
   c->m_dev = b.alloc<int32_t>((int64_t)kSampleSteps * 3 * P);
   c->w_dev = b.alloc<double>((int64_t)kSampleSteps * P);
   c->mkd_dev = b.alloc<double>((int64_t)kSampleSteps * 3 * P);
@@ -448,7 +449,10 @@ extern "C" int rbe_create(rbe_ctx **out, const rbe_params *p, int64_t n_max, int
     delete c;
     return create_fail(RBE_ENOMEM, "device allocation failed");
   }
+  double2 turn_host[kTurnTableEntries];
+  fill_turn_table(turn_host, kTurnTableEntries);
   if (hipMemcpy(c->cdf_dev, c->cdf_host.data(), sizeof(double) * c->mt.total, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->fb.turn_tab, turn_host, sizeof turn_host, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(c->err, 0, sizeof(int)) != hipSuccess ||
       hipMemset(c->counters, 0, 12 * sizeof(unsigned long long)) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {

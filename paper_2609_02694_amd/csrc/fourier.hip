@@ -27,6 +27,14 @@ namespace rbe {
 
 constexpr int kModesPerBlock = 256;
 
+void fill_turn_table(double2 *host, int n) {
+  const long double two_pi = 6.283185307179586476925286766559005768L;
+  for (int k = 0; k < n; ++k) {
+    const long double a = two_pi * (long double)k / (long double)n;
+    host[k] = make_double2((double)sinl(a), (double)cosl(a));
+  }
+}
+
 int rho_chunk(int64_t nq, int P, int prec, int nchunk_max) {
   // enough chunks to fill the chip (about 8k waves), never more than the scratch holds
   const int64_t groups = (P + 63) / 64;
@@ -65,7 +73,12 @@ __device__ inline int wave_rep(int a) {
 __global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f64(int64_t nq, int P, int chunk,
                                                                      const double4 *__restrict__ sq,
                                                                      const double *__restrict__ mkd,
+                                                                     const double2 *__restrict__ turn_tab,
                                                                      double2 *__restrict__ part) {
+  static_assert(kModesPerBlock == kTurnTable, "one table entry per thread");
+  __shared__ double2 tab[kTurnTable];
+  tab[threadIdx.x] = turn_tab[threadIdx.x];
+  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int l0 = blockIdx.y * kModesPerBlock + (threadIdx.x & ~63);  // first mode of this wave
   const int a = min(64, P - l0);                                      // modes of this wave
@@ -81,7 +94,7 @@ __global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f64(int64_t nq, 
       const double4 s = sq[j];
       const double t = turn_fraction(mx, my, mz, s.x, s.y, s.z);
       double sn, cs;
-      sincos_turn_f64(t, &sn, &cs);
+      sincos_turn_tab_f64(t, tab, &sn, &cs);
       re = fma(s.w, cs, re);
       im = fma(s.w, sn, im);
     }
@@ -98,7 +111,7 @@ __global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f64(int64_t nq, 
     const double4 s = sq[j];
     const double t = turn_fraction(mx, my, mz, s.x, s.y, s.z);
     double sn, cs;
-    sincos_turn_f64(t, &sn, &cs);
+    sincos_turn_tab_f64(t, tab, &sn, &cs);
     re = fma(s.w, cs, re);
     im = fma(s.w, sn, im);
   }
@@ -211,7 +224,7 @@ int launch_rho_partial(int prec, int64_t nq, int P, const double4 *sq, const Fou
   if (prec == RBE_FP32C)
     k_rho_partial_f32c<<<grid, kModesPerBlock, 0, st>>>(nq, P, chunk, sq, fb.mkd, fb.part);
   else
-    k_rho_partial_f64<<<grid, kModesPerBlock, 0, st>>>(nq, P, chunk, sq, fb.mkd, fb.part);
+    k_rho_partial_f64<<<grid, kModesPerBlock, 0, st>>>(nq, P, chunk, sq, fb.mkd, fb.turn_tab, fb.part);
   return nchunks;
 }
 
@@ -223,10 +236,14 @@ void launch_rho_final(int nchunks, int P, const FourierBuffers &fb, const double
 // ---------------------------------------------------------------------------
 // force gather (adds F^F into f for the charged range)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_gather_f64(int64_t nq, int P, const double4 *__restrict__ sq,
-                                                    const GatherMode *__restrict__ modes, double kx, double ky,
-                                                    double kz, double *__restrict__ fx, double *__restrict__ fy,
-                                                    double *__restrict__ fz) {
+__global__ void __launch_bounds__(kTurnTable) k_gather_f64(int64_t nq, int P, const double4 *__restrict__ sq,
+                                                           const GatherMode *__restrict__ modes,
+                                                           const double2 *__restrict__ turn_tab, double kx,
+                                                           double ky, double kz, double *__restrict__ fx,
+                                                           double *__restrict__ fy, double *__restrict__ fz) {
+  __shared__ double2 tab[kTurnTable];
+  tab[threadIdx.x] = turn_tab[threadIdx.x];
+  __syncthreads();
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= nq) return;
   const double4 s = sq[i];
@@ -236,7 +253,7 @@ __global__ void __launch_bounds__(256) k_gather_f64(int64_t nq, int P, const dou
     const GatherMode gm = modes[l];
     const double t = turn_fraction(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
     double sn, cs;
-    sincos_turn_f64(t, &sn, &cs);
+    sincos_turn_tab_f64(t, tab, &sn, &cs);
     const double g = gm.a * cs - gm.b * sn;  // w Im(exp(-i theta) rho)
     gx = fma(g, gm.mx, gx);
     gy = fma(g, gm.my, gy);
@@ -281,7 +298,7 @@ void launch_fourier_gather(int prec, int64_t nq, int P, const double4 *sq, const
   if (prec == RBE_FP32C)
     k_gather_f32c<<<blocks, 256, 0, st>>>(nq, P, sq, fb.modes, kx, ky, kz, fx, fy, fz);
   else
-    k_gather_f64<<<blocks, 256, 0, st>>>(nq, P, sq, fb.modes, kx, ky, kz, fx, fy, fz);
+    k_gather_f64<<<blocks, kTurnTable, 0, st>>>(nq, P, sq, fb.modes, fb.turn_tab, kx, ky, kz, fx, fy, fz);
 }
 
 }  // namespace rbe

@@ -44,6 +44,25 @@ __device__ inline void sincos_turn_f64(double t, double *sn, double *cs) {
   *cs = (k == 1 || k == 2) ? -b : b;
 }
 
+// sin and cos of 2 pi t for |t| <= 1/2 (FP64) from a table of the
+// kTurnTable-th turns: j = rint(N t) and f = N t - j are exact (N a power of
+// two), theta = 2 pi f / N lies in [-pi/N, pi/N], its sine and cosine come
+// from Taylor polynomials of degrees 5 and 6 (truncation below 1e-17 for
+// N = 256), and the angle-addition formulas combine them with the table's
+// (sin, cos) of 2 pi j / N. tab is the table in LDS.
+constexpr int kTurnTable = kTurnTableEntries;
+__device__ inline void sincos_turn_tab_f64(double t, const double2 *tab, double *sn, double *cs) {
+  const double u = t * (double)kTurnTable;
+  const double j = rint(u);
+  const double th = (u - j) * (6.283185307179586 / kTurnTable);
+  const double t2 = th * th;
+  const double s = fma(fma(t2, 1.0 / 120.0, -1.0 / 6.0) * t2, th, th);
+  const double c = fma(fma(fma(t2, -1.0 / 720.0, 1.0 / 24.0), t2, -0.5), t2, 1.0);
+  const double2 e = tab[(int)j & (kTurnTable - 1)];  // (sin, cos) of 2 pi j / N
+  *sn = fma(e.x, c, e.y * s);
+  *cs = fma(e.y, c, -(e.x * s));
+}
+
 // Kahan-compensated FP32 sum of products: sum += a b, with the product
 // fused into the compensation step (one rounding instead of two).
 __device__ inline void kahan_fma(float &sum, float &comp, float a, float b) {

@@ -128,8 +128,13 @@ struct FourierBuffers {
   double2 *part;         // [nchunk_max][P] partial structure factors
   double *rho;           // [2 * P] Re | Im
   GatherMode *modes;     // [P]
+  double2 *turn_tab;     // [kTurnTableEntries] (sin, cos) of 2 pi k / kTurnTableEntries (FP64 kernels)
   int nchunk_max;
 };
+constexpr int kTurnTableEntries = 256;
+// Host values of the FP64 kernels' turn table (n entries of (sin, cos) of
+// 2 pi k / n, each rounded once from extended precision).
+void fill_turn_table(double2 *host, int n);
 // Chunk length of the structure-factor partial sums for nq charged particles.
 int rho_chunk(int64_t nq, int P, int prec, int nchunk_max);
 void launch_modes_to_double(int P, const int32_t *m, double *mkd, hipStream_t st);
