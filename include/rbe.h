@@ -53,8 +53,15 @@ typedef enum {
 
 typedef enum { RBE_FP64 = 0, RBE_FP32C = 1 } rbe_precision;
 
-/* Fourier-mode distribution. Only the paper's Gaussian is provided. */
-typedef enum { RBE_KDIST_GAUSS = 0 } rbe_kdist;
+/* Fourier-mode distribution of the importance sample.
+   RBE_KDIST_GAUSS: P(k) ~ exp(-k^2/(4 alpha)) (Eq. 9, the paper's), weights
+     w = (S/P) 4 pi / (V k^2), S = sum_{k != 0} exp(-k^2/(4 alpha)).
+   RBE_KDIST_GAUSS_OVER_K2: P(k) ~ exp(-k^2/(4 alpha))/k^2, weights
+     w = (S2/P) 4 pi / V, S2 = sum_{k != 0} exp(-k^2/(4 alpha))/k^2 over the
+     sampler's lattice; drawn by rejection from the Gaussian (acceptance
+     k_min^2/k^2), so each draw costs more, the more so the larger the box.
+     Not available in the batched form. */
+typedef enum { RBE_KDIST_GAUSS = 0, RBE_KDIST_GAUSS_OVER_K2 = 1 } rbe_kdist;
 
 /* Terms of F to evaluate (bit mask). */
 enum { RBE_TERM_LJ = 1, RBE_TERM_COUL_REAL = 2, RBE_TERM_FOURIER = 4, RBE_TERM_ALL = 7 };
@@ -151,11 +158,13 @@ int rbe_build_cells(rbe_ctx *ctx, const double *x, const double *y, const double
                     int32_t *cell_start, int32_t *perm, void *stream);
 
 /* Importance sample of Eq. 9 for force evaluation `eval`: writes m[3*P]
-   (integer mode vectors, blocks x | y | z, k = 2 pi m / L) and w[P] (weights
-   (S/P) 4 pi / (V k^2)). Draw l, attempt a uses outputs 3a..3a+2 of a
+   (integer mode vectors, blocks x | y | z, k = 2 pi m / L) and w[P] (the
+   weights of p->kdist). Draw l, attempt a uses outputs 3a..3a+2 of a
    SplitMix64 stream keyed by (seed, eval, l); each output is mapped through
    the per-axis inverse CDF of exp(-(pi m / L_d)^2 / alpha) and m = 0 is
-   rejected. on_device = 0: m, w are HOST pointers, computed on the host;
+   rejected. RBE_KDIST_GAUSS_OVER_K2: attempt a uses outputs 4a..4a+2 that
+   way and is accepted when m != 0 and u k^2 < k_min^2 with u = output 4a+3
+   and k_min = 2 pi / max_d L_d. on_device = 0: m, w are HOST pointers, computed on the host;
    on_device = 1: DEVICE pointers, computed by a kernel on `stream`. Both
    paths give identical bits. */
 int rbe_sample_k(const rbe_params *p /* host */, uint64_t eval, int32_t *m, double *w, int on_device,

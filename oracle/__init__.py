@@ -58,6 +58,7 @@ def _load():
         "orc_axis_cutoff": (ctypes.c_int, [d, d]),
         "orc_axis_H": (d, [d, d]),
         "orc_norm_S": (d, [_D, d]),
+        "orc_norm_S2": (d, [_D, d]),
         "orc_sample_k": (ctypes.c_int, [u64, u64, _D, d, i32, i32, _I32, _D]),
         "orc_rho": (None, [i64, _D, _D, _D, _D, _D, i32, _I32, _D, _D]),
         "orc_fourier_force": (None, [i64, _D, _D, _D, _D, _D, i32, _I32, _D, _D, _D, _D, _D, _D]),
@@ -135,6 +136,11 @@ def axis_H(L, alpha) -> float:
 def norm_S(L, alpha) -> float:
     Lv, pL = _d(np.broadcast_to(np.asarray(L, np.float64), (3,)))
     return _load().orc_norm_S(pL, alpha)
+
+
+def norm_S2(L, alpha) -> float:
+    Lv, pL = _d(np.broadcast_to(np.asarray(L, np.float64), (3,)))
+    return _load().orc_norm_S2(pL, alpha)
 
 
 def sample_k(seed, ev, L, alpha, P, kdist=0):

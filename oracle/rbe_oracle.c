@@ -109,14 +109,53 @@ double orc_norm_S(const double L[3], double alpha) {
   return orc_axis_H(L[0], alpha) * orc_axis_H(L[1], alpha) * orc_axis_H(L[2], alpha) - 1.0;
 }
 
+/* k^2 of the mode m (k = 2 pi m / L), summed x, y, z. */
+static double mode_k2(const int mv[3], const double L[3]) {
+  double k2 = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    double kd = TWO_PI * (double)mv[d] / L[d];
+    k2 += kd * kd;
+  }
+  return k2;
+}
+
+/* Normalizer of the alternative proposal P(k) ~ exp(-k^2/4a)/k^2:
+   S2 = sum over the sampler's lattice (|m_d| <= M_d, m != 0) of
+   exp(-k^2/4a)/k^2, the Gaussian factor as the product of the axis factors.
+   The sum runs over up to 10^8 positive terms, so it is compensated (Kahan,
+   same order): plain summation would leave an error of order 1e-11 in
+   every weight. */
+double orc_norm_S2(const double L[3], double alpha) {
+  int M[3];
+  for (int d = 0; d < 3; ++d) M[d] = orc_axis_cutoff(L[d], alpha);
+  double s = 0.0, comp = 0.0;
+  for (int a = -M[0]; a <= M[0]; ++a)
+    for (int b = -M[1]; b <= M[1]; ++b)
+      for (int c = -M[2]; c <= M[2]; ++c) {
+        if (a == 0 && b == 0 && c == 0) continue;
+        const int mv[3] = {a, b, c};
+        double g = axis_weight(a, L[0], alpha) * axis_weight(b, L[1], alpha) * axis_weight(c, L[2], alpha);
+        double y = g / mode_k2(mv, L) - comp;
+        double t = s + y;
+        comp = (t - s) - y;
+        s = t;
+      }
+  return s;
+}
+
 /* Draw of mode l at evaluation `eval`: attempt a uses draws 3a, 3a+1, 3a+2 of
    the stream seeded by K_{e,l} = output l of the stream seeded by
    K_e = output eval of the stream seeded by seed ^ TAG_KSET. Each draw u is
    mapped to m = the first table entry whose cumulative probability exceeds u
-   (inverse CDF). The all-zero vector is rejected (next attempt). */
+   (inverse CDF). The all-zero vector is rejected (next attempt).
+   kdist = 1, P(k) ~ exp(-k^2/4a)/k^2: attempt a uses draws 4a..4a+2 that way
+   and draw 4a+3 = u; it is accepted when m != 0 and u k^2 < k_min^2,
+   k_min^2 = min_d (2 pi / L_d)^2 (so a Gaussian proposal m is kept with
+   probability k_min^2/k^2, which leaves exp(-k^2/4a)/k^2). Weights:
+   (S2/P) 4 pi / V. */
 int orc_sample_k(uint64_t seed, uint64_t eval, const double L[3], double alpha, int32_t P, int32_t kdist,
                  int32_t *m, double *w) {
-  if (P <= 0 || !(alpha > 0) || kdist != 0) return -1;
+  if (P <= 0 || !(alpha > 0) || (kdist != 0 && kdist != 1)) return -1;
   int M[3];
   double *cdf[3];
   double H[3];
@@ -134,32 +173,42 @@ int orc_sample_k(uint64_t seed, uint64_t eval, const double L[3], double alpha, 
   }
   const double S = H[0] * H[1] * H[2] - 1.0;
   const double V = L[0] * L[1] * L[2];
+  double kmin2 = 0.0, S2 = 0.0;
+  if (kdist == 1) {
+    for (int d = 0; d < 3; ++d) {
+      double k = TWO_PI * 1.0 / L[d];
+      if (d == 0 || k * k < kmin2) kmin2 = k * k;
+    }
+    S2 = orc_norm_S2(L, alpha);
+  }
+  const int per = kdist == 1 ? 4 : 3;
+  const long cap = kdist == 1 ? (1L << 20) : 4096;
   uint64_t ke = sm_out(seed ^ TAG_KSET, eval);
   int status = 0;
   for (int32_t l = 0; l < P; ++l) {
     uint64_t kl = sm_out(ke, (uint64_t)l);
     int mv[3] = {0, 0, 0};
     int ok = 0;
-    for (int a = 0; a < 4096 && !ok; ++a) {
+    for (long a = 0; a < cap && !ok; ++a) {
       for (int d = 0; d < 3; ++d) {
-        double u = u53(sm_out(kl, (uint64_t)(3 * a + d)));
+        double u = u53(sm_out(kl, (uint64_t)(per * a + d)));
         int len = 2 * M[d] + 1;
         int i = 0;
         while (i < len - 1 && !(u < cdf[d][i])) ++i; /* first entry with u < cdf */
         mv[d] = i - M[d];
       }
       ok = (mv[0] != 0 || mv[1] != 0 || mv[2] != 0);
+      if (ok && kdist == 1) {
+        double u = u53(sm_out(kl, (uint64_t)(per * a + 3)));
+        ok = u * mode_k2(mv, L) < kmin2;
+      }
     }
     if (!ok) { status = -2; break; }
-    double k2 = 0.0;
-    for (int d = 0; d < 3; ++d) {
-      double kd = TWO_PI * (double)mv[d] / L[d];
-      k2 += kd * kd;
-    }
     m[l] = mv[0];
     m[P + l] = mv[1];
     m[2 * P + l] = mv[2];
-    w[l] = (S / (double)P) * (4.0 * PI / (V * k2));
+    if (kdist == 1) w[l] = (S2 / (double)P) * (4.0 * PI / V);
+    else w[l] = (S / (double)P) * (4.0 * PI / (V * mode_k2(mv, L)));
   }
   for (int d = 0; d < 3; ++d) free(cdf[d]);
   return status;

@@ -40,6 +40,8 @@ double orc_axis_H(double L, double alpha);
 double orc_norm_S(const double L[3], double alpha);
 /* kdist 0: P(k) ~ exp(-k^2/4a) (Eq. 9).  Writes m[3*P] (x block, y block, z
    block) and w[P]. Returns 0 or a negative status. */
+/* normalizer of the exp(-k^2/4a)/k^2 proposal over the sampler's lattice */
+double orc_norm_S2(const double L[3], double alpha);
 int orc_sample_k(uint64_t seed, uint64_t eval, const double L[3], double alpha, int32_t P, int32_t kdist,
                  int32_t *m, double *w);
 

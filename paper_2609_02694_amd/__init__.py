@@ -18,6 +18,7 @@ _lib = None
 RBE_OK, RBE_EINVAL, RBE_EBOX, RBE_ENONNEUTRAL, RBE_ENOMEM, RBE_EDEVICE, RBE_ENONFINITE, RBE_ERANGE = (
     0, -1, -2, -3, -4, -5, -6, -7)
 FP64, FP32C = 0, 1
+KDIST_GAUSS, KDIST_GAUSS_OVER_K2 = 0, 1
 TERM_LJ, TERM_COUL_REAL, TERM_FOURIER, TERM_ALL = 1, 2, 4, 7
 MAX_P = 4096
 MAX_SHELL_BATCH = 32
@@ -105,14 +106,14 @@ def load():
 
 def make_params(L, alpha, r_coul, r_lj, P, r_core=0.0, p_shell=0, prec=FP64, terms=TERM_ALL, ncell=(0, 0, 0),
                 eps=1.0, sigma=1.0, kc=1.0, mass=1.0, dt=0.002, ghost_width=0.0, seed=0, nvt_kT=0.0,
-                nvt_tau=0.0) -> Params:
+                nvt_tau=0.0, kdist=KDIST_GAUSS) -> Params:
     p = Params()
     Lv = L if hasattr(L, "__len__") else (L, L, L)
     for d in range(3):
         p.L[d] = float(Lv[d])
         p.ncell[d] = int(ncell[d])
     p.alpha, p.r_coul, p.r_lj, p.r_core = alpha, r_coul, r_lj, r_core
-    p.p_shell, p.P, p.kdist, p.prec, p.terms = p_shell, P, 0, prec, terms
+    p.p_shell, p.P, p.kdist, p.prec, p.terms = p_shell, P, kdist, prec, terms
     p.lj_eps, p.lj_sigma, p.coulomb_k, p.mass, p.dt = eps, sigma, kc, mass, dt
     p.ghost_width, p.seed = ghost_width, seed
     p.nvt_kT, p.nvt_tau = nvt_kT, nvt_tau
@@ -123,7 +124,8 @@ def params_from_preset(pr: dict, prec=FP64, terms=TERM_ALL, ncell=(0, 0, 0), see
     return make_params(pr["L"], pr["alpha"], pr["r_coul"], pr["r_lj"], pr["P"], pr.get("r_core", 0.0),
                        pr.get("p_shell", 0), prec, terms, ncell, kc=pr.get("kc", 1.0), dt=pr.get("dt", 0.002),
                        ghost_width=pr.get("ghost", 0.0), seed=pr["seed"] if seed is None else seed,
-                       nvt_kT=pr.get("nvt_kT", 0.0), nvt_tau=pr.get("nvt_tau", 0.0))
+                       nvt_kT=pr.get("nvt_kT", 0.0), nvt_tau=pr.get("nvt_tau", 0.0),
+                       kdist=pr.get("kdist", KDIST_GAUSS))
 
 
 def _stream(stream):

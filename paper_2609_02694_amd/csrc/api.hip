@@ -191,7 +191,8 @@ static int validate_params(const rbe_params *p, std::string *why) {
   if (!(p->alpha > 0)) return bad(RBE_EINVAL, "alpha must be positive");
   if (!(p->r_coul > 0) || !(p->r_lj >= 0) || !(p->r_core >= 0)) return bad(RBE_EINVAL, "cutoffs must be positive");
   if (p->P < 1 || p->P > RBE_MAX_P) return bad(RBE_EINVAL, "P must be in [1, RBE_MAX_P]");
-  if (p->kdist != RBE_KDIST_GAUSS) return bad(RBE_EINVAL, "only the Gaussian mode distribution is provided");
+  if (p->kdist != RBE_KDIST_GAUSS && p->kdist != RBE_KDIST_GAUSS_OVER_K2)
+    return bad(RBE_EINVAL, "kdist must be RBE_KDIST_GAUSS or RBE_KDIST_GAUSS_OVER_K2");
   if (p->prec != RBE_FP64 && p->prec != RBE_FP32C) return bad(RBE_EINVAL, "prec must be RBE_FP64 or RBE_FP32C");
   if (p->terms < 0 || p->terms > RBE_TERM_ALL) return bad(RBE_EINVAL, "bad term mask");
   if (p->r_core > 0) {
@@ -365,7 +366,7 @@ extern "C" int rbe_create(rbe_ctx **out, const rbe_params *p, int64_t n_max, int
   // mode tables
   build_mode_table(p->L, p->alpha, &c->mt, nullptr);
   c->cdf_host.resize(c->mt.total);
-  build_mode_table(p->L, p->alpha, &c->mt, c->cdf_host.data());
+  build_mode_table(p->L, p->alpha, &c->mt, c->cdf_host.data(), p->kdist);
 
   // device scratch
   Buf &b = c->buf;
@@ -505,6 +506,8 @@ extern "C" int rbe_create_batch(rbe_ctx **out, int32_t n_sys, const rbe_params *
     return create_fail(RBE_EINVAL, "the ghost shell (ghost_width > 0) is not available in the batched form");
   if (params[0].nvt_tau > 0)
     return create_fail(RBE_EINVAL, "the NVT thermostat (nvt_tau > 0) is not available in the batched form");
+  if (params[0].kdist != RBE_KDIST_GAUSS)
+    return create_fail(RBE_EINVAL, "the batched form samples the Gaussian mode distribution only");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
     return create_fail(RBE_EDEVICE, "no such HIP device");
@@ -791,11 +794,12 @@ extern "C" int rbe_sample_k(const rbe_params *p, uint64_t eval, int32_t *m, doub
   if (p->P < 1 || p->P > RBE_MAX_P || !(p->alpha > 0)) return create_fail(RBE_EINVAL, "bad P or alpha");
   for (int d = 0; d < 3; ++d)
     if (!(p->L[d] > 0)) return create_fail(RBE_EINVAL, "bad box");
-  if (p->kdist != RBE_KDIST_GAUSS) return create_fail(RBE_EINVAL, "only the Gaussian mode distribution is provided");
+  if (p->kdist != RBE_KDIST_GAUSS && p->kdist != RBE_KDIST_GAUSS_OVER_K2)
+    return create_fail(RBE_EINVAL, "kdist must be RBE_KDIST_GAUSS or RBE_KDIST_GAUSS_OVER_K2");
   ModeTable t{};
   build_mode_table(p->L, p->alpha, &t, nullptr);
   std::vector<double> cdf(t.total);
-  build_mode_table(p->L, p->alpha, &t, cdf.data());
+  build_mode_table(p->L, p->alpha, &t, cdf.data(), p->kdist);
   if (!on_device) {
     if (sample_modes_host(t, cdf.data(), p->seed, eval, p->P, m, w) != 0)
       return create_fail(RBE_EINVAL, "mode sampler rejected every attempt");

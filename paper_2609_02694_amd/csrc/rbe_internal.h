@@ -189,11 +189,16 @@ struct ModeTable {
   double V;        // box volume
   double L[3];
   int total;       // total cdf entries
+  int kdist;       // rbe_kdist of the sample
+  double kmin2;    // min_d (2 pi / L_d)^2: the smallest nonzero k^2 (RBE_KDIST_GAUSS_OVER_K2)
+  double S2;       // sum_{k != 0} exp(-k^2/(4 alpha)) / k^2 over the table (RBE_KDIST_GAUSS_OVER_K2)
 };
 
 int axis_cutoff(double L, double alpha);
-// Builds the per-axis cumulative tables (host). cdf must hold table.total entries.
-void build_mode_table(const double L[3], double alpha, ModeTable *t, double *cdf);
+// Builds the per-axis cumulative tables (host). cdf must hold table.total
+// entries; with cdf given and kdist = RBE_KDIST_GAUSS_OVER_K2 also the
+// normalizer S2 (a sum over the whole table's lattice).
+void build_mode_table(const double L[3], double alpha, ModeTable *t, double *cdf, int kdist = 0);
 // Host sampler: draws P modes for (seed, eval).
 int sample_modes_host(const ModeTable &t, const double *cdf, uint64_t seed, uint64_t eval, int P, int32_t *m,
                       double *w);

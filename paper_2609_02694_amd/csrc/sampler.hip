@@ -1,6 +1,7 @@
 // Importance sampling of Fourier modes for the RBE estimator (Sec. 2.1,
 // Eq. 9): P i.i.d. modes k = 2 pi m / L, m != 0, with probability
-// proportional to exp(-k^2/(4 alpha)).
+// proportional to exp(-k^2/(4 alpha)) (or, on request, to
+// exp(-k^2/(4 alpha))/k^2, drawn by rejection from the former).
 //
 // The Gaussian factorizes over the axes, so each component is drawn from its
 // own one-dimensional discrete Gaussian exp(-(pi m / L_d)^2 / alpha) by
@@ -20,7 +21,7 @@ namespace rbe {
 
 int axis_cutoff(double L, double alpha) { return (int)std::ceil(L * std::sqrt(40.0 * alpha) / kPi); }
 
-void build_mode_table(const double L[3], double alpha, ModeTable *t, double *cdf) {
+void build_mode_table(const double L[3], double alpha, ModeTable *t, double *cdf, int kdist) {
   int off = 0;
   double H[3];
   for (int d = 0; d < 3; ++d) {
@@ -43,6 +44,40 @@ void build_mode_table(const double L[3], double alpha, ModeTable *t, double *cdf
   t->total = off;
   t->S = H[0] * H[1] * H[2] - 1.0;
   t->V = L[0] * L[1] * L[2];
+  t->kdist = kdist;
+  t->kmin2 = 0.0;
+  t->S2 = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    const double k = kTwoPi * 1.0 / L[d];
+    if (d == 0 || k * k < t->kmin2) t->kmin2 = k * k;
+  }
+  if (kdist == RBE_KDIST_GAUSS_OVER_K2 && cdf) {
+    // S2 = sum over the table's lattice without m = 0 of
+    // exp(-k^2/(4 alpha))/k^2; the terms of m and -m (per axis) are equal,
+    // so the octant m >= 0 is summed with multiplicity 2^(nonzero
+    // components), Kahan-compensated
+    std::vector<double> g[3];
+    for (int d = 0; d < 3; ++d) {
+      g[d].resize(t->M[d] + 1);
+      for (int i = 0; i <= t->M[d]; ++i) {
+        const double a = kPi * (double)i / L[d];
+        g[d][i] = std::exp(-(a * a) / alpha);
+      }
+    }
+    double sum = 0.0, comp = 0.0;
+    for (int a = 0; a <= t->M[0]; ++a)
+      for (int b = 0; b <= t->M[1]; ++b)
+        for (int c = 0; c <= t->M[2]; ++c) {
+          if (a == 0 && b == 0 && c == 0) continue;
+          const double mult = (double)((a ? 2 : 1) * (b ? 2 : 1) * (c ? 2 : 1));
+          const double v = mult * (g[0][a] * g[1][b] * g[2][c]) / mode_k2(*t, a, b, c);
+          const double y = v - comp;
+          const double s = sum + y;
+          comp = (s - sum) - y;
+          sum = s;
+        }
+    t->S2 = sum;
+  }
 }
 
 int sample_modes_host(const ModeTable &t, const double *cdf, uint64_t seed, uint64_t eval, int P, int32_t *m,

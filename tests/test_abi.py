@@ -45,7 +45,7 @@ def _create(p, n=100):
     ("r_coul", 16.0, rbe.RBE_EBOX),
     ("r_lj", 15.5, rbe.RBE_EBOX),
     ("prec", 7, rbe.RBE_EINVAL),
-    ("kdist", 1, rbe.RBE_EINVAL),
+    ("kdist", 2, rbe.RBE_EINVAL),
     ("mass", 0.0, rbe.RBE_EINVAL),
     ("ghost_width", 1e-3, rbe.RBE_EINVAL),
     ("nvt_tau", -0.1, rbe.RBE_EINVAL),
@@ -75,6 +75,24 @@ def test_create_batch_rejects_thermostat():
     p = [rbe.make_params(12.6, 0.3, 6.0, 2.5, 100, seed=r, nvt_tau=0.1, nvt_kT=1.0) for r in range(2)]
     rc, msg = _create_batch(p, [0, 10, 20])
     assert rc == rbe.RBE_EINVAL and "NVT" in msg
+
+
+def test_host_sampler_over_k2_matches_oracle():
+    """rbe_sample_k's host path (no device needed) for the
+    exp(-k^2/4a)/k^2 proposal: the oracle's draws bit for bit."""
+    import numpy as np
+    import oracle
+    p = rbe.make_params((9.0, 11.0, 13.0), 0.5, 2.0, 1.0, 64, seed=77, kdist=rbe.KDIST_GAUSS_OVER_K2)
+    mh, wh = rbe.sample_k(p, 12)
+    mo, wo = oracle.sample_k(77, 12, (9.0, 11.0, 13.0), 0.5, 64, kdist=1)
+    assert np.array_equal(mh, mo)
+    assert np.allclose(wh, wo, rtol=1e-13, atol=0.0)
+
+
+def test_create_batch_rejects_over_k2_proposal():
+    p = [rbe.make_params(12.6, 0.3, 6.0, 2.5, 100, seed=r, kdist=rbe.KDIST_GAUSS_OVER_K2) for r in range(2)]
+    rc, msg = _create_batch(p, [0, 10, 20])
+    assert rc == rbe.RBE_EINVAL and "Gaussian" in msg
 
 
 def test_create_rejects_bad_capacity():

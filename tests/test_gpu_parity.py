@@ -41,6 +41,34 @@ def test_sample_k_device_equals_host_and_oracle(L, alpha, P):
         assert np.array_equal(mh, mo) and np.array_equal(wh, wo)
 
 
+@pytest.mark.parametrize("L,alpha,P", [(30.0, 0.3, 100), (107.72, 0.35, 50), (12.6, 0.3, 7)])
+def test_sample_k_over_k2_device_equals_host_and_oracle(L, alpha, P):
+    """exp(-k^2/4a)/k^2 proposal: the same draws on the device, on the host
+    and in the oracle (modes bit for bit; weights carry S2, summed in another
+    order by the oracle)."""
+    p = rbe.make_params(L, alpha, 2.0, 1.0, P, seed=4321, kdist=rbe.KDIST_GAUSS_OVER_K2)
+    for ev in (0, 5):
+        mh, wh = rbe.sample_k(p, ev)
+        md, wd = rbe.sample_k(p, ev, on_device=True)
+        assert np.array_equal(mh, md.cpu().numpy()) and np.array_equal(wh, wd.cpu().numpy())
+        mo, wo = oracle.sample_k(4321, ev, L, alpha, P, kdist=1)
+        assert np.array_equal(mh, mo)
+        assert np.allclose(wh, wo, rtol=1e-13, atol=0.0)
+
+
+def test_forces_fp64_over_k2_modes(plain3k):
+    """Forces with the library drawing exp(-k^2/4a)/k^2 modes itself match
+    the oracle fed the oracle's draw of the same proposal."""
+    p, s, _, _, _ = plain3k
+    pk = dict(p, kdist=rbe.KDIST_GAUSS_OVER_K2)
+    m, w = oracle.sample_k(p["seed"], 3, p["L"], p["alpha"], p["P"], kdist=1)
+    ref = oracle_forces(pk, s, m, w, ev=3)
+    F = gpu_forces(pk, s, m=None, w=None, ev=3)
+    e = rel_err(F, ref["F"])
+    print(f"plain3k FP64 over-k2 modes rel err {e:.3e}")
+    assert e < TOL64
+
+
 # ---------------------------------------------------------------------------
 # binning
 # ---------------------------------------------------------------------------

@@ -594,3 +594,63 @@ def test_nvt_conserved_quantity_error_scales_as_dt_squared():
     (d1, xi1), (d2, _) = h_dev(0.02), h_dev(0.01)
     assert abs(xi1) > 1e-2  # the thermostat is active over the run
     assert 2.5 < d1 / d2 < 6.0, (d1, d2)
+
+
+# --------------------------------------------------------------------------
+# Alternative proposal P(k) ~ exp(-k^2/4a)/k^2 (kdist = 1)
+# --------------------------------------------------------------------------
+def test_norm_S2_equals_its_integral_representation():
+    """1/k^2 = int_0^inf exp(-t k^2) dt turns S2 into a 1-D integral of products
+    of 1-D lattice sums over the same truncated lattice (an independent way
+    to the same number)."""
+    from scipy.integrate import quad
+    L, a = (5.0, 6.0, 7.5), 1.1
+    Ms = [oracle.axis_cutoff(Ld, a) for Ld in L]
+
+    def integrand(t):
+        prod = 1.0
+        for Ld, M in zip(L, Ms):
+            k = 2 * math.pi * np.arange(-M, M + 1) / Ld
+            prod *= np.exp(-(1.0 / (4 * a) + t) * k * k).sum()
+        return prod - 1.0
+    val, err = quad(integrand, 0.0, np.inf, epsabs=0.0, epsrel=1e-12, limit=400)
+    assert oracle.norm_S2(L, a) == pytest.approx(val, rel=1e-9)
+
+
+def test_over_k2_sample_frequencies():
+    """Draw frequencies of the most likely modes match
+    exp(-k^2/4a)/(k^2 S2) within 4 standard errors."""
+    L, a, P = 6.0, 0.8, 4000
+    S2 = oracle.norm_S2(L, a)
+    counts = {}
+    ndraw = 0
+    for e in range(10):
+        m, w = oracle.sample_k(5, e, L, a, P, kdist=1)
+        assert np.allclose(w, S2 / P * 4 * math.pi / L ** 3, rtol=1e-15)
+        for c in map(tuple, m.T):
+            counts[c] = counts.get(c, 0) + 1
+        ndraw += P
+    for mv in [(1, 0, 0), (0, -1, 0), (0, 0, 1), (1, 1, 0), (-1, 0, 1), (1, 1, 1)]:
+        k2 = sum((2 * math.pi * c / L) ** 2 for c in mv)
+        p = math.exp(-k2 / (4 * a)) / k2 / S2
+        se = math.sqrt(p * (1 - p) / ndraw)
+        assert abs(counts.get(mv, 0) / ndraw - p) < 4 * se, mv
+
+
+def test_over_k2_estimator_unbiased():
+    """The mean of the Fourier estimate with the exp(-k^2/4a)/k^2 proposal and
+    its weights (S2/P) 4 pi / V converges to the exact Fourier force."""
+    x, y, z, q = random_ions(8, 5.0, 17)
+    L, a, P = 5.0, 1.0, 8
+    M = oracle.axis_cutoff(L, a) + 1
+    mf, wf = oracle.full_lattice(L, a, [M, M, M])
+    Fex, _, _ = oracle.fourier_force(x, y, z, q, L, mf, wf)
+    acc = np.zeros_like(Fex)
+    errs = {}
+    for e in range(1, 8193):
+        m, w = oracle.sample_k(98, e, L, a, P, kdist=1)
+        acc += oracle.fourier_force(x, y, z, q, L, m, w)[0]
+        if e in (128, 8192):
+            errs[e] = np.linalg.norm(acc / e - Fex) / np.linalg.norm(Fex)
+    assert errs[8192] < 0.04
+    assert errs[8192] < errs[128] / 3.0
