@@ -460,6 +460,13 @@ def roofline(kernels, cnt, nq, p, prec, K, workload=None, grid=None):
     dom = every.get(name) or dict(kernel=name, bound="alu", achieved=None, peak=None, unit=None, frac=None)
     dom = dict(dom)
     dom["traffic"] = measured_traffic(workload, name, grid) if workload else None
+    # counted HBM bytes per launch over the live average duration, against the
+    # HBM peak (shown for every kind, whatever bounds it)
+    for k, r in [(name, dom)] + list(every.items()):
+        t = dom["traffic"] if k == name else (measured_traffic(workload, k, grid) if workload else None)
+        if t and kernels[k]["avg_us"] > 0:
+            r["hbm_gbps"] = t / (kernels[k]["avg_us"] * 1e-6) / 1e9
+            r["hbm_frac"] = r["hbm_gbps"] / PEAK_HBM_GBS
     return dom, every
 
 
@@ -481,9 +488,15 @@ def cpu_baseline(p, s):
                              components=False)["F"]
     v = oracle.kick(F, v, p["dt"] / 2)
     dt = time.perf_counter() - t0
+    cpu = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": p["n"] / dt, "unit": "particle-steps/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"one velocity-Verlet step (one force evaluation) of the full {p['n']}-particle system",
-            "seconds": round(dt, 2)}
+            "seconds": round(dt, 2), "cpu_model": cpu}
 
 
 if __name__ == "__main__":

@@ -138,3 +138,22 @@ def test_batch_tuner_cache(tmp_path):
     assert best == (2.0, 3) and not hit
     assert tune.tune_batch_cached(reps, None, None, 1, path, edges=(2.0, 3.0), xsplits=(1, 3), timer=fake) == (
         (2.0, 3), True)
+
+
+def test_roofline_reports_counted_hbm_rate(tmp_path, monkeypatch):
+    b = load_bench()
+    import hashlib
+    src = tmp_path / "k.hip"
+    src.write_text("kernel\n")
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    rec = {"w": {"files": ["k.hip"], "source_sha256": hashlib.sha256(b"kernel\n").hexdigest(), "grid": [4, 2, 2],
+                 "kinds": {"kick": {"read_bytes": 3.0e9, "write_bytes": 1.0e9}}}}
+    (prof / "traffic.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(b, "ROOT", str(tmp_path))
+    kernels = {"kick": dict(avg_us=1000.0, total_ms=5.0), "kick_drift": dict(avg_us=2.0, total_ms=2.0)}
+    dom, every = b.roofline(kernels, None, 0, dict(n=100, P=4), 0, 1, workload="w", grid=[4, 2, 2])
+    # 4 GB per launch over 1 ms: 4000 GB/s, half the HBM peak
+    assert dom["kernel"] == "kick" and dom["traffic"] == 4.0e9
+    assert dom["hbm_gbps"] == pytest.approx(4000.0) and dom["hbm_frac"] == pytest.approx(0.5)
+    assert "hbm_gbps" not in every["kick_drift"]  # not counted
