@@ -91,7 +91,14 @@ typedef struct {
                          > 0: rbe_step runs the NVT step below with thermostat mass
                          Q = N_f nvt_kT nvt_tau^2, N_f = 3N - 3                     */
   uint64_t seed;      /* stream seed of the mode sample and of the shell batches       */
+  int32_t rbl_shell;  /* rbe_shell: population of the shell S_i of Eq. 10              */
 } rbe_params;
+
+/* Shell population of the random batch list. RBE_SHELL_ALL: every particle j
+   with r_core < r <= r_coul (Eq. 10 as written). RBE_SHELL_CHARGED: the
+   charged ones only (a variant: neutral shell members carry no force when
+   r_lj <= r_core, which it requires, so the batch is spent on charges). */
+enum { RBE_SHELL_ALL = 0, RBE_SHELL_CHARGED = 1 };
 
 #define RBE_MAX_P 4096
 #define RBE_MAX_SHELL_BATCH 32

@@ -35,7 +35,8 @@ def build() -> str:
 class OrcSys(ctypes.Structure):
     _fields_ = [("L", ctypes.c_double * 3), ("alpha", ctypes.c_double), ("r_coul", ctypes.c_double),
                 ("r_lj", ctypes.c_double), ("r_core", ctypes.c_double), ("p_shell", ctypes.c_int32),
-                ("eps", ctypes.c_double), ("sigma", ctypes.c_double), ("kc", ctypes.c_double)]
+                ("eps", ctypes.c_double), ("sigma", ctypes.c_double), ("kc", ctypes.c_double),
+                ("shell_charged", ctypes.c_int32)]
 
 
 _D = ctypes.POINTER(ctypes.c_double)
@@ -101,19 +102,20 @@ def num_threads() -> int:
     return _load().orc_num_threads()
 
 
-def make_sys(L, alpha, r_coul, r_lj, r_core=0.0, p_shell=0, eps=1.0, sigma=1.0, kc=1.0) -> OrcSys:
+def make_sys(L, alpha, r_coul, r_lj, r_core=0.0, p_shell=0, eps=1.0, sigma=1.0, kc=1.0, shell_charged=0) -> OrcSys:
     s = OrcSys()
     Lv = np.broadcast_to(np.asarray(L, np.float64), (3,))
     for d in range(3):
         s.L[d] = float(Lv[d])
     s.alpha, s.r_coul, s.r_lj, s.r_core = alpha, r_coul, r_lj, r_core
     s.p_shell, s.eps, s.sigma, s.kc = p_shell, eps, sigma, kc
+    s.shell_charged = shell_charged
     return s
 
 
 def sys_from_preset(p: dict) -> OrcSys:
     return make_sys(p["L"], p["alpha"], p["r_coul"], p["r_lj"], p.get("r_core", 0.0), p.get("p_shell", 0),
-                    kc=p.get("kc", 1.0))
+                    kc=p.get("kc", 1.0), shell_charged=p.get("rbl_shell", 0))
 
 
 # --------------------------------------------------------------------------

@@ -310,6 +310,7 @@ double orc_fourier_virial(int32_t P, const int32_t *m, const double L[3], double
 typedef struct {
   double rc2, rlj2, rcore2, sa, kc, eps, sig2;
   int terms;
+  int shell_charged;
 } pair_consts;
 
 static pair_consts make_consts(const orc_sys *s, int32_t terms) {
@@ -322,6 +323,7 @@ static pair_consts make_consts(const orc_sys *s, int32_t terms) {
   c.eps = s->eps;
   c.sig2 = s->sigma * s->sigma;
   c.terms = terms;
+  c.shell_charged = s->shell_charged;
   return c;
 }
 
@@ -387,10 +389,11 @@ static void visit(const pair_consts *c, int active, double qi, double qj, uint32
     if (r2 <= c->rcore2) { /* core set C_i: exact (Eq. 10-11) */
       double g = pair_scalar(c, r2, qi, qj);
       f[0] += g * dx; f[1] += g * dy; f[2] += g * dz;
-    } else if (r2 <= c->rc2) { /* shell set S_i */
+    } else if (r2 <= c->rc2 && (!c->shell_charged || qj != 0.0)) { /* shell set S_i */
       shell_entry e = {key_j, j, dx, dy, dz, r2};
       shell_push(sb, e);
-    }
+    } /* else: a neutral j beyond the core of a charged-only shell, whose
+         force is zero (no charge, and r > r_core >= r_lj) */
   } else {
     double g = pair_scalar(c, r2, qi, qj);
     f[0] += g * dx; f[1] += g * dy; f[2] += g * dz;

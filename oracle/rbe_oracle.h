@@ -23,6 +23,8 @@ typedef struct {
   int32_t p_shell;  /* shell batch size p of Eq. 11 */
   double eps, sigma;/* LJ parameters of Eq. 2 (one species pair) */
   double kc;        /* Coulomb prefactor */
+  int32_t shell_charged; /* 1: the shell of Eq. 10 holds charged particles only
+                            (variant; needs r_lj <= r_core), 0: every particle */
 } orc_sys;
 
 /* term selection bits */

@@ -19,6 +19,7 @@ RBE_OK, RBE_EINVAL, RBE_EBOX, RBE_ENONNEUTRAL, RBE_ENOMEM, RBE_EDEVICE, RBE_ENON
     0, -1, -2, -3, -4, -5, -6, -7)
 FP64, FP32C = 0, 1
 KDIST_GAUSS, KDIST_GAUSS_OVER_K2 = 0, 1
+SHELL_ALL, SHELL_CHARGED = 0, 1
 TERM_LJ, TERM_COUL_REAL, TERM_FOURIER, TERM_ALL = 1, 2, 4, 7
 MAX_P = 4096
 MAX_SHELL_BATCH = 32
@@ -59,6 +60,7 @@ class Params(ctypes.Structure):
         ("nvt_kT", ctypes.c_double),
         ("nvt_tau", ctypes.c_double),
         ("seed", ctypes.c_uint64),
+        ("rbl_shell", ctypes.c_int32),
     ]
 
 
@@ -106,7 +108,7 @@ def load():
 
 def make_params(L, alpha, r_coul, r_lj, P, r_core=0.0, p_shell=0, prec=FP64, terms=TERM_ALL, ncell=(0, 0, 0),
                 eps=1.0, sigma=1.0, kc=1.0, mass=1.0, dt=0.002, ghost_width=0.0, seed=0, nvt_kT=0.0,
-                nvt_tau=0.0, kdist=KDIST_GAUSS) -> Params:
+                nvt_tau=0.0, kdist=KDIST_GAUSS, rbl_shell=SHELL_ALL) -> Params:
     p = Params()
     Lv = L if hasattr(L, "__len__") else (L, L, L)
     for d in range(3):
@@ -117,6 +119,7 @@ def make_params(L, alpha, r_coul, r_lj, P, r_core=0.0, p_shell=0, prec=FP64, ter
     p.lj_eps, p.lj_sigma, p.coulomb_k, p.mass, p.dt = eps, sigma, kc, mass, dt
     p.ghost_width, p.seed = ghost_width, seed
     p.nvt_kT, p.nvt_tau = nvt_kT, nvt_tau
+    p.rbl_shell = rbl_shell
     return p
 
 
@@ -125,7 +128,7 @@ def params_from_preset(pr: dict, prec=FP64, terms=TERM_ALL, ncell=(0, 0, 0), see
                        pr.get("p_shell", 0), prec, terms, ncell, kc=pr.get("kc", 1.0), dt=pr.get("dt", 0.002),
                        ghost_width=pr.get("ghost", 0.0), seed=pr["seed"] if seed is None else seed,
                        nvt_kT=pr.get("nvt_kT", 0.0), nvt_tau=pr.get("nvt_tau", 0.0),
-                       kdist=pr.get("kdist", KDIST_GAUSS))
+                       kdist=pr.get("kdist", KDIST_GAUSS), rbl_shell=pr.get("rbl_shell", SHELL_ALL))
 
 
 def _stream(stream):

@@ -195,6 +195,10 @@ static int validate_params(const rbe_params *p, std::string *why) {
     return bad(RBE_EINVAL, "kdist must be RBE_KDIST_GAUSS or RBE_KDIST_GAUSS_OVER_K2");
   if (p->prec != RBE_FP64 && p->prec != RBE_FP32C) return bad(RBE_EINVAL, "prec must be RBE_FP64 or RBE_FP32C");
   if (p->terms < 0 || p->terms > RBE_TERM_ALL) return bad(RBE_EINVAL, "bad term mask");
+  if (p->rbl_shell != RBE_SHELL_ALL && p->rbl_shell != RBE_SHELL_CHARGED)
+    return bad(RBE_EINVAL, "rbl_shell must be RBE_SHELL_ALL or RBE_SHELL_CHARGED");
+  if (p->rbl_shell == RBE_SHELL_CHARGED && !(p->r_core > 0 && p->r_lj <= p->r_core))
+    return bad(RBE_EINVAL, "a charged-only shell needs the random batch list and r_lj <= r_core");
   if (p->r_core > 0) {
     if (p->p_shell < 1 || p->p_shell > RBE_MAX_SHELL_BATCH) return bad(RBE_EINVAL, "p_shell must be in [1, 32]");
     if (p->r_core > p->r_coul) return bad(RBE_EINVAL, "r_core must not exceed r_coul");
@@ -280,6 +284,7 @@ static void make_pair_params(const rbe_params &p, const Grid &g, PairParams *out
   pp.do_coul = (p.terms & RBE_TERM_COUL_REAL) != 0;
   pp.do_lj = (p.terms & RBE_TERM_LJ) != 0 && p.r_lj > 0;
   pp.rbl = p.r_core > 0;
+  pp.shell_charged = pp.rbl && p.rbl_shell == RBE_SHELL_CHARGED;
   pp.p_shell = p.p_shell;
 }
 
@@ -706,7 +711,8 @@ static int eval_sorted(rbe_ctx *c, int64_t n, int64_t nq, const int32_t *m, cons
   if (terms & (RBE_TERM_LJ | RBE_TERM_COUL_REAL)) {
     PairParams pp = c->pp;
     pp.shell_key = shell_eval_key(c->p.seed, eval);
-    pp.shell_T0 = shell_first_threshold(pp, n);
+    // the mean shell holds particles of the shell's population: all, or the charged
+    pp.shell_T0 = shell_first_threshold(pp, pp.shell_charged ? nq : n);
     if (pp.rbl && !inv_ready) {
       TScope ts(c, RBE_TK_REORDER, st);
       launch_inverse_ids(n, c->srt.id, c->inv_id, c->err, st);

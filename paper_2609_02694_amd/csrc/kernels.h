@@ -84,6 +84,7 @@ struct PairParams {
   double kc, eps24, sig2;
   int do_coul, do_lj;
   int rbl;               // random batch list on
+  int shell_charged;     // shell of charged particles only (variant; r_lj <= r_core)
   int p_shell;
   uint64_t shell_key;    // stream key of the shell batches for this evaluation
   uint64_t shell_T0;     // first key threshold of the shell selection (<= 2^32)

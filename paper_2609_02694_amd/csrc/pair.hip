@@ -182,7 +182,9 @@ k_pair_plain(PairCtx c) {
 // Random batch list (Eq. 10-11) for the particles of the launch range: exact
 // core, counted and ranked shell, one walk of both species blocks out to
 // r_coul.
-template <bool F32, bool COUNT, bool GHOST>
+// QSHELL: the shell holds charged particles only (variant of Eq. 10; the
+// neutral j beyond the core then carry no force, since r_lj <= r_core).
+template <bool F32, bool COUNT, bool GHOST, bool QSHELL>
 __global__ void __launch_bounds__(64, 5) k_pair_rbl(PairCtx c) {
   __shared__ uint32_t kbuf[kCI * kShellCap];
   __shared__ uint32_t ksel[kCI * RBE_MAX_SHELL_BATCH];
@@ -211,7 +213,7 @@ __global__ void __launch_bounds__(64, 5) k_pair_rbl(PairCtx c) {
     // flat predicates (bitwise, so no branch per condition)
     const bool live = ok & in_group & ((r2 != 0.0) | (j != (int)I.i));
     const bool core = live & (r2 <= pp.rcore2);
-    const bool shell = live & (r2 > pp.rcore2) & (r2 <= pp.rc2);
+    const bool shell = live & (r2 > pp.rcore2) & (r2 <= pp.rc2) & (!QSHELL | (pj.w != 0.0));
     if (COUNT) n_tested += ok & in_group;
     if (core) {
       acc.template add<true, true>(pp, c.pf, r2, I.qi, pj.w, dx, dy, dz);
@@ -226,7 +228,8 @@ __global__ void __launch_bounds__(64, 5) k_pair_rbl(PairCtx c) {
   auto visit_collect = [&](bool ok, int, const double4 &pj, int idj, double shx, double shy, double shz) {
     const double dx = (I.xi - pj.x) - shx, dy = (I.yi - pj.y) - shy, dz = (I.zi - pj.z) - shz;
     const double r2 = sq_dist(dx, dy, dz);
-    if (ok & in_group & (r2 > pp.rcore2) & (r2 <= pp.rc2)) collect(shell_rank(sk, idj));
+    if (ok & in_group & (r2 > pp.rcore2) & (r2 <= pp.rc2) & (!QSHELL | (pj.w != 0.0)))
+      collect(shell_rank(sk, idj));
   };
   const int64_t rowkey = (int64_t)I.cz * g.ny + I.cy;
   auto walk_all = [&](bool active, auto &&fn) {
@@ -357,10 +360,12 @@ template <bool F32, bool COUNT, bool GHOST>
 static void launch_part(PairCtx c, int64_t nq, int part, hipStream_t st) {
   const PairParams pp = c.pp;
   if (part == PAIR_PART_CHARGED) {
-    if (pp.rbl) launch_clusters(k_pair_rbl<F32, COUNT, GHOST>, c, 0, nq, st);
+    if (pp.rbl && pp.shell_charged) launch_clusters(k_pair_rbl<F32, COUNT, GHOST, true>, c, 0, nq, st);
+    else if (pp.rbl) launch_clusters(k_pair_rbl<F32, COUNT, GHOST, false>, c, 0, nq, st);
     else launch_threads(k_pair_plain<F32, COUNT, 1, GHOST>, c, 0, nq, st);
   } else if (part == PAIR_PART_NEUTRAL) {
-    if (pp.rbl && pp.rlj2 > pp.rcore2 && pp.do_lj) launch_clusters(k_pair_rbl<F32, COUNT, GHOST>, c, nq, c.n, st);
+    if (pp.rbl && pp.rlj2 > pp.rcore2 && pp.do_lj)
+      launch_clusters(k_pair_rbl<F32, COUNT, GHOST, false>, c, nq, c.n, st);
     else launch_threads(k_pair_plain<F32, COUNT, 0, GHOST>, c, nq, c.n, st);
   }
 }

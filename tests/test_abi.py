@@ -95,6 +95,16 @@ def test_create_batch_rejects_over_k2_proposal():
     assert rc == rbe.RBE_EINVAL and "Gaussian" in msg
 
 
+def test_create_rejects_bad_shell_population():
+    p = rbe.make_params(30.0, 0.35, 6.0, 2.5, 100, rbl_shell=rbe.SHELL_CHARGED)  # no random batch list
+    assert _create(p)[0] == rbe.RBE_EINVAL
+    p = rbe.make_params(30.0, 0.35, 6.0, 4.0, 100, r_core=3.0, p_shell=20, rbl_shell=rbe.SHELL_CHARGED)
+    rc, msg = _create(p)
+    assert rc == rbe.RBE_EINVAL and "r_lj" in msg  # LJ would reach the shell
+    p = rbe.make_params(30.0, 0.35, 6.0, 2.5, 100, r_core=3.0, p_shell=20, rbl_shell=2)
+    assert _create(p)[0] == rbe.RBE_EINVAL
+
+
 def test_create_rejects_bad_capacity():
     p = rbe.make_params(30.0, 0.3, 8.0, 2.5, 100)
     assert _create(p, n=0)[0] == rbe.RBE_EINVAL

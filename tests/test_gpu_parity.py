@@ -156,6 +156,23 @@ def test_forces_fp64_rbl_electrolyte_20k():
         assert np.abs(F.sum(axis=0)).max() < 1e-8 * np.abs(F).sum() / len(F)  # Eq. 12 + zero net Fourier force
 
 
+@pytest.mark.parametrize("prec,tol", [(rbe.FP64, TOL64), (rbe.FP32C, TOL32)])
+@pytest.mark.parametrize("ghost", [0.0, 6.0])
+def test_forces_rbl_charged_only_shell_20k(prec, tol, ghost):
+    """Variant shell of charged particles only (r_lj <= r_core): the batches
+    and the #S_i scaling follow the oracle's charged-only shell."""
+    p, s = system("electrolyte1m", n=20000, rbl_shell=rbe.SHELL_CHARGED, ghost=ghost)
+    m, w = oracle.sample_k(p["seed"], 2, p["L"], p["alpha"], p["P"])
+    ref = oracle_forces(p, s, m, w, ev=2, cells=False)
+    F = gpu_forces(p, s, prec=prec, m=m, w=w, ev=2)
+    e = rel_err(F, ref["F"])
+    print(f"electrolyte20k charged-only shell prec={prec} ghost={ghost} rel err {e:.3e}")
+    assert e < tol
+    # the literal shell gives a different estimate on the same draw
+    p0 = dict(p, rbl_shell=rbe.SHELL_ALL)
+    assert rel_err(gpu_forces(p0, s, prec=prec, m=m, w=w, ev=2), F) > 1e-6
+
+
 def test_forces_fp64_rbl_small_box_wrapping_stencil():
     """Fewer than 2s+1 cells per axis: stencil rows revisit cells with other images."""
     p, s = system("electrolyte1m", n=1500)  # L = 12.3, r_coul = 6

@@ -654,3 +654,41 @@ def test_over_k2_estimator_unbiased():
             errs[e] = np.linalg.norm(acc / e - Fex) / np.linalg.norm(Fex)
     assert errs[8192] < 0.04
     assert errs[8192] < errs[128] / 3.0
+
+
+# --------------------------------------------------------------------------
+# Variant: shell of charged particles only (r_lj <= r_core)
+# --------------------------------------------------------------------------
+def test_charged_shell_counts_and_full_cutoff_limit():
+    """The charged-only shell holds exactly the charged j in (r_core, r_coul];
+    with a batch covering it the estimate is the full-cutoff force (the
+    neutral j it leaves out carry no force beyond the core)."""
+    x, y, z, q, ids = _lj_ions(1500, 12.0, 27, frac=0.25)
+    full = oracle.make_sys(12.0, 0.35, 6.0, 2.5)
+    chg = oracle.make_sys(12.0, 0.35, 6.0, 2.5, r_core=3.0, p_shell=100000, shell_charged=1)
+    Fr, nsh = oracle.real_force(x, y, z, q, ids, chg, seed=5, ev=1, return_nshell=True)
+    Ff = oracle.real_force(x, y, z, q, ids, full)
+    assert np.abs(Ff - Fr).max() < 1e-12 * np.abs(Ff).max()
+    for i in np.flatnonzero(q != 0)[:5]:
+        d = np.stack([x - x[i], y - y[i], z - z[i]], axis=1)
+        d -= 12.0 * np.rint(d / 12.0)
+        r2 = (d ** 2).sum(axis=1)
+        r2[i] = -1
+        assert nsh[i] == np.count_nonzero((r2 > 9.0) & (r2 <= 36.0) & (q != 0))
+    assert np.all(nsh[q == 0] == -1)
+
+
+def test_charged_shell_unbiased_over_seeds():
+    x, y, z, q, ids = _lj_ions(800, 11.0, 28, frac=0.5)
+    full = oracle.make_sys(11.0, 0.35, 5.4, 2.5)
+    chg = oracle.make_sys(11.0, 0.35, 5.4, 2.5, r_core=2.7, p_shell=10, shell_charged=1)
+    idx = np.flatnonzero(q != 0)[:40]
+    Ff = oracle.real_force(x, y, z, q, ids, full, idx=idx)
+    acc = np.zeros_like(Ff)
+    errs = {}
+    for e in range(1, 1025):
+        acc += oracle.real_force(x, y, z, q, ids, chg, seed=78, ev=e, idx=idx)
+        if e in (64, 1024):
+            errs[e] = np.linalg.norm(acc / e - Ff) / np.linalg.norm(Ff)
+    assert errs[1024] < errs[64] / 2.5
+    assert errs[1024] < 0.02
