@@ -60,8 +60,8 @@ __device__ inline void walk(const PairCtx &c, int blk, int xa, int xb, int cy, i
                             Fn &&fn) {
   auto no_tick = []() {};
   if (GHOST)
-    cluster_walk_ghost<WITH_ID>(c.pp.g, c.cell_start, c.xq, c.ids, c.gcell_start, c.gxq, c.gid, blk, xa, xb, cy, cz,
-                                s, b, fn, no_tick);
+    cluster_walk_ghost<WITH_ID>(c.pp.g, c.cell_start, c.xq, c.ids, c.gcell_start, c.gxq, c.gid, (int)c.n, blk, xa, xb,
+                                cy, cz, s, b, fn, no_tick);
   else
     cluster_walk<WITH_ID>(c.pp.g, c.cell_start, c.xq, c.ids, (int64_t)blk * c.pp.g.ncell, xa, xb, cy, cz, s, b, fn,
                           no_tick);
@@ -211,7 +211,9 @@ __global__ void __launch_bounds__(64, 5) k_pair_rbl(PairCtx c) {
     const double dx = (I.xi - pj.x) - shx, dy = (I.yi - pj.y) - shy, dz = (I.zi - pj.z) - shz;
     const double r2 = sq_dist(dx, dy, dz);
     // flat predicates (bitwise, so no branch per condition)
-    const bool live = ok & in_group & ((r2 != 0.0) | (j != (int)I.i));
+    // j indexes natives, or ghosts offset by n: only i itself has j == i (its
+    // periodic images lie at least L >= 2 r_coul away)
+    const bool live = ok & in_group & (j != (int)I.i);
     const bool core = live & (r2 <= pp.rcore2);
     const bool shell = live & (r2 > pp.rcore2) & (r2 <= pp.rc2) & (!QSHELL | (pj.w != 0.0));
     if (COUNT) n_tested += ok & in_group;

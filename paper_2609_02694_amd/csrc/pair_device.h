@@ -430,14 +430,15 @@ __device__ inline double4 load_record(__amdgpu_buffer_rsrc_t r, int k) {
 }
 
 // fn(ok, j, p_j, id_j, shx, shy, shz) for the records j0..j1-1 taken by this
-// lane (j = j0 + b, j0 + b + kCJ, ...; ok = false on trips where this lane's
-// j is past j1), one record prefetched ahead, then tick() once per trip with
+// lane (j = jofs + j0 + b, jofs + j0 + b + kCJ, ...: jofs separates the index
+// ranges of different arrays, natives 0 and ghosts n; ok = false on trips
+// where this lane's record is past j1), one record prefetched ahead, then tick() once per trip with
 // the whole wave. The trip count depends only on j0, j1, so the loop is the
 // same for the wave; the segment is read through bounded buffer loads, so the
 // lookahead needs no clamping.
 template <bool WITH_ID, class Fn, class Tick>
 __device__ inline void scan_cluster(const double4 *__restrict__ xq, const int32_t *__restrict__ ids, int j0, int j1,
-                                    int b, double shx, double shy, double shz, Fn &&fn, Tick &&tick) {
+                                    int b, double shx, double shy, double shz, Fn &&fn, Tick &&tick, int jofs = 0) {
   j0 = __builtin_amdgcn_readfirstlane(j0);  // uniform by construction; tell the compiler
   j1 = __builtin_amdgcn_readfirstlane(j1);
   if (j0 >= j1) return;
@@ -452,12 +453,12 @@ __device__ inline void scan_cluster(const double4 *__restrict__ xq, const int32_
   for (int base = 0;; base += 2 * kCJ) {
     const double4 r1 = load_record(rx, k + kCJ);
     const int d1 = load_id(k + kCJ);
-    fn(k < cnt, j0 + k, r0, d0, shx, shy, shz);
+    fn(k < cnt, jofs + j0 + k, r0, d0, shx, shy, shz);
     tick();
     if (base + kCJ >= cnt) break;
     r0 = load_record(rx, k + 2 * kCJ);
     d0 = load_id(k + 2 * kCJ);
-    fn(k + kCJ < cnt, j0 + k + kCJ, r1, d1, shx, shy, shz);
+    fn(k + kCJ < cnt, jofs + j0 + k + kCJ, r1, d1, shx, shy, shz);
     tick();
     if (base + 2 * kCJ >= cnt) break;
     k += 2 * kCJ;
@@ -554,12 +555,14 @@ __device__ inline void cluster_walk(const Grid &g, const int32_t *__restrict__ c
 // Ghost-shell walk (no periodic images): the native part of each stencil row
 // clipped to the native grid, then the same row of the padded ghost grid
 // (row tables as in the periodic walk: segment a native, segment b ghost).
+// Ghost records are passed to fn with indices offset by nnat, so no ghost
+// index equals a native one.
 template <bool WITH_ID, class Fn, class Tick>
 __device__ inline void cluster_walk_ghost(const Grid &g, const int32_t *__restrict__ cell_start,
                                           const double4 *__restrict__ xq, const int32_t *__restrict__ ids,
                                           const int32_t *__restrict__ gcell_start, const double4 *__restrict__ gxq,
-                                          const int32_t *__restrict__ gid, int blk, int xa, int xb, int cy, int cz,
-                                          const Sten &s, int b, Fn &&fn, Tick &&tick) {
+                                          const int32_t *__restrict__ gid, int nnat, int blk, int xa, int xb,
+                                          int cy, int cz, const Sten &s, int b, Fn &&fn, Tick &&tick) {
   const int64_t base = (int64_t)blk * g.ncell;
   const int64_t pbase = (int64_t)blk * g.pncell;
   const int na = max(xa - s.x, 0), nb = min(xb + s.x, g.nx - 1);
@@ -583,7 +586,7 @@ __device__ inline void cluster_walk_ghost(const Grid &g, const int32_t *__restri
     for (int k = 0; k < nr; ++k) {
       const RowSegs u = row_segs_at(v, k);
       scan_cluster<WITH_ID>(xq, ids, u.j0a, u.j1a, b, 0.0, 0.0, 0.0, fn, tick);
-      scan_cluster<WITH_ID>(gxq, gid, u.j0b, u.j1b, b, 0.0, 0.0, 0.0, fn, tick);
+      scan_cluster<WITH_ID>(gxq, gid, u.j0b, u.j1b, b, 0.0, 0.0, 0.0, fn, tick, nnat);
     }
   }
 }
