@@ -112,8 +112,8 @@ template <bool GHOST, bool WITH_ID, class Fn>
 __device__ inline void stencil(const PairCtx &c, int blk, int cx, int cy, int cz, const Sten &s, const Reach &R,
                                Fn &&fn) {
   if (GHOST)
-    for_stencil_ghost<WITH_ID>(c.pp.g, c.cell_start, c.xq, c.ids, c.gcell_start, c.gxq, c.gid, blk, cx, cy, cz, s, R,
-                               fn);
+    for_stencil_ghost<WITH_ID>(c.pp.g, c.cell_start, c.xq, c.ids, c.gcell_start, c.gxq, c.gid, (int)c.n, blk, cx, cy,
+                               cz, s, R, fn);
   else
     for_stencil<WITH_ID>(c.pp.g, c.cell_start, c.xq, c.ids, blk, cx, cy, cz, s, R, fn);
 }
@@ -145,7 +145,7 @@ k_pair_plain(PairCtx c) {
     const double dx = (xi - pj.x) - shx, dy = (yi - pj.y) - shy, dz = (zi - pj.z) - shz;
     const double r2 = sq_dist(dx, dy, dz);
     if (COUNT) ++n_tested;
-    if (r2 == 0.0 && j == (int)i) return;
+    if (j == (int)i) return;  // ghosts are indexed from n on
     if (r2 <= pp.rq2) {
       acc.template add<true>(pp, c.pf, r2, qi, pj.w, dx, dy, dz);
       if (COUNT) {
@@ -159,7 +159,7 @@ k_pair_plain(PairCtx c) {
     const double dx = (xi - pj.x) - shx, dy = (yi - pj.y) - shy, dz = (zi - pj.z) - shz;
     const double r2 = sq_dist(dx, dy, dz);
     if (COUNT) ++n_tested;
-    if (r2 == 0.0 && j == (int)i) return;
+    if (j == (int)i) return;  // ghosts are indexed from n on
     if (r2 <= pp.rlj2) {
       acc.template add<false>(pp, c.pf, r2, qi, pj.w, dx, dy, dz);
       if (COUNT) n_lj += pp.do_lj;

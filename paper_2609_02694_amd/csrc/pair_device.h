@@ -217,8 +217,9 @@ __device__ inline double min_image(double a, double L) {
   return a - L * rint(a / L);
 }
 
-// Calls fn(j, p_j, id_j, shx, shy, shz) for the records j0..j1-1 of xq (and
-// ids when WITH_ID, else id_j = 0). Four fixed slots: slot k holds record
+// Calls fn(jofs + j, p_j, id_j, shx, shy, shz) for the records j0..j1-1 of xq
+// (and ids when WITH_ID, else id_j = 0); jofs separates the index ranges of
+// natives (0) and ghosts (n). Four fixed slots: slot k holds record
 // j + k and is reloaded with j + k + 4 right after use, so each load has
 // three candidates of work to complete behind it. The lookahead reads up to
 // kScanPad - 1 records past j1: every array scanned here is allocated with
@@ -226,7 +227,7 @@ __device__ inline double min_image(double a, double L) {
 // (their values are never used), and the addresses are plain increments.
 template <bool WITH_ID, class Fn>
 __device__ inline void scan_range(const double4 *__restrict__ xq, const int32_t *__restrict__ ids, int j0, int j1,
-                                  double shx, double shy, double shz, Fn &&fn) {
+                                  double shx, double shy, double shz, Fn &&fn, int jofs = 0) {
   if (j0 >= j1) return;
   const double4 *p = xq + j0;
   const int32_t *q = WITH_ID ? ids + j0 : ids;
@@ -240,16 +241,16 @@ __device__ inline void scan_range(const double4 *__restrict__ xq, const int32_t 
   }
 #pragma unroll 1
   for (int j = j0; j < j1; j += 4) {
-    fn(j, r0, d0, shx, shy, shz);
+    fn(jofs + j, r0, d0, shx, shy, shz);
     r0 = p[4];
     if (WITH_ID) d0 = q[4];
-    if (j + 1 < j1) fn(j + 1, r1, d1, shx, shy, shz);
+    if (j + 1 < j1) fn(jofs + j + 1, r1, d1, shx, shy, shz);
     r1 = p[5];
     if (WITH_ID) d1 = q[5];
-    if (j + 2 < j1) fn(j + 2, r2, d2, shx, shy, shz);
+    if (j + 2 < j1) fn(jofs + j + 2, r2, d2, shx, shy, shz);
     r2 = p[6];
     if (WITH_ID) d2 = q[6];
-    if (j + 3 < j1) fn(j + 3, r3, d3, shx, shy, shz);
+    if (j + 3 < j1) fn(jofs + j + 3, r3, d3, shx, shy, shz);
     r3 = p[7];
     if (WITH_ID) d3 = q[7];
     p += 4;
@@ -331,13 +332,13 @@ __device__ inline void for_stencil(const Grid &g, const int32_t *__restrict__ ce
 // Ghost-shell traversal (no periodic images): the natives of the stencil
 // rows that lie inside the native grid, then the ghosts of the same rows of
 // the padded grid, each row trimmed to the reach of R. (cx, cy, cz) is a
-// native cell.
+// native cell. Ghosts reach fn with indices offset by nnat.
 template <bool WITH_ID, class Fn>
 __device__ inline void for_stencil_ghost(const Grid &g, const int32_t *__restrict__ cell_start,
                                          const double4 *__restrict__ xq, const int32_t *__restrict__ ids,
                                          const int32_t *__restrict__ gcell_start, const double4 *__restrict__ gxq,
-                                         const int32_t *__restrict__ gid, int blk, int cx, int cy, int cz,
-                                         const Sten &s, const Reach &R, Fn &&fn) {
+                                         const int32_t *__restrict__ gid, int nnat, int blk, int cx, int cy,
+                                         int cz, const Sten &s, const Reach &R, Fn &&fn) {
   const int base = blk * g.ncell;
   const int pbase = blk * g.pncell;
   const double hy = g.L[1] / g.ny, hz = g.L[2] / g.nz;
@@ -357,7 +358,7 @@ __device__ inline void for_stencil_ghost(const Grid &g, const int32_t *__restric
         }
       }
       const int prow = pbase + ((z + g.goff[2]) * g.pny + (y + g.goff[1])) * g.pnx + g.goff[0];
-      scan_range<WITH_ID>(gxq, gid, gcell_start[prow + xa], gcell_start[prow + xb + 1], 0.0, 0.0, 0.0, fn);
+      scan_range<WITH_ID>(gxq, gid, gcell_start[prow + xa], gcell_start[prow + xb + 1], 0.0, 0.0, 0.0, fn, nnat);
     }
   }
 }
