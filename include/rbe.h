@@ -23,8 +23,12 @@
  *
  * Conventions shared by every call
  *  - Pointers are DEVICE pointers unless marked (host).
- *  - `stream` is a hipStream_t passed as void*. Calls are asynchronous on it;
- *    only rbe_sync_check synchronizes.
+ *  - `stream` is a hipStream_t passed as void*. Calls are asynchronous on it,
+ *    with one exception: rbe_forces, rbe_energy and rbe_step wait once, at
+ *    entry, for a few bytes of charge statistics (the neutrality check of
+ *    Eq. 1 and the charged count that sizes the Fourier launches).
+ *    rbe_sync_check synchronizes and reports device-side errors;
+ *    rbe_get_timing and rbe_get_counters synchronize to read their results.
  *  - Particle arrays are structure-of-arrays, FP64 for coordinates,
  *    velocities, forces and charges, int32 for ids.
  *  - Every call returns an rbe_status (0 = success). Host-checkable argument
