@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--tune-cache", default=os.environ.get("RBE_TUNE_CACHE", os.path.join(ROOT, ".tune_cache.json")))
     ap.add_argument("--prec", default=None, choices=["fp64", "fp32c"])
     ap.add_argument("--n", type=int, default=None, help="override the particle count (same density)")
+    ap.add_argument("--rbl-shell", default=None, choices=["all", "charged"],
+                    help="shell population of the random batch list (default: the preset's, i.e. all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel HIP event timing")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -110,6 +112,8 @@ def main():
     if a.workload == "replica256":
         return bench_batch(a)
     p = gen.preset(a.workload, n=a.n)
+    if a.rbl_shell:
+        p["rbl_shell"] = 1 if a.rbl_shell == "charged" else 0
     prec_name = a.prec or ("fp64" if a.workload in ("plain3k", "electrolyte1m", "ljelectrolyte") else "fp32c")
     prec = rbe.FP64 if prec_name == "fp64" else rbe.FP32C
     h = a.edge or DEFAULT_NCELL_H.get(a.workload, 3.0)
@@ -207,6 +211,7 @@ def main():
                    "r_coul": p["r_coul"], "r_lj": p["r_lj"], "r_core": p["r_core"], "p_shell": p["p_shell"],
                    "P": p["P"], "dt": p["dt"], "form": prec_name, "ncell": [nx, nc, nc], "tuned": tuned,
                    "ensemble": "NVT" if p.get("nvt_tau", 0.0) > 0 else "NVE",
+                   "rbl_shell": "charged" if p.get("rbl_shell", 0) else "all",
                    "parallelism": "single GPU"},
         "event_ms_per_step": ev_ms / K,
         "kernels": kernels,

@@ -239,7 +239,9 @@ __global__ void __launch_bounds__(64, 5) k_pair_rbl(PairCtx c) {
       in_group = in;
       const int cy = __shfl(I.cy, leader, 64), cz = __shfl(I.cz, leader, 64);
       walk<GHOST, true>(c, 0, xa, xb, cy, cz, pp.s_coul, I.b, fn);
-      walk<GHOST, true>(c, 1, xa, xb, cy, cz, pp.s_coul, I.b, fn);
+      // with a charged-only shell the neutral block matters inside the core
+      // only (r_lj <= r_core): its walk covers r_core instead of r_coul
+      walk<GHOST, true>(c, 1, xa, xb, cy, cz, QSHELL ? pp.s_core : pp.s_coul, I.b, fn);
     });
   };
   walk_all(I.valid, visit);
