@@ -113,6 +113,10 @@ def main():
         return bench_batch(a)
     p = gen.preset(a.workload, n=a.n)
     if a.rbl_shell:
+        if a.rbl_shell == "charged" and not p.get("r_core", 0.0) > 0.0:
+            print(f"--rbl-shell charged needs a workload with the random batch list ({a.workload} has none)",
+                  file=sys.stderr)
+            sys.exit(2)
         p["rbl_shell"] = 1 if a.rbl_shell == "charged" else 0
     prec_name = a.prec or ("fp64" if a.workload in ("plain3k", "electrolyte1m", "ljelectrolyte") else "fp32c")
     prec = rbe.FP64 if prec_name == "fp64" else rbe.FP32C
