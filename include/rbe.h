@@ -118,7 +118,9 @@ typedef struct {
   int32_t *id; /* unique, 0..n-1 (the shell batches of Eq. 11 are keyed by id) */
   double *nh;  /* NVT (nvt_tau > 0) only: device [2] = {xi, eta}, the thermostat's
                   friction variable and its time integral, advanced by rbe_step;
-                  K + U + Q xi^2/2 + N_f kT eta is the conserved quantity */
+                  with forces that are the gradient of a potential U (fixed
+                  modes, no batch list), K + U + Q xi^2/2 + N_f kT eta is
+                  conserved up to the integrator's O(dt^2) error */
   int64_t n;
 } rbe_state;
 
