@@ -692,3 +692,14 @@ def test_charged_shell_unbiased_over_seeds():
             errs[e] = np.linalg.norm(acc / e - Ff) / np.linalg.norm(Ff)
     assert errs[1024] < errs[64] / 2.5
     assert errs[1024] < 0.02
+
+
+def test_splitmix64_matches_the_published_sequence():
+    """The oracle's stream output n = mix64(seed + (n + 1) gamma) reproduces
+    SplitMix64's reference outputs from state 0, so the draws of Eq. 9 and
+    the keys of Eq. 11 come from the published generator."""
+    with open(os.path.join(HERE, "golden", "splitmix64_seed0.txt")) as f:
+        ref = [int(line, 16) for line in f if line.strip() and not line.startswith("#")]
+    gamma = 0x9E3779B97F4A7C15
+    got = [oracle.mix64(((n + 1) * gamma) & (2 ** 64 - 1)) for n in range(len(ref))]
+    assert got == ref
