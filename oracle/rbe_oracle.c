@@ -60,7 +60,10 @@ uint64_t orc_mix64(uint64_t z) {
 static uint64_t sm_out(uint64_t s, uint64_t n) { return orc_mix64(s + (n + 1) * GAMMA); }
 static double u53(uint64_t h) { return (double)(h >> 11) * 0x1.0p-53; }
 
-/* lowbias32 (C. Wellons, hash-prospector): a bijection of 32-bit integers. */
+/* lowbias32 (C. Wellons, hash-prospector): a bijection of 32-bit integers.
+   Parity unpinned: no published output of it is at hand; the tests pin its
+   bijectivity and the unbiasedness of the batches it selects, and the GPU
+   must reproduce it bit for bit. */
 static uint32_t lowbias32(uint32_t x) {
   x ^= x >> 16;
   x *= 0x7feb352dU;
