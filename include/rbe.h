@@ -23,12 +23,15 @@
  *
  * Conventions shared by every call
  *  - Pointers are DEVICE pointers unless marked (host).
- *  - `stream` is a hipStream_t passed as void*. Calls are asynchronous on it,
- *    with one exception: rbe_forces, rbe_energy and rbe_step wait once, at
- *    entry, for a few bytes of charge statistics (the neutrality check of
- *    Eq. 1 and the charged count that sizes the Fourier launches).
- *    rbe_sync_check synchronizes and reports device-side errors;
- *    rbe_get_timing and rbe_get_counters synchronize to read their results.
+ *  - `stream` is a hipStream_t passed as void*. rbe_forces, rbe_energy and
+ *    rbe_step are asynchronous on it: they never wait for the device, so
+ *    they can be captured in a HIP graph (with timing and counting off).
+ *    Everything that depends on device data is decided on the device: the
+ *    charged count that sizes the near-field and Fourier work is read there,
+ *    and the neutrality of Eq. 1 and finite charges are checked there.
+ *    rbe_sync_check synchronizes and reports device-side errors, among them
+ *    RBE_ENONNEUTRAL and RBE_ENONFINITE; rbe_get_timing and rbe_get_counters
+ *    synchronize to read their results.
  *  - Particle arrays are structure-of-arrays, FP64 for coordinates,
  *    velocities, forces and charges, int32 for ids.
  *  - Every call returns an rbe_status (0 = success). Host-checkable argument
@@ -48,7 +51,8 @@ typedef enum {
   RBE_OK = 0,
   RBE_EINVAL = -1,      /* bad argument (sizes, cutoffs, null pointers)          */
   RBE_EBOX = -2,        /* a cutoff exceeds half the box (minimum image broken)  */
-  RBE_ENONNEUTRAL = -3, /* sum q != 0 (Eq. 1 requires charge neutrality)         */
+  RBE_ENONNEUTRAL = -3, /* sum q != 0 (Eq. 1 requires charge neutrality); checked
+                           on the device, reported by rbe_sync_check            */
   RBE_ENOMEM = -4,      /* device allocation failed in rbe_create                */
   RBE_EDEVICE = -5,     /* a HIP call failed                                     */
   RBE_ENONFINITE = -6,  /* device saw a non-finite position/velocity/force       */
@@ -243,7 +247,12 @@ int rbe_energy(rbe_ctx *ctx, const rbe_state *s, const int32_t *m, const double 
 int rbe_step(rbe_ctx *ctx, rbe_state *s, int32_t nsteps, uint64_t first_eval, void *stream);
 
 /* Synchronize `stream` and report device-side errors recorded since the last
-   check (non-finite values, bad ids). Clears the flag. */
+   check: non-neutral charges (RBE_ENONNEUTRAL; a batched context names the
+   first replica at fault), non-finite charges, velocities or forces
+   (RBE_ENONFINITE), bad ids and ghost-shell overflow (RBE_ERANGE), a mode
+   sampler that rejected every attempt (RBE_EINVAL). Clears the flag. The
+   only call that waits for the device, besides the timing and counter
+   readers. */
 int rbe_sync_check(rbe_ctx *ctx, void *stream);
 
 /* Diagnostic counters of the last rbe_forces/rbe_step force evaluation

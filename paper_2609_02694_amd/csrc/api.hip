@@ -87,7 +87,7 @@ struct rbe_ctx {
   // batched form (nrep > 1)
   struct Batch {
     int nrep = 0;
-    std::vector<RepDesc> reps;  // host copy (nq and chunk layout refreshed per call)
+    std::vector<RepDesc> reps;  // host copy (the nq and chunk fields live on the device only)
     std::vector<int64_t> off;   // [nrep + 1]
     int64_t ntot = 0, nkeys = 0;
     int ntiles = 0, blocks = 0;
@@ -101,12 +101,11 @@ struct rbe_ctx {
     double2 *part = nullptr;
     unsigned *bar = nullptr;
     uint64_t *eval = nullptr;
-    uint64_t eval_stage = 0;
-    int rho_items = 0;
+    int *rho_items = nullptr;  // device: structure-factor items of this call
+    int *bad_rep = nullptr;    // device: first replica that failed the charge checks (-1: none)
     BatchArgs node_args[2]{};  // arguments of the two graph nodes
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int graph_rho_items = -1;
   } bt;
   bool batched() const { return bt.nrep > 0; }
 
@@ -610,6 +609,8 @@ extern "C" int rbe_create_batch(rbe_ctx **out, int32_t n_sys, const rbe_params *
   B.part = b.alloc<double2>(chunks * P);
   B.bar = b.alloc<unsigned>(2);
   B.eval = b.alloc<uint64_t>(1);
+  B.rho_items = b.alloc<int>(1);
+  B.bad_rep = b.alloc<int>(1);
   if (!b.ok) {
     b.release();
     delete c;
@@ -652,48 +653,50 @@ extern "C" const char *rbe_last_error(const rbe_ctx *ctx) {
 }
 
 // ---------------------------------------------------------------------------
-// charge statistics (count of charged particles, neutrality)
+// charge checks (on the device: no call waits for them)
 // ---------------------------------------------------------------------------
-__global__ void k_qstats(int64_t n, const double *__restrict__ q, int32_t *nq, double *stats) {
-  int c = 0;
+// stats[0] += sum q, stats[1] += sum |q| (one atomic per wave, in any order:
+// the sums only feed the neutrality test below); a non-finite charge raises
+// kErrNonFinite.
+__global__ void __launch_bounds__(256) k_qstats(int64_t n, const double *__restrict__ q, double *stats, int *err) {
   double s = 0.0, a = 0.0;
+  bool bad = false;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const double v = q[i];
-    c += v != 0.0;
+    bad |= !isfinite(v);
     s += v;
     a += fabs(v);
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
-    c += __shfl_xor(c, o, 64);
     s += __shfl_xor(s, o, 64);
     a += __shfl_xor(a, o, 64);
   }
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(err, kErrNonFinite);
   if ((threadIdx.x & 63) == 0) {
-    atomicAdd(nq, c);
     atomicAdd(&stats[0], s);
     atomicAdd(&stats[1], a);
   }
 }
 
-// Counts the charged particles and checks neutrality (synchronizes `st`).
-static int charge_stats(rbe_ctx *c, int64_t n, const double *q, hipStream_t st, int64_t *nq_out) {
-  launch_fill_i32(c->nq_dev, 1, 0, st);
+// Eq. 1 asks for a neutral system: |sum q| above 1e-10 sum |q| (and above
+// 1e-12) raises kErrNonNeutral.
+__global__ void k_qverdict(const double *__restrict__ stats, int *err) {
+  const double s = stats[0], a = stats[1];
+  if (isfinite(s) && isfinite(a) && fabs(s) > 1e-10 * fmax(a, 1e-300) && fabs(s) > 1e-12)
+    atomicOr(err, kErrNonNeutral);
+}
+
+// Neutrality and finiteness of the charges, reported through the device flag
+// that rbe_sync_check reads (the counts that size the later launches are read
+// on the device too, so nothing here waits).
+static void launch_charge_check(rbe_ctx *c, int64_t n, const double *q, hipStream_t st) {
   launch_fill_f64(c->qstats, 2, 0.0, st);
   int64_t blocks = (n + 255) / 256;
   if (blocks > 1024) blocks = 1024;
   if (blocks < 1) blocks = 1;
-  k_qstats<<<(unsigned)blocks, 256, 0, st>>>(n, q, c->nq_dev, c->qstats);
-  int32_t nq = 0;
-  double qs[2] = {0, 0};
-  HIP_TRY(c, hipMemcpyAsync(&nq, c->nq_dev, sizeof nq, hipMemcpyDeviceToHost, st));
-  HIP_TRY(c, hipMemcpyAsync(qs, c->qstats, sizeof qs, hipMemcpyDeviceToHost, st));
-  HIP_TRY(c, hipStreamSynchronize(st));
-  if (!std::isfinite(qs[0]) || !std::isfinite(qs[1])) return c->fail(RBE_ENONFINITE, "non-finite charges");
-  if (std::fabs(qs[0]) > 1e-10 * std::fmax(qs[1], 1e-300) && std::fabs(qs[0]) > 1e-12)
-    return c->fail(RBE_ENONNEUTRAL, "total charge %.3e is not zero (sum |q| = %.3e)", qs[0], qs[1]);
-  *nq_out = nq;
-  return RBE_OK;
+  k_qstats<<<(unsigned)blocks, 256, 0, st>>>(n, q, c->qstats, c->err);
+  k_qverdict<<<1, 1, 0, st>>>(c->qstats, c->err);
 }
 
 // ---------------------------------------------------------------------------
@@ -703,16 +706,20 @@ static int charge_stats(rbe_ctx *c, int64_t n, const double *q, hipStream_t st, 
 // inv_ready: the id -> slot map was already written (by the step's reorder)
 // and the ids were validated earlier in the same call. mkd_pre: the modes m
 // as doubles, drawn ahead by rbe_step (then m and w are that draw).
-static int eval_sorted(rbe_ctx *c, int64_t n, int64_t nq, const int32_t *m, const double *w, uint64_t eval,
+static int eval_sorted(rbe_ctx *c, int64_t n, const int32_t *m, const double *w, uint64_t eval,
                        double *rho_out, double *fx, double *fy, double *fz, hipStream_t st, bool inv_ready = false,
                        const double *mkd_pre = nullptr) {
   const int P = c->p.P;
   const int terms = c->p.terms;
+  // charged particles come first in the cell order: their count is the
+  // start of the first neutral cell
+  const int32_t *nq = c->cell_start + c->g.ncell;
   if (terms & (RBE_TERM_LJ | RBE_TERM_COUL_REAL)) {
     PairParams pp = c->pp;
     pp.shell_key = shell_eval_key(c->p.seed, eval);
-    // the mean shell holds particles of the shell's population: all, or the charged
-    pp.shell_T0 = shell_first_threshold(pp, pp.shell_charged ? nq : n);
+    // the mean shell holds particles of the shell's population: all (the
+    // charged-only variant derives its threshold from the device count)
+    pp.shell_T0 = shell_first_threshold(pp, n);
     if (pp.rbl && !inv_ready) {
       TScope ts(c, RBE_TK_REORDER, st);
       launch_inverse_ids(n, c->srt.id, c->inv_id, c->err, st);
@@ -757,18 +764,17 @@ static int eval_sorted(rbe_ctx *c, int64_t n, int64_t nq, const int32_t *m, cons
       }
       launch_modes_to_double(P, m, fb.mkd, st);
     }
-    int nchunks;
     {
       TScope ts(c, RBE_TK_RHO_PARTIAL, st);
-      nchunks = launch_rho_partial(c->p.prec, nq, P, c->srt.sq, fb, st);
+      launch_rho_partial(c->p.prec, nq, n, P, c->srt.sq, fb, st);
     }
     {
       TScope ts(c, RBE_TK_RHO_FINAL, st);
-      launch_rho_final(nchunks, P, fb, w, c->p.coulomb_k, rho_out, st);
+      launch_rho_final(nq, P, fb, w, c->p.coulomb_k, rho_out, st);
     }
     {
       TScope ts(c, RBE_TK_GATHER, st);
-      launch_fourier_gather(c->p.prec, nq, P, c->srt.sq, fb, c->g, fx, fy, fz, st);
+      launch_fourier_gather(c->p.prec, nq, n, P, c->srt.sq, fb, c->g, fx, fy, fz, st);
     }
   }
   return RBE_OK;
@@ -840,38 +846,12 @@ extern "C" int rbe_sample_k(const rbe_params *p, uint64_t eval, int32_t *m, doub
 // ---------------------------------------------------------------------------
 // batched form
 // ---------------------------------------------------------------------------
-// Per-replica charge statistics, neutrality check and the structure-factor
-// chunk layout of this call; uploads the replica descriptors (synchronizes st).
-static int batch_prepare(rbe_ctx *c, const double *q, hipStream_t st) {
+// Per-replica charge statistics, the checks of Eq. 1 (device error flags) and
+// the structure-factor chunk layout of this call, all on the device.
+static void batch_prepare(rbe_ctx *c, const double *q, hipStream_t st) {
   auto &B = c->bt;
-  const int nrep = B.nrep;
-  std::vector<int32_t> nq(nrep);
-  std::vector<double> qs(2 * (size_t)nrep);
-  launch_qstats_rep(nrep, B.off_dev, q, B.nq, B.qs, st);
-  HIP_TRY(c, hipMemcpyAsync(nq.data(), B.nq, sizeof(int32_t) * nrep, hipMemcpyDeviceToHost, st));
-  HIP_TRY(c, hipMemcpyAsync(qs.data(), B.qs, sizeof(double) * 2 * nrep, hipMemcpyDeviceToHost, st));
-  HIP_TRY(c, hipStreamSynchronize(st));
-  const int groups = (c->p.P + 63) / 64;
-  int chunk_off = 0;
-  int64_t items = 0;
-  for (int r = 0; r < nrep; ++r) {
-    const double sq = qs[2 * r], sa = qs[2 * r + 1];
-    if (!std::isfinite(sq) || !std::isfinite(sa)) return c->fail(RBE_ENONFINITE, "replica %d: non-finite charges", r);
-    if (std::fabs(sq) > 1e-10 * std::fmax(sa, 1e-300) && std::fabs(sq) > 1e-12)
-      return c->fail(RBE_ENONNEUTRAL, "replica %d: total charge %.3e is not zero (sum |q| = %.3e)", r, sq, sa);
-    RepDesc &d = B.reps[r];
-    d.nq = nq[r];
-    d.chunk_len = kBatchChunk;
-    d.nchunks = (int)((d.nq + kBatchChunk - 1) / kBatchChunk);
-    d.chunk_off = chunk_off;
-    d.rho_item_off = (int)items;
-    chunk_off += d.nchunks;
-    items += (int64_t)d.nchunks * groups;
-  }
-  if (chunk_off > B.part_chunks || items > 0x7FFFFFFF) return c->fail(RBE_ERANGE, "structure-factor layout overflow");
-  B.rho_items = (int)items;
-  HIP_TRY(c, hipMemcpyAsync(B.reps_dev, B.reps.data(), sizeof(RepDesc) * nrep, hipMemcpyHostToDevice, st));
-  return RBE_OK;
+  launch_qstats_rep(B.nrep, B.off_dev, q, B.nq, B.qs, st);
+  launch_batch_layout(B.nrep, B.nq, B.qs, c->p.P, kBatchChunk, B.reps_dev, B.rho_items, B.bad_rep, c->err, st);
 }
 
 // Launch arguments shared by both modes; the caller sets the state arrays.
@@ -942,22 +922,17 @@ static BatchArgs batch_step_args(rbe_ctx *c, const WorkSet &in, const WorkSet &o
 // Start of a batched call: eval, barrier and histogram start from known values.
 static int batch_begin(rbe_ctx *c, uint64_t eval, hipStream_t st) {
   auto &B = c->bt;
-  B.eval_stage = eval;
-  HIP_TRY(c, hipMemcpyAsync(B.eval, &B.eval_stage, sizeof(uint64_t), hipMemcpyHostToDevice, st));
+  launch_set_u64(B.eval, eval, st);
   launch_fill_i32((int32_t *)B.bar, 2, 0, st);
   launch_fill_i32(B.count, B.nkeys, 0, st);
   return RBE_OK;
 }
 
-// Two-step graph (ws[0] -> ws[1] -> ws[0]); rebuilt when the chunk layout changes.
+// Two-step graph (ws[0] -> ws[1] -> ws[0]), instantiated on the first call
+// with two or more steps (the layout it depends on is read on the device).
 static int batch_graph(rbe_ctx *c) {
   auto &B = c->bt;
-  if (B.exec && B.graph_rho_items == B.rho_items) return RBE_OK;
-  if (B.exec) (void)hipGraphExecDestroy(B.exec);
-  if (B.graph) (void)hipGraphDestroy(B.graph);
-  B.exec = nullptr;
-  B.graph = nullptr;
-  B.graph_rho_items = -1;
+  if (B.exec) return RBE_OK;
   B.node_args[0] = batch_step_args(c, c->ws[0], c->ws[1]);
   B.node_args[1] = batch_step_args(c, c->ws[1], c->ws[0]);
   HIP_TRY(c, hipGraphCreate(&B.graph, 0));
@@ -965,7 +940,6 @@ static int batch_graph(rbe_ctx *c) {
   HIP_TRY(c, add_batch_node(B.graph, &n0, nullptr, 0, c->p.prec, B.blocks, &B.node_args[0]));
   HIP_TRY(c, add_batch_node(B.graph, &n1, &n0, 1, c->p.prec, B.blocks, &B.node_args[1]));
   HIP_TRY(c, hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0));
-  B.graph_rho_items = B.rho_items;
   return RBE_OK;
 }
 
@@ -974,9 +948,8 @@ static int batch_forces(rbe_ctx *c, const rbe_state *s, const int32_t *m, const 
   auto &B = c->bt;
   if (m || w || rho_out) return c->fail(RBE_EINVAL, "a batched context draws its own modes: m, w, rho_out must be NULL");
   if (s->n != B.ntot) return c->fail(RBE_ERANGE, "n = %lld, the batch holds %lld", (long long)s->n, (long long)B.ntot);
-  int rc = batch_prepare(c, s->q, st);
-  if (rc != RBE_OK) return rc;
-  rc = batch_begin(c, eval, st);
+  batch_prepare(c, s->q, st);
+  const int rc = batch_begin(c, eval, st);
   if (rc != RBE_OK) return rc;
   BatchArgs a = batch_args(c, 1);
   a.ix = s->x;
@@ -1012,43 +985,48 @@ static int copy_state(rbe_ctx *c, const double *const src[10], const int32_t *si
   return RBE_OK;
 }
 
+// Batched steps without copying the state: the first step reads the caller's
+// arrays and reorders into ws[0], the steps between alternate between the
+// working sets (pairs of them through the two-step graph), and the last step
+// reorders into the caller's arrays. A single step copies the state into
+// ws[0] first.
 static int batch_step(rbe_ctx *c, rbe_state *s, int32_t nsteps, uint64_t first_eval, hipStream_t st) {
   auto &B = c->bt;
   if (s->n != B.ntot) return c->fail(RBE_ERANGE, "n = %lld, the batch holds %lld", (long long)s->n, (long long)B.ntot);
-  int rc = batch_prepare(c, s->q, st);
-  if (rc != RBE_OK) return rc;
+  batch_prepare(c, s->q, st);
   const int64_t n = s->n;
-  WorkSet &A = c->ws[0];
-  {
+  WorkSet S{s->x, s->y, s->z, s->vx, s->vy, s->vz, s->q, s->fx, s->fy, s->fz, s->id};
+  int rc = batch_begin(c, first_eval, st);
+  if (rc != RBE_OK) return rc;
+  auto direct = [&](const WorkSet &in, const WorkSet &out) {
+    BatchArgs a = batch_step_args(c, in, out);
+    TScope ts(c, RBE_TK_BATCH, st);
+    launch_batch_step(c->p.prec, B.blocks, a, st);
+  };
+  if (nsteps == 1) {
+    WorkSet &A = c->ws[0];
     const double *src[10] = {s->x, s->y, s->z, s->vx, s->vy, s->vz, s->fx, s->fy, s->fz, s->q};
     double *dst[10] = {A.x, A.y, A.z, A.vx, A.vy, A.vz, A.fx, A.fy, A.fz, A.q};
     rc = copy_state(c, src, s->id, dst, A.id, n, st);
     if (rc != RBE_OK) return rc;
-  }
-  rc = batch_begin(c, first_eval, st);
-  if (rc != RBE_OK) return rc;
-  if (nsteps >= 2) {
-    rc = batch_graph(c);
-    if (rc != RBE_OK) return rc;
-    for (int32_t k = 0; k + 1 < nsteps; k += 2) {
-      TScope ts(c, RBE_TK_BATCH, st, 2);
-      HIP_TRY(c, hipGraphLaunch(B.exec, st));
+    direct(A, S);
+  } else {
+    direct(S, c->ws[0]);
+    const int32_t middle = nsteps - 2;
+    if (middle >= 2) {
+      rc = batch_graph(c);
+      if (rc != RBE_OK) return rc;
+      for (int32_t k = 0; k + 1 < middle; k += 2) {
+        TScope ts(c, RBE_TK_BATCH, st, 2);
+        HIP_TRY(c, hipGraphLaunch(B.exec, st));
+      }
     }
-  }
-  const WorkSet *fin = &c->ws[0];
-  if (nsteps & 1) {
-    BatchArgs a = batch_step_args(c, c->ws[0], c->ws[1]);
-    {
-      TScope ts(c, RBE_TK_BATCH, st);
-      launch_batch_step(c->p.prec, B.blocks, a, st);
+    const WorkSet *cur = &c->ws[0];
+    if (middle & 1) {
+      direct(c->ws[0], c->ws[1]);
+      cur = &c->ws[1];
     }
-    fin = &c->ws[1];
-  }
-  {
-    const double *src[10] = {fin->x, fin->y, fin->z, fin->vx, fin->vy, fin->vz, fin->fx, fin->fy, fin->fz, fin->q};
-    double *dst[10] = {s->x, s->y, s->z, s->vx, s->vy, s->vz, s->fx, s->fy, s->fz, s->q};
-    rc = copy_state(c, src, fin->id, dst, s->id, n, st);
-    if (rc != RBE_OK) return rc;
+    direct(*cur, S);
   }
   HIP_TRY(c, hipGetLastError());
   return RBE_OK;
@@ -1065,9 +1043,7 @@ extern "C" int rbe_forces(rbe_ctx *c, const rbe_state *s, const int32_t *m, cons
   hipStream_t st = (hipStream_t)stream;
   if (c->batched()) return batch_forces(c, s, m, w, eval, rho_out, st);
   const int64_t n = s->n;
-  int64_t nq = 0;
-  int rc = charge_stats(c, n, s->q, st, &nq);
-  if (rc != RBE_OK) return rc;
+  launch_charge_check(c, n, s->q, st);
   {
     TScope ts(c, RBE_TK_BIN, st);
     launch_bin(c->bb, c->g, n, s->x, s->y, s->z, s->q, c->cell_start, c->perm, st);
@@ -1077,7 +1053,7 @@ extern "C" int rbe_forces(rbe_ctx *c, const rbe_state *s, const int32_t *m, cons
     launch_gather_sorted(n, c->perm, s->x, s->y, s->z, s->q, s->id, c->g, c->srt, st);
   }
   WorkSet &o = c->ws[1];
-  rc = eval_sorted(c, n, nq, m, w, eval, rho_out, o.fx, o.fy, o.fz, st);
+  const int rc = eval_sorted(c, n, m, w, eval, rho_out, o.fx, o.fy, o.fz, st);
   if (rc != RBE_OK) return rc;
   if (c->pp.rbl && (c->p.terms & (RBE_TERM_LJ | RBE_TERM_COUL_REAL))) launch_sub_mean(n, c->mean, o.fx, o.fy, o.fz, st);
   launch_scatter_forces(n, c->perm, o.fx, o.fy, o.fz, s->fx, s->fy, s->fz, st);
@@ -1099,9 +1075,7 @@ extern "C" int rbe_energy(rbe_ctx *c, const rbe_state *s, const int32_t *m, cons
   HIP_TRY(c, hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
   const int64_t n = s->n;
-  int64_t nq = 0;
-  int rc = charge_stats(c, n, s->q, st, &nq);
-  if (rc != RBE_OK) return rc;
+  launch_charge_check(c, n, s->q, st);
   const bool near = (c->p.terms & (RBE_TERM_LJ | RBE_TERM_COUL_REAL)) != 0;
   const bool fourier = (c->p.terms & RBE_TERM_FOURIER) != 0;
   launch_bin(c->bb, c->g, n, s->x, s->y, s->z, s->q, c->cell_start, c->perm, st);
@@ -1116,8 +1090,9 @@ extern "C" int rbe_energy(rbe_ctx *c, const rbe_state *s, const int32_t *m, cons
     }
     launch_modes_to_double(P, m, c->fb.mkd, st);
     // structure factors always in FP64 here, whatever the context's precision
-    const int nchunks = launch_rho_partial(RBE_FP64, nq, P, c->srt.sq, c->fb, st);
-    launch_rho_final(nchunks, P, c->fb, w, c->p.coulomb_k, rho_out, st);
+    const int32_t *nq = c->cell_start + c->g.ncell;
+    launch_rho_partial(RBE_FP64, nq, n, P, c->srt.sq, c->fb, st);
+    launch_rho_final(nq, P, c->fb, w, c->p.coulomb_k, rho_out, st);
     fin.w = w;
     fin.rho = c->fb.rho;
     fin.mkd = c->fb.mkd;
@@ -1129,8 +1104,8 @@ extern "C" int rbe_energy(rbe_ctx *c, const rbe_state *s, const int32_t *m, cons
   fin.self_coef = c->p.coulomb_k * std::sqrt(c->p.alpha / kPi);
   fin.half_mass = 0.5 * c->p.mass;
   fin.out = u_out;
-  launch_energy(c->pp, 4.0 * c->p.lj_eps, n, nq, c->srt, c->cell_start, near, s->q, s->vx, s->vy, s->vz, c->epart,
-                fin, st);
+  launch_energy(c->pp, 4.0 * c->p.lj_eps, n, c->srt, c->cell_start, near, s->q, s->vx, s->vy, s->vz, c->epart, fin,
+                st);
   HIP_TRY(c, hipGetLastError());
   return RBE_OK;
 }
@@ -1175,22 +1150,17 @@ extern "C" int rbe_step(rbe_ctx *c, rbe_state *s, int32_t nsteps, uint64_t first
   hipStream_t st = (hipStream_t)stream;
   if (c->batched()) return batch_step(c, s, nsteps, first_eval, st);
   const int64_t n = s->n;
-  int64_t nq = 0;
-  int rc = charge_stats(c, n, s->q, st, &nq);
-  if (rc != RBE_OK) return rc;
-  const size_t bd = sizeof(double) * n, bi = sizeof(int32_t) * n;
-  WorkSet *A = &c->ws[0], *B = &c->ws[1];
-  HIP_TRY(c, hipMemcpyAsync(A->x, s->x, bd, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(c, hipMemcpyAsync(A->y, s->y, bd, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(c, hipMemcpyAsync(A->z, s->z, bd, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(c, hipMemcpyAsync(A->vx, s->vx, bd, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(c, hipMemcpyAsync(A->vy, s->vy, bd, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(c, hipMemcpyAsync(A->vz, s->vz, bd, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(c, hipMemcpyAsync(A->fx, s->fx, bd, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(c, hipMemcpyAsync(A->fy, s->fy, bd, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(c, hipMemcpyAsync(A->fz, s->fz, bd, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(c, hipMemcpyAsync(A->q, s->q, bd, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(c, hipMemcpyAsync(A->id, s->id, bi, hipMemcpyDeviceToDevice, st));
+  launch_charge_check(c, n, s->q, st);
+  // Step k advances X_k in place (kick, drift), reorders it into X_{k+1} and
+  // evaluates the force there. X_0 is the caller's state and, with two or
+  // more steps, so is X_nsteps: the last reorder writes the caller's arrays
+  // directly; the steps between alternate between the two working sets.
+  WorkSet S{s->x, s->y, s->z, s->vx, s->vy, s->vz, s->q, s->fx, s->fy, s->fz, s->id};
+  auto next_set = [&](int32_t k) -> WorkSet * {
+    if (nsteps >= 2 && k == nsteps - 1) return &S;
+    return &c->ws[k % 2];
+  };
+  WorkSet *A = &S;
   const double h = 0.5 * c->p.dt / c->p.mass;
   const bool near = (c->p.terms & (RBE_TERM_LJ | RBE_TERM_COUL_REAL)) != 0;
   const bool fourier = (c->p.terms & RBE_TERM_FOURIER) != 0;
@@ -1208,6 +1178,7 @@ extern "C" int rbe_step(rbe_ctx *c, rbe_state *s, int32_t nsteps, uint64_t first
               c->nh_scale, c->err, st);
   }
   for (int32_t k = 0; k < nsteps; ++k) {
+    WorkSet *B = next_set(k);
     {
       // step 0 starts from the caller's forces; later NVE steps fuse the
       // previous step's second half-kick into this one's first half-kick and
@@ -1241,9 +1212,9 @@ extern "C" int rbe_step(rbe_ctx *c, rbe_state *s, int32_t nsteps, uint64_t first
       launch_sample_modes(c->mt, c->cdf_dev, c->p.seed, first_eval + (uint64_t)k, (int)P, c->m_dev, c->w_dev, c->err,
                           st, std::min(kSampleSteps, nsteps - k), c->mkd_dev);
     }
-    rc = eval_sorted(c, n, nq, fourier ? c->m_dev + 3 * P * ks : nullptr, fourier ? c->w_dev + P * ks : nullptr,
-                     first_eval + (uint64_t)k, nullptr, B->fx, B->fy, B->fz, st, k > 0,
-                     fourier ? c->mkd_dev + 3 * P * ks : nullptr);
+    const int rc = eval_sorted(c, n, fourier ? c->m_dev + 3 * P * ks : nullptr, fourier ? c->w_dev + P * ks : nullptr,
+                               first_eval + (uint64_t)k, nullptr, B->fx, B->fy, B->fz, st, k > 0,
+                               fourier ? c->mkd_dev + 3 * P * ks : nullptr);
     if (rc != RBE_OK) return rc;
     if (nvt) {
       // second half-kick, the closing thermostat half of this step and, unless
@@ -1257,19 +1228,15 @@ extern "C" int rbe_step(rbe_ctx *c, rbe_state *s, int32_t nsteps, uint64_t first
       TScope ts(c, RBE_TK_KICK, st);
       launch_kick(n, h, mean, B->fx, B->fy, B->fz, B->vx, B->vy, B->vz, c->err, st);
     }
-    std::swap(A, B);
+    A = B;
   }
-  HIP_TRY(c, hipMemcpyAsync(s->x, A->x, bd, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(c, hipMemcpyAsync(s->y, A->y, bd, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(c, hipMemcpyAsync(s->z, A->z, bd, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(c, hipMemcpyAsync(s->vx, A->vx, bd, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(c, hipMemcpyAsync(s->vy, A->vy, bd, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(c, hipMemcpyAsync(s->vz, A->vz, bd, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(c, hipMemcpyAsync(s->fx, A->fx, bd, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(c, hipMemcpyAsync(s->fy, A->fy, bd, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(c, hipMemcpyAsync(s->fz, A->fz, bd, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(c, hipMemcpyAsync(s->q, A->q, bd, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(c, hipMemcpyAsync(s->id, A->id, bi, hipMemcpyDeviceToDevice, st));
+  if (A != &S) {
+    // a single step ends in a working set
+    const double *src[10] = {A->x, A->y, A->z, A->vx, A->vy, A->vz, A->fx, A->fy, A->fz, A->q};
+    double *dst[10] = {s->x, s->y, s->z, s->vx, s->vy, s->vz, s->fx, s->fy, s->fz, s->q};
+    const int rc = copy_state(c, src, A->id, dst, s->id, n, st);
+    if (rc != RBE_OK) return rc;
+  }
   HIP_TRY(c, hipGetLastError());
   return RBE_OK;
 }
@@ -1278,16 +1245,20 @@ extern "C" int rbe_sync_check(rbe_ctx *c, void *stream) {
   if (!c) return RBE_EINVAL;
   HIP_TRY(c, hipSetDevice(c->device));
   hipStream_t st = (hipStream_t)stream;
-  int flag = 0;
+  int flag = 0, bad_rep = -1;
   HIP_TRY(c, hipMemcpyAsync(&flag, c->err, sizeof flag, hipMemcpyDeviceToHost, st));
+  if (c->batched()) HIP_TRY(c, hipMemcpyAsync(&bad_rep, c->bt.bad_rep, sizeof bad_rep, hipMemcpyDeviceToHost, st));
   HIP_TRY(c, hipStreamSynchronize(st));
   launch_fill_i32(c->err, 1, 0, st);
   HIP_TRY(c, hipStreamSynchronize(st));
-  if (flag & kErrNonFinite) return c->fail(RBE_ENONFINITE, "non-finite velocity or force seen on the device");
+  char who[48] = "";
+  if (bad_rep >= 0) snprintf(who, sizeof who, " (replica %d)", bad_rep);
+  if (flag & kErrNonFinite) return c->fail(RBE_ENONFINITE, "non-finite charge, velocity or force seen on the device%s", who);
   if (flag & kErrBadId) return c->fail(RBE_ERANGE, "a particle id lies outside [0, n)");
   if (flag & kErrSampler) return c->fail(RBE_EINVAL, "mode sampler rejected every attempt");
   if (flag & kErrGhostOverflow) return c->fail(RBE_ERANGE, "the ghost shell exceeded its capacity");
   if (flag & kErrBarrier) return c->fail(RBE_EDEVICE, "a grid barrier of the batched step timed out");
+  if (flag & kErrNonNeutral) return c->fail(RBE_ENONNEUTRAL, "the charges do not sum to zero (Eq. 1)%s", who);
   return RBE_OK;
 }
 

@@ -284,7 +284,8 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchArgs a) {
   }
   if (P > 0 && do_far) {
     const int groups = (P + 63) / 64;
-    for (int64_t it = gwave; it < a.rho_items; it += nwaves) {
+    const int64_t rho_items = *a.rho_items;
+    for (int64_t it = gwave; it < rho_items; it += nwaves) {
       // replica of this item: last r with rho_item_off <= it
       int lo = 0, hi = a.nrep - 1;
       while (lo < hi) {
@@ -490,5 +491,50 @@ __global__ void __launch_bounds__(256) k_qstats_rep(const int64_t *__restrict__ 
 void launch_qstats_rep(int nrep, const int64_t *off, const double *q, int32_t *nq, double *qs, hipStream_t st) {
   k_qstats_rep<<<nrep, 256, 0, st>>>(off, q, nq, qs);
 }
+
+// Per-replica checks of Eq. 1 (flags kErrNonNeutral / kErrNonFinite) and the
+// structure-factor layout of this call from the device counts: replica r's
+// charged particles in chunks of chunk_len, its chunk partials at chunk_off,
+// its (chunk, 64-mode group) items at rho_item_off; *rho_items receives the
+// total, *bad_rep the first replica that failed a check (-1: none). One
+// thread: the replica count is small.
+__global__ void k_batch_layout(int nrep, const int32_t *__restrict__ nq, const double *__restrict__ qs, int groups,
+                               int chunk_len, RepDesc *__restrict__ reps, int *__restrict__ rho_items,
+                               int *__restrict__ bad_rep, int *err) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int chunk_off = 0;
+  int64_t items = 0;
+  int flags = 0, bad = -1;
+  for (int r = 0; r < nrep; ++r) {
+    const double sq = qs[2 * r], sa = qs[2 * r + 1];
+    int f = 0;
+    if (!isfinite(sq) || !isfinite(sa)) f = kErrNonFinite;
+    else if (fabs(sq) > 1e-10 * fmax(sa, 1e-300) && fabs(sq) > 1e-12) f = kErrNonNeutral;
+    if (f && bad < 0) bad = r;
+    flags |= f;
+    RepDesc &d = reps[r];
+    d.nq = nq[r];
+    d.chunk_len = chunk_len;
+    d.nchunks = (d.nq + chunk_len - 1) / chunk_len;
+    d.chunk_off = chunk_off;
+    d.rho_item_off = (int)items;
+    chunk_off += d.nchunks;
+    items += (int64_t)d.nchunks * groups;
+  }
+  *rho_items = (int)items;
+  *bad_rep = bad;
+  if (flags) atomicOr(err, flags);
+}
+
+void launch_batch_layout(int nrep, const int32_t *nq, const double *qs, int P, int chunk_len, RepDesc *reps,
+                         int *rho_items, int *bad_rep, int *err, hipStream_t st) {
+  k_batch_layout<<<1, 64, 0, st>>>(nrep, nq, qs, (P + 63) / 64, chunk_len, reps, rho_items, bad_rep, err);
+}
+
+__global__ void k_set_u64(uint64_t *p, uint64_t v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+void launch_set_u64(uint64_t *p, uint64_t v, hipStream_t st) { k_set_u64<<<1, 64, 0, st>>>(p, v); }
 
 }  // namespace rbe

@@ -41,13 +41,12 @@ __device__ inline double block_sum(double v, double *lds) {
 //         r^2 G = erfc(sqrt(a) r)/r + 2 sqrt(a/pi) exp(-a r^2),
 //         r^2 G_LJ = 24 eps (2 (sigma/r)^12 - (sigma/r)^6)        (Eq. 8)
 // over the minimum image. Species layout as in the force kernels: charged i
-// ([0, nq)) walk the charged block out to max(r_coul, r_lj) and the neutral
+// (q_i != 0, the range [0, nq) of the cell order) walk the charged block out to max(r_coul, r_lj) and the neutral
 // block out to r_lj; neutral i walk both blocks out to r_lj.
 // part[4 b + 0..3] = Coulomb energy, LJ energy, Coulomb virial, LJ virial of
 // block b.
 __global__ void __launch_bounds__(kEnergyThreads) k_energy_near(PairParams pp, double lj4, double two_sqrt_a_pi,
-                                                                int64_t n, int64_t nq,
-                                                                const double4 *__restrict__ xq,
+                                                                int64_t n, const double4 *__restrict__ xq,
                                                                 const int32_t *__restrict__ cell_start,
                                                                 double *__restrict__ part) {
   __shared__ double lds[kEnergyThreads / 64];
@@ -78,7 +77,7 @@ __global__ void __launch_bounds__(kEnergyThreads) k_energy_near(PairParams pp, d
       }
     };
     const Reach rq{xi, yi, zi, pp.rq2}, rlj{xi, yi, zi, pp.rlj2};
-    if (i < nq) {
+    if (qi != 0.0) {
       for_stencil<false>(g, cell_start, xq, nullptr, 0, cx, cy, cz, pp.s_coul, rq, visit);
       if (pp.do_lj) for_stencil<false>(g, cell_start, xq, nullptr, 1, cx, cy, cz, pp.s_lj, rlj, visit);
     } else if (pp.do_lj) {
@@ -173,14 +172,14 @@ int energy_part_len(int64_t n_max) {
   return (int)(4 * nb + 2 * kEnergySqBlocks);
 }
 
-void launch_energy(const PairParams &pp, double lj4, int64_t n, int64_t nq, const Sorted &s,
+void launch_energy(const PairParams &pp, double lj4, int64_t n, const Sorted &s,
                    const int32_t *cell_start, bool near, const double *q, const double *vx, const double *vy,
                    const double *vz, double *part, EnergyFinal fin, hipStream_t st) {
   int64_t nb_near = 0;
   if (near && n > 0) {
     nb_near = (n + kEnergyThreads - 1) / kEnergyThreads;
-    k_energy_near<<<(unsigned)nb_near, kEnergyThreads, 0, st>>>(pp, lj4, 2.0 * std::sqrt(pp.alpha / kPi), n, nq,
-                                                                 s.xq, cell_start, part);
+    k_energy_near<<<(unsigned)nb_near, kEnergyThreads, 0, st>>>(pp, lj4, 2.0 * std::sqrt(pp.alpha / kPi), n, s.xq,
+                                                                 cell_start, part);
   }
   double *sq_part = part + 4 * nb_near;
   int64_t nb_sq = (n + kEnergyThreads - 1) / kEnergyThreads;

@@ -35,18 +35,6 @@ void fill_turn_table(double2 *host, int n) {
   }
 }
 
-int rho_chunk(int64_t nq, int P, int prec, int nchunk_max) {
-  // enough chunks to fill the chip (about 8k waves), never more than the scratch holds
-  const int64_t groups = (P + 63) / 64;
-  int64_t target_waves = 8192;
-  int64_t chunks = (target_waves + groups - 1) / groups;
-  int64_t len = (nq + chunks - 1) / chunks;
-  if (len < 64) len = 64;
-  while ((nq + len - 1) / len > nchunk_max) len *= 2;
-  (void)prec;
-  return (int)len;
-}
-
 __global__ void k_modes_to_double(int P, const int32_t *__restrict__ m, double *__restrict__ mkd) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l < 3 * P) mkd[l] = (double)m[l];
@@ -70,12 +58,17 @@ __device__ inline int wave_rep(int a) {
   return rep;
 }
 
-__global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f64(int64_t nq, int P, int chunk,
+__global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f64(const int32_t *__restrict__ nq_ptr, int P,
+                                                                     int nchunk_max,
                                                                      const double4 *__restrict__ sq,
                                                                      const double *__restrict__ mkd,
                                                                      const double2 *__restrict__ turn_tab,
                                                                      double2 *__restrict__ part) {
   static_assert(kModesPerBlock == kTurnTable, "one table entry per thread");
+  const int64_t nq = *nq_ptr;
+  int nchunks;
+  const int chunk = rho_layout(nq, P, nchunk_max, &nchunks);
+  if ((int)blockIdx.x >= nchunks) return;
   __shared__ double2 tab[kTurnTable];
   tab[threadIdx.x] = turn_tab[threadIdx.x];
   __syncthreads();
@@ -122,10 +115,15 @@ __global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f64(int64_t nq, 
   if (active && ph == 0) part[(int64_t)blockIdx.x * P + l] = make_double2(re, im);
 }
 
-__global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f32c(int64_t nq, int P, int chunk,
+__global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f32c(const int32_t *__restrict__ nq_ptr, int P,
+                                                                      int nchunk_max,
                                                                       const double4 *__restrict__ sq,
                                                                       const double *__restrict__ mkd,
                                                                       double2 *__restrict__ part) {
+  const int64_t nq = *nq_ptr;
+  int nchunks;
+  const int chunk = rho_layout(nq, P, nchunk_max, &nchunks);
+  if ((int)blockIdx.x >= nchunks) return;
   const int lane = threadIdx.x & 63;
   const int l0 = blockIdx.y * kModesPerBlock + (threadIdx.x & ~63);
   const int a = min(64, P - l0);
@@ -168,13 +166,16 @@ __global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f32c(int64_t nq,
 // butterfly in each wave, then the waves in index order). Also forms the
 // gather coefficients of each mode.
 constexpr int kRhoFinalThreads = 256;
-__global__ void __launch_bounds__(kRhoFinalThreads) k_rho_final(int nchunks, int P, const double2 *__restrict__ part,
+__global__ void __launch_bounds__(kRhoFinalThreads) k_rho_final(const int32_t *__restrict__ nq_ptr, int nchunk_max, int P,
+                                                                const double2 *__restrict__ part,
                                                                 const double *__restrict__ mkd,
                                                                 const double *__restrict__ w, double kc,
                                                                 double *__restrict__ rho,
                                                                 GatherMode *__restrict__ modes,
                                                                 double *__restrict__ rho_out) {
   __shared__ double2 wsum[kRhoFinalThreads / 64];
+  int nchunks;
+  (void)rho_layout(*nq_ptr, P, nchunk_max, &nchunks);
   const int l = blockIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double re = 0.0, im = 0.0;
@@ -216,31 +217,33 @@ __global__ void __launch_bounds__(kRhoFinalThreads) k_rho_final(int nchunks, int
   }
 }
 
-int launch_rho_partial(int prec, int64_t nq, int P, const double4 *sq, const FourierBuffers &fb, hipStream_t st) {
-  const int chunk = rho_chunk(nq, P, prec, fb.nchunk_max);
-  int nchunks = (int)((nq + chunk - 1) / chunk);
-  if (nchunks < 1) nchunks = 1;
+void launch_rho_partial(int prec, const int32_t *nq, int64_t nq_max, int P, const double4 *sq,
+                        const FourierBuffers &fb, hipStream_t st) {
+  const int nchunks = rho_max_chunks(nq_max, P, fb.nchunk_max);
   dim3 grid((unsigned)nchunks, (unsigned)((P + kModesPerBlock - 1) / kModesPerBlock));
   if (prec == RBE_FP32C)
-    k_rho_partial_f32c<<<grid, kModesPerBlock, 0, st>>>(nq, P, chunk, sq, fb.mkd, fb.part);
+    k_rho_partial_f32c<<<grid, kModesPerBlock, 0, st>>>(nq, P, fb.nchunk_max, sq, fb.mkd, fb.part);
   else
-    k_rho_partial_f64<<<grid, kModesPerBlock, 0, st>>>(nq, P, chunk, sq, fb.mkd, fb.turn_tab, fb.part);
-  return nchunks;
+    k_rho_partial_f64<<<grid, kModesPerBlock, 0, st>>>(nq, P, fb.nchunk_max, sq, fb.mkd, fb.turn_tab, fb.part);
 }
 
-void launch_rho_final(int nchunks, int P, const FourierBuffers &fb, const double *w, double kc, double *rho_out,
-                      hipStream_t st) {
-  k_rho_final<<<P, kRhoFinalThreads, 0, st>>>(nchunks, P, fb.part, fb.mkd, w, kc, fb.rho, fb.modes, rho_out);
+void launch_rho_final(const int32_t *nq, int P, const FourierBuffers &fb, const double *w, double kc,
+                      double *rho_out, hipStream_t st) {
+  k_rho_final<<<P, kRhoFinalThreads, 0, st>>>(nq, fb.nchunk_max, P, fb.part, fb.mkd, w, kc, fb.rho, fb.modes,
+                                              rho_out);
 }
 
 // ---------------------------------------------------------------------------
 // force gather (adds F^F into f for the charged range)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kTurnTable) k_gather_f64(int64_t nq, int P, const double4 *__restrict__ sq,
+__global__ void __launch_bounds__(kTurnTable) k_gather_f64(const int32_t *__restrict__ nq_ptr, int P,
+                                                           const double4 *__restrict__ sq,
                                                            const GatherMode *__restrict__ modes,
                                                            const double2 *__restrict__ turn_tab, double kx,
                                                            double ky, double kz, double *__restrict__ fx,
                                                            double *__restrict__ fy, double *__restrict__ fz) {
+  const int64_t nq = *nq_ptr;
+  if ((int64_t)blockIdx.x * blockDim.x >= nq) return;
   __shared__ double2 tab[kTurnTable];
   tab[threadIdx.x] = turn_tab[threadIdx.x];
   __syncthreads();
@@ -265,12 +268,13 @@ __global__ void __launch_bounds__(kTurnTable) k_gather_f64(int64_t nq, int P, co
   fz[i] -= q * kz * gz;
 }
 
-__global__ void __launch_bounds__(256) k_gather_f32c(int64_t nq, int P, const double4 *__restrict__ sq,
+__global__ void __launch_bounds__(256) k_gather_f32c(const int32_t *__restrict__ nq_ptr, int P,
+                                                     const double4 *__restrict__ sq,
                                                      const GatherMode *__restrict__ modes, double kx, double ky,
                                                      double kz, double *__restrict__ fx, double *__restrict__ fy,
                                                      double *__restrict__ fz) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= nq) return;
+  if (i >= *nq_ptr) return;
   const double4 s = sq[i];
   float gx = 0.f, gy = 0.f, gz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
 #pragma unroll 4
@@ -290,10 +294,11 @@ __global__ void __launch_bounds__(256) k_gather_f32c(int64_t nq, int P, const do
   fz[i] -= q * kz * ((double)gz - (double)cz);
 }
 
-void launch_fourier_gather(int prec, int64_t nq, int P, const double4 *sq, const FourierBuffers &fb, const Grid &g,
-                           double *fx, double *fy, double *fz, hipStream_t st) {
-  if (nq <= 0) return;
-  const unsigned blocks = (unsigned)((nq + 255) / 256);
+void launch_fourier_gather(int prec, const int32_t *nq, int64_t nq_max, int P, const double4 *sq,
+                           const FourierBuffers &fb, const Grid &g, double *fx, double *fy, double *fz,
+                           hipStream_t st) {
+  if (nq_max <= 0) return;
+  const unsigned blocks = (unsigned)((nq_max + 255) / 256);
   const double kx = kTwoPi / g.L[0], ky = kTwoPi / g.L[1], kz = kTwoPi / g.L[2];
   if (prec == RBE_FP32C)
     k_gather_f32c<<<blocks, 256, 0, st>>>(nq, P, sq, fb.modes, kx, ky, kz, fx, fy, fz);

@@ -102,17 +102,26 @@ constexpr int kShellCap = 128;
 // scan reads (sorted natives, ghosts, batch): its lookahead loads may run
 // up to this many records minus one past the end of a range.
 constexpr int kScanPad = 8;
-uint64_t shell_first_threshold(const PairParams &pp, int64_t n);
+__host__ __device__ inline uint64_t shell_first_threshold(const PairParams &pp, int64_t n) {
+  const double V = pp.g.L[0] * pp.g.L[1] * pp.g.L[2];
+  const double rc = sqrt(pp.rc2), r0 = sqrt(pp.rcore2);
+  const double m_mean = (double)n / V * (4.0 / 3.0) * kPi * (rc * rc * rc - r0 * r0 * r0);
+  if (!(m_mean > 0.5 * kShellCap)) return 1ull << 32;
+  const double f = 3.0 * pp.p_shell / m_mean;
+  if (f >= 1.0) return 1ull << 32;
+  return (uint64_t)(f * 4294967296.0);
+}
 struct PairCounters {
   unsigned long long *c;  // [4] or nullptr
 };
 // Near-field force; charged particles are [0, nq) of the sorted order,
-// neutral ones [nq, n). Launched in two parts: charged particles (plain
-// sums, or core and shell of the random batch list) and neutral particles.
+// neutral ones [nq, n), with nq read on the device (*nq). Launched in two
+// parts: charged particles (plain sums, or core and shell of the random batch
+// list) and neutral particles.
 // PAIR_PART_SHELL launches nothing (kept for the counter layout).
 enum { PAIR_PART_CHARGED = 0, PAIR_PART_SHELL = 1, PAIR_PART_NEUTRAL = 2 };
 // gb: ghost shell of the natives (nullptr for the periodic traversal).
-void launch_pair(int prec, int part, const PairParams &pp, int64_t n, int64_t nq, const Sorted &s,
+void launch_pair(int prec, int part, const PairParams &pp, int64_t n, const int32_t *nq, const Sorted &s,
                  const int32_t *cell_start, const int32_t *inv_id, const GhostBuffers *gb, double *fx, double *fy,
                  double *fz, PairCounters cnt, hipStream_t st);
 
@@ -136,17 +145,43 @@ constexpr int kTurnTableEntries = 256;
 // Host values of the FP64 kernels' turn table (n entries of (sin, cos) of
 // 2 pi k / n, each rounded once from extended precision).
 void fill_turn_table(double2 *host, int n);
-// Chunk length of the structure-factor partial sums for nq charged particles.
-int rho_chunk(int64_t nq, int P, int prec, int nchunk_max);
+// Chunk layout of the structure-factor partial sums of nq charged particles:
+// enough chunks to fill the chip (about 8k waves), chunks of at least 64
+// particles, never more chunks than the scratch holds. Returns the chunk
+// length; *nchunks receives the chunk count (at least 1). Evaluated on the
+// device from the device-side count, so the launches need no host copy of nq.
+__host__ __device__ inline int rho_layout(int64_t nq, int P, int nchunk_max, int *nchunks) {
+  const int64_t groups = (P + 63) / 64;
+  const int64_t target = (8192 + groups - 1) / groups;
+  int64_t len = (nq + target - 1) / target;
+  if (len < 64) len = 64;
+  while ((nq + len - 1) / len > nchunk_max) len *= 2;
+  const int64_t nc = (nq + len - 1) / len;
+  *nchunks = nc < 1 ? 1 : (int)nc;
+  return (int)len;
+}
+// Upper bound of rho_layout's chunk count over every nq <= nq_max (the grid
+// of the partial-sum launch; blocks past the actual count exit at once).
+inline int rho_max_chunks(int64_t nq_max, int P, int nchunk_max) {
+  const int64_t groups = (P + 63) / 64;
+  int64_t m = (8192 + groups - 1) / groups;
+  if (m > nchunk_max) m = nchunk_max;
+  const int64_t by_len = (nq_max + 63) / 64;
+  if (m > by_len) m = by_len;
+  return m < 1 ? 1 : (int)m;
+}
 void launch_modes_to_double(int P, const int32_t *m, double *mkd, hipStream_t st);
-// Returns the number of chunk partials written.
-int launch_rho_partial(int prec, int64_t nq, int P, const double4 *sq, const FourierBuffers &fb, hipStream_t st);
+// The charged count nq is read on the device (*nq, the first neutral cell
+// start); nq_max bounds it (sizes the grids).
+void launch_rho_partial(int prec, const int32_t *nq, int64_t nq_max, int P, const double4 *sq,
+                        const FourierBuffers &fb, hipStream_t st);
 // The gather coefficients take the weights times kc (the Coulomb prefactor
 // scales the Fourier force like every other Coulomb term).
-void launch_rho_final(int nchunks, int P, const FourierBuffers &fb, const double *w, double kc, double *rho_out,
-                      hipStream_t st);
-void launch_fourier_gather(int prec, int64_t nq, int P, const double4 *sq, const FourierBuffers &fb, const Grid &g,
-                           double *fx, double *fy, double *fz, hipStream_t st);
+void launch_rho_final(const int32_t *nq, int P, const FourierBuffers &fb, const double *w, double kc,
+                      double *rho_out, hipStream_t st);
+void launch_fourier_gather(int prec, const int32_t *nq, int64_t nq_max, int P, const double4 *sq,
+                           const FourierBuffers &fb, const Grid &g, double *fx, double *fy, double *fz,
+                           hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // energy terms (diagnostics, FP64)
@@ -169,7 +204,7 @@ int energy_part_len(int64_t n_max);
 // Near-field energies of the sorted particles (when near), the q^2 and v^2
 // sums of the caller's arrays (vx may be nullptr), and the final fixed-order
 // combination into fin.out.
-void launch_energy(const PairParams &pp, double lj4, int64_t n, int64_t nq, const Sorted &s,
+void launch_energy(const PairParams &pp, double lj4, int64_t n, const Sorted &s,
                    const int32_t *cell_start, bool near, const double *q, const double *vx, const double *vy,
                    const double *vz, double *part, EnergyFinal fin, hipStream_t st);
 
@@ -240,7 +275,7 @@ struct BatchArgs {
   int ntiles;
   int P;
   int mode;               // 0: step, 1: force evaluation only
-  int rho_items;          // total structure-factor items (chunk x 64-mode group)
+  const int *rho_items;   // total structure-factor items (chunk x 64-mode group), on the device
   int do_far;             // Fourier part on
   PairParams pp;          // physics shared by all replicas (grid fields unused)
   PairF32 pf;
@@ -272,5 +307,13 @@ hipError_t add_batch_node(hipGraph_t graph, hipGraphNode_t *node, const hipGraph
                           int blocks, BatchArgs *a);
 // Per-replica charge statistics: nq[r] charged count, qs[2r] = sum q, qs[2r+1] = sum |q|.
 void launch_qstats_rep(int nrep, const int64_t *off, const double *q, int32_t *nq, double *qs, hipStream_t st);
+// Checks of Eq. 1 per replica (device error flags) and the structure-factor
+// layout of every replica from the device counts (writes the nq, chunk and
+// item fields of reps[] on the device, the item total and the first replica
+// that failed a check, -1 if none).
+void launch_batch_layout(int nrep, const int32_t *nq, const double *qs, int P, int chunk_len, RepDesc *reps,
+                         int *rho_items, int *bad_rep, int *err, hipStream_t st);
+// *p = v on the stream (a kernel, so graph capture records no memset node).
+void launch_set_u64(uint64_t *p, uint64_t v, hipStream_t st);
 
 }  // namespace rbe

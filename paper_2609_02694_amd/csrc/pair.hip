@@ -46,7 +46,8 @@ struct PairCtx {
   double *__restrict__ fy;
   double *__restrict__ fz;
   unsigned long long *__restrict__ counters;  // [4] when counting
-  int64_t i0, i1;                             // particle range of this launch
+  const int32_t *__restrict__ nq_ptr;         // charged count (device): [0, nq) charged, [nq, n) neutral
+  int charged;                                // this launch: 1 the charged range, 0 the neutral range
   int64_t n;                                  // all particles
   // ghost shell (GHOST kernels only)
   const double4 *__restrict__ gxq;
@@ -78,6 +79,21 @@ __device__ inline void flush_counts(const PairCtx &c, unsigned long long n_coul,
   }
 }
 
+// Particle range of this launch, read on the device (the charged count is the
+// first neutral cell start), and the first particle of this block's share of
+// per_block particles: the grid is sized for all n particles, blocks past the
+// range's share exit at once, and the active blocks are spread over the XCDs
+// (each XCD takes a contiguous run of the range).
+__device__ inline bool part_block(const PairCtx &c, int per_block, int64_t *first, int64_t *end) {
+  const int64_t nq = *c.nq_ptr;
+  const int64_t a = c.charged ? 0 : nq, b = c.charged ? nq : c.n;
+  const int64_t nb = (b - a + per_block - 1) / per_block;
+  if ((int64_t)blockIdx.x >= nb) return false;
+  *first = a + xcd_block(blockIdx.x, nb) * per_block;
+  *end = b;
+  return true;
+}
+
 // i-side data of a cluster lane.
 struct ClusterI {
   int a, b;
@@ -87,14 +103,14 @@ struct ClusterI {
   int cx, cy, cz;
 };
 
-__device__ inline ClusterI load_cluster_i(const PairCtx &c) {
+__device__ inline ClusterI load_cluster_i(const PairCtx &c, int64_t first, int64_t end) {
   ClusterI r;
   const int lane = threadIdx.x;
   r.a = lane / kCJ;
   r.b = lane % kCJ;
-  const int64_t i_raw = c.i0 + xcd_block(blockIdx.x, gridDim.x) * kCI + r.a;
-  r.valid = i_raw < c.i1;
-  r.i = r.valid ? i_raw : c.i1 - 1;
+  const int64_t i_raw = first + r.a;
+  r.valid = i_raw < end;
+  r.i = r.valid ? i_raw : end - 1;
   const double4 p = c.xq[r.i];
   r.xi = p.x;
   r.yi = p.y;
@@ -129,8 +145,10 @@ __device__ inline void stencil(const PairCtx &c, int blk, int cx, int cy, int cz
 template <bool F32, bool COUNT, int MODE, bool GHOST>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F32 ? (MODE ? 6 : 7) : (MODE ? 3 : 7))))
 k_pair_plain(PairCtx c) {
-  const int64_t i = c.i0 + xcd_block(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= c.i1) return;
+  int64_t first, end;
+  if (!part_block(c, blockDim.x, &first, &end)) return;
+  const int64_t i = first + threadIdx.x;
+  if (i >= end) return;
   const PairParams &pp = c.pp;
   const Grid &g = pp.g;
   const double4 pi4 = c.xq[i];
@@ -189,15 +207,19 @@ __global__ void __launch_bounds__(64, 5) k_pair_rbl(PairCtx c) {
   __shared__ uint32_t kbuf[kCI * kShellCap];
   __shared__ uint32_t ksel[kCI * RBE_MAX_SHELL_BATCH];
   __shared__ int kcnt[kCI];
-  const ClusterI I = load_cluster_i(c);
+  int64_t first, end;
+  if (!part_block(c, kCI, &first, &end)) return;
+  const ClusterI I = load_cluster_i(c, first, end);
   const PairParams &pp = c.pp;
   const Grid &g = pp.g;
   const int p = pp.p_shell;
   const ShellKey sk = shell_key_of(pp.shell_key, c.ids[I.i]);
   ForceAcc<F32> acc;
   unsigned long long n_coul = 0, n_lj = 0, n_tested = 0;
-  int ns = 0;                // shell members seen by this lane
-  uint64_t T = pp.shell_T0;  // keys below T are collected
+  int ns = 0;  // shell members seen by this lane
+  // keys below T are collected; the mean shell of the charged-only variant
+  // holds charged particles, whose count is known on the device only
+  uint64_t T = QSHELL ? shell_first_threshold(pp, *c.nq_ptr) : pp.shell_T0;
   bool in_group = false;
   if (I.b == 0) kcnt[I.a] = 0;
   __syncthreads();
@@ -316,16 +338,6 @@ __global__ void __launch_bounds__(64, 5) k_pair_rbl(PairCtx c) {
   flush_counts<COUNT>(c, n_coul, n_lj, n_tested, I.b == 0 && I.valid ? (unsigned long long)m : 0ull);
 }
 
-uint64_t shell_first_threshold(const PairParams &pp, int64_t n) {
-  const double V = pp.g.L[0] * pp.g.L[1] * pp.g.L[2];
-  const double rc = std::sqrt(pp.rc2), r0 = std::sqrt(pp.rcore2);
-  const double m_mean = (double)n / V * (4.0 / 3.0) * kPi * (rc * rc * rc - r0 * r0 * r0);
-  if (!(m_mean > 0.5 * kShellCap)) return 1ull << 32;
-  const double f = 3.0 * pp.p_shell / m_mean;
-  if (f >= 1.0) return 1ull << 32;
-  return (uint64_t)(f * 4294967296.0);
-}
-
 PairF32 make_pair_f32(const PairParams &pp) {
   PairF32 pf;
   pf.sqrt_alpha = (float)pp.sqrt_alpha;
@@ -338,20 +350,15 @@ PairF32 make_pair_f32(const PairParams &pp) {
 }
 
 // Thread form: 256 particles per block. Cluster form: one wave of kCI
-// particles per block.
+// particles per block. Grids cover all n particles (the part's range is read
+// on the device; surplus blocks exit at once).
 template <class K>
-static void launch_threads(K kernel, PairCtx c, int64_t i0, int64_t i1, hipStream_t st) {
-  if (i1 <= i0) return;
-  c.i0 = i0;
-  c.i1 = i1;
-  kernel<<<(unsigned)((i1 - i0 + 255) / 256), 256, 0, st>>>(c);
+static void launch_threads(K kernel, PairCtx c, hipStream_t st) {
+  kernel<<<(unsigned)((c.n + 255) / 256), 256, 0, st>>>(c);
 }
 template <class K>
-static void launch_clusters(K kernel, PairCtx c, int64_t i0, int64_t i1, hipStream_t st) {
-  if (i1 <= i0) return;
-  c.i0 = i0;
-  c.i1 = i1;
-  kernel<<<(unsigned)((i1 - i0 + kCI - 1) / kCI), 64, 0, st>>>(c);
+static void launch_clusters(K kernel, PairCtx c, hipStream_t st) {
+  kernel<<<(unsigned)((c.n + kCI - 1) / kCI), 64, 0, st>>>(c);
 }
 
 // Charged particles occupy [0, nq) of the sorted order, neutral ones [nq, n).
@@ -361,31 +368,32 @@ static void launch_clusters(K kernel, PairCtx c, int64_t i0, int64_t i1, hipStre
 // part: PAIR_PART_CHARGED, PAIR_PART_SHELL (nothing left to do: the shell is
 // fused into the charged part) or PAIR_PART_NEUTRAL.
 template <bool F32, bool COUNT, bool GHOST>
-static void launch_part(PairCtx c, int64_t nq, int part, hipStream_t st) {
+static void launch_part(PairCtx c, int part, hipStream_t st) {
   const PairParams pp = c.pp;
   if (part == PAIR_PART_CHARGED) {
-    if (pp.rbl && pp.shell_charged) launch_clusters(k_pair_rbl<F32, COUNT, GHOST, true>, c, 0, nq, st);
-    else if (pp.rbl) launch_clusters(k_pair_rbl<F32, COUNT, GHOST, false>, c, 0, nq, st);
-    else launch_threads(k_pair_plain<F32, COUNT, 1, GHOST>, c, 0, nq, st);
+    c.charged = 1;
+    if (pp.rbl && pp.shell_charged) launch_clusters(k_pair_rbl<F32, COUNT, GHOST, true>, c, st);
+    else if (pp.rbl) launch_clusters(k_pair_rbl<F32, COUNT, GHOST, false>, c, st);
+    else launch_threads(k_pair_plain<F32, COUNT, 1, GHOST>, c, st);
   } else if (part == PAIR_PART_NEUTRAL) {
-    if (pp.rbl && pp.rlj2 > pp.rcore2 && pp.do_lj)
-      launch_clusters(k_pair_rbl<F32, COUNT, GHOST, false>, c, nq, c.n, st);
-    else launch_threads(k_pair_plain<F32, COUNT, 0, GHOST>, c, nq, c.n, st);
+    c.charged = 0;
+    if (pp.rbl && pp.rlj2 > pp.rcore2 && pp.do_lj) launch_clusters(k_pair_rbl<F32, COUNT, GHOST, false>, c, st);
+    else launch_threads(k_pair_plain<F32, COUNT, 0, GHOST>, c, st);
   }
 }
 
 template <bool GHOST>
-static void launch_prec(int prec, PairCtx c, int64_t nq, int part, hipStream_t st) {
+static void launch_prec(int prec, PairCtx c, int part, hipStream_t st) {
   if (prec == RBE_FP32C) {
-    if (c.counters) launch_part<true, true, GHOST>(c, nq, part, st);
-    else launch_part<true, false, GHOST>(c, nq, part, st);
+    if (c.counters) launch_part<true, true, GHOST>(c, part, st);
+    else launch_part<true, false, GHOST>(c, part, st);
   } else {
-    if (c.counters) launch_part<false, true, GHOST>(c, nq, part, st);
-    else launch_part<false, false, GHOST>(c, nq, part, st);
+    if (c.counters) launch_part<false, true, GHOST>(c, part, st);
+    else launch_part<false, false, GHOST>(c, part, st);
   }
 }
 
-void launch_pair(int prec, int part, const PairParams &pp, int64_t n, int64_t nq, const Sorted &s,
+void launch_pair(int prec, int part, const PairParams &pp, int64_t n, const int32_t *nq, const Sorted &s,
                  const int32_t *cell_start, const int32_t *inv_id, const GhostBuffers *gb, double *fx, double *fy,
                  double *fz, PairCounters cnt, hipStream_t st) {
   if (n <= 0) return;
@@ -401,13 +409,13 @@ void launch_pair(int prec, int part, const PairParams &pp, int64_t n, int64_t nq
   c.fz = fz;
   c.counters = cnt.c;
   c.n = n;
-  c.i0 = 0;
-  c.i1 = n;
+  c.nq_ptr = nq;
+  c.charged = part == PAIR_PART_CHARGED;
   c.gxq = gb ? gb->xq : nullptr;
   c.gid = gb ? gb->id : nullptr;
   c.gcell_start = gb ? gb->cell_start : nullptr;
-  if (gb) launch_prec<true>(prec, c, nq, part, st);
-  else launch_prec<false>(prec, c, nq, part, st);
+  if (gb) launch_prec<true>(prec, c, part, st);
+  else launch_prec<false>(prec, c, part, st);
 }
 
 }  // namespace rbe

@@ -197,7 +197,9 @@ def test_batched_rejects_caller_modes_and_charge_imbalance():
     i = int(np.nonzero(q[off[1]:] > 0)[0][0]) + off[1]
     q[i] = 0.0  # replica 1 no longer neutral
     st.q.copy_(torch.as_tensor(q))
+    ctx.sync_check()
+    ctx.forces(st, None, None, 0)  # checked on the device: reported by the next sync_check
     with pytest.raises(rbe.RbeError) as e:
-        ctx.forces(st, None, None, 0)
+        ctx.sync_check()
     assert e.value.code == rbe.RBE_ENONNEUTRAL and "replica 1" in str(e.value)
     ctx.close()

@@ -265,6 +265,8 @@ def test_step_fp64_plain3k_trajectory():
 # errors reported through the ABI
 # ---------------------------------------------------------------------------
 def test_non_neutral_rejected(plain3k):
+    """Neutrality (Eq. 1) and finite charges are checked on the device (no
+    call waits for them): rbe_sync_check reports the flag."""
     p, s, m, w, _ = plain3k
     s2 = dict(s)
     s2["q"] = s["q"].copy()
@@ -272,6 +274,20 @@ def test_non_neutral_rejected(plain3k):
     with pytest.raises(rbe.RbeError) as e:
         gpu_forces(p, s2, m=m, w=w)
     assert e.value.code == rbe.RBE_ENONNEUTRAL
+    params = rbe.params_from_preset(p)
+    ctx = rbe.Context(params, p["n"])
+    st = to_device(s2)
+    ctx.step(st, 2, 1)
+    with pytest.raises(rbe.RbeError) as e:
+        ctx.sync_check()
+    assert e.value.code == rbe.RBE_ENONNEUTRAL
+    st = to_device(s)
+    st.q[7] = float("nan")
+    ctx.forces(st, None, None, 0)
+    with pytest.raises(rbe.RbeError) as e:
+        ctx.sync_check()
+    assert e.value.code == rbe.RBE_ENONFINITE
+    ctx.close()
 
 
 def test_capacity_and_nonfinite_reported(plain3k):
