@@ -102,6 +102,14 @@ def num_threads() -> int:
     return _load().orc_num_threads()
 
 
+def set_num_threads(k: int) -> None:
+    """Threads of the oracle's parallel loops (the results do not depend on it)."""
+    lib = _load()
+    lib.orc_set_num_threads.argtypes = [ctypes.c_int]
+    lib.orc_set_num_threads.restype = None
+    lib.orc_set_num_threads(int(k))
+
+
 def make_sys(L, alpha, r_coul, r_lj, r_core=0.0, p_shell=0, eps=1.0, sigma=1.0, kc=1.0, shell_charged=0) -> OrcSys:
     s = OrcSys()
     Lv = np.broadcast_to(np.asarray(L, np.float64), (3,))

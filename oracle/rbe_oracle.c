@@ -43,6 +43,16 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Threads of the parallel loops that follow (timing only: every loop here
+   partitions its work deterministically, so the results do not change). */
+void orc_set_num_threads(int k) {
+#ifdef _OPENMP
+  if (k > 0) omp_set_num_threads(k);
+#else
+  (void)k;
+#endif
+}
+
 /* ===================================================================== */
 /* Counter-based generators                                               */
 /* ===================================================================== */

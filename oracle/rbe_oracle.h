@@ -103,4 +103,5 @@ void orc_drift_wrap(int64_t n, double dt, const double L[3], const double *vx, c
                     double *x, double *y, double *z);
 
 int orc_num_threads(void);
+void orc_set_num_threads(int k);
 #endif

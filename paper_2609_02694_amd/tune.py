@@ -17,7 +17,7 @@ import json
 import math
 import os
 
-from . import Context, Particles, params_from_preset
+from . import TERM_ALL, Context, Particles, params_from_preset
 
 BATCH_EDGES = (2.0, 2.5, 3.0, 3.5, 4.0, 6.0)
 
@@ -86,13 +86,13 @@ def default_ncell(preset: dict) -> int:
     return max(1, int(math.floor(preset["L"] / h)))
 
 
-def batch_params(reps, edge: float, prec: int, xsplit: int = 1):
+def batch_params(reps, edge: float, prec: int, xsplit: int = 1, terms: int = TERM_ALL):
     """Per-replica params of a batch with cells of edge about `edge` along y and
     z (at least one per axis) and `xsplit` times as many along x."""
     out = []
     for p, _ in reps:
         n = max(1, int(p["L"] // edge))
-        out.append(params_from_preset(p, prec=prec, ncell=(xsplit * n, n, n), seed=p["stream_seed"]))
+        out.append(params_from_preset(p, prec=prec, terms=terms, ncell=(xsplit * n, n, n), seed=p["stream_seed"]))
     return out
 
 

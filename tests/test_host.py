@@ -37,14 +37,16 @@ def test_roofline_hbm_kernel_arithmetic():
     assert r["work_per_launch"] == 120 * 1_000_000
 
 
-def test_roofline_pair_kernel_counts_flops_of_pairs_and_shell_members():
+def test_roofline_pair_kernel_counts_flops_of_in_cutoff_pairs_only():
     b = load_bench()
     p = dict(n=1000, P=10)
     kernels = {"pair_charged": dict(avg_us=1.0, total_ms=1.0)}
     cnt = {"pair_charged": (10, 20, 5000, 30)}  # coul pairs, lj pairs, candidates, shell members
     r = b.kernel_roofline("pair_charged", kernels, cnt, 0, p, 0)
-    work = b.FLOPS_COUL_PAIR * 10 + b.FLOPS_LJ_PAIR * 20 + b.OPS_SHELL_MEMBER * 30
-    assert r["work_per_launch"] == work  # candidates are overhead, not work
+    # candidates outside the cutoffs and the shell's walk and ranking are overhead, not work
+    assert r["work_per_launch"] == b.FLOPS_COUL_PAIR * 10 + b.FLOPS_LJ_PAIR * 20
+    assert r["shell_members_per_s"] == pytest.approx(30 / 1e-6)  # reported apart
+    assert r["achieved"] == pytest.approx((27 * 10 + 22 * 20) / 1e-6 / 1e12)
     assert r["peak"] == b.PEAK_FP64_TFLOPS
     r32 = b.kernel_roofline("pair_charged", kernels, cnt, 0, p, 1)
     assert r32["peak"] == b.PEAK_FP32_TFLOPS
@@ -65,7 +67,7 @@ def test_dominant_kernel_is_the_largest_total_time():
     b = load_bench()
     p = dict(n=100, P=4)
     kernels = {"kick": dict(avg_us=1.0, total_ms=5.0), "kick_drift": dict(avg_us=2.0, total_ms=2.0)}
-    dom, every = b.roofline(kernels, None, 0, p, 0, 1)
+    dom, every = b.roofline(kernels, None, 0, p, 0)
     assert dom["kernel"] == "kick" and set(every) == {"kick", "kick_drift"}
     assert dom["traffic"] is None  # no workload named: no counter data
 
@@ -152,8 +154,38 @@ def test_roofline_reports_counted_hbm_rate(tmp_path, monkeypatch):
     (prof / "traffic.json").write_text(json.dumps(rec))
     monkeypatch.setattr(b, "ROOT", str(tmp_path))
     kernels = {"kick": dict(avg_us=1000.0, total_ms=5.0), "kick_drift": dict(avg_us=2.0, total_ms=2.0)}
-    dom, every = b.roofline(kernels, None, 0, dict(n=100, P=4), 0, 1, workload="w", grid=[4, 2, 2])
+    dom, every = b.roofline(kernels, None, 0, dict(n=100, P=4), 0, workload="w", grid=[4, 2, 2])
     # 4 GB per launch over 1 ms: 4000 GB/s, half the HBM peak
     assert dom["kernel"] == "kick" and dom["traffic"] == 4.0e9
     assert dom["hbm_gbps"] == pytest.approx(4000.0) and dom["hbm_frac"] == pytest.approx(0.5)
     assert "hbm_gbps" not in every["kick_drift"]  # not counted
+
+
+def test_repeat_stats_median_min_max():
+    b = load_bench()
+    r = b.repeat_stats(1000, 10, [0.05, 0.01, 0.02, 0.03, 0.04])
+    assert r["repeats"] == 5
+    assert r["median_ms"] == pytest.approx(3.0) and r["min_ms"] == pytest.approx(1.0)
+    assert r["max_ms"] == pytest.approx(5.0)
+    assert r["particle_steps_per_s"] == pytest.approx(1000 / 3.0e-3)
+
+
+def test_sampled_rows_cover_charged_neutral_faces_and_ends():
+    import numpy as np
+    b = load_bench()
+    n = 5000
+    rng = np.random.default_rng(0)
+    L = 20.0
+    s = dict(x=rng.random(n) * L, q=np.where(np.arange(n) < 500, 1.0, 0.0), L=np.array([L, L, L]))
+    rows = b.sampled_rows(s, 64)
+    assert len(rows) == len(set(rows.tolist()))
+    assert (s["q"][rows] != 0).any() and (s["q"][rows] == 0).any()
+    assert n - 1 in rows and 0 in rows
+    assert (np.minimum(s["x"][rows], L - s["x"][rows]) < 0.05).sum() >= 8
+
+
+def test_cpu_info_reports_model_and_threads():
+    b = load_bench()
+    info = b.cpu_info()
+    assert info["oracle_threads"] >= 1 and info["logical_cpus"] >= 1
+    assert info["model"]
