@@ -78,7 +78,6 @@ struct rbe_ctx {
   double *epart = nullptr;   // energy partial sums
   double *nh_part = nullptr, *nh_scale = nullptr;  // thermostat: |v|^2 partials, pending velocity scaling
   int *err = nullptr;
-  int32_t *nq_dev = nullptr;
   double *qstats = nullptr;  // [sum q, sum |q|]
   unsigned long long *counters = nullptr;
   bool counting = false;
@@ -307,34 +306,17 @@ static Grid make_grid(const rbe_params &p, const int nc[3]) {
   return g;
 }
 
-// ---------------------------------------------------------------------------
-// create / destroy
-// ---------------------------------------------------------------------------
-extern "C" int rbe_create(rbe_ctx **out, const rbe_params *p, int64_t n_max, int device) {
-  if (!out) return create_fail(RBE_EINVAL, "out is NULL");
-  *out = nullptr;
-  if (!p) return create_fail(RBE_EINVAL, "params is NULL");
-  if (n_max < 1 || n_max > (int64_t)0x7FFFFFFF) return create_fail(RBE_EINVAL, "n_max must be in [1, 2^31)");
-  if (p && p->ghost_width > 0 && 8 * n_max >= (int64_t)0x7FFFFFFF)
-    return create_fail(RBE_EINVAL, "with a ghost shell n_max must be below 2^28 (image offsets are 32-bit)");
-  std::string why;
-  int rc = validate_params(p, &why);
-  if (rc != RBE_OK) return create_fail(rc, why.c_str());
-  int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
-    return create_fail(RBE_EDEVICE, "no such HIP device");
-  if (hipSetDevice(device) != hipSuccess) return create_fail(RBE_EDEVICE, "hipSetDevice failed");
-
-  rbe_ctx *c = new rbe_ctx();
-  c->device = device;
+// Parameters, cell grid (with ghost layers when the shell is on) and pair
+// constants of a single-system context (host only).
+static int ctx_geometry(rbe_ctx *c, const rbe_params *p, int64_t n_max, std::string *why) {
   c->p = *p;
   if (c->p.terms == 0) c->p.terms = RBE_TERM_ALL;
   c->n_max = n_max;
   int nc[3];
   choose_grid(&c->p, nc);
   if ((int64_t)nc[0] * nc[1] * nc[2] >= (1LL << 29)) {
-    delete c;
-    return create_fail(RBE_EINVAL, "cell grid too large");
+    *why = "cell grid too large";
+    return RBE_EINVAL;
   }
   Grid &g = c->g;
   g.nx = nc[0];
@@ -362,10 +344,39 @@ extern "C" int rbe_create(rbe_ctx **out, const rbe_params *p, int64_t n_max, int
   g.pnz = g.nz + 2 * g.goff[2];
   g.pncell = g.pnx * g.pny * g.pnz;
   if (p->ghost_width > 0 && (int64_t)g.pnx * g.pny * g.pnz >= (1LL << 29)) {
-    delete c;
-    return create_fail(RBE_EINVAL, "padded cell grid too large");
+    *why = "padded cell grid too large";
+    return RBE_EINVAL;
   }
   c->pp.g = g;
+  return RBE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// create / destroy
+// ---------------------------------------------------------------------------
+extern "C" int rbe_create(rbe_ctx **out, const rbe_params *p, int64_t n_max, int device) {
+  if (!out) return create_fail(RBE_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!p) return create_fail(RBE_EINVAL, "params is NULL");
+  if (n_max < 1 || n_max > (int64_t)0x7FFFFFFF) return create_fail(RBE_EINVAL, "n_max must be in [1, 2^31)");
+  if (p && p->ghost_width > 0 && 8 * n_max >= (int64_t)0x7FFFFFFF)
+    return create_fail(RBE_EINVAL, "with a ghost shell n_max must be below 2^28 (image offsets are 32-bit)");
+  std::string why;
+  int rc = validate_params(p, &why);
+  if (rc != RBE_OK) return create_fail(rc, why.c_str());
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return create_fail(RBE_EDEVICE, "no such HIP device");
+  if (hipSetDevice(device) != hipSuccess) return create_fail(RBE_EDEVICE, "hipSetDevice failed");
+
+  rbe_ctx *c = new rbe_ctx();
+  c->device = device;
+  rc = ctx_geometry(c, p, n_max, &why);
+  if (rc != RBE_OK) {
+    delete c;
+    return create_fail(rc, why.c_str());
+  }
+  const Grid &g = c->g;
 
   // mode tables
   build_mode_table(p->L, p->alpha, &c->mt, nullptr);
@@ -419,7 +430,6 @@ extern "C" int rbe_create(rbe_ctx **out, const rbe_params *p, int64_t n_max, int
   c->nh_part = b.alloc<double>(nh_part_len());
   c->nh_scale = b.alloc<double>(1);
   c->err = b.alloc<int>(1);
-  c->nq_dev = b.alloc<int32_t>(1);
   c->qstats = b.alloc<double>(2);
   c->counters = b.alloc<unsigned long long>(12);
   if (p->ghost_width > 0) {
@@ -1032,16 +1042,11 @@ static int batch_step(rbe_ctx *c, rbe_state *s, int32_t nsteps, uint64_t first_e
   return RBE_OK;
 }
 
-extern "C" int rbe_forces(rbe_ctx *c, const rbe_state *s, const int32_t *m, const double *w, uint64_t eval,
-                          double *rho_out, void *stream) {
-  if (!c) return RBE_EINVAL;
-  if (!state_ok(s, false)) return c->fail(RBE_EINVAL, "state has a null array");
-  if (s->n < 1 || s->n > c->n_max)
-    return c->fail(RBE_ERANGE, "n = %lld outside [1, n_max = %lld]", (long long)s->n, (long long)c->n_max);
-  if ((m == nullptr) != (w == nullptr)) return c->fail(RBE_EINVAL, "m and w must both be given or both be NULL");
-  HIP_TRY(c, hipSetDevice(c->device));
-  hipStream_t st = (hipStream_t)stream;
-  if (c->batched()) return batch_forces(c, s, m, w, eval, rho_out, st);
+// One force evaluation of a single-system context on the state as given:
+// charge checks, binning, sorted records, near field and Fourier part, Eq. 12,
+// forces scattered back to the caller's order.
+static int forces_body(rbe_ctx *c, const rbe_state *s, const int32_t *m, const double *w, uint64_t eval,
+                       double *rho_out, hipStream_t st) {
   const int64_t n = s->n;
   launch_charge_check(c, n, s->q, st);
   {
@@ -1059,6 +1064,19 @@ extern "C" int rbe_forces(rbe_ctx *c, const rbe_state *s, const int32_t *m, cons
   launch_scatter_forces(n, c->perm, o.fx, o.fy, o.fz, s->fx, s->fy, s->fz, st);
   HIP_TRY(c, hipGetLastError());
   return RBE_OK;
+}
+
+extern "C" int rbe_forces(rbe_ctx *c, const rbe_state *s, const int32_t *m, const double *w, uint64_t eval,
+                          double *rho_out, void *stream) {
+  if (!c) return RBE_EINVAL;
+  if (!state_ok(s, false)) return c->fail(RBE_EINVAL, "state has a null array");
+  if (s->n < 1 || s->n > c->n_max)
+    return c->fail(RBE_ERANGE, "n = %lld outside [1, n_max = %lld]", (long long)s->n, (long long)c->n_max);
+  if ((m == nullptr) != (w == nullptr)) return c->fail(RBE_EINVAL, "m and w must both be given or both be NULL");
+  HIP_TRY(c, hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  if (c->batched()) return batch_forces(c, s, m, w, eval, rho_out, st);
+  return forces_body(c, s, m, w, eval, rho_out, st);
 }
 
 extern "C" int rbe_energy(rbe_ctx *c, const rbe_state *s, const int32_t *m, const double *w, uint64_t eval,
@@ -1312,3 +1330,4 @@ extern "C" int rbe_get_timing(rbe_ctx *c, double *ms_out, int64_t *launches_out,
   }
   return RBE_OK;
 }
+

@@ -14,6 +14,23 @@ def rel_err(a, b):
     return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
 
 
+def max_row_err(a, b):
+    """Largest per-particle error |a_i - b_i| (Euclidean over components) in
+    units of the RMS particle force of b: one bad row cannot hide in the RMS."""
+    a = np.asarray(a, np.float64).reshape(-1, 3)
+    b = np.asarray(b, np.float64).reshape(-1, 3)
+    frms = np.sqrt((b ** 2).sum() / len(b))
+    return float(np.sqrt(((a - b) ** 2).sum(axis=1)).max() / (frms if frms > 0 else 1.0))
+
+
+# Per-row bounds (in units of the RMS particle force) beside the RMS bounds:
+# FP64 rows agree to about 1e-13 of the RMS force; FP32C rows carry the
+# single-precision rounding of up to ~100 pair terms scaled by the largest
+# forces (a few times the RMS), measured up to a few 1e-6.
+ROW64 = 1e-10
+ROW32 = 2e-4
+
+
 def system(name, n=None, **over):
     p = gen.preset(name, n=n, **over)
     return p, gen.make_system(p)

@@ -169,10 +169,13 @@ def test_batched_trajectory_fp64_against_oracle():
         gx = np.stack([g["x"], g["y"], g["z"]], axis=1)
         d = np.abs(gx - rr)
         d = np.minimum(d, p["L"] - d)  # periodic distance
-        assert d.max() < 1e-11, (r, d.max())
         gv = np.stack([g["vx"], g["vy"], g["vz"]], axis=1)
-        assert rel_err(gv, v) < 1e-11, r
-        assert rel_err(g["F"], F) < 1e-10, r
+        ex, ev_, ef = d.max() / p["L"], rel_err(gv, v), rel_err(g["F"], F)
+        print(f"replica {r} (n={p['n']}): |dx|/L {ex:.2e}, v {ev_:.2e}, F {ef:.2e}")
+        # the single-system bounds (the FP64 path's 1e-12)
+        assert ex < 1e-12, r
+        assert ev_ < 1e-12, r
+        assert ef < 1e-12, r
 
 
 def test_batched_graph_replays_are_deterministic():

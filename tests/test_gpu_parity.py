@@ -9,7 +9,7 @@ import pytest
 
 import gen
 import oracle
-from gpu_common import gpu_forces, oracle_forces, rel_err, system, to_device
+from gpu_common import ROW32, ROW64, gpu_forces, max_row_err, oracle_forces, rel_err, system, to_device
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -108,8 +108,9 @@ def test_forces_fp64_plain3k_total_and_rho(plain3k):
     F, re, im = gpu_forces(p, s, m=m, w=w, want_rho=True)
     assert rel_err(re, ref["rho_re"]) < TOL64 and rel_err(im, ref["rho_im"]) < TOL64
     e = rel_err(F, ref["F"])
-    print(f"plain3k FP64 total rel err {e:.3e}")
+    print(f"plain3k FP64 total rel err {e:.3e}, max row {max_row_err(F, ref['F']):.3e}")
     assert e < TOL64
+    assert max_row_err(F, ref["F"]) < ROW64
 
 
 @pytest.mark.parametrize("term,key", [(rbe.TERM_LJ, "lj"), (rbe.TERM_COUL_REAL, "coul"), (rbe.TERM_FOURIER, "fourier")])
@@ -119,6 +120,7 @@ def test_forces_fp64_plain3k_each_term(plain3k, term, key):
     e = rel_err(F, ref[key])
     print(f"plain3k FP64 {key} rel err {e:.3e}")
     assert e < TOL64
+    assert max_row_err(F, ref[key]) < ROW64
 
 
 @pytest.mark.parametrize("ncell", [(3, 3, 3), (7, 7, 7), (13, 11, 12)])
@@ -151,8 +153,9 @@ def test_forces_fp64_rbl_electrolyte_20k():
         ref = oracle_forces(p, s, m, w, ev=ev, cells=False)
         F = gpu_forces(p, s, m=m, w=w, ev=ev)
         e = rel_err(F, ref["F"])
-        print(f"electrolyte20k FP64 ev={ev} rel err {e:.3e}")
+        print(f"electrolyte20k FP64 ev={ev} rel err {e:.3e}, max row {max_row_err(F, ref['F']):.3e}")
         assert e < TOL64
+        assert max_row_err(F, ref["F"]) < ROW64
         assert np.abs(F.sum(axis=0)).max() < 1e-8 * np.abs(F).sum() / len(F)  # Eq. 12 + zero net Fourier force
 
 
@@ -206,8 +209,9 @@ def test_forces_fp32c_plain3k(plain3k):
                       (rbe.TERM_ALL, "F")):
         F = gpu_forces(p, s, prec=rbe.FP32C, terms=term, m=m, w=w)
         e = rel_err(F, ref[key])
-        print(f"plain3k FP32C {key} rel err {e:.3e}")
+        print(f"plain3k FP32C {key} rel err {e:.3e}, max row {max_row_err(F, ref[key]):.3e}")
         assert e < TOL32
+        assert max_row_err(F, ref[key]) < ROW32
 
 
 def test_forces_fp32c_rbl_electrolyte_20k():
@@ -216,8 +220,9 @@ def test_forces_fp32c_rbl_electrolyte_20k():
     ref = oracle_forces(p, s, m, w, ev=2, cells=False)
     F = gpu_forces(p, s, prec=rbe.FP32C, m=m, w=w, ev=2)
     e = rel_err(F, ref["F"])
-    print(f"electrolyte20k FP32C rel err {e:.3e}")
+    print(f"electrolyte20k FP32C rel err {e:.3e}, max row {max_row_err(F, ref['F']):.3e}")
     assert e < TOL32
+    assert max_row_err(F, ref["F"]) < ROW32
 
 
 # ---------------------------------------------------------------------------
