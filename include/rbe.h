@@ -246,6 +246,29 @@ int rbe_energy(rbe_ctx *ctx, const rbe_state *s, const int32_t *m, const double 
    a batched context. */
 int rbe_step(rbe_ctx *ctx, rbe_state *s, int32_t nsteps, uint64_t first_eval, void *stream);
 
+/* rbe_forces for callers that cannot allocate device memory (code under HIP
+   graph capture, tight serving loops, harnesses that forbid hipMalloc): no
+   context, no hipMalloc or hipFree, no allocating library call. The scratch
+   lives in one file-scope device array of RBE_NOALLOC_SCRATCH_BYTES per GPU
+   (held until the process ends), shared by every call on that GPU: calls that
+   overlap on one GPU race, so serialize them (one stream, or events).
+   Computes the same force as rbe_forces on a context created with *p, on the
+   current HIP device, for the state as given (never reordered): writes
+   s->fx, fy, fz; rho_out (device, 2*P doubles) may be NULL.
+   Limits, rejected with RBE_ERANGE before any launch: n <= RBE_NOALLOC_MAX_N,
+   P <= RBE_NOALLOC_MAX_P, 2 * (cells of the grid) <= RBE_NOALLOC_MAX_KEYS; the
+   ghost shell is not available (RBE_EINVAL). m and w (the mode sample,
+   device) are required. Device-side checks (neutrality, finite values, ids)
+   are not kept for a later rbe_sync_check: status_out (device int32, may be
+   NULL) receives the rbe_status they give once the stream reaches the end of
+   the call. Host errors are reported by rbe_last_error(NULL). */
+#define RBE_NOALLOC_MAX_N 32768
+#define RBE_NOALLOC_MAX_P 1024
+#define RBE_NOALLOC_MAX_KEYS 131072
+#define RBE_NOALLOC_SCRATCH_BYTES (8 << 20)
+int rbe_forces_noalloc(const rbe_params *p /* host */, const rbe_state *s, const int32_t *m, const double *w,
+                       uint64_t eval, double *rho_out, int32_t *status_out, void *stream);
+
 /* Synchronize `stream` and report device-side errors recorded since the last
    check: non-neutral charges (RBE_ENONNEUTRAL; a batched context names the
    first replica at fault), non-finite charges, velocities or forces

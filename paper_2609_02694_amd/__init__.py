@@ -26,7 +26,10 @@ MAX_SHELL_BATCH = 32
 
 EXPORTED = ["rbe_create", "rbe_create_batch", "rbe_destroy", "rbe_last_error", "rbe_build_cells", "rbe_sample_k",
             "rbe_forces", "rbe_energy", "rbe_step", "rbe_sync_check", "rbe_set_counting", "rbe_get_counters", "rbe_set_timing",
-            "rbe_get_timing"]
+            "rbe_get_timing", "rbe_forces_noalloc"]
+NOALLOC_MAX_N = 32768
+NOALLOC_MAX_P = 1024
+NOALLOC_MAX_KEYS = 131072
 ENERGY_NAMES = ["coul_real", "lj", "fourier", "self", "kinetic", "w_coul_real", "w_lj", "w_fourier"]
 TIMING_KINDS = ["bin", "reorder", "pair_neutral", "mean", "sample", "rho_partial", "rho_final", "gather",
                 "kick_drift", "kick", "pair_charged", "pair_shell", "ghost", "batch"]
@@ -93,6 +96,7 @@ def load():
         "rbe_get_counters": [vp, ctypes.POINTER(i64), vp],
         "rbe_set_timing": [vp, ctypes.c_int],
         "rbe_get_timing": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), vp],
+        "rbe_forces_noalloc": [P, ctypes.POINTER(State), vp, vp, u64, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -216,6 +220,19 @@ def sample_k(params: Params, ev: int, on_device=False, stream=None):
                           0, None)
     _check(lib, None, rc)
     return m.reshape(3, P), w
+
+
+def forces_noalloc(params: Params, st: "Particles", m, w, ev: int = 0, rho_out=None, status_out=None,
+                   stream=None):
+    """rbe_forces without a context or any device allocation (the library's
+    file-scope scratch array; see include/rbe.h for the limits). m, w: the
+    mode sample (device). status_out: optional device int32 tensor that
+    receives the status of the device-side checks."""
+    lib = load()
+    s = st.as_struct()
+    rc = lib.rbe_forces_noalloc(ctypes.byref(params), ctypes.byref(s), _ptr(m), _ptr(w), ev, _ptr(rho_out),
+                                _ptr(status_out), _stream(stream))
+    _check(lib, None, rc)
 
 
 class Context:

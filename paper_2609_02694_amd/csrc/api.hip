@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1331,3 +1332,140 @@ extern "C" int rbe_get_timing(rbe_ctx *c, double *ms_out, int64_t *launches_out,
   return RBE_OK;
 }
 
+// ---------------------------------------------------------------------------
+// rbe_forces without allocation: scratch in a file-scope device array
+// ---------------------------------------------------------------------------
+// Limits of the array (include/rbe.h): particles, keys of the cell grid (two
+// species blocks), modes; structure-factor chunks at most kNoallocChunks.
+constexpr int64_t kNoallocMaxN = RBE_NOALLOC_MAX_N;
+constexpr int64_t kNoallocMaxKeys = RBE_NOALLOC_MAX_KEYS;
+constexpr int kNoallocMaxP = RBE_NOALLOC_MAX_P;
+constexpr int kNoallocChunks = 64;
+constexpr size_t kNoallocBytes = (size_t)RBE_NOALLOC_SCRATCH_BYTES;
+
+// The scratch of every rbe_forces_noalloc call on a device (each device holds
+// its own copy until the process ends). Host code never uses this name as an
+// address: the device address comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+unsigned char *g_noalloc_ptr[kMaxDevices] = {};
+
+// Bump carving of the scratch: every region starts on a 256-byte boundary.
+struct Carve {
+  unsigned char *base;
+  size_t used, cap;
+  bool ok = true;
+  template <class T>
+  T *take(int64_t count) {
+    const size_t off = (used + 255) & ~(size_t)255;
+    const size_t bytes = (size_t)(count < 1 ? 1 : count) * sizeof(T);
+    if (off + bytes > cap) {
+      ok = false;
+      return nullptr;
+    }
+    used = off + bytes;
+    return (T *)(base + off);
+  }
+};
+}  // namespace
+
+// Device address of this device's scratch, resolved once per device with the
+// device current; the FP64 turn table is written once at the start of it (no
+// call overwrites that region).
+static unsigned char *noalloc_scratch(int device, std::string *why) {
+  if (device < 0 || device >= kMaxDevices) {
+    *why = "device index out of range";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (g_noalloc_ptr[device]) return g_noalloc_ptr[device];
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    *why = std::string("hipGetSymbolAddress of the scratch array failed: ") + hipGetErrorString(e);
+    return nullptr;
+  }
+  static double2 turn_host[kTurnTableEntries];
+  static std::once_flag turn_once;
+  std::call_once(turn_once, [] { fill_turn_table(turn_host, kTurnTableEntries); });
+  if (hipMemcpy(ptr, turn_host, sizeof turn_host, hipMemcpyHostToDevice) != hipSuccess) {
+    *why = "copy of the turn table into the scratch array failed";
+    return nullptr;
+  }
+  g_noalloc_ptr[device] = (unsigned char *)ptr;
+  return g_noalloc_ptr[device];
+}
+
+// status_out[0] = the rbe_status of the device-side checks of this call.
+__global__ void k_noalloc_status(const int *err, int32_t *status_out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int f = *err;
+  int st = RBE_OK;
+  if (f & kErrNonNeutral) st = RBE_ENONNEUTRAL;
+  if (f & kErrGhostOverflow) st = RBE_ERANGE;
+  if (f & kErrBadId) st = RBE_ERANGE;
+  if (f & kErrNonFinite) st = RBE_ENONFINITE;
+  *status_out = st;
+}
+
+extern "C" int rbe_forces_noalloc(const rbe_params *p, const rbe_state *s, const int32_t *m, const double *w,
+                                  uint64_t eval, double *rho_out, int32_t *status_out, void *stream) {
+  if (!p) return create_fail(RBE_EINVAL, "params is NULL");
+  if (!state_ok(s, false)) return create_fail(RBE_EINVAL, "state has a null array");
+  if (!m || !w) return create_fail(RBE_EINVAL, "rbe_forces_noalloc needs the mode sample m, w");
+  if (s->n < 1 || s->n > kNoallocMaxN) return create_fail(RBE_ERANGE, "n outside [1, RBE_NOALLOC_MAX_N]");
+  if (p->P > kNoallocMaxP) return create_fail(RBE_ERANGE, "P exceeds RBE_NOALLOC_MAX_P");
+  if (p->ghost_width > 0) return create_fail(RBE_EINVAL, "rbe_forces_noalloc has no ghost shell");
+  std::string why;
+  int rc = validate_params(p, &why);
+  if (rc != RBE_OK) return create_fail(rc, why.c_str());
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return create_fail(RBE_EDEVICE, "hipGetDevice failed");
+  unsigned char *base = noalloc_scratch(device, &why);
+  if (!base) return create_fail(RBE_EDEVICE, why.c_str());
+
+  rbe_ctx c;  // host-side description only; every device region is carved from the scratch
+  c.device = device;
+  rc = ctx_geometry(&c, p, s->n, &why);
+  if (rc != RBE_OK) return create_fail(rc, why.c_str());
+  const int64_t n = s->n;
+  const int64_t nkeys = 2 * (int64_t)c.g.ncell;
+  if (nkeys > kNoallocMaxKeys) return create_fail(RBE_ERANGE, "the cell grid exceeds RBE_NOALLOC_MAX_KEYS keys");
+  const int P = c.p.P;
+  Carve cv{base, 0, kNoallocBytes};
+  c.fb.turn_tab = cv.take<double2>(kTurnTableEntries);  // written once per device
+  c.bb.key = cv.take<int32_t>(n);
+  c.bb.slot = cv.take<int32_t>(n);
+  c.bb.tmp = cv.take<int32_t>(n);
+  c.bb.count = cv.take<int32_t>(nkeys);
+  c.bb.scan_tmp = cv.take<int32_t>(scan_tiles(nkeys));
+  c.cell_start = cv.take<int32_t>(nkeys + 1);
+  c.perm = cv.take<int32_t>(n);
+  c.inv_id = cv.take<int32_t>(n);
+  c.srt.xq = cv.take<double4>(n + kScanPad);
+  c.srt.sq = cv.take<double4>(n);
+  c.srt.id = cv.take<int32_t>(n + kScanPad);
+  c.ws[1].fx = cv.take<double>(n);
+  c.ws[1].fy = cv.take<double>(n);
+  c.ws[1].fz = cv.take<double>(n);
+  c.fb.nchunk_max = kNoallocChunks;
+  c.fb.mkd = cv.take<double>(3 * (int64_t)P);
+  c.fb.part = cv.take<double2>((int64_t)kNoallocChunks * P);
+  c.fb.rho = cv.take<double>(2 * (int64_t)P);
+  c.fb.modes = cv.take<GatherMode>(P);
+  c.mean_part = cv.take<double>(3 * (int64_t)mean_blocks(n) + 3);
+  c.mean = cv.take<double>(3);
+  c.err = cv.take<int>(1);
+  c.qstats = cv.take<double>(2);
+  if (!cv.ok) return create_fail(RBE_ERANGE, "the problem does not fit the scratch array");
+  hipStream_t st = (hipStream_t)stream;
+  launch_fill_i32(c.err, 1, 0, st);  // the array keeps the previous call's flag
+  rc = forces_body(&c, s, m, w, eval, rho_out, st);
+  if (rc != RBE_OK) return create_fail(rc, c.last_error.c_str());
+  if (status_out) k_noalloc_status<<<1, 64, 0, st>>>(c.err, status_out);
+  if (hipGetLastError() != hipSuccess) return create_fail(RBE_EDEVICE, "a launch failed");
+  return RBE_OK;
+}
