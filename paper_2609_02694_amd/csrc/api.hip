@@ -434,30 +434,23 @@ extern "C" int rbe_create(rbe_ctx **out, const rbe_params *p, int64_t n_max, int
   c->qstats = b.alloc<double>(2);
   c->counters = b.alloc<unsigned long long>(12);
   if (p->ghost_width > 0) {
-    // ghost capacity: the expected image count of a uniform fluid with 30 %
-    // headroom (at most 7 images per native); overflow is flagged, not written
+    // ghost capacity: the expected image count of a uniform fluid in the
+    // shell (goff[d] cells thick) with 30 % headroom (at most 7 images per
+    // native); overflow is flagged, and the cells past it are left empty
     double vol = 1.0;
-    for (int d = 0; d < 3; ++d) vol *= 1.0 + 2.0 * p->ghost_width / p->L[d];
+    for (int d = 0; d < 3; ++d) vol *= 1.0 + 2.0 * g.goff[d] * (p->L[d] / (d == 0 ? g.nx : d == 1 ? g.ny : g.nz)) / p->L[d];
     int64_t cap = (int64_t)std::ceil(1.3 * (double)n_max * (vol - 1.0)) + 4096;
     if (cap > 7 * n_max + 4096) cap = 7 * n_max + 4096;
     if (cap + n_max >= (int64_t)0x7FFFFFFF) cap = (int64_t)0x7FFFFFFF - n_max - 1;
     GhostBuffers &gb = c->gb;
     gb.cap = cap;
     const int64_t pkeys = 2 * (int64_t)g.pncell;
-    gb.raw_xq = b.alloc<double4>(cap);
-    gb.raw_id = b.alloc<int32_t>(cap);
     gb.xq = b.alloc<double4>(cap + kScanPad);
     gb.id = b.alloc<int32_t>(cap + kScanPad);
     gb.cell_start = b.alloc<int32_t>(pkeys + 1);
     gb.cell_count = b.alloc<int32_t>(pkeys);
     gb.cell_scan_tmp = b.alloc<int32_t>(scan_tiles(pkeys));
-    gb.flags = b.alloc<int32_t>(n_max + cap);
-    gb.offs = b.alloc<int32_t>(n_max + cap + 1);
-    gb.scan_tmp = b.alloc<int32_t>(scan_tiles(n_max + cap));
     gb.count = b.alloc<int32_t>(1);
-    gb.key = b.alloc<int32_t>(cap);
-    gb.slot = b.alloc<int32_t>(cap);
-    gb.tmp = b.alloc<int32_t>(cap);
     c->ghosts = true;
   }
   if (!b.ok) {
@@ -738,20 +731,42 @@ static int eval_sorted(rbe_ctx *c, int64_t n, const int32_t *m, const double *w,
     const GhostBuffers *gb = nullptr;
     if (c->ghosts) {
       TScope ts(c, RBE_TK_GHOST, st);
-      launch_build_ghosts(c->g, n, c->srt, c->gb, c->err, st);
+      launch_build_ghosts(c->g, n, c->cell_start, c->srt, c->gb, c->err, st);
       gb = &c->gb;
     }
     if (c->counting) launch_fill_i32((int32_t *)c->counters, 24, 0, st);
     auto part_cnt = [&](int part) { return PairCounters{c->counting ? c->counters + 4 * part : nullptr}; };
-    {
-      TScope ts(c, RBE_TK_PAIR_CHARGED, st);
-      launch_pair(c->p.prec, PAIR_PART_CHARGED, pp, n, nq, c->srt, c->cell_start, c->inv_id, gb, fx, fy, fz,
-                  part_cnt(PAIR_PART_CHARGED), st);
-    }
-    {
-      TScope ts(c, RBE_TK_PAIR, st);
-      launch_pair(c->p.prec, PAIR_PART_NEUTRAL, pp, n, nq, c->srt, c->cell_start, c->inv_id, gb, fx, fy, fz,
-                  part_cnt(PAIR_PART_NEUTRAL), st);
+    const bool tiles = lj_tile_applicable(c->p.prec, pp, n);
+    if (!pp.rbl && tiles) {
+      // LJ terms of every particle over LDS-staged cell tiles, then the
+      // screened Coulomb terms of the charged particles added
+      {
+        TScope ts(c, RBE_TK_PAIR, st);
+        launch_lj_tile(c->p.prec, pp, n, 3, c->srt, c->cell_start, gb, fx, fy, fz, part_cnt(PAIR_PART_NEUTRAL).c,
+                       c->err, st);
+      }
+      if (pp.do_coul) {
+        TScope ts(c, RBE_TK_PAIR_CHARGED, st);
+        launch_pair(c->p.prec, PAIR_PART_COULOMB, pp, n, nq, c->srt, c->cell_start, c->inv_id, gb, fx, fy, fz,
+                    part_cnt(PAIR_PART_CHARGED), st);
+      }
+    } else {
+      {
+        TScope ts(c, RBE_TK_PAIR_CHARGED, st);
+        launch_pair(c->p.prec, PAIR_PART_CHARGED, pp, n, nq, c->srt, c->cell_start, c->inv_id, gb, fx, fy, fz,
+                    part_cnt(PAIR_PART_CHARGED), st);
+      }
+      {
+        // neutral particles: LJ over the tiles when all their LJ terms lie in
+        // the core (list on) or always (list off), else the list's cluster walk
+        TScope ts(c, RBE_TK_PAIR, st);
+        if (tiles && pp.rbl && !(pp.rlj2 > pp.rcore2))
+          launch_lj_tile(c->p.prec, pp, n, 2, c->srt, c->cell_start, gb, fx, fy, fz,
+                         part_cnt(PAIR_PART_NEUTRAL).c, c->err, st);
+        else
+          launch_pair(c->p.prec, PAIR_PART_NEUTRAL, pp, n, nq, c->srt, c->cell_start, c->inv_id, gb, fx, fy, fz,
+                      part_cnt(PAIR_PART_NEUTRAL), st);
+      }
     }
     if (pp.rbl) {
       TScope ts(c, RBE_TK_MEAN, st);
@@ -1278,6 +1293,8 @@ extern "C" int rbe_sync_check(rbe_ctx *c, void *stream) {
   if (flag & kErrGhostOverflow) return c->fail(RBE_ERANGE, "the ghost shell exceeded its capacity");
   if (flag & kErrBarrier) return c->fail(RBE_EDEVICE, "a grid barrier of the batched step timed out");
   if (flag & kErrNonNeutral) return c->fail(RBE_ENONNEUTRAL, "the charges do not sum to zero (Eq. 1)%s", who);
+  if (flag & kErrTileOverflow)
+    return c->fail(RBE_ERANGE, "a cell row of the near-field tiles exceeded the LDS staging (density far above the mean)");
   return RBE_OK;
 }
 
@@ -1405,7 +1422,7 @@ __global__ void k_noalloc_status(const int *err, int32_t *status_out) {
   const int f = *err;
   int st = RBE_OK;
   if (f & kErrNonNeutral) st = RBE_ENONNEUTRAL;
-  if (f & kErrGhostOverflow) st = RBE_ERANGE;
+  if (f & (kErrGhostOverflow | kErrTileOverflow)) st = RBE_ERANGE;
   if (f & kErrBadId) st = RBE_ERANGE;
   if (f & kErrNonFinite) st = RBE_ENONFINITE;
   *status_out = st;

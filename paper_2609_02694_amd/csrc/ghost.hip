@@ -1,155 +1,95 @@
 // Ghost shell of a subdomain (Sec. 2.3.2): copies of the native particles
-// that lie within the ghost width w of a face, shifted by one box edge, so
-// the near-field kernels can treat the box as a padded, non-periodic region
-// in which natives and ghosts share one traversal path.
+// near a face, shifted by whole box edges, so the near-field kernels can
+// treat the box as a padded, non-periodic region in which natives and ghosts
+// share one traversal path.
 //
-// The images are those of a staged exchange x, then y, then z in which each
-// stage also forwards the ghosts of the earlier stages (edge and corner
-// images arrive by forwarding). A native within w of a face on a set A of
-// axes (at most one face per axis, since w <= L/2) therefore has one image
-// per non-empty subset of A, shifted by one box edge along each axis of the
-// subset; they are made in one pass: count (2^|A| - 1) per native, scan,
-// write. Only positions, charges and ids are copied (the fields the near
-// field reads); ghosts are never integrated.
-//
-// The ghosts are then sorted by (species, padded cell) with the same stable
-// counting sort as the natives, on the padded grid.
+// The shell is built directly in the padded grid's cell order. A padded cell
+// P outside the native grid holds the images of the natives of its periodic
+// source cell wrap(P), shifted by the box edges that take the source cell to
+// P: the images a staged x, then y, then z exchange delivers into P when each
+// stage forwards the earlier stages' ghosts (edge and corner cells receive
+// their images by forwarding). The natives are already sorted by (species,
+// cell), so the shell is a count per padded cell, a scan and a copy, and its
+// records come out sorted. The layer is goff[d] cells thick, at least the
+// ghost width: images beyond the ghost width but inside the layer are kept;
+// they lie farther than every cutoff from every native, so the near field
+// passes over them. Only positions, charges and ids are copied (the fields
+// the near field reads); ghosts are never integrated.
 #include "kernels.h"
 
 namespace rbe {
 
-// Face bits of a native: bit d set when coordinate d lies within w of a
-// face of axis d.
-__device__ inline int face_bits(const double4 &r, const Grid &g, double w) {
-  int f = 0;
-  if (r.x < w || r.x >= g.L[0] - w) f |= 1;
-  if (r.y < w || r.y >= g.L[1] - w) f |= 2;
-  if (r.z < w || r.z >= g.L[2] - w) f |= 4;
-  return f;
+// Padded key -> (species block, unwrapped cell relative to the native grid).
+// Returns false for cells of the native grid (they hold no ghosts).
+__device__ inline bool ghost_cell(const Grid &g, int64_t key, int *blk, int *x, int *y, int *z) {
+  *blk = (int)(key / g.pncell);
+  const int64_t p = key - (int64_t)*blk * g.pncell;
+  *x = (int)(p % g.pnx) - g.goff[0];
+  *y = (int)((p / g.pnx) % g.pny) - g.goff[1];
+  *z = (int)(p / ((int64_t)g.pnx * g.pny)) - g.goff[2];
+  return !(*x >= 0 && *x < g.nx && *y >= 0 && *y < g.ny && *z >= 0 && *z < g.nz);
 }
 
-// counts[s] = number of images of native s (2^|A| - 1).
-__global__ void __launch_bounds__(256) k_ghost_count(int64_t n, const double4 *__restrict__ xq, Grid g, double w,
-                                                     int32_t *__restrict__ counts) {
-  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (s >= n) return;
-  counts[s] = (1 << __popc(face_bits(xq[s], g, w))) - 1;
-}
-
-// Writes the images of native s at offs[s] onwards, subsets in increasing
-// bit order (x, y, xy, z, xz, yz, xyz).
-__global__ void __launch_bounds__(256) k_ghost_emit(int64_t n, int64_t cap, const double4 *__restrict__ xq,
-                                                    const int32_t *__restrict__ ids, Grid g, double w,
-                                                    const int32_t *__restrict__ offs, double4 *__restrict__ graw,
-                                                    int32_t *__restrict__ gid, int *err) {
-  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (s >= n) return;
-  const double4 r = xq[s];
-  const int f = face_bits(r, g, w);
-  if (f == 0) return;
-  // shifted coordinate of each axis (low face: +L, high face: -L)
-  const double sx = r.x < w ? r.x + g.L[0] : r.x - g.L[0];
-  const double sy = r.y < w ? r.y + g.L[1] : r.y - g.L[1];
-  const double sz = r.z < w ? r.z + g.L[2] : r.z - g.L[2];
-  int64_t dst = offs[s];
-  for (int sub = 1; sub < 8; ++sub) {
-    if ((sub & f) != sub) continue;
-    if (dst < 0 || dst >= cap) {
-      atomicOr(err, kErrGhostOverflow);
-      return;
-    }
-    graw[dst] = make_double4((sub & 1) ? sx : r.x, (sub & 2) ? sy : r.y, (sub & 4) ? sz : r.z, r.w);
-    gid[dst] = ids[s];
-    ++dst;
+// count[key] = natives of the source cell of ghost cell key (0 for native cells).
+__global__ void __launch_bounds__(256) k_ghost_cell_counts(Grid g, const int32_t *__restrict__ cell_start,
+                                                           int32_t *__restrict__ count) {
+  const int64_t key = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (key >= 2 * (int64_t)g.pncell) return;
+  int blk, x, y, z;
+  int c = 0;
+  if (ghost_cell(g, key, &blk, &x, &y, &z)) {
+    const int wx = x - floor_div(x, g.nx) * g.nx, wy = y - floor_div(y, g.ny) * g.ny,
+              wz = z - floor_div(z, g.nz) * g.nz;
+    const int64_t src = (int64_t)blk * g.ncell + ((int64_t)wz * g.ny + wy) * g.nx + wx;
+    c = cell_start[src + 1] - cell_start[src];
   }
+  count[key] = c;
 }
 
-// ghost count = min(total images, capacity)
-__global__ void k_ghost_total(int32_t *gcount, const int32_t *total, int64_t cap) {
-  const int64_t v = *total;
-  *gcount = (int32_t)(v < cap ? v : cap);
-}
-
-// Padded cell index along one axis: goff + floor(x * inv_h), clamped to the
-// padded grid (a NaN lands in cell 0).
-__device__ inline int padded_coord(double x, double inv_h, int off, int pn) {
-  const double t = floor(x * inv_h) + (double)off;
-  if (t >= 0.0 && t < (double)pn) return (int)t;
-  return t >= (double)pn ? pn - 1 : 0;
-}
-
-__global__ void __launch_bounds__(256) k_ghost_keys(int64_t cap, const int32_t *__restrict__ gcount,
-                                                    const double4 *__restrict__ graw, Grid g,
-                                                    int32_t *__restrict__ key, int32_t *__restrict__ slot,
-                                                    int32_t *__restrict__ count) {
-  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t n = min(cap, (int64_t)*gcount);
-  if (k - (threadIdx.x & 63) >= n) return;  // whole wave past the end
-  const bool active = k < n;
-  int kk = -1 - (int)(threadIdx.x & 63);  // lanes past the end: a key no other lane has
-  if (active) {
-    const double4 r = graw[k];
-    const int cx = padded_coord(r.x, g.inv_h[0], g.goff[0], g.pnx);
-    const int cy = padded_coord(r.y, g.inv_h[1], g.goff[1], g.pny);
-    const int cz = padded_coord(r.z, g.inv_h[2], g.goff[2], g.pnz);
-    kk = (r.w == 0.0 ? g.pncell : 0) + (cz * g.pny + cy) * g.pnx + cx;
-    key[k] = kk;
-  }
-  const int sl = run_slot(kk, active, count);  // every lane of the wave takes part
-  if (active) slot[k] = sl;
-}
-
-__global__ void __launch_bounds__(256) k_ghost_scatter(int64_t cap, const int32_t *__restrict__ gcount,
-                                                       const int32_t *__restrict__ key,
-                                                       const int32_t *__restrict__ slot,
-                                                       const int32_t *__restrict__ start, int32_t *__restrict__ tmp) {
-  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (k >= cap || k >= *gcount) return;
-  tmp[start[key[k]] + slot[k]] = (int32_t)k;
-}
-
-// Stable placement per bucket (entries in increasing creation order), then
-// the gather of the records into that order.
-__global__ void __launch_bounds__(256) k_ghost_buckets(int64_t nkeys, const int32_t *__restrict__ start,
-                                                       const int32_t *__restrict__ tmp, int32_t *__restrict__ perm) {
-  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (b >= nkeys) return;
-  place_bucket(start[b], start[b + 1], tmp, perm);
-}
-
-__global__ void __launch_bounds__(256) k_ghost_gather(int64_t cap, const int32_t *__restrict__ gcount,
-                                                      const int32_t *__restrict__ perm,
-                                                      const double4 *__restrict__ graw,
-                                                      const int32_t *__restrict__ gid_raw, double4 *__restrict__ gxq,
-                                                      int32_t *__restrict__ gid) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= cap || t >= *gcount) return;
-  const int k = perm[t];
-  gxq[t] = graw[k];
-  gid[t] = gid_raw[k];
-}
-
-void launch_build_ghosts(const Grid &g, int64_t n, const Sorted &s, const GhostBuffers &gb, int *err,
-                         hipStream_t st) {
-  launch_fill_i32(gb.count, 1, 0, st);
-  const double w = g.ghost_width;
-  if (n > 0) {
-    const unsigned blocks = (unsigned)((n + 255) / 256);
-    k_ghost_count<<<blocks, 256, 0, st>>>(n, s.xq, g, w, gb.flags);
-    launch_exclusive_scan(gb.flags, n, gb.offs, gb.scan_tmp, st);
-    k_ghost_emit<<<blocks, 256, 0, st>>>(n, gb.cap, s.xq, s.id, g, w, gb.offs, gb.raw_xq, gb.raw_id, err);
-    k_ghost_total<<<1, 1, 0, st>>>(gb.count, gb.offs + n, gb.cap);
-  }
-  // sort by (species, padded cell)
+// Copies the shifted natives of each ghost cell's source cell to its slots
+// and clamps the cell starts to the capacity (cells past it end up empty and
+// the overflow is flagged), so no reader goes past the ghost arrays. One
+// thread per padded key, plus one for the end entry.
+__global__ void __launch_bounds__(256) k_ghost_fill(Grid g, int64_t cap, const int32_t *__restrict__ cell_start,
+                                                    const double4 *__restrict__ xq, const int32_t *__restrict__ ids,
+                                                    int32_t *__restrict__ gstart, double4 *__restrict__ gxq,
+                                                    int32_t *__restrict__ gid, int32_t *__restrict__ gcount,
+                                                    int *err) {
+  const int64_t key = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t nkeys = 2 * (int64_t)g.pncell;
-  launch_fill_i32(gb.cell_count, nkeys, 0, st);
-  const unsigned cblocks = (unsigned)((gb.cap + 255) / 256);
-  k_ghost_keys<<<cblocks, 256, 0, st>>>(gb.cap, gb.count, gb.raw_xq, g, gb.key, gb.slot, gb.cell_count);
+  if (key > nkeys) return;
+  const int64_t d0 = gstart[key];
+  if (key == nkeys) {
+    if (d0 > cap) atomicOr(err, kErrGhostOverflow);
+    *gcount = (int32_t)(d0 < cap ? d0 : cap);
+    gstart[key] = (int32_t)(d0 < cap ? d0 : cap);
+    return;
+  }
+  int blk, x, y, z;
+  if (ghost_cell(g, key, &blk, &x, &y, &z)) {
+    const int qx = floor_div(x, g.nx), qy = floor_div(y, g.ny), qz = floor_div(z, g.nz);
+    const int wx = x - qx * g.nx, wy = y - qy * g.ny, wz = z - qz * g.nz;
+    const double sx = (double)qx * g.L[0], sy = (double)qy * g.L[1], sz = (double)qz * g.L[2];
+    const int64_t src = (int64_t)blk * g.ncell + ((int64_t)wz * g.ny + wy) * g.nx + wx;
+    int64_t d = d0;
+    for (int j = cell_start[src]; j < cell_start[src + 1] && d < cap; ++j, ++d) {
+      const double4 r = xq[j];
+      gxq[d] = make_double4(r.x + sx, r.y + sy, r.z + sz, r.w);
+      gid[d] = ids[j];
+    }
+  }
+  gstart[key] = (int32_t)(d0 < cap ? d0 : cap);
+}
+
+void launch_build_ghosts(const Grid &g, int64_t n, const int32_t *cell_start, const Sorted &s,
+                         const GhostBuffers &gb, int *err, hipStream_t st) {
+  (void)n;
+  const int64_t nkeys = 2 * (int64_t)g.pncell;
+  const unsigned blocks = (unsigned)((nkeys + 255) / 256);
+  k_ghost_cell_counts<<<blocks, 256, 0, st>>>(g, cell_start, gb.cell_count);
   launch_exclusive_scan(gb.cell_count, nkeys, gb.cell_start, gb.cell_scan_tmp, st);
-  k_ghost_scatter<<<cblocks, 256, 0, st>>>(gb.cap, gb.count, gb.key, gb.slot, gb.cell_start, gb.tmp);
-  // the keys are no longer needed: their array receives the placement
-  k_ghost_buckets<<<(unsigned)((nkeys + 255) / 256), 256, 0, st>>>(nkeys, gb.cell_start, gb.tmp, gb.key);
-  k_ghost_gather<<<cblocks, 256, 0, st>>>(gb.cap, gb.count, gb.key, gb.raw_xq, gb.raw_id, gb.xq, gb.id);
+  k_ghost_fill<<<(unsigned)((nkeys + 1 + 255) / 256), 256, 0, st>>>(g, gb.cap, cell_start, s.xq, s.id, gb.cell_start,
+                                                                    gb.xq, gb.id, gb.count, err);
 }
 
 }  // namespace rbe

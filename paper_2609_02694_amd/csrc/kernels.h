@@ -48,22 +48,17 @@ void launch_scatter_forces(int64_t n, const int32_t *perm, const double *fx, con
 // ---------------------------------------------------------------------------
 struct GhostBuffers {
   int64_t cap;             // ghost capacity
-  double4 *raw_xq;         // [cap] ghost records in creation order
-  int32_t *raw_id;         // [cap]
-  double4 *xq;             // [cap] sorted by (species, padded cell)
-  int32_t *id;             // [cap]
-  int32_t *cell_start;     // [2 * pncell + 1]
+  double4 *xq;             // [cap + kScanPad] ghost records in padded cell order
+  int32_t *id;             // [cap + kScanPad] ids of their natives
+  int32_t *cell_start;     // [2 * pncell + 1] first ghost of every padded key (clamped to cap)
   int32_t *cell_count;     // [2 * pncell]
   int32_t *cell_scan_tmp;  // [scan_tiles(2 * pncell)]
-  int32_t *flags;          // [n_max + cap]
-  int32_t *offs;           // [n_max + cap + 1]
-  int32_t *scan_tmp;       // [scan_tiles(n_max + cap)]
   int32_t *count;          // [1] ghosts made (device)
-  int32_t *key, *slot, *tmp;  // [cap]
 };
-// Builds and sorts the ghost shell of the sorted natives s[0..n).
-void launch_build_ghosts(const Grid &g, int64_t n, const Sorted &s, const GhostBuffers &gb, int *err,
-                         hipStream_t st);
+// Builds the ghost shell of the sorted natives s[0..n) (cell_start: their
+// cell table) in padded cell order.
+void launch_build_ghosts(const Grid &g, int64_t n, const int32_t *cell_start, const Sorted &s,
+                         const GhostBuffers &gb, int *err, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // near field
@@ -119,11 +114,23 @@ struct PairCounters {
 // parts: charged particles (plain sums, or core and shell of the random batch
 // list) and neutral particles.
 // PAIR_PART_SHELL launches nothing (kept for the counter layout).
-enum { PAIR_PART_CHARGED = 0, PAIR_PART_SHELL = 1, PAIR_PART_NEUTRAL = 2 };
+// PAIR_PART_COULOMB: the charged particles' screened Coulomb terms only,
+// added to f (which holds their LJ terms from launch_lj_tile).
+enum { PAIR_PART_CHARGED = 0, PAIR_PART_SHELL = 1, PAIR_PART_NEUTRAL = 2, PAIR_PART_COULOMB = 3 };
 // gb: ghost shell of the natives (nullptr for the periodic traversal).
 void launch_pair(int prec, int part, const PairParams &pp, int64_t n, const int32_t *nq, const Sorted &s,
                  const int32_t *cell_start, const int32_t *inv_id, const GhostBuffers *gb, double *fx, double *fy,
                  double *fz, PairCounters cnt, hipStream_t st);
+
+// LJ terms of every particle of the species blocks in iblk (bit 0 charged,
+// bit 1 neutral) over LDS-staged cell tiles: writes f of those particles
+// (counters [4] or nullptr: [1] LJ pair terms, [2] candidates). Used by the
+// FP32C form on grids whose mean cell occupancy suits the staging
+// (lj_tile_applicable); the other cases keep the thread-form walks.
+bool lj_tile_applicable(int prec, const PairParams &pp, int64_t n);
+void launch_lj_tile(int prec, const PairParams &pp, int64_t n, int iblk, const Sorted &s, const int32_t *cell_start,
+                    const GhostBuffers *gb, double *fx, double *fy, double *fz, unsigned long long *counters,
+                    int *err, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Fourier part

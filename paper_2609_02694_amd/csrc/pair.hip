@@ -138,13 +138,16 @@ __device__ inline void stencil(const PairCtx &c, int blk, int cx, int cy, int cz
 // MI355X this beats the cluster form when most candidates within reach are
 // summed, i.e. without the shell test of the random batch list). MODE 0:
 // neutral i (LJ over both species blocks out to r_lj); MODE 1: charged i
-// (charged block out to max(r_coul, r_lj), neutral block out to r_lj).
+// (charged block out to max(r_coul, r_lj), neutral block out to r_lj); MODE
+// 2: charged i, screened Coulomb terms only (charged block out to r_coul),
+// added to f, which holds the LJ terms of the tile pass.
 // Occupancy asked of the compiler: FP32 forms six (charged) or seven
 // (neutral) waves per SIMD, FP64 forms three or seven (measured best; the
 // FP64 charged form spills at four).
 template <bool F32, bool COUNT, int MODE, bool GHOST>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F32 ? (MODE ? 6 : 7) : (MODE ? 3 : 7))))
 k_pair_plain(PairCtx c) {
+  static_assert(MODE >= 0 && MODE <= 2, "mode");
   int64_t first, end;
   if (!part_block(c, blockDim.x, &first, &end)) return;
   const int64_t i = first + threadIdx.x;
@@ -184,16 +187,25 @@ k_pair_plain(PairCtx c) {
     }
   };
   const Reach rq{xi, yi, zi, pp.rq2}, rlj{xi, yi, zi, pp.rlj2};
-  if (MODE == 1) {
-    stencil<GHOST, false>(c, 0, cx, cy, cz, pp.s_coul, rq, visit_q);
-    if (pp.do_lj) stencil<GHOST, false>(c, 1, cx, cy, cz, pp.s_lj, rlj, visit_lj);
-  } else if (pp.do_lj) {
-    stencil<GHOST, false>(c, 0, cx, cy, cz, pp.s_lj, rlj, visit_lj);
-    stencil<GHOST, false>(c, 1, cx, cy, cz, pp.s_lj, rlj, visit_lj);
+  if (MODE == 2) {
+    // pp.do_lj is off for this launch: visit_q adds the screened Coulomb term only
+    const Reach rc{xi, yi, zi, pp.rc2};
+    stencil<GHOST, false>(c, 0, cx, cy, cz, pp.s_coul, rc, visit_q);
+    c.fx[i] += acc.get(0);
+    c.fy[i] += acc.get(1);
+    c.fz[i] += acc.get(2);
+  } else {
+    if (MODE == 1) {
+      stencil<GHOST, false>(c, 0, cx, cy, cz, pp.s_coul, rq, visit_q);
+      if (pp.do_lj) stencil<GHOST, false>(c, 1, cx, cy, cz, pp.s_lj, rlj, visit_lj);
+    } else if (pp.do_lj) {
+      stencil<GHOST, false>(c, 0, cx, cy, cz, pp.s_lj, rlj, visit_lj);
+      stencil<GHOST, false>(c, 1, cx, cy, cz, pp.s_lj, rlj, visit_lj);
+    }
+    c.fx[i] = acc.get(0);
+    c.fy[i] = acc.get(1);
+    c.fz[i] = acc.get(2);
   }
-  c.fx[i] = acc.get(0);
-  c.fy[i] = acc.get(1);
-  c.fz[i] = acc.get(2);
   flush_counts<COUNT>(c, n_coul, n_lj, n_tested, 0);
 }
 
@@ -375,6 +387,10 @@ static void launch_part(PairCtx c, int part, hipStream_t st) {
     if (pp.rbl && pp.shell_charged) launch_clusters(k_pair_rbl<F32, COUNT, GHOST, true>, c, st);
     else if (pp.rbl) launch_clusters(k_pair_rbl<F32, COUNT, GHOST, false>, c, st);
     else launch_threads(k_pair_plain<F32, COUNT, 1, GHOST>, c, st);
+  } else if (part == PAIR_PART_COULOMB) {
+    c.charged = 1;
+    c.pp.do_lj = 0;
+    launch_threads(k_pair_plain<F32, COUNT, 2, GHOST>, c, st);
   } else if (part == PAIR_PART_NEUTRAL) {
     c.charged = 0;
     if (pp.rbl && pp.rlj2 > pp.rcore2 && pp.do_lj) launch_clusters(k_pair_rbl<F32, COUNT, GHOST, false>, c, st);

@@ -212,6 +212,6 @@ void launch_sample_modes(const ModeTable &t, const double *cdf_dev, uint64_t see
 // Error flag bits (device int)
 // ---------------------------------------------------------------------------
 enum : int { kErrNonFinite = 1, kErrBadId = 2, kErrSampler = 4, kErrGhostOverflow = 8, kErrBarrier = 16,
-             kErrNonNeutral = 32 };
+             kErrNonNeutral = 32, kErrTileOverflow = 64 };
 
 }  // namespace rbe

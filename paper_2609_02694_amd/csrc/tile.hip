@@ -1,0 +1,586 @@
+// Near field over LDS-staged cell tiles (Sec. 2.1, Eq. 7-8; Sec. 2.2 cell
+// lists), for the plain cutoff sums (no random batch list):
+//
+//   LJ pass      every particle i of the launch's species blocks against every
+//                j (both species) with r <= r_lj: G_LJ(r) d;
+//   Coulomb pass every charged i against every charged j with r <= r_coul:
+//                kc q_i q_j G(r) d (its result is added to the LJ pass's).
+//
+// A workgroup owns a tile of TX x TY x TZ cells. It stages the records of the
+// tile's halo (the cells within the stencil of any own cell) in LDS once,
+// converted to the tile's frame: FP32 coordinates relative to the tile's
+// centre in the FP32C form, FP64 coordinates (with the periodic image shift
+// applied) in the FP64 form. Each thread then takes one particle i of the
+// tile and walks the halo rows its reach sphere touches, each row trimmed to
+// the x-cells the sphere spans, reading the candidates from LDS. Halo cells
+// are met once per unwrapped cell index, i.e. once per (cell, periodic image),
+// so no image is counted twice (the cutoffs are at most half the box).
+//
+// FP32C: r^2 in FP32 from the frame coordinates; a pair whose r^2 lies within
+// a relative band of 2^-16 around the cutoff is re-classified from the FP64
+// records (minimum image), so cutoff membership is the FP64 one. The pair
+// terms of a row are summed in FP32 and each row's sum is added to the total
+// with Kahan compensation.
+//
+// A halo larger than the LDS staging is processed in chunks of whole rows
+// (any density is handled; a single row beyond capacity is flagged).
+#include "pair_device.h"
+
+namespace rbe {
+
+struct TileCtx {
+  PairParams pp;
+  PairF32 pf;
+  int TX, TY, TZ;          // own cells per tile
+  Sten s;                  // halo radius in cells
+  int ntx, nty, ntz;       // tiles per axis
+  int cap;                 // records the LDS staging holds
+  int kind;                // 0: LJ pass, 1: Coulomb pass
+  int iblk;                // species blocks supplying i (bit 0 charged, bit 1 neutral)
+  int accumulate;          // add to f (Coulomb pass) instead of writing it
+  const double4 *__restrict__ xq;
+  const int32_t *__restrict__ cell_start;
+  const double4 *__restrict__ gxq;          // ghost shell (GHOST)
+  const int32_t *__restrict__ gcell_start;
+  int64_t n;                                // natives; ghost records are indexed from n on
+  double *__restrict__ fx;
+  double *__restrict__ fy;
+  double *__restrict__ fz;
+  unsigned long long *__restrict__ counters;  // [4] when counting
+  int *err;
+};
+
+constexpr int kTileThreads = 256;
+constexpr int kTileMaxSegs = 64;    // own row segments (rows x species blocks) of a tile
+constexpr int kTileMaxChunks = 64;  // halo chunks of a tile whose halo exceeds the staging
+constexpr int kTileIMax = 512;      // particles of a tile grouped by quadrant (more: cell order)
+
+// Record of the LDS staging: frame coordinates and the charge (Coulomb pass)
+// or the record's index as bits (LJ pass, which needs no charge).
+template <bool F32>
+struct TileRec;
+template <>
+struct TileRec<true> {
+  using T = float;
+  using V = float4;
+};
+template <>
+struct TileRec<false> {
+  using T = double;
+  using V = double4;
+};
+
+// Records of one halo cell, in two sources per species block (natives and
+// ghosts). Unwrapped cell (xc, yc, zc); returns the image shift (periodic).
+struct CellSrc {
+  int a[4], b[4];       // [natives blk 0, ghosts blk 0, natives blk 1, ghosts blk 1) ranges
+  double sx, sy, sz;    // image shift (periodic traversal)
+};
+
+template <bool GHOST>
+__device__ inline void cell_sources(const TileCtx &c, int xc, int yc, int zc, CellSrc *out) {
+  const Grid &g = c.pp.g;
+  for (int k = 0; k < 4; ++k) out->a[k] = out->b[k] = 0;
+  out->sx = out->sy = out->sz = 0.0;
+  const int nb = c.kind == 0 ? 2 : 1;  // LJ: both species; Coulomb: charged only
+  if (GHOST) {
+    const bool native = xc >= 0 && xc < g.nx && yc >= 0 && yc < g.ny && zc >= 0 && zc < g.nz;
+    const int px = xc + g.goff[0], py = yc + g.goff[1], pz = zc + g.goff[2];
+    const bool padded = px >= 0 && px < g.pnx && py >= 0 && py < g.pny && pz >= 0 && pz < g.pnz;
+    for (int b = 0; b < nb; ++b) {
+      if (native) {
+        const int64_t key = (int64_t)b * g.ncell + ((int64_t)zc * g.ny + yc) * g.nx + xc;
+        out->a[2 * b] = c.cell_start[key];
+        out->b[2 * b] = c.cell_start[key + 1];
+      }
+      if (padded) {
+        const int64_t key = (int64_t)b * g.pncell + ((int64_t)pz * g.pny + py) * g.pnx + px;
+        out->a[2 * b + 1] = c.gcell_start[key];
+        out->b[2 * b + 1] = c.gcell_start[key + 1];
+      }
+    }
+  } else {
+    const int qx = floor_div(xc, g.nx), qy = floor_div(yc, g.ny), qz = floor_div(zc, g.nz);
+    const int wx = xc - qx * g.nx, wy = yc - qy * g.ny, wz = zc - qz * g.nz;
+    out->sx = (double)qx * g.L[0];
+    out->sy = (double)qy * g.L[1];
+    out->sz = (double)qz * g.L[2];
+    for (int b = 0; b < nb; ++b) {
+      const int64_t key = (int64_t)b * g.ncell + ((int64_t)wz * g.ny + wy) * g.nx + wx;
+      out->a[2 * b] = c.cell_start[key];
+      out->b[2 * b] = c.cell_start[key + 1];
+    }
+  }
+}
+
+// Block-wide exclusive scan of v[0..m) in LDS (in place); returns the total.
+__device__ inline int tile_scan(int *v, int m, int *wsum) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int per = (m + kTileThreads - 1) / kTileThreads;
+  const int lo = min(m, tid * per), hi = min(m, lo + per);
+  int s = 0;
+  for (int k = lo; k < hi; ++k) s += v[k];
+  int incl = s;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  int off = 0, tot = 0;
+  for (int w = 0; w < kTileThreads / 64; ++w) {
+    if (w < wave) off += wsum[w];
+    tot += wsum[w];
+  }
+  int run = off + incl - s;
+  for (int k = lo; k < hi; ++k) {
+    const int x = v[k];
+    v[k] = run;
+    run += x;
+  }
+  __syncthreads();
+  return tot;
+}
+
+// Distance of p to the slab [lo, lo + h), less the margin, at least 0.
+template <class T>
+__device__ inline T tile_gap(T p, T lo, T h, T margin) {
+  const T d = lo - p > T(0) ? lo - p : (p - (lo + h) > T(0) ? p - (lo + h) : T(0));
+  return d > margin ? d - margin : T(0);
+}
+
+// Pair scalars without the cutoff test (the caller masks). LJ: the shape
+// u (2 sigma^6 u - 1) / r^2 with u = r^-6, so that G_LJ(r) of Eq. 8 is
+// 24 eps sigma^6 times it (the constant is applied once to the sum); and
+// kc q_i q_j G(r) with G the screened Coulomb factor of Eq. 8.
+template <class T>
+__device__ inline T lj_shape(T r2, T two_s6) {
+  T rinv2;
+  if constexpr (sizeof(T) == 4) rinv2 = __builtin_amdgcn_rcpf(r2);
+  else rinv2 = rcp_f64(r2);
+  const T u = rinv2 * rinv2 * rinv2;
+  return u * fma(u, two_s6, T(-1)) * rinv2;
+}
+__device__ inline float pair_coul_f32(const PairF32 &pf, float r2, float qq) {
+  const float rinv = __builtin_amdgcn_rsqf(r2);
+  const float rinv2 = rinv * rinv;
+  const float x = pf.sqrt_alpha * (r2 * rinv);
+  const float e = __builtin_amdgcn_exp2f(pf.neg_alpha_log2e * r2);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, x, 1.0f));
+  const float erfc_x = e * erfcx_poly(t);
+  const float G = fmaf(erfc_x * rinv, rinv2, pf.two_sqrt_alpha_over_sqrt_pi * e * rinv2);
+  return pf.kc * qq * G;
+}
+__device__ inline double pair_coul_f64(const PairParams &pp, double r2, double qq) {
+  const double rinv = rsqrt_f64(r2);
+  const double inv_r2 = rinv * rinv;
+  const double e = exp_nonpos_f64<true>(-pp.alpha * r2);
+  const double R = erfc_scaled_f64<true>(pp.sqrt_alpha * (r2 * rinv));
+  const double G = e * inv_r2 * fma(R, rinv, pp.two_sqrt_alpha_over_sqrt_pi);
+  return pp.kc * qq * G;
+}
+
+// s += v with Kahan compensation c (FP32); plain sum in FP64.
+__device__ inline void tile_kahan(float &s, float &c, float v) {
+#pragma clang fp contract(off)
+  const float y = v - c;
+  const float t = s + y;
+  c = (t - s) - y;
+  s = t;
+}
+__device__ inline void tile_kahan(double &s, double &, double v) { s += v; }
+
+template <bool F32, bool GHOST, int KIND, bool COUNT>
+__global__ void __launch_bounds__(kTileThreads) k_pair_tile(TileCtx c) {
+  using T = typename TileRec<F32>::T;
+  using V = typename TileRec<F32>::V;
+  extern __shared__ __align__(16) unsigned char tile_lds[];
+  __shared__ int wsum[kTileThreads / 64];
+  __shared__ int seg_n[kTileMaxSegs];       // own row segments: i count, then prefix
+  __shared__ int seg_g0[kTileMaxSegs];      // first native index of each segment
+  __shared__ int seg_i0[kTileMaxSegs + 1];
+  __shared__ int chunk_r0[kTileMaxChunks], chunk_r1[kTileMaxChunks];  // row ranges staged together
+  __shared__ int nchunk_s;
+  __shared__ int ilist[kTileIMax];  // the tile's particles grouped by quadrant
+  __shared__ int qcnt[4], qoff[4];
+
+  const PairParams &pp = c.pp;
+  const Grid &g = pp.g;
+  const int tid = threadIdx.x;
+  const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
+  const int tx = tile % c.ntx, ty = (tile / c.ntx) % c.nty, tz = tile / (c.ntx * c.nty);
+  const int x0 = tx * c.TX, y0 = ty * c.TY, z0 = tz * c.TZ;
+  const int HX = c.TX + 2 * c.s.x, HY = c.TY + 2 * c.s.y, HZ = c.TZ + 2 * c.s.z;
+  const int nrows = HY * HZ, ncells = nrows * HX;
+  const double hx = g.L[0] / g.nx, hy = g.L[1] / g.ny, hz = g.L[2] / g.nz;
+  // frame: FP32C relative to the tile centre, FP64 absolute (unwrapped)
+  const double ox = F32 ? (x0 + 0.5 * c.TX) * hx : 0.0;
+  const double oy = F32 ? (y0 + 0.5 * c.TY) * hy : 0.0;
+  const double oz = F32 ? (z0 + 0.5 * c.TZ) * hz : 0.0;
+  // low corner of the halo in the frame, cell edges and their inverse
+  const T X0 = (T)((x0 - c.s.x) * hx - ox), Y0 = (T)((y0 - c.s.y) * hy - oy), Z0 = (T)((z0 - c.s.z) * hz - oz);
+  const T Hy = (T)hy, Hz = (T)hz, invHx = (T)(1.0 / hx);
+  const T margin = F32 ? T(1e-4) : T(kTrimMargin);
+  constexpr bool coul = KIND == 1;
+  const T rc2 = (T)(coul ? pp.rc2 : pp.rlj2);
+  const double rc2d = coul ? pp.rc2 : pp.rlj2;
+  const T band = rc2 * T(1.52587890625e-05);  // 2^-16 relative
+  // LJ: sigma^6 and the force constant 24 eps sigma^6 of the shape function
+  const double s6 = pp.sig2 * pp.sig2 * pp.sig2;
+  const T two_s6 = (T)(2.0 * s6);
+  const double lj_scale = pp.eps24 * s6;
+
+  // LDS: cell starts [ncells + 1], records [cap], record indices [cap] (Coulomb)
+  int *cs = (int *)tile_lds;
+  V *rec = (V *)(tile_lds + ((size_t)(ncells + 1) * sizeof(int) + 15) / 16 * 16);
+  int *ridx = (int *)(rec + c.cap);
+
+  // ---- own row segments (one per own row and species block) ----------------
+  const int nsegs = 2 * c.TY * c.TZ;
+  if (tid < nsegs) {
+    const int b = tid / (c.TY * c.TZ), rr = tid % (c.TY * c.TZ);
+    const int yy = y0 + rr % c.TY, zz = z0 + rr / c.TY;
+    const int xe = min(x0 + c.TX, g.nx);
+    int a = 0, e = 0;
+    if (((c.iblk >> b) & 1) && yy < g.ny && zz < g.nz && x0 < xe) {
+      const int64_t key = (int64_t)b * g.ncell + ((int64_t)zz * g.ny + yy) * g.nx;
+      a = c.cell_start[key + x0];
+      e = c.cell_start[key + xe];
+    }
+    seg_n[tid] = e - a;
+    seg_g0[tid] = a;
+  }
+  // ---- halo cell counts -----------------------------------------------------
+  for (int h = tid; h < ncells; h += kTileThreads) {
+    const int ix = h % HX, row = h / HX;
+    CellSrc src;
+    cell_sources<GHOST>(c, x0 - c.s.x + ix, y0 - c.s.y + row % HY, z0 - c.s.z + row / HY, &src);
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cnt += src.b[k] - src.a[k];
+    cs[h] = cnt;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int tot = 0;
+    for (int k = 0; k < nsegs; ++k) {
+      seg_i0[k] = tot;
+      tot += seg_n[k];
+    }
+    seg_i0[nsegs] = tot;
+  }
+  const int total = tile_scan(cs, ncells, wsum);
+  const int ni = seg_i0[nsegs];
+  if (ni == 0) return;  // uniform: no particle of these species in the tile
+  // chunks of whole rows that fit the staging (normally one); a single row
+  // beyond the staging is left out (an empty chunk) and flagged
+  if (tid == 0) {
+    cs[ncells] = total;
+    int nch = 0, row0 = 0;
+    while (row0 < nrows && nch < kTileMaxChunks) {
+      int r1 = row0;
+      while (r1 < nrows && cs[(r1 + 1) * HX] - cs[row0 * HX] <= c.cap) ++r1;
+      if (r1 == row0) {
+        atomicOr(c.err, kErrTileOverflow);
+        chunk_r0[nch] = chunk_r1[nch] = row0;
+        r1 = row0 + 1;
+      } else {
+        chunk_r0[nch] = row0;
+        chunk_r1[nch] = r1;
+      }
+      ++nch;
+      row0 = r1;
+    }
+    if (row0 < nrows) atomicOr(c.err, kErrTileOverflow);
+    nchunk_s = nch;
+  }
+  __syncthreads();
+  const int nchunk = nchunk_s;
+
+  auto stage = [&](int r0, int r1) {
+    const int base = cs[r0 * HX];
+    for (int h = r0 * HX + tid; h < r1 * HX; h += kTileThreads) {
+      const int ix = h % HX, row = h / HX;
+      CellSrc src;
+      cell_sources<GHOST>(c, x0 - c.s.x + ix, y0 - c.s.y + row % HY, z0 - c.s.z + row / HY, &src);
+      int d = cs[h] - base;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const bool ghost = GHOST && (k & 1);
+        for (int j = src.a[k]; j < src.b[k]; ++j, ++d) {
+          const double4 p = ghost ? c.gxq[j] : c.xq[j];
+          const int gj = ghost ? (int)c.n + j : j;
+          V v;
+          v.x = (T)((p.x + src.sx) - ox);
+          v.y = (T)((p.y + src.sy) - oy);
+          v.z = (T)((p.z + src.sz) - oz);
+          if (coul) {
+            v.w = (T)p.w;
+            ridx[d] = gj;
+          } else {
+            if constexpr (F32) v.w = __int_as_float(gj);
+            else v.w = (double)gj;
+          }
+          rec[d] = v;
+        }
+      }
+    }
+  };
+  if (nchunk == 1) stage(chunk_r0[0], chunk_r1[0]);
+  __syncthreads();
+
+  // The tile's particles in cell order, regrouped by the quadrant of their
+  // cell's y/z cross-section they sit in: the threads of a wave then have
+  // similar distances to each stencil row, hence similar trimmed row
+  // lengths, and fewer lanes idle while the longest row is walked. (Which
+  // thread takes a particle does not change its result.)
+  auto nth_particle = [&](int li) {
+    int sgi = 0;
+    while (sgi + 1 < nsegs && seg_i0[sgi + 1] <= li) ++sgi;
+    return seg_g0[sgi] + (li - seg_i0[sgi]);
+  };
+  const bool grouped = ni <= kTileIMax;
+  if (grouped) {
+    if (tid < 4) qcnt[tid] = 0;
+    __syncthreads();
+    for (int li = tid; li < ni; li += kTileThreads) {
+      const double4 p = c.xq[nth_particle(li)];
+      const int qy = p.y - cell_coord(p.y, g.inv_h[1], g.ny) * hy >= 0.5 * hy;
+      const int qz = p.z - cell_coord(p.z, g.inv_h[2], g.nz) * hz >= 0.5 * hz;
+      atomicAdd(&qcnt[qy + 2 * qz], 1);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int o = 0;
+      for (int q = 0; q < 4; ++q) {
+        qoff[q] = o;
+        o += qcnt[q];
+      }
+    }
+    __syncthreads();
+    for (int li = tid; li < ni; li += kTileThreads) {
+      const int gi = nth_particle(li);
+      const double4 p = c.xq[gi];
+      const int qy = p.y - cell_coord(p.y, g.inv_h[1], g.ny) * hy >= 0.5 * hy;
+      const int qz = p.z - cell_coord(p.z, g.inv_h[2], g.nz) * hz >= 0.5 * hz;
+      ilist[atomicAdd(&qoff[qy + 2 * qz], 1)] = gi;
+    }
+    __syncthreads();
+  }
+
+  unsigned long long n_pairs = 0, n_cand = 0;
+  const int rounds = (ni + kTileThreads - 1) / kTileThreads;
+  for (int round = 0; round < rounds; ++round) {
+    const int li = round * kTileThreads + tid;
+    const bool active = li < ni;
+    int gi = 0;
+    if (active) gi = grouped ? ilist[li] : nth_particle(li);
+    const double4 pi = c.xq[active ? gi : 0];
+    const T xi = (T)(pi.x - ox), yi = (T)(pi.y - oy), zi = (T)(pi.z - oz);
+    const T qi = (T)pi.w;
+    // i's halo cell (an own cell: clamped there, so every row index below
+    // stays inside the halo)
+    const int ix = min(max(cell_coord(pi.x, g.inv_h[0], g.nx) - (x0 - c.s.x), c.s.x), c.s.x + c.TX - 1);
+    const int iy = min(max(cell_coord(pi.y, g.inv_h[1], g.ny) - (y0 - c.s.y), c.s.y), c.s.y + c.TY - 1);
+    const int iz = min(max(cell_coord(pi.z, g.inv_h[2], g.nz) - (z0 - c.s.z), c.s.z), c.s.z + c.TZ - 1);
+    T S[3] = {T(0), T(0), T(0)}, K[3] = {T(0), T(0), T(0)};
+    for (int ch = 0; ch < nchunk; ++ch) {
+      const int r0 = chunk_r0[ch], r1 = chunk_r1[ch];
+      if (nchunk > 1) {
+        __syncthreads();
+        stage(r0, r1);
+        __syncthreads();
+      }
+      if (!active || r0 == r1) continue;
+      const int base = cs[r0 * HX];
+      auto cand = [&](int k, const V &v, T &px, T &py, T &pz) {
+        const T dx = xi - v.x, dy_ = yi - v.y, dz_ = zi - v.z;
+        T r2;
+        if constexpr (F32) r2 = fmaf(dz_, dz_, fmaf(dy_, dy_, dx * dx));
+        else r2 = sq_dist(dx, dy_, dz_);
+        int gj;
+        if constexpr (coul) gj = ridx[k];
+        else if constexpr (F32) gj = __float_as_int(v.w);
+        else gj = (int)v.w;
+        bool in = (r2 <= rc2) & (gj != gi);
+        if constexpr (F32) {
+          if (fabsf(r2 - rc2) <= band && gj != gi) {
+            // near the cutoff: classify with the FP64 records (minimum image)
+            const double4 pj = gj < c.n ? c.xq[gj] : c.gxq[gj - c.n];
+            const double ex = min_image(pi.x - pj.x, g.L[0]), ey = min_image(pi.y - pj.y, g.L[1]),
+                         ez = min_image(pi.z - pj.z, g.L[2]);
+            in = sq_dist(ex, ey, ez) <= rc2d;
+          }
+        }
+        T f;
+        if constexpr (coul) {
+          if constexpr (F32) f = pair_coul_f32(c.pf, r2, qi * v.w);
+          else f = pair_coul_f64(pp, r2, qi * v.w);
+        } else {
+          f = lj_shape(r2, two_s6);
+        }
+        f = in ? f : T(0);
+        px = fma(f, dx, px);
+        py = fma(f, dy_, py);
+        pz = fma(f, dz_, pz);
+        if (COUNT) {
+          ++n_cand;
+          n_pairs += in;
+        }
+      };
+      // the rows the reach sphere touches, each trimmed to the x-cells it
+      // spans; a row's terms are summed in FP32 and its sum added to the
+      // total with Kahan compensation
+      for (int dz = -c.s.z; dz <= c.s.z; ++dz) {
+        const int rz = iz + dz;
+        const T gz = tile_gap(zi, Z0 + (T)rz * Hz, Hz, margin);
+        if (gz * gz > rc2) continue;
+        for (int dy = -c.s.y; dy <= c.s.y; ++dy) {
+          const int ry = iy + dy;
+          const int row = rz * HY + ry;
+          if (row < r0 || row >= r1) continue;
+          const T gy = tile_gap(yi, Y0 + (T)ry * Hy, Hy, margin);
+          const T rem = rc2 - (gy * gy + gz * gz);
+          if (rem < T(0)) continue;
+          const T ext = sqrt(rem) + margin;
+          int xa = (int)floor((xi - ext - X0) * invHx), xb = (int)floor((xi + ext - X0) * invHx);
+          xa = max(xa, max(ix - c.s.x, 0));
+          xb = min(xb, min(ix + c.s.x, HX - 1));
+          if (xa > xb) continue;
+          const int ka = cs[row * HX + xa] - base, kb = cs[row * HX + xb + 1] - base;
+          T px = T(0), py = T(0), pz = T(0);
+          // two candidates per trip: both records are requested before use
+          int k = ka;
+          for (; k + 1 < kb; k += 2) {
+            const V va = rec[k], vb = rec[k + 1];
+            cand(k, va, px, py, pz);
+            cand(k + 1, vb, px, py, pz);
+          }
+          if (k < kb) cand(k, rec[k], px, py, pz);
+          tile_kahan(S[0], K[0], px);
+          tile_kahan(S[1], K[1], py);
+          tile_kahan(S[2], K[2], pz);
+        }
+      }
+    }
+    if (active) {
+      const double sc = coul ? 1.0 : lj_scale;
+      const double fx = sc * ((double)S[0] - (double)K[0]), fy = sc * ((double)S[1] - (double)K[1]),
+                   fz = sc * ((double)S[2] - (double)K[2]);
+      if (c.accumulate) {
+        c.fx[gi] += fx;
+        c.fy[gi] += fy;
+        c.fz[gi] += fz;
+      } else {
+        c.fx[gi] = fx;
+        c.fy[gi] = fy;
+        c.fz[gi] = fz;
+      }
+    }
+  }
+  if (COUNT) {
+    atomicAdd(&c.counters[coul ? 0 : 1], n_pairs);
+    atomicAdd(&c.counters[2], n_cand);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launch
+// ---------------------------------------------------------------------------
+constexpr size_t kTileLdsBytes = 48 * 1024;
+
+// Tile of the LJ pass: y/z extent of about 4-5 sigma, x extent such that a
+// tile holds about one particle per thread at the mean density, and its halo
+// stays within the LDS staging (the staging is sized for the halo of the
+// mean density with room to spare; denser halos are processed in chunks).
+static void tile_geometry(const PairParams &pp, const Sten &s, int64_t n, int rec_bytes, TileCtx *c) {
+  const Grid &g = pp.g;
+  const double hyz = std::fmax(g.L[1] / g.ny, g.L[2] / g.nz);
+  const int T = hyz >= 2.0 ? 2 : 4;  // 2 T^2 own row segments <= kTileMaxSegs
+  c->TY = std::min(T, g.ny);
+  c->TZ = std::min(T, g.nz);
+  c->s = s;
+  const double dens = (double)n / (double)g.ncell;  // records per cell (both species)
+  const int HYZ = (c->TY + 2 * s.y) * (c->TZ + 2 * s.z);
+  int tx = (int)(kTileThreads / std::fmax(dens * c->TY * c->TZ, 1e-9));
+  tx = std::max(1, std::min(tx, g.nx));
+  // the FP32 frame spans at most about 10 sigma either side of the tile centre
+  const double hx = g.L[0] / g.nx;
+  tx = std::max(1, std::min(tx, (int)(2.0 * (10.0 / hx - s.x))));
+  // records of the mean halo within 60 % of the most the staging may hold
+  auto cap_of = [&](int t) {
+    const int ncells = HYZ * (t + 2 * s.x);
+    const size_t fixed = ((size_t)(ncells + 1) * sizeof(int) + 15) / 16 * 16;
+    return fixed >= kTileLdsBytes ? 0 : (int)((kTileLdsBytes - fixed) / rec_bytes);
+  };
+  while (tx > 1 && 0.6 * cap_of(tx) < dens * HYZ * (tx + 2 * s.x)) --tx;
+  c->TX = tx;
+  // the staging holds the mean halo with 25 % headroom (about 7 standard
+  // deviations of a uniform fluid's halo count); denser halos go in chunks
+  const int want = (int)std::ceil(1.25 * dens * HYZ * (tx + 2 * s.x)) + 64;
+  c->cap = std::min(cap_of(tx), std::max(want, 256));
+  c->ntx = (g.nx + c->TX - 1) / c->TX;
+  c->nty = (g.ny + c->TY - 1) / c->TY;
+  c->ntz = (g.nz + c->TZ - 1) / c->TZ;
+}
+
+template <bool F32, bool GHOST>
+static void launch_tile_t(const TileCtx &c, hipStream_t st) {
+  const int ncells = (c.TY + 2 * c.s.y) * (c.TZ + 2 * c.s.z) * (c.TX + 2 * c.s.x);
+  const size_t lds = ((size_t)(ncells + 1) * sizeof(int) + 15) / 16 * 16 +
+                     (size_t)c.cap * (F32 ? sizeof(float4) : sizeof(double4)) +
+                     (c.kind == 1 ? (size_t)c.cap * sizeof(int) : 0);
+  const unsigned tiles = (unsigned)((int64_t)c.ntx * c.nty * c.ntz);
+  if (c.counters)
+    k_pair_tile<F32, GHOST, 0, true><<<tiles, kTileThreads, lds, st>>>(c);
+  else
+    k_pair_tile<F32, GHOST, 0, false><<<tiles, kTileThreads, lds, st>>>(c);
+}
+
+bool lj_tile_applicable(int prec, const PairParams &pp, int64_t n) {
+  if (prec != RBE_FP32C || !pp.do_lj || n <= 0) return false;
+  TileCtx c{};
+  tile_geometry(pp, pp.s_lj, n, (int)sizeof(float4), &c);
+  // a halo row of the mean density must fill at most an eighth of the
+  // staging, so only rows far denser than the mean need a chunk of their own
+  const double dens = (double)n / (double)pp.g.ncell;
+  const Grid &g = pp.g;
+  // rows about as wide as the LJ reach (wider rows waste most candidates);
+  // a halo row of the mean density fills at most an eighth of the staging
+  const double hyz = std::fmax(g.L[1] / g.ny, g.L[2] / g.nz);
+  return hyz <= 1.2 * std::sqrt(pp.rlj2) && c.cap >= 512 && dens * (c.TX + 2 * c.s.x) <= c.cap / 8.0;
+}
+
+void launch_lj_tile(int prec, const PairParams &pp, int64_t n, int iblk, const Sorted &s, const int32_t *cell_start,
+                    const GhostBuffers *gb, double *fx, double *fy, double *fz, unsigned long long *counters,
+                    int *err, hipStream_t st) {
+  if (n <= 0) return;
+  TileCtx c{};
+  c.pp = pp;
+  c.pf = make_pair_f32(pp);
+  c.kind = 0;
+  c.iblk = iblk;
+  c.accumulate = 0;
+  c.xq = s.xq;
+  c.cell_start = cell_start;
+  c.gxq = gb ? gb->xq : nullptr;
+  c.gcell_start = gb ? gb->cell_start : nullptr;
+  c.n = n;
+  c.fx = fx;
+  c.fy = fy;
+  c.fz = fz;
+  c.counters = counters;
+  c.err = err;
+  const bool f32 = prec == RBE_FP32C;
+  tile_geometry(pp, pp.s_lj, n, f32 ? (int)sizeof(float4) : (int)sizeof(double4), &c);
+  if (f32) {
+    if (gb) launch_tile_t<true, true>(c, st);
+    else launch_tile_t<true, false>(c, st);
+  } else {
+    if (gb) launch_tile_t<false, true>(c, st);
+    else launch_tile_t<false, false>(c, st);
+  }
+}
+
+}  // namespace rbe

@@ -484,3 +484,28 @@ def test_forces_degenerate_sizes(prec, tol, n, n_charged, r_core, p_shell, P):
     F = gpu_forces(p, s, prec=prec, m=m, w=w, ev=2)
     assert np.all(np.isfinite(F))
     assert rel_err(F, ref["F"]) < tol
+
+
+# ---------------------------------------------------------------------------
+# near-field tiles: a halo denser than the staging is processed in row chunks
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec,tol", [(rbe.FP64, TOL64), (rbe.FP32C, TOL32)])
+@pytest.mark.parametrize("ghost", [0.0, 6.0])
+def test_forces_dense_cluster_in_sparse_box(prec, tol, ghost):
+    """All particles packed (minimum separation 0.55) into a 9-sigma cube of a
+    40-sigma box: tiles sized for the mean density meet halos tens of times
+    denser, which they stage in chunks of rows; forces still match."""
+    L, n = 40.0, 2000
+    x, y, z = gen.rsa_positions(77, 0, n, [9.0, 9.0, 9.0], dmin=0.55)
+    q = gen.charges(77, 0, n, 150, 150)
+    s = dict(x=x + 15.0, y=y + 15.5, z=z + 16.0, q=q, id=np.arange(n, dtype=np.int32),
+             L=np.array([L, L, L]))
+    p = dict(seed=77, n=n, L=L, alpha=0.3, r_coul=6.0, r_lj=2.5, r_core=0.0, p_shell=0, P=50, dt=0.002,
+             ghost=ghost)
+    m, w = oracle.sample_k(p["seed"], 0, L, p["alpha"], p["P"])
+    ref = oracle_forces(p, s, m, w, cells=False)
+    for ncell in ((0, 0, 0), (64, 16, 16)):
+        F = gpu_forces(p, s, prec=prec, m=m, w=w, ncell=ncell)
+        e, r = rel_err(F, ref["F"]), max_row_err(F, ref["F"])
+        print(f"dense cluster prec={prec} ghost={ghost} ncell={ncell}: rel err {e:.3e}, max row {r:.3e}")
+        assert e < tol and r < (ROW64 if prec == rbe.FP64 else ROW32)
