@@ -20,12 +20,16 @@
 //
 // FP32C form: the turn reduction stays FP64; the hardware turn-argument
 // sine/cosine (v_sin_f32 / v_cos_f32 compute sin(2 pi x), cos(2 pi x)) run on
-// the FP32 fraction; sums are FP32 with Kahan compensation.
+// the FP32 fraction; sums are FP32: blocks of 8 terms summed plainly, the
+// block sums added with Kahan compensation.
 #include "fourier_device.h"
 
 namespace rbe {
 
 constexpr int kModesPerBlock = 256;
+// Terms summed in plain FP32 before their sum joins the Kahan-compensated
+// total (FP32C kernels).
+constexpr int kSumBlock = 8;
 
 void fill_turn_table(double2 *host, int n) {
   const long double two_pi = 6.283185307179586476925286766559005768L;
@@ -137,14 +141,32 @@ __global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f32c(const int32
   const double mx = mkd[l], my = mkd[P + l], mz = mkd[2 * P + l];
   float re = 0.f, re_c = 0.f, im = 0.f, im_c = 0.f;
   if (rep == 1) {
-#pragma unroll 4
-    for (int64_t j = j0; j < j1; ++j) {
+    // blocks of kSumBlock terms summed in FP32, each block sum added to the
+    // chunk's sum with Kahan compensation
+    int64_t j = j0;
+    for (; j + kSumBlock <= j1; j += kSumBlock) {
+      float br = 0.f, bi = 0.f;
+#pragma unroll
+      for (int u = 0; u < kSumBlock; ++u) {
+        const double4 s = sq[j + u];
+        const float t = (float)turn_fraction(mx, my, mz, s.x, s.y, s.z);
+        const float q = (float)s.w;
+        br = fmaf(q, __builtin_amdgcn_cosf(t), br);
+        bi = fmaf(q, __builtin_amdgcn_sinf(t), bi);
+      }
+      kahan_add(re, re_c, br);
+      kahan_add(im, im_c, bi);
+    }
+    float br = 0.f, bi = 0.f;
+    for (; j < j1; ++j) {
       const double4 s = sq[j];
       const float t = (float)turn_fraction(mx, my, mz, s.x, s.y, s.z);
       const float q = (float)s.w;
-      kahan_fma(re, re_c, q, __builtin_amdgcn_cosf(t));
-      kahan_fma(im, im_c, q, __builtin_amdgcn_sinf(t));
+      br = fmaf(q, __builtin_amdgcn_cosf(t), br);
+      bi = fmaf(q, __builtin_amdgcn_sinf(t), bi);
     }
+    kahan_add(re, re_c, br);
+    kahan_add(im, im_c, bi);
   } else {
     for (int64_t j = j0 + ph; j < j1; j += rep) {
       const double4 s = sq[j];
@@ -277,16 +299,31 @@ __global__ void __launch_bounds__(256) k_gather_f32c(const int32_t *__restrict__
   if (i >= *nq_ptr) return;
   const double4 s = sq[i];
   float gx = 0.f, gy = 0.f, gz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
-#pragma unroll 4
-  for (int l = 0; l < P; ++l) {
+  // blocks of kSumBlock modes summed in FP32, each block sum added with
+  // Kahan compensation
+  auto term = [&](int l, float &bx, float &by, float &bz) {
     const GatherMode gm = modes[l];
     const float t = (float)turn_fraction(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
-    const float cs = __builtin_amdgcn_cosf(t);
-    const float sn = __builtin_amdgcn_sinf(t);
-    const float g = fmaf(gm.af, cs, -gm.bf * sn);
-    kahan_fma(gx, cx, g, gm.mxf);
-    kahan_fma(gy, cy, g, gm.myf);
-    kahan_fma(gz, cz, g, gm.mzf);
+    const float g = fmaf(gm.af, __builtin_amdgcn_cosf(t), -gm.bf * __builtin_amdgcn_sinf(t));
+    bx = fmaf(g, gm.mxf, bx);
+    by = fmaf(g, gm.myf, by);
+    bz = fmaf(g, gm.mzf, bz);
+  };
+  int l = 0;
+  for (; l + kSumBlock <= P; l += kSumBlock) {
+    float bx = 0.f, by = 0.f, bz = 0.f;
+#pragma unroll
+    for (int u = 0; u < kSumBlock; ++u) term(l + u, bx, by, bz);
+    kahan_add(gx, cx, bx);
+    kahan_add(gy, cy, by);
+    kahan_add(gz, cz, bz);
+  }
+  {
+    float bx = 0.f, by = 0.f, bz = 0.f;
+    for (; l < P; ++l) term(l, bx, by, bz);
+    kahan_add(gx, cx, bx);
+    kahan_add(gy, cy, by);
+    kahan_add(gz, cz, bz);
   }
   const double q = s.w;
   fx[i] -= q * kx * ((double)gx - (double)cx);
