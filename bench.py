@@ -289,15 +289,20 @@ def eps_sampled_near(rbe, p, s, grid, precs, nrows, ev=0):
 
 
 # ---------------------------------------------------------------------------
-# rooflines (SURVEY-style accounting: in-cutoff pair terms only)
+# rooflines (algorithmic accounting: in-cutoff pair terms only)
 # ---------------------------------------------------------------------------
-# Fourier kernels, issue-slot model: per (charged particle, mode) two
-# transcendentals (sin, cos of the phase; quarter rate, 4 lane slots each)
-# plus 5 FP64 phase operations and 2 (structure factor) or 5 (gather) FMAs;
-# against 256 CU x 64 lanes x 2.4 GHz = 39.3 T lane-slots/s.
+# Fourier kernels, issue-slot model backed by rocprofv3 SQ counters
+# (profiles/step_subdomain64m_fp32c.md): the hardware sine and cosine of the
+# FP32C kernels are counted apart (SQ_INSTS_VALU_TRANS_F32) because they issue
+# on the transcendental pipe beside the other VALU work, so the bound used is
+# the VALU issue rate, 256 CU x 64 lanes x 2.4 GHz = 39.3 T lane-slots/s.
+# Algorithmic lane slots per (charged particle, mode): the FP64 phase (3
+# multiply-adds, rint, subtract: 5) and its conversion to FP32 (1), then 2
+# FMAs (structure factor) or 5 (gather: g = a cos - b sin, then g m
+# accumulated); the two transcendentals are reported as a rate of their own.
 PEAK_LANE_SLOTS_T = 256 * 64 * 2.4e9 / 1e12
-SLOTS_RHO_IK = 2 * 4 + 5 + 2
-SLOTS_GATHER_IK = 2 * 4 + 5 + 5
+SLOTS_RHO_IK = 5 + 1 + 2
+SLOTS_GATHER_IK = 5 + 1 + 5
 
 
 def pair_flops(c):
@@ -329,7 +334,9 @@ def kernel_roofline(name, kernels, cnt, nq, p, prec):
         work = per * nq * P
         ach = work / avg_s / 1e12
         return dict(kernel=name, bound="alu", achieved=ach, peak=PEAK_LANE_SLOTS_T, unit="Tslot/s",
-                    frac=ach / PEAK_LANE_SLOTS_T, work_per_launch=work, model="issue slots (quarter-rate sin/cos)")
+                    frac=ach / PEAK_LANE_SLOTS_T, work_per_launch=work,
+                    model="non-transcendental VALU issue slots; sin/cos on the transcendental pipe",
+                    transcendentals_per_s=2 * nq * P / avg_s)
     per_bytes = {"kick_drift": BYTES_KICK_DRIFT, "kick": BYTES_KICK}.get(name)
     if per_bytes is None:
         return None
@@ -347,7 +354,11 @@ def measured_traffic(workload, name, grid=None, form=None):
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
-    d = json.load(open(path)).get(workload)
+    recs = json.load(open(path))
+    # a record per workload and form ("subdomain64m:fp64"), or one for the
+    # workload whose "form" names the form it was counted on
+    d = recs.get(f"{workload}:{form}") if form is not None else None
+    d = d or recs.get(workload)
     if not d or name not in d.get("kinds", {}):
         return None
     if form is not None and d.get("form") not in (None, form):

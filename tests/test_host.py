@@ -91,6 +91,27 @@ def test_measured_traffic_needs_same_sources_and_grid(tmp_path, monkeypatch):
     assert b.measured_traffic("w", "pair_charged", [6, 2, 2]) is None  # sources changed since
 
 
+def test_measured_traffic_is_per_form(tmp_path, monkeypatch):
+    b = load_bench()
+    import hashlib
+    src = tmp_path / "k.hip"
+    src.write_text("kernel\n")
+    h = hashlib.sha256(b"kernel\n").hexdigest()
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    rec = {"w": {"files": ["k.hip"], "source_sha256": h, "grid": [6, 2, 2], "form": "fp32c",
+                 "kinds": {"pair_neutral": {"read_bytes": 100.0, "write_bytes": 20.0}}},
+           "w:fp64": {"files": ["k.hip"], "source_sha256": h, "grid": [6, 2, 2], "form": "fp64",
+                      "kinds": {"pair_neutral": {"read_bytes": 300.0, "write_bytes": 40.0}}}}
+    (prof / "traffic.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(b, "ROOT", str(tmp_path))
+    assert b.measured_traffic("w", "pair_neutral", [6, 2, 2], "fp32c") == 120.0
+    assert b.measured_traffic("w", "pair_neutral", [6, 2, 2], "fp64") == 340.0
+    rec.pop("w:fp64")
+    (prof / "traffic.json").write_text(json.dumps(rec))
+    assert b.measured_traffic("w", "pair_neutral", [6, 2, 2], "fp64") is None  # counted on the other form
+
+
 def test_tuner_grid_candidates():
     from paper_2609_02694_amd import tune
     g = tune.candidate_grids(30.0, 6.0, edges=(3.0, 3.05, 5.0), xsplits=(1, 2))
