@@ -108,7 +108,9 @@ typedef struct {
    r_lj <= r_core, which it requires, so the batch is spent on charges). */
 enum { RBE_SHELL_ALL = 0, RBE_SHELL_CHARGED = 1 };
 
-#define RBE_MAX_P 4096
+/* Sampled mode counts stay far below this; the bound is set by the full
+   lattice of an exact Ewald reference run (rbe_lattice_modes). */
+#define RBE_MAX_P 262144
 #define RBE_MAX_SHELL_BATCH 32
 
 /* Caller-owned particle state (device arrays of length n). The library never
@@ -186,6 +188,33 @@ int rbe_build_cells(rbe_ctx *ctx, const double *x, const double *y, const double
    paths give identical bits. */
 int rbe_sample_k(const rbe_params *p /* host */, uint64_t eval, int32_t *m, double *w, int on_device,
                  void *stream);
+
+/* The Ewald reciprocal sum (Eq. 5 with every lattice mode, Sec. 2.1) as a
+   mode table: the modes 0 < |k| <= k_max, k = 2 pi (m_x/L_x, m_y/L_y, m_z/L_z),
+   of the half space (m_x > 0, or m_x = 0 and m_y > 0, or m_x = m_y = 0 and
+   m_z > 0), each standing for itself and -k, with weight
+   w = 2 * 4 pi exp(-k^2/(4 alpha)) / (V k^2). Given to rbe_forces,
+   rbe_energy or rbe_set_modes on a context with P = the count, the Fourier
+   part is the deterministic Ewald sum truncated at k_max instead of the
+   importance sample of Eq. 9 (a reference for accuracy checks; its cost
+   grows as k_max^3 V). Host function: reads p->L and p->alpha only.
+   m == NULL: only *count is set. Otherwise m (host, 3 rows of cap entries:
+   m_x, then m_y, then m_z) and w (host, cap entries) are filled, cap must
+   equal the count (RBE_ERANGE otherwise), in the order of increasing m_x,
+   then m_y, then m_z. RBE_ERANGE also when k_max spans more than 4096 modes
+   along an axis. */
+int rbe_lattice_modes(const rbe_params *p /* host */, double k_max, int32_t *m /* host */, double *w /* host */,
+                      int32_t cap, int32_t *count /* host */);
+
+/* Fixes the mode table of a single-system context: from this call on,
+   rbe_forces and rbe_energy with m == NULL and every step of rbe_step use
+   (m, w) (device, 3*P and P entries as rbe_sample_k lays them out; copied
+   on `stream`, so the caller may free them after the stream has run)
+   instead of drawing the sample of each evaluation. With the table of
+   rbe_lattice_modes and r_core = 0 the dynamics is plain Ewald molecular
+   dynamics, the reference the random batch estimates are compared with.
+   m == w == NULL returns to drawing. RBE_EINVAL on a batched context. */
+int rbe_set_modes(rbe_ctx *ctx, const int32_t *m, const double *w, void *stream);
 
 /* One force evaluation F = F^N + F^F on the state as given (never reorders
    it): writes s->fx, fy, fz in the caller's particle order. (m, w) is the

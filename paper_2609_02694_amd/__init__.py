@@ -21,12 +21,12 @@ FP64, FP32C = 0, 1
 KDIST_GAUSS, KDIST_GAUSS_OVER_K2 = 0, 1
 SHELL_ALL, SHELL_CHARGED = 0, 1
 TERM_LJ, TERM_COUL_REAL, TERM_FOURIER, TERM_ALL = 1, 2, 4, 7
-MAX_P = 4096
+MAX_P = 262144
 MAX_SHELL_BATCH = 32
 
 EXPORTED = ["rbe_create", "rbe_create_batch", "rbe_destroy", "rbe_last_error", "rbe_build_cells", "rbe_sample_k",
             "rbe_forces", "rbe_energy", "rbe_step", "rbe_sync_check", "rbe_set_counting", "rbe_get_counters", "rbe_set_timing",
-            "rbe_get_timing", "rbe_forces_noalloc"]
+            "rbe_get_timing", "rbe_forces_noalloc", "rbe_lattice_modes", "rbe_set_modes"]
 NOALLOC_MAX_N = 32768
 NOALLOC_MAX_P = 1024
 NOALLOC_MAX_KEYS = 131072
@@ -97,6 +97,8 @@ def load():
         "rbe_set_timing": [vp, ctypes.c_int],
         "rbe_get_timing": [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), vp],
         "rbe_forces_noalloc": [P, ctypes.POINTER(State), vp, vp, u64, vp, vp, vp],
+        "rbe_lattice_modes": [P, ctypes.c_double, vp, vp, i32, ctypes.POINTER(i32)],
+        "rbe_set_modes": [vp, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -222,6 +224,21 @@ def sample_k(params: Params, ev: int, on_device=False, stream=None):
     return m.reshape(3, P), w
 
 
+def lattice_modes(params: Params, k_max: float):
+    """Ewald reciprocal-sum mode table (m[3, P], w[P], numpy) of the half-space
+    lattice modes with 0 < |k| <= k_max (weights doubled for -k)."""
+    import numpy as np
+    lib = load()
+    cnt = ctypes.c_int32()
+    _check(lib, None, lib.rbe_lattice_modes(ctypes.byref(params), k_max, None, None, 0, ctypes.byref(cnt)))
+    P = cnt.value
+    m = np.empty(3 * P, np.int32)
+    w = np.empty(P, np.float64)
+    _check(lib, None, lib.rbe_lattice_modes(ctypes.byref(params), k_max, ctypes.c_void_p(m.ctypes.data),
+                                            ctypes.c_void_p(w.ctypes.data), P, ctypes.byref(cnt)))
+    return m.reshape(3, P), w
+
+
 def forces_noalloc(params: Params, st: "Particles", m, w, ev: int = 0, rho_out=None, status_out=None,
                    stream=None):
     """rbe_forces without a context or any device allocation (the library's
@@ -311,6 +328,11 @@ class Context:
     def step(self, st: Particles, nsteps: int, first_eval: int, stream=None):
         s = st.as_struct()
         self._ok(self.lib.rbe_step(self.h, ctypes.byref(s), nsteps, first_eval, _stream(stream)))
+
+    def set_modes(self, m=None, w=None, stream=None):
+        """Fix the mode table (device m[3, P] int32, w[P] float64) for every
+        later evaluation with no explicit modes; None returns to drawing."""
+        self._ok(self.lib.rbe_set_modes(self.h, _ptr(m), _ptr(w), _stream(stream)))
 
     def sync_check(self, stream=None):
         self._ok(self.lib.rbe_sync_check(self.h, _stream(stream)))

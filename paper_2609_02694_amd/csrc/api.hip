@@ -75,6 +75,7 @@ struct rbe_ctx {
   int32_t *m_dev = nullptr;  // [kSampleSteps][3][P] mode samples (rbe_step draws them ahead)
   double *w_dev = nullptr;   // [kSampleSteps][P]
   double *mkd_dev = nullptr; // [kSampleSteps][3][P] the same modes as doubles
+  bool fixed_modes = false;  // rbe_set_modes: slot 0 of m_dev/w_dev/mkd_dev is the caller's table
   double *mean_part = nullptr, *mean = nullptr;
   double *epart = nullptr;   // energy partial sums
   double *nh_part = nullptr, *nh_scale = nullptr;  // thermostat: |v|^2 partials, pending velocity scaling
@@ -781,6 +782,10 @@ static int eval_sorted(rbe_ctx *c, int64_t n, const int32_t *m, const double *w,
     FourierBuffers fb = c->fb;
     if (mkd_pre) {
       fb.mkd = const_cast<double *>(mkd_pre);  // drawn ahead with the modes
+    } else if (!m && c->fixed_modes) {
+      m = c->m_dev;  // the fixed table (rbe_set_modes), converted when it was set
+      w = c->w_dev;
+      fb.mkd = c->mkd_dev;
     } else {
       TScope ts(c, RBE_TK_SAMPLE, st);
       if (!m) {
@@ -1058,6 +1063,66 @@ static int batch_step(rbe_ctx *c, rbe_state *s, int32_t nsteps, uint64_t first_e
   return RBE_OK;
 }
 
+extern "C" int rbe_lattice_modes(const rbe_params *p, double k_max, int32_t *m, double *w, int32_t cap,
+                                 int32_t *count) {
+  if (!p || !count) return create_fail(RBE_EINVAL, "null argument");
+  if (!(p->alpha > 0) || !(k_max > 0) || !std::isfinite(k_max)) return create_fail(RBE_EINVAL, "bad alpha or k_max");
+  for (int d = 0; d < 3; ++d)
+    if (!(p->L[d] > 0) || !std::isfinite(p->L[d])) return create_fail(RBE_EINVAL, "bad box");
+  const double two_pi = 6.283185307179586476925286766559005768;
+  int64_t M[3];
+  for (int d = 0; d < 3; ++d) {
+    const double md = std::floor(k_max * p->L[d] / two_pi);
+    if (md > 4096) return create_fail(RBE_ERANGE, "k_max spans more than 4096 modes along an axis");
+    M[d] = (int64_t)md;
+  }
+  const double V = p->L[0] * p->L[1] * p->L[2];
+  const double k2max = k_max * k_max;
+  int64_t cnt = 0;
+  // half space: m_x > 0, or m_x = 0 and m_y > 0, or m_x = m_y = 0 and m_z > 0;
+  // each mode stands for itself and its negative (same term), so its weight
+  // is twice the Ewald coefficient
+  for (int64_t mx = 0; mx <= M[0]; ++mx)
+    for (int64_t my = mx ? -M[1] : 0; my <= M[1]; ++my)
+      for (int64_t mz = (mx || my) ? -M[2] : 1; mz <= M[2]; ++mz) {
+        const double kx = two_pi * (double)mx / p->L[0], ky = two_pi * (double)my / p->L[1],
+                     kz = two_pi * (double)mz / p->L[2];
+        const double k2 = kx * kx + ky * ky + kz * kz;
+        if (k2 > k2max) continue;
+        if (m) {
+          if (cnt >= cap) return create_fail(RBE_ERANGE, "cap is smaller than the mode count");
+          m[cnt] = (int32_t)mx;
+          m[cap + cnt] = (int32_t)my;
+          m[2 * (int64_t)cap + cnt] = (int32_t)mz;
+          w[cnt] = 2.0 * 4.0 * M_PI * std::exp(-k2 / (4.0 * p->alpha)) / (V * k2);
+        }
+        ++cnt;
+      }
+  if (cnt > INT32_MAX) return create_fail(RBE_ERANGE, "mode count exceeds int32");
+  *count = (int32_t)cnt;
+  if (m && cnt != cap) return create_fail(RBE_ERANGE, "cap must equal the mode count");
+  return RBE_OK;
+}
+
+extern "C" int rbe_set_modes(rbe_ctx *c, const int32_t *m, const double *w, void *stream) {
+  if (!c) return RBE_EINVAL;
+  if (c->batched()) return c->fail(RBE_EINVAL, "rbe_set_modes is not available on a batched context");
+  if ((m == nullptr) != (w == nullptr)) return c->fail(RBE_EINVAL, "m and w must both be given or both be NULL");
+  if (!m) {
+    c->fixed_modes = false;
+    return RBE_OK;
+  }
+  HIP_TRY(c, hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t P = c->p.P;
+  HIP_TRY(c, hipMemcpyAsync(c->m_dev, m, sizeof(int32_t) * 3 * P, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, hipMemcpyAsync(c->w_dev, w, sizeof(double) * P, hipMemcpyDeviceToDevice, st));
+  launch_modes_to_double((int)P, c->m_dev, c->mkd_dev, st);
+  HIP_TRY(c, hipGetLastError());
+  c->fixed_modes = true;
+  return RBE_OK;
+}
+
 // One force evaluation of a single-system context on the state as given:
 // charge checks, binning, sorted records, near field and Fourier part, Eq. 12,
 // forces scattered back to the caller's order.
@@ -1117,7 +1182,10 @@ extern "C" int rbe_energy(rbe_ctx *c, const rbe_state *s, const int32_t *m, cons
   const int P = c->p.P;
   EnergyFinal fin{};
   if (fourier) {
-    if (!m) {
+    if (!m && c->fixed_modes) {
+      m = c->m_dev;
+      w = c->w_dev;
+    } else if (!m) {
       launch_sample_modes(c->mt, c->cdf_dev, c->p.seed, eval, P, c->m_dev, c->w_dev, c->err, st);
       m = c->m_dev;
       w = c->w_dev;
@@ -1239,8 +1307,9 @@ extern "C" int rbe_step(rbe_ctx *c, rbe_state *s, int32_t nsteps, uint64_t first
                                                                    c->srt.xq, c->srt.sq, c->srt.id, inv);
     }
     const int64_t P = c->p.P;
-    const int ks = k % kSampleSteps;
-    if (fourier && ks == 0) {
+    // a fixed table (rbe_set_modes) sits in slot 0 and is never redrawn
+    const int ks = c->fixed_modes ? 0 : k % kSampleSteps;
+    if (fourier && !c->fixed_modes && ks == 0) {
       // the mode samples of the next kSampleSteps evaluations in one launch
       TScope ts(c, RBE_TK_SAMPLE, st);
       launch_sample_modes(c->mt, c->cdf_dev, c->p.seed, first_eval + (uint64_t)k, (int)P, c->m_dev, c->w_dev, c->err,

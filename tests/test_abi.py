@@ -147,3 +147,46 @@ def test_create_batch_requires_shared_physics():
     p = [rbe.make_params(12.6, 0.3, 6.0, 2.5, 100), rbe.make_params(11.0, 0.3, 6.0, 2.5, 100)]
     rc, msg = _create_batch(p, [0, 10, 20])
     assert rc == rbe.RBE_EBOX and "replica 1" in msg
+
+
+def test_lattice_modes_are_the_oracle_lattice_folded_to_a_half_space():
+    """rbe_lattice_modes: every mode of the oracle's full lattice with
+    0 < |k| <= k_max appears once, as itself or as its negative, with twice
+    the oracle's Ewald weight (same sum, half the modes)."""
+    import numpy as np
+    from oracle import full_lattice
+    L, alpha, kmax = (9.0, 10.0, 11.5), 0.6, 4.0
+    p = rbe.make_params(L, alpha, 4.0, 2.5, 100)
+    m, w = rbe.lattice_modes(p, kmax)
+    M = [int(np.floor(kmax * Ld / (2 * np.pi))) + 1 for Ld in L]
+    mo, wo = full_lattice(L, alpha, M)
+    k2 = sum((2 * np.pi * mo[d] / L[d]) ** 2 for d in range(3))
+    keep = (k2 > 0) & (k2 <= kmax * kmax)
+    ref = {tuple(int(v) for v in mo[:, j]): wo[j] for j in np.nonzero(keep)[0]}
+    assert 2 * m.shape[1] == len(ref)
+    seen = set()
+    for j in range(m.shape[1]):
+        t = tuple(int(v) for v in m[:, j])
+        neg = tuple(-v for v in t)
+        assert t in ref and neg in ref and t not in seen and neg not in seen
+        seen.update((t, neg))
+        assert w[j] == pytest.approx(2 * ref[t], rel=1e-14)
+    # half space: first nonzero component positive
+    for j in range(m.shape[1]):
+        first = next(v for v in m[:, j] if v != 0)
+        assert first > 0
+
+
+def test_lattice_modes_rejects_a_wrong_cap():
+    import numpy as np
+    lib = rbe.load()
+    p = rbe.make_params(10.0, 0.5, 4.0, 2.5, 100)
+    cnt = ctypes.c_int32()
+    assert lib.rbe_lattice_modes(ctypes.byref(p), 3.0, None, None, 0, ctypes.byref(cnt)) == rbe.RBE_OK
+    n = cnt.value
+    m = np.empty(3 * (n + 1), np.int32)
+    w = np.empty(n + 1)
+    rc = lib.rbe_lattice_modes(ctypes.byref(p), 3.0, ctypes.c_void_p(m.ctypes.data), ctypes.c_void_p(w.ctypes.data),
+                               n + 1, ctypes.byref(cnt))
+    assert rc == rbe.RBE_ERANGE and "cap" in lib.rbe_last_error(None).decode()
+    assert lib.rbe_lattice_modes(ctypes.byref(p), -1.0, None, None, 0, ctypes.byref(cnt)) == rbe.RBE_EINVAL
