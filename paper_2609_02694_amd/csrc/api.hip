@@ -419,7 +419,9 @@ extern "C" int rbe_create(rbe_ctx **out, const rbe_params *p, int64_t n_max, int
   if (nchunk > 8192) nchunk = 8192;
   c->fb.nchunk_max = (int)nchunk;
   c->fb.mkd = b.alloc<double>(3 * P);
-  c->fb.part = b.alloc<double2>(nchunk * P);
+  // the partial launch never uses more chunks than this for any nq <= n_max
+  c->fb.part = b.alloc<double2>((int64_t)rho_max_chunks(n_max, P, (int)nchunk) * P);
+  c->fb.gpart = b.alloc<double4>(kGatherPartMax);
   c->fb.rho = b.alloc<double>(2 * P);
   c->fb.modes = b.alloc<GatherMode>(P);
   c->fb.turn_tab = b.alloc<double2>(kTurnTableEntries);
@@ -1542,6 +1544,7 @@ extern "C" int rbe_forces_noalloc(const rbe_params *p, const rbe_state *s, const
   c.fb.part = cv.take<double2>((int64_t)kNoallocChunks * P);
   c.fb.rho = cv.take<double>(2 * (int64_t)P);
   c.fb.modes = cv.take<GatherMode>(P);
+  c.fb.gpart = nullptr;  // no mode split in the scratch-only form
   c.mean_part = cv.take<double>(3 * (int64_t)mean_blocks(n) + 3);
   c.mean = cv.take<double>(3);
   c.err = cv.take<int>(1);

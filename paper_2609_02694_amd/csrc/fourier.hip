@@ -69,49 +69,48 @@ __global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f64(const int32_
                                                                      const double2 *__restrict__ turn_tab,
                                                                      double2 *__restrict__ part) {
   static_assert(kModesPerBlock == kTurnTable, "one table entry per thread");
+  __shared__ double2 tab[kTurnTable];
+  __shared__ double4 rec[kModesPerBlock];  // the chunk's records, staged a round at a time
   const int64_t nq = *nq_ptr;
   int nchunks;
   const int chunk = rho_layout(nq, P, nchunk_max, &nchunks);
-  if ((int)blockIdx.x >= nchunks) return;
-  __shared__ double2 tab[kTurnTable];
+  if ((int)blockIdx.x >= nchunks) return;  // uniform over the block
   tab[threadIdx.x] = turn_tab[threadIdx.x];
-  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int l0 = blockIdx.y * kModesPerBlock + (threadIdx.x & ~63);  // first mode of this wave
-  const int a = min(64, P - l0);                                      // modes of this wave
-  if (a <= 0) return;
+  const int a = max(0, min(64, P - l0));  // modes of this wave (0: it only stages records)
   const int64_t j0 = (int64_t)blockIdx.x * chunk;
   const int64_t j1 = min(nq, j0 + chunk);
-  if (a == 64) {
-    const int l = l0 + lane;
-    const double mx = mkd[l], my = mkd[P + l], mz = mkd[2 * P + l];
-    double re = 0.0, im = 0.0;
-#pragma unroll 4
-    for (int64_t j = j0; j < j1; ++j) {
-      const double4 s = sq[j];
-      const double t = turn_fraction(mx, my, mz, s.x, s.y, s.z);
-      double sn, cs;
-      sincos_turn_tab_f64(t, tab, &sn, &cs);
-      re = fma(s.w, cs, re);
-      im = fma(s.w, sn, im);
-    }
-    part[(int64_t)blockIdx.x * P + l] = make_double2(re, im);
-    return;
-  }
-  const int rep = wave_rep(a);
+  // a == 64: one mode per lane; fewer: rep lanes per mode, each taking every
+  // rep-th record, added by a fixed butterfly
+  const int rep = a == 64 ? 1 : (a > 0 ? wave_rep(a) : 64);
   const int mi = lane / rep, ph = lane % rep;
   const bool active = mi < a;
   const int l = l0 + (active ? mi : 0);
-  const double mx = mkd[l], my = mkd[P + l], mz = mkd[2 * P + l];
-  double re = 0.0, im = 0.0;
-  for (int64_t j = j0 + ph; j < j1; j += rep) {
-    const double4 s = sq[j];
-    const double t = turn_fraction(mx, my, mz, s.x, s.y, s.z);
-    double sn, cs;
-    sincos_turn_tab_f64(t, tab, &sn, &cs);
-    re = fma(s.w, cs, re);
-    im = fma(s.w, sn, im);
+  double mx = 0.0, my = 0.0, mz = 0.0;
+  if (a > 0) {
+    mx = mkd[l];
+    my = mkd[P + l];
+    mz = mkd[2 * P + l];
   }
+  double re = 0.0, im = 0.0;
+  for (int64_t b = j0; b < j1; b += kModesPerBlock) {
+    const int cnt = (int)min((int64_t)kModesPerBlock, j1 - b);
+    __syncthreads();  // the table is written; the previous round is no longer read
+    if ((int)threadIdx.x < cnt) rec[threadIdx.x] = sq[b + threadIdx.x];
+    __syncthreads();
+    if (a == 0) continue;
+#pragma unroll 4
+    for (int u = ph; u < cnt; u += rep) {
+      const double4 r = rec[u];
+      const double t = turn_fraction(mx, my, mz, r.x, r.y, r.z);
+      double sn, cs;
+      sincos_turn_tab_f64(t, tab, &sn, &cs);
+      re = fma(r.w, cs, re);
+      im = fma(r.w, sn, im);
+    }
+  }
+  if (a == 0) return;
   for (int o = rep >> 1; o > 0; o >>= 1) {
     re += __shfl_xor(re, o, 64);
     im += __shfl_xor(im, o, 64);
@@ -119,63 +118,79 @@ __global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f64(const int32_
   if (active && ph == 0) part[(int64_t)blockIdx.x * P + l] = make_double2(re, im);
 }
 
+// Record: x, y, z as doubles, the FP32 charge in the low word of w.
+__device__ inline float rec_q(const double4 &r) { return __int_as_float(__double2loint(r.w)); }
+
 __global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f32c(const int32_t *__restrict__ nq_ptr, int P,
                                                                       int nchunk_max,
                                                                       const double4 *__restrict__ sq,
                                                                       const double *__restrict__ mkd,
                                                                       double2 *__restrict__ part) {
+  __shared__ double4 rec[kModesPerBlock];
   const int64_t nq = *nq_ptr;
   int nchunks;
   const int chunk = rho_layout(nq, P, nchunk_max, &nchunks);
-  if ((int)blockIdx.x >= nchunks) return;
+  if ((int)blockIdx.x >= nchunks) return;  // uniform over the block
   const int lane = threadIdx.x & 63;
   const int l0 = blockIdx.y * kModesPerBlock + (threadIdx.x & ~63);
-  const int a = min(64, P - l0);
-  if (a <= 0) return;
+  // a wave past the last mode still stages records for the others
+  const int a = max(0, min(64, P - l0));
   const int64_t j0 = (int64_t)blockIdx.x * chunk;
   const int64_t j1 = min(nq, j0 + chunk);
-  const int rep = a == 64 ? 1 : wave_rep(a);
+  const int rep = a == 64 ? 1 : (a > 0 ? wave_rep(a) : 64);
   const int mi = lane / rep, ph = lane % rep;
   const bool active = mi < a;
   const int l = l0 + (active ? mi : 0);
-  const double mx = mkd[l], my = mkd[P + l], mz = mkd[2 * P + l];
+  double mx = 0.0, my = 0.0, mz = 0.0;
+  if (a > 0) {
+    mx = mkd[l];
+    my = mkd[P + l];
+    mz = mkd[2 * P + l];
+  }
   float re = 0.f, re_c = 0.f, im = 0.f, im_c = 0.f;
-  if (rep == 1) {
-    // blocks of kSumBlock terms summed in FP32, each block sum added to the
-    // chunk's sum with Kahan compensation
-    int64_t j = j0;
-    for (; j + kSumBlock <= j1; j += kSumBlock) {
-      float br = 0.f, bi = 0.f;
+  auto term = [&](const double4 &r, float &br, float &bi) {
+    const float t = (float)turn_fraction(mx, my, mz, r.x, r.y, r.z);
+    const float q = rec_q(r);
+    br = fmaf(q, __builtin_amdgcn_cosf(t), br);
+    bi = fmaf(q, __builtin_amdgcn_sinf(t), bi);
+  };
+  for (int64_t b = j0; b < j1; b += kModesPerBlock) {
+    const int cnt = (int)min((int64_t)kModesPerBlock, j1 - b);
+    __syncthreads();  // the previous round's records are no longer read
+    if ((int)threadIdx.x < cnt) {
+      const double4 s = sq[b + threadIdx.x];
+      rec[threadIdx.x] = make_double4(s.x, s.y, s.z, __hiloint2double(0, __float_as_int((float)s.w)));
+    }
+    __syncthreads();
+    if (a == 0) continue;
+    if (rep == 1) {
+      // blocks of kSumBlock terms summed in FP32, each block sum added to
+      // the chunk's sum with Kahan compensation
+      int u = 0;
+      for (; u + kSumBlock <= cnt; u += kSumBlock) {
+        double4 r[kSumBlock];  // all loads issued before the arithmetic
 #pragma unroll
-      for (int u = 0; u < kSumBlock; ++u) {
-        const double4 s = sq[j + u];
-        const float t = (float)turn_fraction(mx, my, mz, s.x, s.y, s.z);
-        const float q = (float)s.w;
-        br = fmaf(q, __builtin_amdgcn_cosf(t), br);
-        bi = fmaf(q, __builtin_amdgcn_sinf(t), bi);
+        for (int v = 0; v < kSumBlock; ++v) r[v] = rec[u + v];
+        float br = 0.f, bi = 0.f;
+#pragma unroll
+        for (int v = 0; v < kSumBlock; ++v) term(r[v], br, bi);
+        kahan_add(re, re_c, br);
+        kahan_add(im, im_c, bi);
       }
+      float br = 0.f, bi = 0.f;
+      for (; u < cnt; ++u) term(rec[u], br, bi);
       kahan_add(re, re_c, br);
       kahan_add(im, im_c, bi);
-    }
-    float br = 0.f, bi = 0.f;
-    for (; j < j1; ++j) {
-      const double4 s = sq[j];
-      const float t = (float)turn_fraction(mx, my, mz, s.x, s.y, s.z);
-      const float q = (float)s.w;
-      br = fmaf(q, __builtin_amdgcn_cosf(t), br);
-      bi = fmaf(q, __builtin_amdgcn_sinf(t), bi);
-    }
-    kahan_add(re, re_c, br);
-    kahan_add(im, im_c, bi);
-  } else {
-    for (int64_t j = j0 + ph; j < j1; j += rep) {
-      const double4 s = sq[j];
-      const float t = (float)turn_fraction(mx, my, mz, s.x, s.y, s.z);
-      const float q = (float)s.w;
-      kahan_fma(re, re_c, q, __builtin_amdgcn_cosf(t));
-      kahan_fma(im, im_c, q, __builtin_amdgcn_sinf(t));
+    } else {
+      for (int u = ph; u < cnt; u += rep) {
+        const double4 r = rec[u];
+        const float t = (float)turn_fraction(mx, my, mz, r.x, r.y, r.z);
+        kahan_fma(re, re_c, rec_q(r), __builtin_amdgcn_cosf(t));
+        kahan_fma(im, im_c, rec_q(r), __builtin_amdgcn_sinf(t));
+      }
     }
   }
+  if (a == 0) return;
   double dre = (double)re - (double)re_c, dim = (double)im - (double)im_c;
   for (int o = rep >> 1; o > 0; o >>= 1) {
     dre += __shfl_xor(dre, o, 64);
@@ -258,23 +273,28 @@ void launch_rho_final(const int32_t *nq, int P, const FourierBuffers &fb, const 
 // ---------------------------------------------------------------------------
 // force gather (adds F^F into f for the charged range)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kTurnTable) k_gather_f64(const int32_t *__restrict__ nq_ptr, int P,
+// Mode groups: blockIdx.y = g sums the modes [g M, min(P, (g + 1) M)); with
+// one group the force is applied here, with several the group's sums go to
+// gpart[g * stride + i] and k_gather_reduce adds the groups in order.
+__global__ void __launch_bounds__(kTurnTable) k_gather_f64(const int32_t *__restrict__ nq_ptr, int P, int M,
                                                            const double4 *__restrict__ sq,
                                                            const GatherMode *__restrict__ modes,
                                                            const double2 *__restrict__ turn_tab, double kx,
                                                            double ky, double kz, double *__restrict__ fx,
-                                                           double *__restrict__ fy, double *__restrict__ fz) {
-  const int64_t nq = *nq_ptr;
-  if ((int64_t)blockIdx.x * blockDim.x >= nq) return;
+                                                           double *__restrict__ fy, double *__restrict__ fz,
+                                                           double4 *__restrict__ gpart, int64_t stride) {
   __shared__ double2 tab[kTurnTable];
+  const int64_t nq = *nq_ptr;
+  if ((int64_t)blockIdx.x * blockDim.x >= nq) return;  // uniform over the block
   tab[threadIdx.x] = turn_tab[threadIdx.x];
   __syncthreads();
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= nq) return;
   const double4 s = sq[i];
   double gx = 0.0, gy = 0.0, gz = 0.0;
+  const int lb = blockIdx.y * M, le = min(P, lb + M);
 #pragma unroll 4
-  for (int l = 0; l < P; ++l) {
+  for (int l = lb; l < le; ++l) {
     const GatherMode gm = modes[l];
     const double t = turn_fraction(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
     double sn, cs;
@@ -284,23 +304,31 @@ __global__ void __launch_bounds__(kTurnTable) k_gather_f64(const int32_t *__rest
     gy = fma(g, gm.my, gy);
     gz = fma(g, gm.mz, gz);
   }
+  if (gpart) {
+    gpart[blockIdx.y * stride + i] = make_double4(gx, gy, gz, 0.0);
+    return;
+  }
   const double q = s.w;
   fx[i] -= q * kx * gx;
   fy[i] -= q * ky * gy;
   fz[i] -= q * kz * gz;
 }
 
-__global__ void __launch_bounds__(256) k_gather_f32c(const int32_t *__restrict__ nq_ptr, int P,
-                                                     const double4 *__restrict__ sq,
-                                                     const GatherMode *__restrict__ modes, double kx, double ky,
-                                                     double kz, double *__restrict__ fx, double *__restrict__ fy,
-                                                     double *__restrict__ fz) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+// One thread per charged particle; every lane reads the same mode at a time
+// (wave-uniform scalar loads, which deliver a record once per wave: staging
+// the modes in LDS instead measured slower, the broadcast LDS reads costing
+// more than the load latency they hide).
+constexpr int kGatherThreads = 256;
+__global__ void __launch_bounds__(kGatherThreads) k_gather_f32c(const int32_t *__restrict__ nq_ptr, int P, int M,
+                                                                const double4 *__restrict__ sq,
+                                                                const GatherMode *__restrict__ modes, double kx,
+                                                                double ky, double kz, double *__restrict__ fx,
+                                                                double *__restrict__ fy, double *__restrict__ fz,
+                                                                double4 *__restrict__ gpart, int64_t stride) {
+  const int64_t i = blockIdx.x * (int64_t)kGatherThreads + threadIdx.x;
   if (i >= *nq_ptr) return;
   const double4 s = sq[i];
   float gx = 0.f, gy = 0.f, gz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
-  // blocks of kSumBlock modes summed in FP32, each block sum added with
-  // Kahan compensation
   auto term = [&](int l, float &bx, float &by, float &bz) {
     const GatherMode gm = modes[l];
     const float t = (float)turn_fraction(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
@@ -309,8 +337,12 @@ __global__ void __launch_bounds__(256) k_gather_f32c(const int32_t *__restrict__
     by = fmaf(g, gm.myf, by);
     bz = fmaf(g, gm.mzf, bz);
   };
-  int l = 0;
-  for (; l + kSumBlock <= P; l += kSumBlock) {
+  // blocks of kSumBlock modes summed in FP32, each block sum added with
+  // Kahan compensation (a group's first mode is a multiple of kSumBlock, so
+  // the blocks run over the modes in order and only the last one is short)
+  const int lb = blockIdx.y * M, le = min(P, lb + M);
+  int l = lb;
+  for (; l + kSumBlock <= le; l += kSumBlock) {
     float bx = 0.f, by = 0.f, bz = 0.f;
 #pragma unroll
     for (int u = 0; u < kSumBlock; ++u) term(l + u, bx, by, bz);
@@ -320,15 +352,57 @@ __global__ void __launch_bounds__(256) k_gather_f32c(const int32_t *__restrict__
   }
   {
     float bx = 0.f, by = 0.f, bz = 0.f;
-    for (; l < P; ++l) term(l, bx, by, bz);
+    for (; l < le; ++l) term(l, bx, by, bz);
     kahan_add(gx, cx, bx);
     kahan_add(gy, cy, by);
     kahan_add(gz, cz, bz);
   }
+  const double sx = (double)gx - (double)cx, sy = (double)gy - (double)cy, sz = (double)gz - (double)cz;
+  if (gpart) {
+    gpart[blockIdx.y * stride + i] = make_double4(sx, sy, sz, 0.0);
+    return;
+  }
   const double q = s.w;
-  fx[i] -= q * kx * ((double)gx - (double)cx);
-  fy[i] -= q * ky * ((double)gy - (double)cy);
-  fz[i] -= q * kz * ((double)gz - (double)cz);
+  fx[i] -= q * kx * sx;
+  fy[i] -= q * ky * sy;
+  fz[i] -= q * kz * sz;
+}
+
+// The groups' sums of each charged particle added in group order (FP64),
+// then applied like the single-group gather.
+__global__ void __launch_bounds__(256) k_gather_reduce(const int32_t *__restrict__ nq_ptr, int G, int64_t stride,
+                                                       const double4 *__restrict__ gpart,
+                                                       const double4 *__restrict__ sq, double kx, double ky,
+                                                       double kz, double *__restrict__ fx, double *__restrict__ fy,
+                                                       double *__restrict__ fz) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= *nq_ptr) return;
+  double gx = 0.0, gy = 0.0, gz = 0.0;
+  for (int g = 0; g < G; ++g) {
+    const double4 v = gpart[g * stride + i];
+    gx += v.x;
+    gy += v.y;
+    gz += v.z;
+  }
+  const double q = sq[i].w;
+  fx[i] -= q * kx * gx;
+  fy[i] -= q * ky * gy;
+  fz[i] -= q * kz * gz;
+}
+
+// Mode groups of the gather: one unless the charged range alone gives too few
+// blocks to fill the GPU (a small system with many modes, such as the full
+// Ewald lattice), then enough groups of M modes (a multiple of the staging
+// round) for about 1024 blocks, within the partial-sum buffer.
+static int gather_split(int64_t nq_max, int P, const FourierBuffers &fb, int *M) {
+  const int64_t pb = (nq_max + 255) / 256;
+  *M = P;
+  if (!fb.gpart || pb >= 512 || P < 4 * kGatherThreads) return 1;
+  int64_t G = (1024 + pb - 1) / pb;
+  while (G > 1 && G * pb * 256 > kGatherPartMax) --G;
+  const int64_t m = ((P + G - 1) / G + kGatherThreads - 1) / kGatherThreads * kGatherThreads;
+  *M = (int)m;
+  return (int)((P + m - 1) / m);
 }
 
 void launch_fourier_gather(int prec, const int32_t *nq, int64_t nq_max, int P, const double4 *sq,
@@ -337,10 +411,17 @@ void launch_fourier_gather(int prec, const int32_t *nq, int64_t nq_max, int P, c
   if (nq_max <= 0) return;
   const unsigned blocks = (unsigned)((nq_max + 255) / 256);
   const double kx = kTwoPi / g.L[0], ky = kTwoPi / g.L[1], kz = kTwoPi / g.L[2];
+  int M;
+  const int G = gather_split(nq_max, P, fb, &M);
+  double4 *gp = G > 1 ? fb.gpart : nullptr;
+  const int64_t stride = (int64_t)blocks * 256;
+  const dim3 grid(blocks, (unsigned)G);
   if (prec == RBE_FP32C)
-    k_gather_f32c<<<blocks, 256, 0, st>>>(nq, P, sq, fb.modes, kx, ky, kz, fx, fy, fz);
+    k_gather_f32c<<<grid, kGatherThreads, 0, st>>>(nq, P, M, sq, fb.modes, kx, ky, kz, fx, fy, fz, gp, stride);
   else
-    k_gather_f64<<<blocks, kTurnTable, 0, st>>>(nq, P, sq, fb.modes, fb.turn_tab, kx, ky, kz, fx, fy, fz);
+    k_gather_f64<<<grid, kTurnTable, 0, st>>>(nq, P, M, sq, fb.modes, fb.turn_tab, kx, ky, kz, fx, fy, fz, gp,
+                                              stride);
+  if (G > 1) k_gather_reduce<<<blocks, 256, 0, st>>>(nq, G, stride, gp, sq, kx, ky, kz, fx, fy, fz);
 }
 
 }  // namespace rbe

@@ -146,8 +146,12 @@ struct FourierBuffers {
   double *rho;           // [2 * P] Re | Im
   GatherMode *modes;     // [P]
   double2 *turn_tab;     // [kTurnTableEntries] (sin, cos) of 2 pi k / kTurnTableEntries (FP64 kernels)
+  double4 *gpart;        // [kGatherPartMax] per-group gather sums (mode split); nullptr: no split
   int nchunk_max;
 };
+// Entries of the gather's per-group partial sums: the mode split is used only
+// while groups x (charged range rounded to blocks) fits.
+constexpr int64_t kGatherPartMax = 262144;
 constexpr int kTurnTableEntries = 256;
 // Host values of the FP64 kernels' turn table (n entries of (sin, cos) of
 // 2 pi k / n, each rounded once from extended precision).

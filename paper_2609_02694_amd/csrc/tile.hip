@@ -443,21 +443,46 @@ __global__ void __launch_bounds__(kTileThreads) k_pair_tile(TileCtx c) {
           const T gy = tile_gap(yi, Y0 + (T)ry * Hy, Hy, margin);
           const T rem = rc2 - (gy * gy + gz * gz);
           if (rem < T(0)) continue;
-          const T ext = sqrt(rem) + margin;
+          // the hardware square root (within 1 ulp) suffices: the margin
+          // (1e-4 in FP32) covers its error many times over
+          T ext;
+          if constexpr (F32) ext = __builtin_amdgcn_sqrtf(rem) + margin;
+          else ext = sqrt(rem) + margin;
           int xa = (int)floor((xi - ext - X0) * invHx), xb = (int)floor((xi + ext - X0) * invHx);
           xa = max(xa, max(ix - c.s.x, 0));
           xb = min(xb, min(ix + c.s.x, HX - 1));
           if (xa > xb) continue;
           const int ka = cs[row * HX + xa] - base, kb = cs[row * HX + xb + 1] - base;
           T px = T(0), py = T(0), pz = T(0);
-          // two candidates per trip: both records are requested before use
-          int k = ka;
-          for (; k + 1 < kb; k += 2) {
-            const V va = rec[k], vb = rec[k + 1];
-            cand(k, va, px, py, pz);
-            cand(k + 1, vb, px, py, pz);
+          if constexpr (!coul) {
+            // four candidates per trip, all records requested before use; the
+            // trip count runs on the record pointer alone
+            const V *q = rec + ka;
+            const V *const qe = rec + kb, *const qe4 = qe - 3;
+            for (; q < qe4; q += 4) {
+              const V v0 = q[0], v1 = q[1], v2 = q[2], v3 = q[3];
+              cand(0, v0, px, py, pz);
+              cand(0, v1, px, py, pz);
+              cand(0, v2, px, py, pz);
+              cand(0, v3, px, py, pz);
+            }
+            if (q + 1 < qe) {
+              const V v0 = q[0], v1 = q[1];
+              cand(0, v0, px, py, pz);
+              cand(0, v1, px, py, pz);
+              q += 2;
+            }
+            if (q < qe) cand(0, q[0], px, py, pz);
+          } else {
+            // two candidates per trip: both records are requested before use
+            int k = ka;
+            for (; k + 1 < kb; k += 2) {
+              const V va = rec[k], vb = rec[k + 1];
+              cand(k, va, px, py, pz);
+              cand(k + 1, vb, px, py, pz);
+            }
+            if (k < kb) cand(k, rec[k], px, py, pz);
           }
-          if (k < kb) cand(k, rec[k], px, py, pz);
           tile_kahan(S[0], K[0], px);
           tile_kahan(S[1], K[1], py);
           tile_kahan(S[2], K[2], pz);

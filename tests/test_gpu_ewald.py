@@ -50,6 +50,26 @@ def device_table(m, w):
             torch.as_tensor(np.ascontiguousarray(w, np.float64)).cuda())
 
 
+def test_lattice_modes_fp32c_match_exact_ewald():
+    """FP32C with a full lattice (tens of thousands of modes for a few
+    hundred charges: the gather splits the modes over block groups)."""
+    L, alpha, rc = 10.0, 1.4, 5.0
+    p, s = small_ions(216, L, alpha, rc, seed=2103)
+    params = rbe.make_params(L, alpha, rc, 2.5, 1, terms=rbe.TERM_COUL_REAL | rbe.TERM_FOURIER, prec=rbe.FP32C)
+    m, w = rbe.lattice_modes(params, kmax_for(alpha))
+    params.P = m.shape[1]
+    ctx = rbe.Context(params, p["n"])
+    st = to_device(s)
+    md, wd = device_table(m, w)
+    ctx.forces(st, md, wd, 0)
+    F = np.stack([st.fx.cpu().numpy(), st.fy.cpu().numpy(), st.fz.cpu().numpy()], axis=1)
+    torch.cuda.synchronize()
+    ctx.sync_check()
+    ex = oracle.ewald_exact(s["x"], s["y"], s["z"], s["q"], L, alpha)
+    assert rel_err(F, ex["F"]) < 1e-5
+    ctx.close()
+
+
 def test_lattice_modes_give_the_exact_ewald_force():
     L, alpha, rc = 10.0, 1.4, 5.0
     p, s = small_ions(216, L, alpha, rc, seed=2101)
