@@ -124,14 +124,14 @@ __device__ inline ClusterI load_cluster_i(const PairCtx &c, int64_t first, int64
 }
 
 // Periodic or ghost-shell stencil walk of one particle (thread form).
-template <bool GHOST, bool WITH_ID, class Fn>
+template <bool GHOST, bool WITH_ID, class Fn, class RowEnd>
 __device__ inline void stencil(const PairCtx &c, int blk, int cx, int cy, int cz, const Sten &s, const Reach &R,
-                               Fn &&fn) {
+                               Fn &&fn, RowEnd &&row_end) {
   if (GHOST)
     for_stencil_ghost<WITH_ID>(c.pp.g, c.cell_start, c.xq, c.ids, c.gcell_start, c.gxq, c.gid, (int)c.n, blk, cx, cy,
-                               cz, s, R, fn);
+                               cz, s, R, fn, row_end);
   else
-    for_stencil<WITH_ID>(c.pp.g, c.cell_start, c.xq, c.ids, blk, cx, cy, cz, s, R, fn);
+    for_stencil<WITH_ID>(c.pp.g, c.cell_start, c.xq, c.ids, blk, cx, cy, cz, s, R, fn, 0, row_end);
 }
 
 // Plain cutoff sums, one thread per particle i walking its own stencil (on
@@ -141,11 +141,12 @@ __device__ inline void stencil(const PairCtx &c, int blk, int cx, int cy, int cz
 // (charged block out to max(r_coul, r_lj), neutral block out to r_lj); MODE
 // 2: charged i, screened Coulomb terms only (charged block out to r_coul),
 // added to f, which holds the LJ terms of the tile pass.
-// Occupancy asked of the compiler: FP32 forms six (charged) or seven
-// (neutral) waves per SIMD, FP64 forms three or seven (measured best; the
-// FP64 charged form spills at four).
+// Occupancy asked of the compiler: FP32 forms five (charged) or six
+// (neutral) waves per SIMD, the most without spills once a row's partial
+// sums are held; FP64 forms three or seven (measured best; the FP64 charged
+// form spills at four).
 template <bool F32, bool COUNT, int MODE, bool GHOST>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F32 ? (MODE ? 6 : 7) : (MODE ? 3 : 7))))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F32 ? (MODE ? 5 : 6) : (MODE ? 3 : 7))))
 k_pair_plain(PairCtx c) {
   static_assert(MODE >= 0 && MODE <= 2, "mode");
   int64_t first, end;
@@ -168,7 +169,7 @@ k_pair_plain(PairCtx c) {
     if (COUNT) ++n_tested;
     if (j == (int)i) return;  // ghosts are indexed from n on
     if (r2 <= pp.rq2) {
-      acc.template add<true>(pp, c.pf, r2, qi, pj.w, dx, dy, dz);
+      acc.template add_row<true>(pp, c.pf, r2, qi, pj.w, dx, dy, dz);
       if (COUNT) {
         n_coul += (pp.do_coul && r2 <= pp.rc2);
         n_lj += (pp.do_lj && r2 <= pp.rlj2);
@@ -182,25 +183,26 @@ k_pair_plain(PairCtx c) {
     if (COUNT) ++n_tested;
     if (j == (int)i) return;  // ghosts are indexed from n on
     if (r2 <= pp.rlj2) {
-      acc.template add<false>(pp, c.pf, r2, qi, pj.w, dx, dy, dz);
+      acc.template add_row<false>(pp, c.pf, r2, qi, pj.w, dx, dy, dz);
       if (COUNT) n_lj += pp.do_lj;
     }
   };
+  auto row_end = [&]() { acc.flush_row(); };
   const Reach rq{xi, yi, zi, pp.rq2}, rlj{xi, yi, zi, pp.rlj2};
   if (MODE == 2) {
     // pp.do_lj is off for this launch: visit_q adds the screened Coulomb term only
     const Reach rc{xi, yi, zi, pp.rc2};
-    stencil<GHOST, false>(c, 0, cx, cy, cz, pp.s_coul, rc, visit_q);
+    stencil<GHOST, false>(c, 0, cx, cy, cz, pp.s_coul, rc, visit_q, row_end);
     c.fx[i] += acc.get(0);
     c.fy[i] += acc.get(1);
     c.fz[i] += acc.get(2);
   } else {
     if (MODE == 1) {
-      stencil<GHOST, false>(c, 0, cx, cy, cz, pp.s_coul, rq, visit_q);
-      if (pp.do_lj) stencil<GHOST, false>(c, 1, cx, cy, cz, pp.s_lj, rlj, visit_lj);
+      stencil<GHOST, false>(c, 0, cx, cy, cz, pp.s_coul, rq, visit_q, row_end);
+      if (pp.do_lj) stencil<GHOST, false>(c, 1, cx, cy, cz, pp.s_lj, rlj, visit_lj, row_end);
     } else if (pp.do_lj) {
-      stencil<GHOST, false>(c, 0, cx, cy, cz, pp.s_lj, rlj, visit_lj);
-      stencil<GHOST, false>(c, 1, cx, cy, cz, pp.s_lj, rlj, visit_lj);
+      stencil<GHOST, false>(c, 0, cx, cy, cz, pp.s_lj, rlj, visit_lj, row_end);
+      stencil<GHOST, false>(c, 1, cx, cy, cz, pp.s_lj, rlj, visit_lj, row_end);
     }
     c.fx[i] = acc.get(0);
     c.fy[i] = acc.get(1);

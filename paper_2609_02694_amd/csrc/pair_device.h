@@ -296,10 +296,16 @@ __device__ inline bool row_range(const Grid &g, const Reach &R, double gy, doubl
 // (2 s.x + 1)(2 s.y + 1)(2 s.z + 1) cells around (cx, cy, cz) that the reach
 // of R can touch;
 // (shx, shy, shz) is the image shift of j (its image lies at r_j + shift).
-template <bool WITH_ID, class Fn>
+// row_end() is called after each stencil row (the FP32C accumulators close a
+// row's plain partial sum there).
+struct NoRowEnd {
+  __device__ inline void operator()() const {}
+};
+template <bool WITH_ID, class Fn, class RowEnd = NoRowEnd>
 __device__ inline void for_stencil(const Grid &g, const int32_t *__restrict__ cell_start,
                                    const double4 *__restrict__ xq, const int32_t *__restrict__ ids, int blk, int cx,
-                                   int cy, int cz, const Sten &s, const Reach &R, Fn &&fn, int64_t cell_base = 0) {
+                                   int cy, int cz, const Sten &s, const Reach &R, Fn &&fn, int64_t cell_base = 0,
+                                   RowEnd row_end = RowEnd()) {
   const int64_t base = cell_base + (int64_t)blk * g.ncell;
   const double hy = g.L[1] / g.ny, hz = g.L[2] / g.nz;
   for (int oz = -s.z; oz <= s.z; ++oz) {
@@ -325,6 +331,7 @@ __device__ inline void for_stencil(const Grid &g, const int32_t *__restrict__ ce
         scan_range<WITH_ID>(xq, ids, j0, j1, (double)qx * g.L[0], shy, shz, fn);
         a = b + 1;
       }
+      row_end();
     }
   }
 }
@@ -333,12 +340,13 @@ __device__ inline void for_stencil(const Grid &g, const int32_t *__restrict__ ce
 // rows that lie inside the native grid, then the ghosts of the same rows of
 // the padded grid, each row trimmed to the reach of R. (cx, cy, cz) is a
 // native cell. Ghosts reach fn with indices offset by nnat.
-template <bool WITH_ID, class Fn>
+template <bool WITH_ID, class Fn, class RowEnd = NoRowEnd>
 __device__ inline void for_stencil_ghost(const Grid &g, const int32_t *__restrict__ cell_start,
                                          const double4 *__restrict__ xq, const int32_t *__restrict__ ids,
                                          const int32_t *__restrict__ gcell_start, const double4 *__restrict__ gxq,
                                          const int32_t *__restrict__ gid, int nnat, int blk, int cx, int cy,
-                                         int cz, const Sten &s, const Reach &R, Fn &&fn) {
+                                         int cz, const Sten &s, const Reach &R, Fn &&fn,
+                                         RowEnd row_end = RowEnd()) {
   const int base = blk * g.ncell;
   const int pbase = blk * g.pncell;
   const double hy = g.L[1] / g.ny, hz = g.L[2] / g.nz;
@@ -359,6 +367,7 @@ __device__ inline void for_stencil_ghost(const Grid &g, const int32_t *__restric
       }
       const int prow = pbase + ((z + g.goff[2]) * g.pny + (y + g.goff[1])) * g.pnx + g.goff[0];
       scan_range<WITH_ID>(gxq, gid, gcell_start[prow + xa], gcell_start[prow + xb + 1], 0.0, 0.0, 0.0, fn, nnat);
+      row_end();
     }
   }
 }
@@ -380,10 +389,34 @@ struct ForceAcc<false> {
     v[2] = fma(sc, dz, v[2]);
   }
   __device__ inline double get(int k) const { return v[k]; }
+  // the thread-form walks: same as add (FP64 sums need no row partials)
+  template <bool COUL, bool TABLE = false>
+  __device__ inline void add_row(const PairParams &pp, const PairF32 &pf, double r2, double qi, double qj, double dx,
+                                 double dy, double dz) {
+    add<COUL, TABLE>(pp, pf, r2, qi, qj, dx, dy, dz);
+  }
+  __device__ inline void flush_row() {}
 };
 template <>
 struct ForceAcc<true> {
   Kahan3 k;
+  float p[3] = {0.f, 0.f, 0.f};  // the current row's plain partial sums (add_row)
+  // the thread-form walks: a row's terms summed plainly in FP32, the row sum
+  // added with Kahan compensation at flush_row
+  template <bool COUL, bool TABLE = false>
+  __device__ inline void add_row(const PairParams &pp, const PairF32 &pf, double r2, double qi, double qj, double dx,
+                                 double dy, double dz) {
+    const float sc = COUL ? pair_scalar_f32(pp, pf, r2, (float)(qi * qj)) : pair_scalar_lj_f32(pp, pf, r2);
+    p[0] = fmaf(sc, (float)dx, p[0]);
+    p[1] = fmaf(sc, (float)dy, p[1]);
+    p[2] = fmaf(sc, (float)dz, p[2]);
+  }
+  __device__ inline void flush_row() {
+    for (int c = 0; c < 3; ++c) {
+      k.add(c, p[c]);
+      p[c] = 0.f;
+    }
+  }
   template <bool COUL, bool TABLE = false>
   __device__ inline void add(const PairParams &pp, const PairF32 &pf, double r2, double qi, double qj, double dx,
                              double dy, double dz) {
