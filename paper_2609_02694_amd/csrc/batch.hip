@@ -99,22 +99,25 @@ __device__ inline void batch_pair(const BatchArgs &a, const RepDesc &R, int64_t 
     const double dx = (xi - pj.x) - shx, dy = (yi - pj.y) - shy, dz = (zi - pj.z) - shz;
     const double r2 = sq_dist(dx, dy, dz);
     if (r2 == 0.0 && j == (int)i) return;
-    if (r2 <= pp.rq2) acc.template add<true>(pp, a.pf, r2, qi, pj.w, dx, dy, dz);
+    if (r2 <= pp.rq2) acc.template add_row<true>(pp, a.pf, r2, qi, pj.w, dx, dy, dz);
   };
   auto visit_lj = [&](int j, const double4 &pj, int, double shx, double shy, double shz) {
     const double dx = (xi - pj.x) - shx, dy = (yi - pj.y) - shy, dz = (zi - pj.z) - shz;
     const double r2 = sq_dist(dx, dy, dz);
     if (r2 == 0.0 && j == (int)i) return;
-    if (r2 <= pp.rlj2) acc.template add<false>(pp, a.pf, r2, qi, pj.w, dx, dy, dz);
+    if (r2 <= pp.rlj2) acc.template add_row<false>(pp, a.pf, r2, qi, pj.w, dx, dy, dz);
   };
+  // FP32C: a row's terms summed plainly, the row sum added with Kahan compensation
+  auto row_end = [&]() { acc.flush_row(); };
   const Reach rq{xi, yi, zi, pp.rq2}, rlj{xi, yi, zi, pp.rlj2};
   if (qi != 0.0) {
     if (pp.do_coul || pp.do_lj)
-      for_stencil<false>(g, a.cell_start, a.xq, a.sid, 0, cx, cy, cz, R.s_coul, rq, visit_q, R.c0);
-    if (pp.do_lj) for_stencil<false>(g, a.cell_start, a.xq, a.sid, 1, cx, cy, cz, R.s_lj, rlj, visit_lj, R.c0);
+      for_stencil<false>(g, a.cell_start, a.xq, a.sid, 0, cx, cy, cz, R.s_coul, rq, visit_q, R.c0, row_end);
+    if (pp.do_lj)
+      for_stencil<false>(g, a.cell_start, a.xq, a.sid, 1, cx, cy, cz, R.s_lj, rlj, visit_lj, R.c0, row_end);
   } else if (pp.do_lj) {
-    for_stencil<false>(g, a.cell_start, a.xq, a.sid, 0, cx, cy, cz, R.s_lj, rlj, visit_lj, R.c0);
-    for_stencil<false>(g, a.cell_start, a.xq, a.sid, 1, cx, cy, cz, R.s_lj, rlj, visit_lj, R.c0);
+    for_stencil<false>(g, a.cell_start, a.xq, a.sid, 0, cx, cy, cz, R.s_lj, rlj, visit_lj, R.c0, row_end);
+    for_stencil<false>(g, a.cell_start, a.xq, a.sid, 1, cx, cy, cz, R.s_lj, rlj, visit_lj, R.c0, row_end);
   }
   a.ofx[i] = acc.get(0);
   a.ofy[i] = acc.get(1);

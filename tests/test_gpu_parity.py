@@ -509,3 +509,37 @@ def test_forces_dense_cluster_in_sparse_box(prec, tol, ghost):
         e, r = rel_err(F, ref["F"]), max_row_err(F, ref["F"])
         print(f"dense cluster prec={prec} ghost={ghost} ncell={ncell}: rel err {e:.3e}, max row {r:.3e}")
         assert e < tol and r < (ROW64 if prec == rbe.FP64 else ROW32)
+
+
+def test_tile_row_beyond_the_staging_is_reported():
+    """One y/z cell row packed far above the mean density (about 1,840 records
+    in a tile's halo row, where the tile's staging holds about 1,350 at this
+    mean density): the row cannot be staged, the kernel leaves it out and
+    rbe_sync_check reports RBE_ERANGE instead of returning incomplete forces
+    silently."""
+    # cells of 0.628 x 2.51 x 2.51: the LJ stencil is 4 x 1 x 1 cells
+    L, ncell = 20.1, (32, 8, 8)
+    bx, by, bz = gen.rsa_positions(91, 0, 2400, [L, L, L], dmin=0.8)
+    # the row of y/z cell (2, 2): y, z in [5, 7.5)
+    keep = ~((by >= 4.6) & (by < 7.9) & (bz >= 4.6) & (bz < 7.9))
+    rx, ry, rz = gen.rsa_positions(92, 0, 1900, [L, 2.4, 2.4], dmin=0.3)
+    x = np.concatenate([bx[keep], rx])
+    y = np.concatenate([by[keep], ry + 5.05])
+    z = np.concatenate([bz[keep], rz + 5.05])
+    n = len(x)
+    nq = 100
+    q = np.zeros(n)
+    q[:nq] = 1.0
+    q[nq:2 * nq] = -1.0
+    s = dict(x=x, y=y, z=z, vx=np.zeros(n), vy=np.zeros(n), vz=np.zeros(n), q=q,
+             id=np.arange(n, dtype=np.int32), L=np.array([L, L, L]))
+    params = rbe.make_params(L, 0.35, 6.0, 2.5, 50, prec=rbe.FP32C, ncell=ncell)
+    ctx = rbe.Context(params, n)
+    st = to_device(s)
+    print(f"dense row: n={n}, {len(rx)} in one cell row", flush=True)
+    ctx.forces(st, None, None, 0)
+    torch.cuda.synchronize()
+    with pytest.raises(rbe.RbeError) as e:
+        ctx.sync_check()
+    assert e.value.code == rbe.RBE_ERANGE and "LDS staging" in str(e.value)
+    ctx.close()
