@@ -1288,17 +1288,21 @@ extern "C" int rbe_step(rbe_ctx *c, rbe_state *s, int32_t nsteps, uint64_t first
       // previous step's second half-kick into this one's first half-kick and
       // drift (NVT steps cannot: the thermostat needs the kinetic energy
       // between the two half-kicks)
+      // the drift also writes the binning keys and run slots of the new
+      // positions (the keys pass of the counting sort, fused)
       TScope ts(c, RBE_TK_KICK_DRIFT, st);
+      launch_bin_clear(c->bb, c->g, st);
+      const BinKeyOut bk{A->q, c->bb.key, c->bb.slot, c->bb.count};
       if (k == 0 || nvt)
         launch_kick_drift(n, h, c->p.dt, c->g, nvt ? c->nh_scale : nullptr, A->fx, A->fy, A->fz, A->vx, A->vy, A->vz,
-                          A->x, A->y, A->z, c->err, st);
+                          A->x, A->y, A->z, c->err, bk, st);
       else
         launch_kick_kick_drift(n, h, c->p.dt, c->g, mean, A->fx, A->fy, A->fz, A->vx, A->vy, A->vz, A->x, A->y,
-                               A->z, c->err, st);
+                               A->z, c->err, bk, st);
     }
     {
       TScope ts(c, RBE_TK_BIN, st);
-      launch_bin(c->bb, c->g, n, A->x, A->y, A->z, A->q, c->cell_start, c->perm, st);
+      launch_bin_place(c->bb, c->g, n, c->cell_start, c->perm, st);
     }
     {
       TScope ts(c, RBE_TK_REORDER, st);

@@ -175,20 +175,29 @@ __global__ void __launch_bounds__(256) k_place_buckets(int64_t nkeys, const int3
   place_bucket(start[k], start[k + 1], tmp, perm);
 }
 
-void launch_bin(const BinBuffers &b, const Grid &g, int64_t n, const double *x, const double *y, const double *z,
-                const double *q, int32_t *cell_start, int32_t *perm, hipStream_t st) {
+void launch_bin_clear(const BinBuffers &b, const Grid &g, hipStream_t st) {
+  launch_fill_i32(b.count, 2 * (int64_t)g.ncell, 0, st);
+}
+
+void launch_bin_place(const BinBuffers &b, const Grid &g, int64_t n, int32_t *cell_start, int32_t *perm,
+                      hipStream_t st) {
   const int64_t nkeys = 2 * (int64_t)g.ncell;
-  launch_fill_i32(b.count, nkeys, 0, st);
-  if (n > 0) {
-    const unsigned blocks = (unsigned)((n + 255) / 256);
-    k_bin_keys<<<blocks, 256, 0, st>>>(n, x, y, z, q, g, b.key, b.slot, b.count);
-  }
   launch_exclusive_scan(b.count, nkeys, cell_start, b.scan_tmp, st);
   if (n > 0) {
     const unsigned blocks = (unsigned)((n + 255) / 256);
     k_scatter_prov<<<blocks, 256, 0, st>>>(n, b.key, b.slot, cell_start, b.tmp);
     k_place_buckets<<<(unsigned)((nkeys + 255) / 256), 256, 0, st>>>(nkeys, cell_start, b.tmp, perm);
   }
+}
+
+void launch_bin(const BinBuffers &b, const Grid &g, int64_t n, const double *x, const double *y, const double *z,
+                const double *q, int32_t *cell_start, int32_t *perm, hipStream_t st) {
+  launch_bin_clear(b, g, st);
+  if (n > 0) {
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    k_bin_keys<<<blocks, 256, 0, st>>>(n, x, y, z, q, g, b.key, b.slot, b.count);
+  }
+  launch_bin_place(b, g, n, cell_start, perm, st);
 }
 
 }  // namespace rbe

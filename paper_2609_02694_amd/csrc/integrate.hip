@@ -185,33 +185,55 @@ void launch_sub_mean(int64_t n, const double *mean, double *fx, double *fy, doub
 
 // v <- s v + h f (s = *scale when given: the thermostat's velocity scaling
 // of the NVT step; the NVE step passes no scale); x <- wrap(x + dt v).
+// Binning key of a drifted particle, computed from the stored (wrapped)
+// position exactly as the keys pass of the counting sort computes it, and its
+// run slot (every lane of the wave takes part; lanes past n carry a key no
+// other lane has).
+__device__ inline void drift_key(const BinKeyOut &bk, const Grid &g, int64_t i, bool active, double x, double y,
+                                 double z) {
+  int k = -1 - (int)(threadIdx.x & 63);
+  if (active) {
+    const int cx = cell_coord(wrap_coord(x, g.L[0]), g.inv_h[0], g.nx);
+    const int cy = cell_coord(wrap_coord(y, g.L[1]), g.inv_h[1], g.ny);
+    const int cz = cell_coord(wrap_coord(z, g.L[2]), g.inv_h[2], g.nz);
+    k = (bk.q[i] == 0.0 ? g.ncell : 0) + (cz * g.ny + cy) * g.nx + cx;
+    bk.key[i] = k;
+  }
+  const int sl = run_slot(k, active, bk.count);
+  if (active) bk.slot[i] = sl;
+}
+
 __global__ void __launch_bounds__(256) k_kick_drift(int64_t n, double h, double dt, Grid g,
                                                     const double *__restrict__ scale,
                                                     const double *__restrict__ fx, const double *__restrict__ fy,
                                                     const double *__restrict__ fz, double *__restrict__ vx,
                                                     double *__restrict__ vy, double *__restrict__ vz,
                                                     double *__restrict__ x, double *__restrict__ y,
-                                                    double *__restrict__ z, int *err) {
+                                                    double *__restrict__ z, int *err, BinKeyOut bk) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double v0x = vx[i], v0y = vy[i], v0z = vz[i];
-  if (scale) {
-    const double sc = *scale;
-    v0x *= sc;
-    v0y *= sc;
-    v0z *= sc;
+  const bool active = i < n;
+  double nx = 0.0, ny = 0.0, nz = 0.0;
+  if (active) {
+    double v0x = vx[i], v0y = vy[i], v0z = vz[i];
+    if (scale) {
+      const double sc = *scale;
+      v0x *= sc;
+      v0y *= sc;
+      v0z *= sc;
+    }
+    const double u = v0x + h * fx[i], v = v0y + h * fy[i], w = v0z + h * fz[i];
+    vx[i] = u;
+    vy[i] = v;
+    vz[i] = w;
+    nx = wrap_coord(x[i] + dt * u, g.L[0]);
+    ny = wrap_coord(y[i] + dt * v, g.L[1]);
+    nz = wrap_coord(z[i] + dt * w, g.L[2]);
+    x[i] = nx;
+    y[i] = ny;
+    z[i] = nz;
+    if (!isfinite(u) || !isfinite(v) || !isfinite(w)) atomicOr(err, kErrNonFinite);
   }
-  const double u = v0x + h * fx[i], v = v0y + h * fy[i], w = v0z + h * fz[i];
-  vx[i] = u;
-  vy[i] = v;
-  vz[i] = w;
-  const double nx = wrap_coord(x[i] + dt * u, g.L[0]);
-  const double ny = wrap_coord(y[i] + dt * v, g.L[1]);
-  const double nz = wrap_coord(z[i] + dt * w, g.L[2]);
-  x[i] = nx;
-  y[i] = ny;
-  z[i] = nz;
-  if (!isfinite(u) || !isfinite(v) || !isfinite(w)) atomicOr(err, kErrNonFinite);
+  if (bk.key) drift_key(bk, g, i, active, nx, ny, nz);
 }
 
 // The second half-kick of one step followed by the first half-kick and drift
@@ -226,40 +248,47 @@ __global__ void __launch_bounds__(256) k_kick_kick_drift(int64_t n, double h, do
                                                          const double *__restrict__ fz, double *__restrict__ vx,
                                                          double *__restrict__ vy, double *__restrict__ vz,
                                                          double *__restrict__ x, double *__restrict__ y,
-                                                         double *__restrict__ z, int *err) {
+                                                         double *__restrict__ z, int *err, BinKeyOut bk) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double a = fx[i], b = fy[i], c = fz[i];
-  if (mean) {
-    a -= mean[0];
-    b -= mean[1];
-    c -= mean[2];
+  const bool active = i < n;
+  double nx = 0.0, ny = 0.0, nz = 0.0;
+  if (active) {
+    double a = fx[i], b = fy[i], c = fz[i];
+    if (mean) {
+      a -= mean[0];
+      b -= mean[1];
+      c -= mean[2];
+    }
+    const double u1 = vx[i] + h * a, v1 = vy[i] + h * b, w1 = vz[i] + h * c;
+    const double u = u1 + h * a, v = v1 + h * b, w = w1 + h * c;
+    vx[i] = u;
+    vy[i] = v;
+    vz[i] = w;
+    nx = wrap_coord(x[i] + dt * u, g.L[0]);
+    ny = wrap_coord(y[i] + dt * v, g.L[1]);
+    nz = wrap_coord(z[i] + dt * w, g.L[2]);
+    x[i] = nx;
+    y[i] = ny;
+    z[i] = nz;
+    if (!isfinite(u1) || !isfinite(v1) || !isfinite(w1) || !isfinite(u) || !isfinite(v) || !isfinite(w))
+      atomicOr(err, kErrNonFinite);
   }
-  const double u1 = vx[i] + h * a, v1 = vy[i] + h * b, w1 = vz[i] + h * c;
-  const double u = u1 + h * a, v = v1 + h * b, w = w1 + h * c;
-  vx[i] = u;
-  vy[i] = v;
-  vz[i] = w;
-  x[i] = wrap_coord(x[i] + dt * u, g.L[0]);
-  y[i] = wrap_coord(y[i] + dt * v, g.L[1]);
-  z[i] = wrap_coord(z[i] + dt * w, g.L[2]);
-  if (!isfinite(u1) || !isfinite(v1) || !isfinite(w1) || !isfinite(u) || !isfinite(v) || !isfinite(w))
-    atomicOr(err, kErrNonFinite);
+  if (bk.key) drift_key(bk, g, i, active, nx, ny, nz);
 }
 void launch_kick_kick_drift(int64_t n, double h, double dt, const Grid &g, const double *mean, const double *fx,
                             const double *fy, const double *fz, double *vx, double *vy, double *vz, double *x,
-                            double *y, double *z, int *err, hipStream_t st) {
+                            double *y, double *z, int *err, BinKeyOut bk, hipStream_t st) {
   if (n <= 0) return;
   k_kick_kick_drift<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, h, dt, g, mean, fx, fy, fz, vx, vy, vz, x, y, z,
-                                                                 err);
+                                                                 err, bk);
 }
 
 void launch_kick_drift(int64_t n, double h, double dt, const Grid &g, const double *scale, const double *fx,
                        const double *fy, const double *fz, double *vx, double *vy, double *vz, double *x, double *y,
-                       double *z, int *err, hipStream_t st) {
+                       double *z, int *err, BinKeyOut bk, hipStream_t st) {
   if (n <= 0) return;
   k_kick_drift<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, h, dt, g, scale, fx, fy, fz, vx, vy, vz, x, y, z,
-                                                            err);
+                                                            err, bk);
 }
 
 // ---------------------------------------------------------------------------

@@ -20,6 +20,11 @@ void launch_fill_f64(double *p, int64_t n, double v, hipStream_t st);
 void launch_exclusive_scan(const int32_t *cnt, int64_t n, int32_t *start, int32_t *tmp, hipStream_t st);
 void launch_bin(const BinBuffers &b, const Grid &g, int64_t n, const double *x, const double *y, const double *z,
                 const double *q, int32_t *cell_start, int32_t *perm, hipStream_t st);
+// The passes of launch_bin around its keys pass, for a keys pass fused into
+// another kernel: clearing the histogram, then scan, scatter and placement.
+void launch_bin_clear(const BinBuffers &b, const Grid &g, hipStream_t st);
+void launch_bin_place(const BinBuffers &b, const Grid &g, int64_t n, int32_t *cell_start, int32_t *perm,
+                      hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // sorted working copies
@@ -232,13 +237,20 @@ void launch_kick(int64_t n, double h, const double *mean, double *fx, double *fy
 // f -= mean in place.
 void launch_sub_mean(int64_t n, const double *mean, double *fx, double *fy, double *fz, hipStream_t st);
 // v += h f; x <- wrap(x + dt v).
+// Binning keys of the drifted positions, written by the drift kernels for the
+// step's counting sort (key, run slot and histogram as the keys pass of
+// launch_bin; the histogram must be cleared before). key == nullptr: none.
+struct BinKeyOut {
+  const double *q;
+  int32_t *key, *slot, *count;
+};
 void launch_kick_kick_drift(int64_t n, double h, double dt, const Grid &g, const double *mean, const double *fx,
                             const double *fy, const double *fz, double *vx, double *vy, double *vz, double *x,
-                            double *y, double *z, int *err, hipStream_t st);
+                            double *y, double *z, int *err, BinKeyOut bk, hipStream_t st);
 // v <- s v + h f with s = *scale (nullptr: s = 1); x <- wrap(x + dt v).
 void launch_kick_drift(int64_t n, double h, double dt, const Grid &g, const double *scale, const double *fx,
                        const double *fy, const double *fz, double *vx, double *vy, double *vz, double *x, double *y,
-                       double *z, int *err, hipStream_t st);
+                       double *z, int *err, BinKeyOut bk, hipStream_t st);
 // Nose-Hoover thermostat: constants of the half-steps.
 struct NhParams {
   double dt, nf, kT, Q, mass;  // time step, degrees of freedom 3N - 3, target kT, thermostat mass, particle mass
