@@ -142,3 +142,26 @@ def test_batched_step_split_over_calls_is_bit_identical():
         torch.cuda.synchronize()
         ctx.sync_check()
         ctx.close()
+
+
+@pytest.mark.parametrize("name,n,prec,ncell", [
+    ("plain3k", None, rbe.FP64, (12, 4, 4)),
+    ("electrolyte1m", 20_000, rbe.FP32C, (40, 10, 10)),
+    ("subdomain64m", 40_000, rbe.FP32C, (48, 12, 12)),
+])
+def test_step_returns_cell_order(name, n, prec, ncell):
+    """rbe_step returns the particles sorted by the cell keys of their final
+    positions (the drift kernels compute those keys): binning the returned
+    state again with rbe_build_cells is the identity permutation."""
+    p, s = system(name, n=n)
+    params = rbe.params_from_preset(p, prec=prec, ncell=ncell)
+    ctx = rbe.Context(params, p["n"])
+    st = to_device(s)
+    ctx.forces(st, None, None, 0)
+    for nsteps in (1, 3):
+        ctx.step(st, nsteps, 1)
+        cs, perm = ctx.build_cells(st.x, st.y, st.z, st.q)
+        torch.cuda.synchronize()
+        assert torch.equal(perm.cpu(), torch.arange(p["n"], dtype=torch.int32)), nsteps
+    ctx.sync_check()
+    ctx.close()
