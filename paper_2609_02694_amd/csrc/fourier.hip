@@ -314,28 +314,38 @@ __global__ void __launch_bounds__(kTurnTable) k_gather_f64(const int32_t *__rest
   fz[i] -= q * kz * gz;
 }
 
-// One thread per charged particle; every lane reads the same mode at a time
-// (wave-uniform scalar loads, which deliver a record once per wave: staging
-// the modes in LDS instead measured slower, the broadcast LDS reads costing
-// more than the load latency they hide).
+// Two charged particles per thread (i and i + 256 of the block's 512); every
+// lane reads the same mode at a time (wave-uniform scalar loads, which
+// deliver a record once per wave), and each mode read serves both particles.
+// Staging the modes in LDS instead measured slower: the broadcast LDS reads
+// cost more than the load latency they hide.
 constexpr int kGatherThreads = 256;
+constexpr int kGatherPerBlock = 2 * kGatherThreads;
 __global__ void __launch_bounds__(kGatherThreads) k_gather_f32c(const int32_t *__restrict__ nq_ptr, int P, int M,
                                                                 const double4 *__restrict__ sq,
                                                                 const GatherMode *__restrict__ modes, double kx,
                                                                 double ky, double kz, double *__restrict__ fx,
                                                                 double *__restrict__ fy, double *__restrict__ fz,
                                                                 double4 *__restrict__ gpart, int64_t stride) {
-  const int64_t i = blockIdx.x * (int64_t)kGatherThreads + threadIdx.x;
-  if (i >= *nq_ptr) return;
-  const double4 s = sq[i];
+  const int64_t nq = *nq_ptr;
+  const int64_t i = blockIdx.x * (int64_t)kGatherPerBlock + threadIdx.x, i2 = i + kGatherThreads;
+  if (i >= nq) return;
+  const bool two = i2 < nq;
+  const double4 s = sq[i], s2 = two ? sq[i2] : s;
   float gx = 0.f, gy = 0.f, gz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
-  auto term = [&](int l, float &bx, float &by, float &bz) {
+  float hx = 0.f, hy = 0.f, hz = 0.f, dx = 0.f, dy = 0.f, dz = 0.f;
+  auto term = [&](int l, float &bx, float &by, float &bz, float &ex, float &ey, float &ez) {
     const GatherMode gm = modes[l];
     const float t = (float)turn_fraction(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
+    const float t2 = (float)turn_fraction(gm.mx, gm.my, gm.mz, s2.x, s2.y, s2.z);
     const float g = fmaf(gm.af, __builtin_amdgcn_cosf(t), -gm.bf * __builtin_amdgcn_sinf(t));
+    const float g2 = fmaf(gm.af, __builtin_amdgcn_cosf(t2), -gm.bf * __builtin_amdgcn_sinf(t2));
     bx = fmaf(g, gm.mxf, bx);
     by = fmaf(g, gm.myf, by);
     bz = fmaf(g, gm.mzf, bz);
+    ex = fmaf(g2, gm.mxf, ex);
+    ey = fmaf(g2, gm.myf, ey);
+    ez = fmaf(g2, gm.mzf, ez);
   };
   // blocks of kSumBlock modes summed in FP32, each block sum added with
   // Kahan compensation (a group's first mode is a multiple of kSumBlock, so
@@ -343,29 +353,39 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather_f32c(const int32_t *_
   const int lb = blockIdx.y * M, le = min(P, lb + M);
   int l = lb;
   for (; l + kSumBlock <= le; l += kSumBlock) {
-    float bx = 0.f, by = 0.f, bz = 0.f;
+    float bx = 0.f, by = 0.f, bz = 0.f, ex = 0.f, ey = 0.f, ez = 0.f;
 #pragma unroll
-    for (int u = 0; u < kSumBlock; ++u) term(l + u, bx, by, bz);
+    for (int u = 0; u < kSumBlock; ++u) term(l + u, bx, by, bz, ex, ey, ez);
     kahan_add(gx, cx, bx);
     kahan_add(gy, cy, by);
     kahan_add(gz, cz, bz);
+    kahan_add(hx, dx, ex);
+    kahan_add(hy, dy, ey);
+    kahan_add(hz, dz, ez);
   }
   {
-    float bx = 0.f, by = 0.f, bz = 0.f;
-    for (; l < le; ++l) term(l, bx, by, bz);
+    float bx = 0.f, by = 0.f, bz = 0.f, ex = 0.f, ey = 0.f, ez = 0.f;
+    for (; l < le; ++l) term(l, bx, by, bz, ex, ey, ez);
     kahan_add(gx, cx, bx);
     kahan_add(gy, cy, by);
     kahan_add(gz, cz, bz);
+    kahan_add(hx, dx, ex);
+    kahan_add(hy, dy, ey);
+    kahan_add(hz, dz, ez);
   }
-  const double sx = (double)gx - (double)cx, sy = (double)gy - (double)cy, sz = (double)gz - (double)cz;
-  if (gpart) {
-    gpart[blockIdx.y * stride + i] = make_double4(sx, sy, sz, 0.0);
-    return;
-  }
-  const double q = s.w;
-  fx[i] -= q * kx * sx;
-  fy[i] -= q * ky * sy;
-  fz[i] -= q * kz * sz;
+  auto put = [&](int64_t k, const double4 &sk, float ax, float acx, float ay, float acy, float az, float acz) {
+    const double sx = (double)ax - (double)acx, sy = (double)ay - (double)acy, sz = (double)az - (double)acz;
+    if (gpart) {
+      gpart[blockIdx.y * stride + k] = make_double4(sx, sy, sz, 0.0);
+      return;
+    }
+    const double q = sk.w;
+    fx[k] -= q * kx * sx;
+    fy[k] -= q * ky * sy;
+    fz[k] -= q * kz * sz;
+  };
+  put(i, s, gx, cx, gy, cy, gz, cz);
+  if (two) put(i2, s2, hx, dx, hy, dy, hz, dz);
 }
 
 // The groups' sums of each charged particle added in group order (FP64),
@@ -417,7 +437,8 @@ void launch_fourier_gather(int prec, const int32_t *nq, int64_t nq_max, int P, c
   const int64_t stride = (int64_t)blocks * 256;
   const dim3 grid(blocks, (unsigned)G);
   if (prec == RBE_FP32C)
-    k_gather_f32c<<<grid, kGatherThreads, 0, st>>>(nq, P, M, sq, fb.modes, kx, ky, kz, fx, fy, fz, gp, stride);
+    k_gather_f32c<<<dim3((unsigned)((nq_max + kGatherPerBlock - 1) / kGatherPerBlock), (unsigned)G), kGatherThreads,
+                    0, st>>>(nq, P, M, sq, fb.modes, kx, ky, kz, fx, fy, fz, gp, stride);
   else
     k_gather_f64<<<grid, kTurnTable, 0, st>>>(nq, P, M, sq, fb.modes, fb.turn_tab, kx, ky, kz, fx, fy, fz, gp,
                                               stride);
