@@ -745,7 +745,7 @@ static int eval_sorted(rbe_ctx *c, int64_t n, const int32_t *m, const double *w,
       // screened Coulomb terms of the charged particles added
       {
         TScope ts(c, RBE_TK_PAIR, st);
-        launch_lj_tile(c->p.prec, pp, n, 3, c->srt, c->cell_start, gb, fx, fy, fz, part_cnt(PAIR_PART_NEUTRAL).c,
+        launch_lj_tile(pp, n, 3, c->srt, c->cell_start, gb, fx, fy, fz, part_cnt(PAIR_PART_NEUTRAL).c,
                        c->err, st);
       }
       if (pp.do_coul) {
@@ -764,7 +764,7 @@ static int eval_sorted(rbe_ctx *c, int64_t n, const int32_t *m, const double *w,
         // the core (list on) or always (list off), else the list's cluster walk
         TScope ts(c, RBE_TK_PAIR, st);
         if (tiles && pp.rbl && !(pp.rlj2 > pp.rcore2))
-          launch_lj_tile(c->p.prec, pp, n, 2, c->srt, c->cell_start, gb, fx, fy, fz,
+          launch_lj_tile(pp, n, 2, c->srt, c->cell_start, gb, fx, fy, fz,
                          part_cnt(PAIR_PART_NEUTRAL).c, c->err, st);
         else
           launch_pair(c->p.prec, PAIR_PART_NEUTRAL, pp, n, nq, c->srt, c->cell_start, c->inv_id, gb, fx, fy, fz,

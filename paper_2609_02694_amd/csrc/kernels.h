@@ -128,12 +128,13 @@ void launch_pair(int prec, int part, const PairParams &pp, int64_t n, const int3
                  double *fz, PairCounters cnt, hipStream_t st);
 
 // LJ terms of every particle of the species blocks in iblk (bit 0 charged,
-// bit 1 neutral) over LDS-staged cell tiles: writes f of those particles
-// (counters [4] or nullptr: [1] LJ pair terms, [2] candidates). Used by the
-// FP32C form on grids whose mean cell occupancy suits the staging
-// (lj_tile_applicable); the other cases keep the thread-form walks.
+// bit 1 neutral) over LDS-staged cell tiles, FP32C form: writes f of those
+// particles (counters [4] or nullptr: [1] LJ pair terms, [2] candidates).
+// Used on grids whose mean cell occupancy suits the staging
+// (lj_tile_applicable, false for every other precision); the other cases
+// keep the thread-form walks.
 bool lj_tile_applicable(int prec, const PairParams &pp, int64_t n);
-void launch_lj_tile(int prec, const PairParams &pp, int64_t n, int iblk, const Sorted &s, const int32_t *cell_start,
+void launch_lj_tile(const PairParams &pp, int64_t n, int iblk, const Sorted &s, const int32_t *cell_start,
                     const GhostBuffers *gb, double *fx, double *fy, double *fz, unsigned long long *counters,
                     int *err, hipStream_t st);
 

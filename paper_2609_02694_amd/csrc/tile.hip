@@ -1,22 +1,19 @@
-// Near field over LDS-staged cell tiles (Sec. 2.1, Eq. 7-8; Sec. 2.2 cell
-// lists), for the plain cutoff sums (no random batch list):
-//
-//   LJ pass      every particle i of the launch's species blocks against every
-//                j (both species) with r <= r_lj: G_LJ(r) d;
-//   Coulomb pass every charged i against every charged j with r <= r_coul:
-//                kc q_i q_j G(r) d (its result is added to the LJ pass's).
+// LJ sums of the FP32C form over LDS-staged cell tiles (Sec. 2.1, Eq. 8;
+// Sec. 2.2 cell lists): every particle i of the launch's species blocks
+// against every j (both species) with r <= r_lj, G_LJ(r) d. The charged
+// particles' screened Coulomb terms are summed by the thread-form walks.
 //
 // A workgroup owns a tile of TX x TY x TZ cells. It stages the records of the
 // tile's halo (the cells within the stencil of any own cell) in LDS once,
 // converted to the tile's frame: FP32 coordinates relative to the tile's
-// centre in the FP32C form, FP64 coordinates (with the periodic image shift
-// applied) in the FP64 form. Each thread then takes one particle i of the
+// centre (the periodic image shift applied first, in FP64). Each thread then
+// takes one particle i of the
 // tile and walks the halo rows its reach sphere touches, each row trimmed to
 // the x-cells the sphere spans, reading the candidates from LDS. Halo cells
 // are met once per unwrapped cell index, i.e. once per (cell, periodic image),
 // so no image is counted twice (the cutoffs are at most half the box).
 //
-// FP32C: r^2 in FP32 from the frame coordinates; a pair whose r^2 lies within
+// r^2 in FP32 from the frame coordinates; a pair whose r^2 lies within
 // a relative band of 2^-16 around the cutoff is re-classified from the FP64
 // records (minimum image), so cutoff membership is the FP64 one. The pair
 // terms of a row are summed in FP32 and each row's sum is added to the total
@@ -30,14 +27,11 @@ namespace rbe {
 
 struct TileCtx {
   PairParams pp;
-  PairF32 pf;
   int TX, TY, TZ;          // own cells per tile
   Sten s;                  // halo radius in cells
   int ntx, nty, ntz;       // tiles per axis
   int cap;                 // records the LDS staging holds
-  int kind;                // 0: LJ pass, 1: Coulomb pass
   int iblk;                // species blocks supplying i (bit 0 charged, bit 1 neutral)
-  int accumulate;          // add to f (Coulomb pass) instead of writing it
   const double4 *__restrict__ xq;
   const int32_t *__restrict__ cell_start;
   const double4 *__restrict__ gxq;          // ghost shell (GHOST)
@@ -55,20 +49,8 @@ constexpr int kTileMaxSegs = 64;    // own row segments (rows x species blocks) 
 constexpr int kTileMaxChunks = 64;  // halo chunks of a tile whose halo exceeds the staging
 constexpr int kTileIMax = 512;      // particles of a tile grouped by quadrant (more: cell order)
 
-// Record of the LDS staging: frame coordinates and the charge (Coulomb pass)
-// or the record's index as bits (LJ pass, which needs no charge).
-template <bool F32>
-struct TileRec;
-template <>
-struct TileRec<true> {
-  using T = float;
-  using V = float4;
-};
-template <>
-struct TileRec<false> {
-  using T = double;
-  using V = double4;
-};
+// A record of the LDS staging is a float4: the FP32 frame coordinates and,
+// in w, the record's index as bits (the LJ terms need no charge).
 
 // Records of one halo cell, in two sources per species block (natives and
 // ghosts). Unwrapped cell (xc, yc, zc); returns the image shift (periodic).
@@ -82,12 +64,11 @@ __device__ inline void cell_sources(const TileCtx &c, int xc, int yc, int zc, Ce
   const Grid &g = c.pp.g;
   for (int k = 0; k < 4; ++k) out->a[k] = out->b[k] = 0;
   out->sx = out->sy = out->sz = 0.0;
-  const int nb = c.kind == 0 ? 2 : 1;  // LJ: both species; Coulomb: charged only
   if (GHOST) {
     const bool native = xc >= 0 && xc < g.nx && yc >= 0 && yc < g.ny && zc >= 0 && zc < g.nz;
     const int px = xc + g.goff[0], py = yc + g.goff[1], pz = zc + g.goff[2];
     const bool padded = px >= 0 && px < g.pnx && py >= 0 && py < g.pny && pz >= 0 && pz < g.pnz;
-    for (int b = 0; b < nb; ++b) {
+    for (int b = 0; b < 2; ++b) {
       if (native) {
         const int64_t key = (int64_t)b * g.ncell + ((int64_t)zc * g.ny + yc) * g.nx + xc;
         out->a[2 * b] = c.cell_start[key];
@@ -105,7 +86,7 @@ __device__ inline void cell_sources(const TileCtx &c, int xc, int yc, int zc, Ce
     out->sx = (double)qx * g.L[0];
     out->sy = (double)qy * g.L[1];
     out->sz = (double)qz * g.L[2];
-    for (int b = 0; b < nb; ++b) {
+    for (int b = 0; b < 2; ++b) {
       const int64_t key = (int64_t)b * g.ncell + ((int64_t)wz * g.ny + wy) * g.nx + wx;
       out->a[2 * b] = c.cell_start[key];
       out->b[2 * b] = c.cell_start[key + 1];
@@ -144,44 +125,21 @@ __device__ inline int tile_scan(int *v, int m, int *wsum) {
 }
 
 // Distance of p to the slab [lo, lo + h), less the margin, at least 0.
-template <class T>
-__device__ inline T tile_gap(T p, T lo, T h, T margin) {
-  const T d = lo - p > T(0) ? lo - p : (p - (lo + h) > T(0) ? p - (lo + h) : T(0));
-  return d > margin ? d - margin : T(0);
+__device__ inline float tile_gap(float p, float lo, float h, float margin) {
+  const float d = lo - p > 0.0f ? lo - p : (p - (lo + h) > 0.0f ? p - (lo + h) : 0.0f);
+  return d > margin ? d - margin : 0.0f;
 }
 
-// Pair scalars without the cutoff test (the caller masks). LJ: the shape
+// LJ pair scalar without the cutoff test (the caller masks): the shape
 // u (2 sigma^6 u - 1) / r^2 with u = r^-6, so that G_LJ(r) of Eq. 8 is
-// 24 eps sigma^6 times it (the constant is applied once to the sum); and
-// kc q_i q_j G(r) with G the screened Coulomb factor of Eq. 8.
-template <class T>
-__device__ inline T lj_shape(T r2, T two_s6) {
-  T rinv2;
-  if constexpr (sizeof(T) == 4) rinv2 = __builtin_amdgcn_rcpf(r2);
-  else rinv2 = rcp_f64(r2);
-  const T u = rinv2 * rinv2 * rinv2;
-  return u * fma(u, two_s6, T(-1)) * rinv2;
-}
-__device__ inline float pair_coul_f32(const PairF32 &pf, float r2, float qq) {
-  const float rinv = __builtin_amdgcn_rsqf(r2);
-  const float rinv2 = rinv * rinv;
-  const float x = pf.sqrt_alpha * (r2 * rinv);
-  const float e = __builtin_amdgcn_exp2f(pf.neg_alpha_log2e * r2);
-  const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, x, 1.0f));
-  const float erfc_x = e * erfcx_poly(t);
-  const float G = fmaf(erfc_x * rinv, rinv2, pf.two_sqrt_alpha_over_sqrt_pi * e * rinv2);
-  return pf.kc * qq * G;
-}
-__device__ inline double pair_coul_f64(const PairParams &pp, double r2, double qq) {
-  const double rinv = rsqrt_f64(r2);
-  const double inv_r2 = rinv * rinv;
-  const double e = exp_nonpos_f64<true>(-pp.alpha * r2);
-  const double R = erfc_scaled_f64<true>(pp.sqrt_alpha * (r2 * rinv));
-  const double G = e * inv_r2 * fma(R, rinv, pp.two_sqrt_alpha_over_sqrt_pi);
-  return pp.kc * qq * G;
+// 24 eps sigma^6 times it (the constant is applied once to the sum).
+__device__ inline float lj_shape(float r2, float two_s6) {
+  const float rinv2 = __builtin_amdgcn_rcpf(r2);
+  const float u = rinv2 * rinv2 * rinv2;
+  return u * fmaf(u, two_s6, -1.0f) * rinv2;
 }
 
-// s += v with Kahan compensation c (FP32); plain sum in FP64.
+// s += v with Kahan compensation c.
 __device__ inline void tile_kahan(float &s, float &c, float v) {
 #pragma clang fp contract(off)
   const float y = v - c;
@@ -189,12 +147,11 @@ __device__ inline void tile_kahan(float &s, float &c, float v) {
   c = (t - s) - y;
   s = t;
 }
-__device__ inline void tile_kahan(double &s, double &, double v) { s += v; }
 
-template <bool F32, bool GHOST, int KIND, bool COUNT>
+template <bool GHOST, bool COUNT>
 __global__ void __launch_bounds__(kTileThreads) k_pair_tile(TileCtx c) {
-  using T = typename TileRec<F32>::T;
-  using V = typename TileRec<F32>::V;
+  using T = float;
+  using V = float4;
   extern __shared__ __align__(16) unsigned char tile_lds[];
   __shared__ int wsum[kTileThreads / 64];
   __shared__ int seg_n[kTileMaxSegs];       // own row segments: i count, then prefix
@@ -214,27 +171,25 @@ __global__ void __launch_bounds__(kTileThreads) k_pair_tile(TileCtx c) {
   const int HX = c.TX + 2 * c.s.x, HY = c.TY + 2 * c.s.y, HZ = c.TZ + 2 * c.s.z;
   const int nrows = HY * HZ, ncells = nrows * HX;
   const double hx = g.L[0] / g.nx, hy = g.L[1] / g.ny, hz = g.L[2] / g.nz;
-  // frame: FP32C relative to the tile centre, FP64 absolute (unwrapped)
-  const double ox = F32 ? (x0 + 0.5 * c.TX) * hx : 0.0;
-  const double oy = F32 ? (y0 + 0.5 * c.TY) * hy : 0.0;
-  const double oz = F32 ? (z0 + 0.5 * c.TZ) * hz : 0.0;
+  // frame: relative to the tile centre
+  const double ox = (x0 + 0.5 * c.TX) * hx;
+  const double oy = (y0 + 0.5 * c.TY) * hy;
+  const double oz = (z0 + 0.5 * c.TZ) * hz;
   // low corner of the halo in the frame, cell edges and their inverse
   const T X0 = (T)((x0 - c.s.x) * hx - ox), Y0 = (T)((y0 - c.s.y) * hy - oy), Z0 = (T)((z0 - c.s.z) * hz - oz);
   const T Hy = (T)hy, Hz = (T)hz, invHx = (T)(1.0 / hx);
-  const T margin = F32 ? T(1e-4) : T(kTrimMargin);
-  constexpr bool coul = KIND == 1;
-  const T rc2 = (T)(coul ? pp.rc2 : pp.rlj2);
-  const double rc2d = coul ? pp.rc2 : pp.rlj2;
+  const T margin = T(1e-4);
+  const T rc2 = (T)pp.rlj2;
+  const double rc2d = pp.rlj2;
   const T band = rc2 * T(1.52587890625e-05);  // 2^-16 relative
   // LJ: sigma^6 and the force constant 24 eps sigma^6 of the shape function
   const double s6 = pp.sig2 * pp.sig2 * pp.sig2;
   const T two_s6 = (T)(2.0 * s6);
   const double lj_scale = pp.eps24 * s6;
 
-  // LDS: cell starts [ncells + 1], records [cap], record indices [cap] (Coulomb)
+  // LDS: cell starts [ncells + 1], records [cap]
   int *cs = (int *)tile_lds;
   V *rec = (V *)(tile_lds + ((size_t)(ncells + 1) * sizeof(int) + 15) / 16 * 16);
-  int *ridx = (int *)(rec + c.cap);
 
   // ---- own row segments (one per own row and species block) ----------------
   const int nsegs = 2 * c.TY * c.TZ;
@@ -315,13 +270,7 @@ __global__ void __launch_bounds__(kTileThreads) k_pair_tile(TileCtx c) {
           v.x = (T)((p.x + src.sx) - ox);
           v.y = (T)((p.y + src.sy) - oy);
           v.z = (T)((p.z + src.sz) - oz);
-          if (coul) {
-            v.w = (T)p.w;
-            ridx[d] = gj;
-          } else {
-            if constexpr (F32) v.w = __int_as_float(gj);
-            else v.w = (double)gj;
-          }
+          v.w = __int_as_float(gj);
           rec[d] = v;
         }
       }
@@ -378,7 +327,6 @@ __global__ void __launch_bounds__(kTileThreads) k_pair_tile(TileCtx c) {
     if (active) gi = grouped ? ilist[li] : nth_particle(li);
     const double4 pi = c.xq[active ? gi : 0];
     const T xi = (T)(pi.x - ox), yi = (T)(pi.y - oy), zi = (T)(pi.z - oz);
-    const T qi = (T)pi.w;
     // i's halo cell (an own cell: clamped there, so every row index below
     // stays inside the halo)
     const int ix = min(max(cell_coord(pi.x, g.inv_h[0], g.nx) - (x0 - c.s.x), c.s.x), c.s.x + c.TX - 1);
@@ -394,36 +342,23 @@ __global__ void __launch_bounds__(kTileThreads) k_pair_tile(TileCtx c) {
       }
       if (!active || r0 == r1) continue;
       const int base = cs[r0 * HX];
-      auto cand = [&](int k, const V &v, T &px, T &py, T &pz) {
+      auto cand = [&](const V &v, T &px, T &py, T &pz) {
         const T dx = xi - v.x, dy_ = yi - v.y, dz_ = zi - v.z;
-        T r2;
-        if constexpr (F32) r2 = fmaf(dz_, dz_, fmaf(dy_, dy_, dx * dx));
-        else r2 = sq_dist(dx, dy_, dz_);
-        int gj;
-        if constexpr (coul) gj = ridx[k];
-        else if constexpr (F32) gj = __float_as_int(v.w);
-        else gj = (int)v.w;
+        const T r2 = fmaf(dz_, dz_, fmaf(dy_, dy_, dx * dx));
+        const int gj = __float_as_int(v.w);
         bool in = (r2 <= rc2) & (gj != gi);
-        if constexpr (F32) {
-          if (fabsf(r2 - rc2) <= band && gj != gi) {
-            // near the cutoff: classify with the FP64 records (minimum image)
-            const double4 pj = gj < c.n ? c.xq[gj] : c.gxq[gj - c.n];
-            const double ex = min_image(pi.x - pj.x, g.L[0]), ey = min_image(pi.y - pj.y, g.L[1]),
-                         ez = min_image(pi.z - pj.z, g.L[2]);
-            in = sq_dist(ex, ey, ez) <= rc2d;
-          }
+        if (fabsf(r2 - rc2) <= band && gj != gi) {
+          // near the cutoff: classify with the FP64 records (minimum image)
+          const double4 pj = gj < c.n ? c.xq[gj] : c.gxq[gj - c.n];
+          const double ex = min_image(pi.x - pj.x, g.L[0]), ey = min_image(pi.y - pj.y, g.L[1]),
+                       ez = min_image(pi.z - pj.z, g.L[2]);
+          in = sq_dist(ex, ey, ez) <= rc2d;
         }
-        T f;
-        if constexpr (coul) {
-          if constexpr (F32) f = pair_coul_f32(c.pf, r2, qi * v.w);
-          else f = pair_coul_f64(pp, r2, qi * v.w);
-        } else {
-          f = lj_shape(r2, two_s6);
-        }
+        T f = lj_shape(r2, two_s6);
         f = in ? f : T(0);
-        px = fma(f, dx, px);
-        py = fma(f, dy_, py);
-        pz = fma(f, dz_, pz);
+        px = fmaf(f, dx, px);
+        py = fmaf(f, dy_, py);
+        pz = fmaf(f, dz_, pz);
         if (COUNT) {
           ++n_cand;
           n_pairs += in;
@@ -445,44 +380,31 @@ __global__ void __launch_bounds__(kTileThreads) k_pair_tile(TileCtx c) {
           if (rem < T(0)) continue;
           // the hardware square root (within 1 ulp) suffices: the margin
           // (1e-4 in FP32) covers its error many times over
-          T ext;
-          if constexpr (F32) ext = __builtin_amdgcn_sqrtf(rem) + margin;
-          else ext = sqrt(rem) + margin;
+          const T ext = __builtin_amdgcn_sqrtf(rem) + margin;
           int xa = (int)floor((xi - ext - X0) * invHx), xb = (int)floor((xi + ext - X0) * invHx);
           xa = max(xa, max(ix - c.s.x, 0));
           xb = min(xb, min(ix + c.s.x, HX - 1));
           if (xa > xb) continue;
           const int ka = cs[row * HX + xa] - base, kb = cs[row * HX + xb + 1] - base;
           T px = T(0), py = T(0), pz = T(0);
-          if constexpr (!coul) {
-            // four candidates per trip, all records requested before use; the
-            // trip count runs on the record pointer alone
-            const V *q = rec + ka;
-            const V *const qe = rec + kb, *const qe4 = qe - 3;
-            for (; q < qe4; q += 4) {
-              const V v0 = q[0], v1 = q[1], v2 = q[2], v3 = q[3];
-              cand(0, v0, px, py, pz);
-              cand(0, v1, px, py, pz);
-              cand(0, v2, px, py, pz);
-              cand(0, v3, px, py, pz);
-            }
-            if (q + 1 < qe) {
-              const V v0 = q[0], v1 = q[1];
-              cand(0, v0, px, py, pz);
-              cand(0, v1, px, py, pz);
-              q += 2;
-            }
-            if (q < qe) cand(0, q[0], px, py, pz);
-          } else {
-            // two candidates per trip: both records are requested before use
-            int k = ka;
-            for (; k + 1 < kb; k += 2) {
-              const V va = rec[k], vb = rec[k + 1];
-              cand(k, va, px, py, pz);
-              cand(k + 1, vb, px, py, pz);
-            }
-            if (k < kb) cand(k, rec[k], px, py, pz);
+          // four candidates per trip, all records requested before use; the
+          // trip count runs on the record pointer alone
+          const V *q = rec + ka;
+          const V *const qe = rec + kb, *const qe4 = qe - 3;
+          for (; q < qe4; q += 4) {
+            const V v0 = q[0], v1 = q[1], v2 = q[2], v3 = q[3];
+            cand(v0, px, py, pz);
+            cand(v1, px, py, pz);
+            cand(v2, px, py, pz);
+            cand(v3, px, py, pz);
           }
+          if (q + 1 < qe) {
+            const V v0 = q[0], v1 = q[1];
+            cand(v0, px, py, pz);
+            cand(v1, px, py, pz);
+            q += 2;
+          }
+          if (q < qe) cand(q[0], px, py, pz);
           tile_kahan(S[0], K[0], px);
           tile_kahan(S[1], K[1], py);
           tile_kahan(S[2], K[2], pz);
@@ -490,22 +412,13 @@ __global__ void __launch_bounds__(kTileThreads) k_pair_tile(TileCtx c) {
       }
     }
     if (active) {
-      const double sc = coul ? 1.0 : lj_scale;
-      const double fx = sc * ((double)S[0] - (double)K[0]), fy = sc * ((double)S[1] - (double)K[1]),
-                   fz = sc * ((double)S[2] - (double)K[2]);
-      if (c.accumulate) {
-        c.fx[gi] += fx;
-        c.fy[gi] += fy;
-        c.fz[gi] += fz;
-      } else {
-        c.fx[gi] = fx;
-        c.fy[gi] = fy;
-        c.fz[gi] = fz;
-      }
+      c.fx[gi] = lj_scale * ((double)S[0] - (double)K[0]);
+      c.fy[gi] = lj_scale * ((double)S[1] - (double)K[1]);
+      c.fz[gi] = lj_scale * ((double)S[2] - (double)K[2]);
     }
   }
   if (COUNT) {
-    atomicAdd(&c.counters[coul ? 0 : 1], n_pairs);
+    atomicAdd(&c.counters[1], n_pairs);
     atomicAdd(&c.counters[2], n_cand);
   }
 }
@@ -519,7 +432,7 @@ constexpr size_t kTileLdsBytes = 48 * 1024;
 // tile holds about one particle per thread at the mean density, and its halo
 // stays within the LDS staging (the staging is sized for the halo of the
 // mean density with room to spare; denser halos are processed in chunks).
-static void tile_geometry(const PairParams &pp, const Sten &s, int64_t n, int rec_bytes, TileCtx *c) {
+static void tile_geometry(const PairParams &pp, const Sten &s, int64_t n, TileCtx *c) {
   const Grid &g = pp.g;
   const double hyz = std::fmax(g.L[1] / g.ny, g.L[2] / g.nz);
   const int T = hyz >= 2.0 ? 2 : 4;  // 2 T^2 own row segments <= kTileMaxSegs
@@ -537,7 +450,7 @@ static void tile_geometry(const PairParams &pp, const Sten &s, int64_t n, int re
   auto cap_of = [&](int t) {
     const int ncells = HYZ * (t + 2 * s.x);
     const size_t fixed = ((size_t)(ncells + 1) * sizeof(int) + 15) / 16 * 16;
-    return fixed >= kTileLdsBytes ? 0 : (int)((kTileLdsBytes - fixed) / rec_bytes);
+    return fixed >= kTileLdsBytes ? 0 : (int)((kTileLdsBytes - fixed) / sizeof(float4));
   };
   while (tx > 1 && 0.6 * cap_of(tx) < dens * HYZ * (tx + 2 * s.x)) --tx;
   c->TX = tx;
@@ -550,43 +463,37 @@ static void tile_geometry(const PairParams &pp, const Sten &s, int64_t n, int re
   c->ntz = (g.nz + c->TZ - 1) / c->TZ;
 }
 
-template <bool F32, bool GHOST>
+template <bool GHOST>
 static void launch_tile_t(const TileCtx &c, hipStream_t st) {
   const int ncells = (c.TY + 2 * c.s.y) * (c.TZ + 2 * c.s.z) * (c.TX + 2 * c.s.x);
-  const size_t lds = ((size_t)(ncells + 1) * sizeof(int) + 15) / 16 * 16 +
-                     (size_t)c.cap * (F32 ? sizeof(float4) : sizeof(double4)) +
-                     (c.kind == 1 ? (size_t)c.cap * sizeof(int) : 0);
+  const size_t lds = ((size_t)(ncells + 1) * sizeof(int) + 15) / 16 * 16 + (size_t)c.cap * sizeof(float4);
   const unsigned tiles = (unsigned)((int64_t)c.ntx * c.nty * c.ntz);
   if (c.counters)
-    k_pair_tile<F32, GHOST, 0, true><<<tiles, kTileThreads, lds, st>>>(c);
+    k_pair_tile<GHOST, true><<<tiles, kTileThreads, lds, st>>>(c);
   else
-    k_pair_tile<F32, GHOST, 0, false><<<tiles, kTileThreads, lds, st>>>(c);
+    k_pair_tile<GHOST, false><<<tiles, kTileThreads, lds, st>>>(c);
 }
 
 bool lj_tile_applicable(int prec, const PairParams &pp, int64_t n) {
   if (prec != RBE_FP32C || !pp.do_lj || n <= 0) return false;
   TileCtx c{};
-  tile_geometry(pp, pp.s_lj, n, (int)sizeof(float4), &c);
-  // a halo row of the mean density must fill at most an eighth of the
-  // staging, so only rows far denser than the mean need a chunk of their own
+  tile_geometry(pp, pp.s_lj, n, &c);
   const double dens = (double)n / (double)pp.g.ncell;
   const Grid &g = pp.g;
   // rows about as wide as the LJ reach (wider rows waste most candidates);
-  // a halo row of the mean density fills at most an eighth of the staging
+  // a halo row of the mean density fills at most an eighth of the staging,
+  // so only rows far denser than the mean need a chunk of their own
   const double hyz = std::fmax(g.L[1] / g.ny, g.L[2] / g.nz);
   return hyz <= 1.2 * std::sqrt(pp.rlj2) && c.cap >= 512 && dens * (c.TX + 2 * c.s.x) <= c.cap / 8.0;
 }
 
-void launch_lj_tile(int prec, const PairParams &pp, int64_t n, int iblk, const Sorted &s, const int32_t *cell_start,
+void launch_lj_tile(const PairParams &pp, int64_t n, int iblk, const Sorted &s, const int32_t *cell_start,
                     const GhostBuffers *gb, double *fx, double *fy, double *fz, unsigned long long *counters,
                     int *err, hipStream_t st) {
   if (n <= 0) return;
   TileCtx c{};
   c.pp = pp;
-  c.pf = make_pair_f32(pp);
-  c.kind = 0;
   c.iblk = iblk;
-  c.accumulate = 0;
   c.xq = s.xq;
   c.cell_start = cell_start;
   c.gxq = gb ? gb->xq : nullptr;
@@ -597,15 +504,9 @@ void launch_lj_tile(int prec, const PairParams &pp, int64_t n, int iblk, const S
   c.fz = fz;
   c.counters = counters;
   c.err = err;
-  const bool f32 = prec == RBE_FP32C;
-  tile_geometry(pp, pp.s_lj, n, f32 ? (int)sizeof(float4) : (int)sizeof(double4), &c);
-  if (f32) {
-    if (gb) launch_tile_t<true, true>(c, st);
-    else launch_tile_t<true, false>(c, st);
-  } else {
-    if (gb) launch_tile_t<false, true>(c, st);
-    else launch_tile_t<false, false>(c, st);
-  }
+  tile_geometry(pp, pp.s_lj, n, &c);
+  if (gb) launch_tile_t<true>(c, st);
+  else launch_tile_t<false>(c, st);
 }
 
 }  // namespace rbe
