@@ -181,7 +181,15 @@ __global__ void __launch_bounds__(kTileThreads) k_pair_tile(TileCtx c) {
   const T margin = T(1e-4);
   const T rc2 = (T)pp.rlj2;
   const double rc2d = pp.rlj2;
-  const T band = rc2 * T(1.52587890625e-05);  // 2^-16 relative
+  // FP32 classes of r^2 from its bits (non-negative floats order as their
+  // bit patterns), lo = rc2 (1 - 2^-16), hi = rc2 (1 + 2^-16): with
+  // d = bits(r^2) - 1 - bits(lo) (mod 2^32), d >= 2^32 - bits(lo) is
+  // 0 < r^2 <= lo (r^2 = 0, the particle itself, wraps out of it), and
+  // d < bits(hi) - bits(lo) is the guard band lo < r^2 <= hi, classified
+  // from the FP64 records
+  const T band = rc2 * T(1.52587890625e-05);
+  const unsigned lo_bits = __float_as_uint(rc2 - band), hi_bits = __float_as_uint(rc2 + band);
+  const unsigned d_off = ~lo_bits, in_min = 0u - lo_bits, band_w = hi_bits - lo_bits;
   // LJ: sigma^6 and the force constant 24 eps sigma^6 of the shape function
   const double s6 = pp.sig2 * pp.sig2 * pp.sig2;
   const T two_s6 = (T)(2.0 * s6);
@@ -342,27 +350,45 @@ __global__ void __launch_bounds__(kTileThreads) k_pair_tile(TileCtx c) {
       }
       if (!active || r0 == r1) continue;
       const int base = cs[r0 * HX];
-      auto cand = [&](const V &v, T &px, T &py, T &pz) {
-        const T dx = xi - v.x, dy_ = yi - v.y, dz_ = zi - v.z;
-        const T r2 = fmaf(dz_, dz_, fmaf(dy_, dy_, dx * dx));
+      // one candidate: displacement, r^2 and its FP32 class
+      struct Cand {
+        T dx, dy, dz, r2;
+        bool in, band;
+      };
+      auto prep = [&](const V &v) {
+        Cand k;
+        k.dx = xi - v.x;
+        k.dy = yi - v.y;
+        k.dz = zi - v.z;
+        k.r2 = fmaf(k.dz, k.dz, fmaf(k.dy, k.dy, k.dx * k.dx));
+        const unsigned d = __float_as_uint(k.r2) + d_off;
+        k.in = d >= in_min;
+        k.band = d < band_w;
+        return k;
+      };
+      // near the cutoff: the class from the FP64 records (minimum image)
+      auto fp64_in = [&](const V &v) {
         const int gj = __float_as_int(v.w);
-        bool in = (r2 <= rc2) & (gj != gi);
-        if (fabsf(r2 - rc2) <= band && gj != gi) {
-          // near the cutoff: classify with the FP64 records (minimum image)
-          const double4 pj = gj < c.n ? c.xq[gj] : c.gxq[gj - c.n];
-          const double ex = min_image(pi.x - pj.x, g.L[0]), ey = min_image(pi.y - pj.y, g.L[1]),
-                       ez = min_image(pi.z - pj.z, g.L[2]);
-          in = sq_dist(ex, ey, ez) <= rc2d;
-        }
-        T f = lj_shape(r2, two_s6);
-        f = in ? f : T(0);
-        px = fmaf(f, dx, px);
-        py = fmaf(f, dy_, py);
-        pz = fmaf(f, dz_, pz);
+        const double4 pj = gj < c.n ? c.xq[gj] : c.gxq[gj - c.n];
+        const double ex = min_image(pi.x - pj.x, g.L[0]), ey = min_image(pi.y - pj.y, g.L[1]),
+                     ez = min_image(pi.z - pj.z, g.L[2]);
+        return sq_dist(ex, ey, ez) <= rc2d;
+      };
+      auto add = [&](const Cand &k, T &px, T &py, T &pz) {
+        T f = lj_shape(k.r2, two_s6);
+        f = k.in ? f : T(0);
+        px = fmaf(f, k.dx, px);
+        py = fmaf(f, k.dy, py);
+        pz = fmaf(f, k.dz, pz);
         if (COUNT) {
           ++n_cand;
-          n_pairs += in;
+          n_pairs += k.in;
         }
+      };
+      auto cand = [&](const V &v, T &px, T &py, T &pz) {
+        Cand k = prep(v);
+        if (k.band) k.in = fp64_in(v);
+        add(k, px, py, pz);
       };
       // the rows the reach sphere touches, each trimmed to the x-cells it
       // spans; a row's terms are summed in FP32 and its sum added to the
@@ -393,10 +419,20 @@ __global__ void __launch_bounds__(kTileThreads) k_pair_tile(TileCtx c) {
           const V *const qe = rec + kb, *const qe4 = qe - 3;
           for (; q < qe4; q += 4) {
             const V v0 = q[0], v1 = q[1], v2 = q[2], v3 = q[3];
-            cand(v0, px, py, pz);
-            cand(v1, px, py, pz);
-            cand(v2, px, py, pz);
-            cand(v3, px, py, pz);
+            Cand k0 = prep(v0), k1 = prep(v1), k2 = prep(v2), k3 = prep(v3);
+            // one wave-uniform branch for the rare guard-band candidates of
+            // the trip (the lane masks are combined as scalars)
+            if (__builtin_amdgcn_ballot_w64(k0.band) | __builtin_amdgcn_ballot_w64(k1.band) |
+                __builtin_amdgcn_ballot_w64(k2.band) | __builtin_amdgcn_ballot_w64(k3.band)) {
+              if (k0.band) k0.in = fp64_in(v0);
+              if (k1.band) k1.in = fp64_in(v1);
+              if (k2.band) k2.in = fp64_in(v2);
+              if (k3.band) k3.in = fp64_in(v3);
+            }
+            add(k0, px, py, pz);
+            add(k1, px, py, pz);
+            add(k2, px, py, pz);
+            add(k3, px, py, pz);
           }
           if (q + 1 < qe) {
             const V v0 = q[0], v1 = q[1];
