@@ -358,15 +358,20 @@ __device__ inline void for_stencil_ghost(const Grid &g, const int32_t *__restric
       const int y = cy + oy;
       int xa, xb;
       if (!row_range(g, R, slab_gap(R.y, y, hy), gz, cx, s.x, &xa, &xb)) continue;
-      if (z >= 0 && z < g.nz && y >= 0 && y < g.ny) {
+      const bool inner = z >= 0 && z < g.nz && y >= 0 && y < g.ny;
+      if (inner) {
         const int na = max(xa, 0), nb = min(xb, g.nx - 1);
         if (na <= nb) {
           const int row = base + (z * g.ny + y) * g.nx;
           scan_range<WITH_ID>(xq, ids, cell_start[row + na], cell_start[row + nb + 1], 0.0, 0.0, 0.0, fn);
         }
       }
-      const int prow = pbase + ((z + g.goff[2]) * g.pny + (y + g.goff[1])) * g.pnx + g.goff[0];
-      scan_range<WITH_ID>(gxq, gid, gcell_start[prow + xa], gcell_start[prow + xb + 1], 0.0, 0.0, 0.0, fn, nnat);
+      // the padded cells over the native grid hold no ghosts: a row range
+      // inside it has none to scan
+      if (!inner || xa < 0 || xb >= g.nx) {
+        const int prow = pbase + ((z + g.goff[2]) * g.pny + (y + g.goff[1])) * g.pnx + g.goff[0];
+        scan_range<WITH_ID>(gxq, gid, gcell_start[prow + xa], gcell_start[prow + xb + 1], 0.0, 0.0, 0.0, fn, nnat);
+      }
       row_end();
     }
   }
