@@ -310,7 +310,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchArgs a) {
 #pragma unroll 4
         for (int64_t j = j0; j < j1; ++j) {
           const double4 s = a.sq[j];
-          const float t = (float)turn_fraction(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
+          const float t = turn_f32(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
           const float q = (float)s.w;
           kahan_fma(re, rc, q, __builtin_amdgcn_cosf(t));
           kahan_fma(im, ic, q, __builtin_amdgcn_sinf(t));
@@ -374,7 +374,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchArgs a) {
 #pragma unroll 4
         for (int l = 0; l < P; ++l) {
           const GatherMode gm = md[l];
-          const float t = (float)turn_fraction(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
+          const float t = turn_f32(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
           const float g = fmaf(gm.af, __builtin_amdgcn_cosf(t), -gm.bf * __builtin_amdgcn_sinf(t));
           kahan_fma(gx, ex, g, gm.mxf);
           kahan_fma(gy, ey, g, gm.myf);

@@ -149,7 +149,7 @@ __global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f32c(const int32
   }
   float re = 0.f, re_c = 0.f, im = 0.f, im_c = 0.f;
   auto term = [&](const double4 &r, float &br, float &bi) {
-    const float t = (float)turn_fraction(mx, my, mz, r.x, r.y, r.z);
+    const float t = turn_f32(mx, my, mz, r.x, r.y, r.z);
     const float q = rec_q(r);
     br = fmaf(q, __builtin_amdgcn_cosf(t), br);
     bi = fmaf(q, __builtin_amdgcn_sinf(t), bi);
@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(kModesPerBlock) k_rho_partial_f32c(const int32
     } else {
       for (int u = ph; u < cnt; u += rep) {
         const double4 r = rec[u];
-        const float t = (float)turn_fraction(mx, my, mz, r.x, r.y, r.z);
+        const float t = turn_f32(mx, my, mz, r.x, r.y, r.z);
         kahan_fma(re, re_c, rec_q(r), __builtin_amdgcn_cosf(t));
         kahan_fma(im, im_c, rec_q(r), __builtin_amdgcn_sinf(t));
       }
@@ -336,8 +336,8 @@ __global__ void __launch_bounds__(kGatherThreads) k_gather_f32c(const int32_t *_
   float hx = 0.f, hy = 0.f, hz = 0.f, dx = 0.f, dy = 0.f, dz = 0.f;
   auto term = [&](int l, float &bx, float &by, float &bz, float &ex, float &ey, float &ez) {
     const GatherMode gm = modes[l];
-    const float t = (float)turn_fraction(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
-    const float t2 = (float)turn_fraction(gm.mx, gm.my, gm.mz, s2.x, s2.y, s2.z);
+    const float t = turn_f32(gm.mx, gm.my, gm.mz, s.x, s.y, s.z);
+    const float t2 = turn_f32(gm.mx, gm.my, gm.mz, s2.x, s2.y, s2.z);
     const float g = fmaf(gm.af, __builtin_amdgcn_cosf(t), -gm.bf * __builtin_amdgcn_sinf(t));
     const float g2 = fmaf(gm.af, __builtin_amdgcn_cosf(t2), -gm.bf * __builtin_amdgcn_sinf(t2));
     bx = fmaf(g, gm.mxf, bx);

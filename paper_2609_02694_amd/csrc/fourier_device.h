@@ -12,6 +12,15 @@ __device__ inline double turn_fraction(double mx, double my, double mz, double s
   return t - rint(t);
 }
 
+// The same phase as an FP32 argument of the hardware sin/cos, which take
+// turns: any representative of m . s mod 1 serves, so the reduction is the
+// fractional part in [0, 1) (one instruction), then rounded to FP32 (at most
+// 2^-25 turns off).
+__device__ inline float turn_f32(double mx, double my, double mz, double sx, double sy, double sz) {
+  const double t = fma(mx, sx, fma(my, sy, mz * sz));
+  return (float)__builtin_amdgcn_fract(t);
+}
+
 // sin and cos of 2 pi t for |t| <= 1/2 (FP64): u = 4t and f = u - rint(u)
 // are exact, theta = f pi/2 lies in [-pi/4, pi/4], sin theta and cos theta
 // come from their Taylor series to degrees 15 and 16 (truncation below
