@@ -47,7 +47,7 @@ struct TileCtx {
 constexpr int kTileThreads = 256;
 constexpr int kTileMaxSegs = 64;    // own row segments (rows x species blocks) of a tile
 constexpr int kTileMaxChunks = 64;  // halo chunks of a tile whose halo exceeds the staging
-constexpr int kTileIMax = 512;      // particles of a tile grouped by quadrant (more: cell order)
+constexpr int kTileIMax = 320;      // particles of a tile grouped by quadrant (more: cell order)
 
 // A record of the LDS staging is a float4: the FP32 frame coordinates and,
 // in w, the record's index as bits (the LJ terms need no charge).
@@ -148,8 +148,10 @@ __device__ inline void tile_kahan(float &s, float &c, float v) {
   s = t;
 }
 
+// Five waves per SIMD (at most 96 VGPRs, two of them spilled outside the
+// candidate loop): 25.8 against 27.3 ms per 64M step at four.
 template <bool GHOST, bool COUNT>
-__global__ void __launch_bounds__(kTileThreads) k_pair_tile(TileCtx c) {
+__global__ void __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(5))) k_pair_tile(TileCtx c) {
   using T = float;
   using V = float4;
   extern __shared__ __align__(16) unsigned char tile_lds[];
@@ -490,9 +492,12 @@ static void tile_geometry(const PairParams &pp, const Sten &s, int64_t n, TileCt
   };
   while (tx > 1 && 0.6 * cap_of(tx) < dens * HYZ * (tx + 2 * s.x)) --tx;
   c->TX = tx;
-  // the staging holds the mean halo with 25 % headroom (about 7 standard
-  // deviations of a uniform fluid's halo count); denser halos go in chunks
-  const int want = (int)std::ceil(1.25 * dens * HYZ * (tx + 2 * s.x)) + 64;
+  // the staging holds the mean halo with 15 % and 64 records of headroom
+  // (6-7 standard deviations of a Poisson halo count of this size); denser
+  // halos go in chunks. A block then takes about 31 KB of LDS at the
+  // subdomain's density, so that five blocks share a CU (the five waves per
+  // SIMD the kernel is compiled for)
+  const int want = (int)std::ceil(1.15 * dens * HYZ * (tx + 2 * s.x)) + 64;
   c->cap = std::min(cap_of(tx), std::max(want, 256));
   c->ntx = (g.nx + c->TX - 1) / c->TX;
   c->nty = (g.ny + c->TY - 1) / c->TY;
