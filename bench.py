@@ -90,6 +90,8 @@ def parse():
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel HIP event pass")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (scale of the HBM byte counters)")
+    ap.add_argument("--calibrate-valu", action="store_true",
+                    help="only run the vector-ALU issue-rate probe (include/rbe_probe.h), each mix twice")
     return ap.parse_args()
 
 
@@ -110,6 +112,16 @@ def calibrate_copy(mib):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"calibrate_copy_mib": mib, "bytes_per_copy": 2 * n * 8}), flush=True)
+
+
+def calibrate_valu(rbe):
+    """The vector-ALU issue-rate probe, each instruction mix twice (the first
+    launch warms up): the SIMD cycles one wave64 instruction of the mix takes
+    follow from rocprofv3's SQ_INSTS_VALU and GRBM_GUI_ACTIVE of the second."""
+    blocks, iters = 4096, 4000
+    for kind in rbe.PROBE_KINDS:
+        ms = [rbe.probe_valu(kind, blocks, iters) for _ in range(2)]
+        print(json.dumps({"calibrate_valu": kind, "blocks": blocks, "iters": iters, "ms": ms[1]}), flush=True)
 
 
 # ---------------------------------------------------------------------------
@@ -808,6 +820,8 @@ def main():
     torch.cuda.set_device(0)
     if a.calibrate_copy:
         return calibrate_copy(a.calibrate_copy)
+    if a.calibrate_valu:
+        return calibrate_valu(rbe)
     rbe.load()
     t_start = time.time()
     common = {"metric": METRIC, "unit": "particle-steps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,

@@ -27,6 +27,9 @@ MAX_SHELL_BATCH = 32
 EXPORTED = ["rbe_create", "rbe_create_batch", "rbe_destroy", "rbe_last_error", "rbe_build_cells", "rbe_sample_k",
             "rbe_forces", "rbe_energy", "rbe_step", "rbe_sync_check", "rbe_set_counting", "rbe_get_counters", "rbe_set_timing",
             "rbe_get_timing", "rbe_forces_noalloc", "rbe_lattice_modes", "rbe_set_modes"]
+# measurement support (include/rbe_probe.h)
+PROBE_EXPORTED = ["rbe_probe_valu"]
+PROBE_KINDS = ["fma_f32", "mul_add_f32", "lj_body", "rcp_f32"]
 NOALLOC_MAX_N = 32768
 NOALLOC_MAX_P = 1024
 NOALLOC_MAX_KEYS = 131072
@@ -99,6 +102,7 @@ def load():
         "rbe_forces_noalloc": [P, ctypes.POINTER(State), vp, vp, u64, vp, vp, vp],
         "rbe_lattice_modes": [P, ctypes.c_double, vp, vp, i32, ctypes.POINTER(i32)],
         "rbe_set_modes": [vp, vp, vp, vp],
+        "rbe_probe_valu": [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(ctypes.c_float), vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -237,6 +241,20 @@ def lattice_modes(params: Params, k_max: float):
     _check(lib, None, lib.rbe_lattice_modes(ctypes.byref(params), k_max, ctypes.c_void_p(m.ctypes.data),
                                             ctypes.c_void_p(w.ctypes.data), P, ctypes.byref(cnt)))
     return m.reshape(3, P), w
+
+
+def probe_valu(kind: str, blocks: int = 4096, iters: int = 4000, stream=None) -> float:
+    """Duration in ms of one rbe_probe_valu launch of the given instruction
+    mix (PROBE_KINDS; measurement support, see include/rbe_probe.h)."""
+    import torch
+    lib = load()
+    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    ms = ctypes.c_float()
+    _check(lib, None, lib.rbe_probe_valu(PROBE_KINDS.index(kind), blocks, iters, _ptr(out), ctypes.byref(ms),
+                                         _stream(stream)))
+    if not torch.isfinite(out).all():
+        raise RbeError(RBE_ENONFINITE, f"probe {kind} produced non-finite values")
+    return ms.value
 
 
 def forces_noalloc(params: Params, st: "Particles", m, w, ev: int = 0, rho_out=None, status_out=None,

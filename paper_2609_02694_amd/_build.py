@@ -8,7 +8,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpaper_rbe.so")
-SOURCES = ["api.hip", "batch.hip", "bin.hip", "energy.hip", "fourier.hip", "ghost.hip", "integrate.hip", "pair.hip", "sampler.hip", "tile.hip"]
+SOURCES = ["api.hip", "batch.hip", "bin.hip", "energy.hip", "fourier.hip", "ghost.hip", "integrate.hip", "pair.hip", "probe.hip", "sampler.hip", "tile.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

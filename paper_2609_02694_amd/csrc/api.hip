@@ -128,6 +128,8 @@ static int create_fail(int code, const char *msg) {
   return code;
 }
 
+int rbe::fail_without_context(int code, const char *msg) { return create_fail(code, msg); }
+
 #define HIP_TRY(ctx, expr)                                                                     \
   do {                                                                                         \
     hipError_t e_ = (expr);                                                                    \

@@ -340,4 +340,8 @@ void launch_batch_layout(int nrep, const int32_t *nq, const double *qs, int P, i
 // *p = v on the stream (a kernel, so graph capture records no memset node).
 void launch_set_u64(uint64_t *p, uint64_t v, hipStream_t st);
 
+// Error of a call without a context: the message rbe_last_error(NULL)
+// returns, and the status code passed through.
+int fail_without_context(int code, const char *msg);
+
 }  // namespace rbe

@@ -11,17 +11,35 @@ import paper_2609_02694_amd as rbe
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_symbols():
-    text = open(os.path.join(ROOT, "include", "rbe.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*\*?\s*(rbe_\w+)\s*\(", text, flags=re.M)))
+def declared_symbols(header=None):
+    """Entry points declared in include/<header> (every header when None)."""
+    names = [header] if header else sorted(f for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h"))
+    syms = set()
+    for h in names:
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        syms |= set(re.findall(r"^\s*(?:int|void|const char \*)\s*\*?\s*(rbe_\w+)\s*\(", text, flags=re.M))
+    return sorted(syms)
 
 
 def test_header_declares_the_documented_calls():
-    syms = declared_symbols()
+    syms = declared_symbols("rbe.h")
     for s in ("rbe_create", "rbe_build_cells", "rbe_sample_k", "rbe_forces", "rbe_step", "rbe_sync_check"):
         assert s in syms
     assert set(syms) == set(rbe.EXPORTED)
+    assert declared_symbols("rbe_probe.h") == rbe.PROBE_EXPORTED
+
+
+def test_probe_rejects_bad_arguments_on_the_host():
+    lib = rbe.load()
+    ms = ctypes.c_float()
+    out = ctypes.c_void_p(16)  # never dereferenced: every call below fails its host checks
+    assert lib.rbe_probe_valu(7, 1, 1, out, ctypes.byref(ms), None) == rbe.RBE_EINVAL
+    assert "unknown probe kind" in lib.rbe_last_error(None).decode()
+    assert lib.rbe_probe_valu(0, 0, 1, out, ctypes.byref(ms), None) == rbe.RBE_EINVAL
+    assert lib.rbe_probe_valu(0, 1, 0, out, ctypes.byref(ms), None) == rbe.RBE_EINVAL
+    assert lib.rbe_probe_valu(0, 1, 1, None, ctypes.byref(ms), None) == rbe.RBE_EINVAL
+    assert lib.rbe_probe_valu(0, 1, 1, out, None, None) == rbe.RBE_EINVAL
 
 
 def test_library_exports_every_declared_symbol():
