@@ -1,10 +1,12 @@
 // Batched form: many independent systems ("replicas") of uneven size advanced
-// together, one persistent fused launch per velocity-Verlet step.
+// together, three launches per velocity-Verlet step.
 //
 // All replicas live in concatenated arrays; replica r owns particles
 // [p0, p0 + n) and binning keys [c0, c0 + 2 C_r) (its charged cells, then its
-// neutral cells). One kernel runs the whole step for every replica, phase by
-// phase, with a grid-wide barrier between phases:
+// neutral cells). A persistent kernel runs the step for every replica, phase
+// by phase, with a grid-wide barrier between phases, in two launches: P0-P6,
+// then P7-P9. Between them a plain kernel sums the near field of every
+// particle, with the occupancy of its own register count:
 //
 //   P0  half-kick + drift + wrap; binning keys + histogram; mode sample of
 //       every replica (Eq. 9)
@@ -15,7 +17,8 @@
 //   P4  provisional scatter (atomic slots)
 //   P5  stable placement (each bucket's entries in increasing input order)
 //   P6  reorder of the state and packing of the sorted records
-//   P7  near field of every particle; structure-factor partials (chunk x mode)
+//   --  near field of every particle (k_batch_near)
+//   P7  structure-factor partials (chunk x mode)
 //   P8  structure factors: fixed-order sum of the chunk partials per mode
 //   P9  Fourier gather + second half-kick
 //
@@ -135,156 +138,150 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchArgs a) {
   const int64_t gwave = xcd_block(blockIdx.x, gridDim.x) * (kBatchThreads / 64) + (tid >> 6);
   const int64_t nwaves = (int64_t)gridDim.x * (kBatchThreads / 64);
   const int P = a.P;
-  const bool do_near = (a.pp.do_coul || a.pp.do_lj);
   const bool do_far = a.do_far != 0;
   const uint64_t eval = *((volatile uint64_t *)a.eval);
 
-  // ---- P0: drift, keys + histogram, mode sample ----------------------------
-  // wave-uniform trip count (every lane takes part in the slot vote)
-  for (int64_t i = gtid; i - lane < a.ntot; i += gstride) {
-    const bool active = i < a.ntot;
-    int k = -1 - lane;  // lanes past the end: a key no other lane has
-    if (active) {
-      const RepDesc &R = a.reps[a.rep_of[i]];
-      double x = a.ix[i], y = a.iy[i], z = a.iz[i];
-      if (a.mode == 0) {
-        const double u = a.ivx[i] + a.h * a.ifx[i], v = a.ivy[i] + a.h * a.ify[i], w = a.ivz[i] + a.h * a.ifz[i];
-        a.ivx[i] = u;
-        a.ivy[i] = v;
-        a.ivz[i] = w;
-        x = wrap_coord(x + a.dt * u, R.g.L[0]);
-        y = wrap_coord(y + a.dt * v, R.g.L[1]);
-        z = wrap_coord(z + a.dt * w, R.g.L[2]);
-        a.ix[i] = x;
-        a.iy[i] = y;
-        a.iz[i] = z;
-        if (!isfinite(u) || !isfinite(v) || !isfinite(w)) atomicOr(a.err, kErrNonFinite);
-      } else {
-        x = wrap_coord(x, R.g.L[0]);
-        y = wrap_coord(y, R.g.L[1]);
-        z = wrap_coord(z, R.g.L[2]);
+  if (a.launch_part == 1) {
+    // ---- P0: drift, keys + histogram, mode sample ----------------------------
+    // wave-uniform trip count (every lane takes part in the slot vote)
+    for (int64_t i = gtid; i - lane < a.ntot; i += gstride) {
+      const bool active = i < a.ntot;
+      int k = -1 - lane;  // lanes past the end: a key no other lane has
+      if (active) {
+        const RepDesc &R = a.reps[a.rep_of[i]];
+        double x = a.ix[i], y = a.iy[i], z = a.iz[i];
+        if (a.mode == 0) {
+          const double u = a.ivx[i] + a.h * a.ifx[i], v = a.ivy[i] + a.h * a.ify[i], w = a.ivz[i] + a.h * a.ifz[i];
+          a.ivx[i] = u;
+          a.ivy[i] = v;
+          a.ivz[i] = w;
+          x = wrap_coord(x + a.dt * u, R.g.L[0]);
+          y = wrap_coord(y + a.dt * v, R.g.L[1]);
+          z = wrap_coord(z + a.dt * w, R.g.L[2]);
+          a.ix[i] = x;
+          a.iy[i] = y;
+          a.iz[i] = z;
+          if (!isfinite(u) || !isfinite(v) || !isfinite(w)) atomicOr(a.err, kErrNonFinite);
+        } else {
+          x = wrap_coord(x, R.g.L[0]);
+          y = wrap_coord(y, R.g.L[1]);
+          z = wrap_coord(z, R.g.L[2]);
+        }
+        const int cx = cell_coord(x, R.g.inv_h[0], R.g.nx);
+        const int cy = cell_coord(y, R.g.inv_h[1], R.g.ny);
+        const int cz = cell_coord(z, R.g.inv_h[2], R.g.nz);
+        k = (int)(R.c0 + (a.iq[i] == 0.0 ? R.g.ncell : 0) + (cz * R.g.ny + cy) * R.g.nx + cx);
+        a.key[i] = k;
       }
-      const int cx = cell_coord(x, R.g.inv_h[0], R.g.nx);
-      const int cy = cell_coord(y, R.g.inv_h[1], R.g.ny);
-      const int cz = cell_coord(z, R.g.inv_h[2], R.g.nz);
-      k = (int)(R.c0 + (a.iq[i] == 0.0 ? R.g.ncell : 0) + (cz * R.g.ny + cy) * R.g.nx + cx);
-      a.key[i] = k;
+      const int sl = run_slot(k, active, a.count);
+      if (active) a.slot[i] = sl;
     }
-    const int sl = run_slot(k, active, a.count);
-    if (active) a.slot[i] = sl;
-  }
-  if (P > 0) {
-    for (int64_t it = gtid; it < (int64_t)a.nrep * P; it += gstride) {
-      const int r = (int)(it / P), l = (int)(it % P);
-      const RepDesc &R = a.reps[r];
-      const uint64_t ek = stream_out(R.seed ^ kTagModes, eval);
-      int mv[3];
-      if (!draw_mode(R.mt, a.cdf + R.cdf_off, ek, l, mv)) {
-        atomicOr(a.err, kErrSampler);
-        mv[0] = 1;
-        mv[1] = 0;
-        mv[2] = 0;
+    if (P > 0) {
+      for (int64_t it = gtid; it < (int64_t)a.nrep * P; it += gstride) {
+        const int r = (int)(it / P), l = (int)(it % P);
+        const RepDesc &R = a.reps[r];
+        const uint64_t ek = stream_out(R.seed ^ kTagModes, eval);
+        int mv[3];
+        if (!draw_mode(R.mt, a.cdf + R.cdf_off, ek, l, mv)) {
+          atomicOr(a.err, kErrSampler);
+          mv[0] = 1;
+          mv[1] = 0;
+          mv[2] = 0;
+        }
+        GatherMode gm;
+        gm.mx = (double)mv[0];
+        gm.my = (double)mv[1];
+        gm.mz = (double)mv[2];
+        gm.a = 0.0;
+        gm.b = 0.0;
+        gather_floats(gm);
+        a.modes[it] = gm;
+        a.wk[it] = mode_weight(R.mt, P, mv[0], mv[1], mv[2]);
       }
-      GatherMode gm;
-      gm.mx = (double)mv[0];
-      gm.my = (double)mv[1];
-      gm.mz = (double)mv[2];
-      gm.a = 0.0;
-      gm.b = 0.0;
-      gather_floats(gm);
-      a.modes[it] = gm;
-      a.wk[it] = mode_weight(R.mt, P, mv[0], mv[1], mv[2]);
     }
-  }
-  grid_barrier(a.bar, a.err);
+    grid_barrier(a.bar, a.err);
 
-  // ---- P1: tile sums -------------------------------------------------------
-  for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-    const int64_t base = (int64_t)t * kScanTileB + (int64_t)tid * 8;
-    int s = 0;
-    for (int k = 0; k < 8; ++k)
-      if (base + k < a.nkeys) s += a.count[base + k];
-    int tot;
-    block_scan_excl(s, lds, &tot);
-    if (tid == 0) a.tile_sum[t] = tot;
-  }
-  grid_barrier(a.bar, a.err);
-
-  // ---- P2: scan of the tile sums (one block) --------------------------------
-  if (blockIdx.x == 0) {
-    int carry = 0;
-    for (int b = 0; b < a.ntiles; b += kBatchThreads) {
-      const int t = b + tid;
-      const int v = t < a.ntiles ? a.tile_sum[t] : 0;
+    // ---- P1: tile sums -------------------------------------------------------
+    for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+      const int64_t base = (int64_t)t * kScanTileB + (int64_t)tid * 8;
+      int s = 0;
+      for (int k = 0; k < 8; ++k)
+        if (base + k < a.nkeys) s += a.count[base + k];
       int tot;
-      const int ex = block_scan_excl(v, lds, &tot);
-      if (t < a.ntiles) a.tile_sum[t] = carry + ex;
-      carry += tot;
+      block_scan_excl(s, lds, &tot);
+      if (tid == 0) a.tile_sum[t] = tot;
     }
-    if (tid == 0) a.cell_start[a.nkeys] = carry;
+    grid_barrier(a.bar, a.err);
+
+    // ---- P2: scan of the tile sums (one block) --------------------------------
+    if (blockIdx.x == 0) {
+      int carry = 0;
+      for (int b = 0; b < a.ntiles; b += kBatchThreads) {
+        const int t = b + tid;
+        const int v = t < a.ntiles ? a.tile_sum[t] : 0;
+        int tot;
+        const int ex = block_scan_excl(v, lds, &tot);
+        if (t < a.ntiles) a.tile_sum[t] = carry + ex;
+        carry += tot;
+      }
+      if (tid == 0) a.cell_start[a.nkeys] = carry;
+    }
+    grid_barrier(a.bar, a.err);
+
+    // ---- P3: cell starts -------------------------------------------------------
+    for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+      const int64_t base = (int64_t)t * kScanTileB + (int64_t)tid * 8;
+      int v[8];
+      int s = 0;
+      for (int k = 0; k < 8; ++k) {
+        v[k] = base + k < a.nkeys ? a.count[base + k] : 0;
+        s += v[k];
+      }
+      int tot;
+      int run = a.tile_sum[t] + block_scan_excl(s, lds, &tot);
+      for (int k = 0; k < 8; ++k) {
+        if (base + k < a.nkeys) a.cell_start[base + k] = run;
+        run += v[k];
+      }
+    }
+    grid_barrier(a.bar, a.err);
+
+    // ---- P4: provisional scatter -----------------------------------------------
+    for (int64_t i = gtid; i < a.ntot; i += gstride) a.tmp[a.cell_start[a.key[i]] + a.slot[i]] = (int32_t)i;
+    grid_barrier(a.bar, a.err);
+
+    // ---- P5: stable placement; clear the histogram for the next step -----------
+    for (int64_t k = gtid; k < a.nkeys; k += gstride) place_bucket(a.cell_start[k], a.cell_start[k + 1], a.tmp, a.perm);
+    for (int64_t k = gtid; k < a.nkeys; k += gstride) a.count[k] = 0;
+    grid_barrier(a.bar, a.err);
+
+    // ---- P6: reorder + pack ------------------------------------------------------
+    for (int64_t k = gtid; k < a.ntot; k += gstride) {
+      const int j = a.perm[k];
+      const RepDesc &R = a.reps[a.rep_of[k]];
+      const double x = wrap_coord(a.ix[j], R.g.L[0]), y = wrap_coord(a.iy[j], R.g.L[1]),
+                   z = wrap_coord(a.iz[j], R.g.L[2]), q = a.iq[j];
+      const int32_t id = a.iid[j];
+      a.ox[k] = x;
+      a.oy[k] = y;
+      a.oz[k] = z;
+      a.oq[k] = q;
+      a.oid[k] = id;
+      if (a.mode == 0) {
+        a.ovx[k] = a.ivx[j];
+        a.ovy[k] = a.ivy[j];
+        a.ovz[k] = a.ivz[j];
+      }
+      a.xq[k] = make_double4(x, y, z, q);
+      if (q != 0.0) a.sq[k] = make_double4(x / R.g.L[0], y / R.g.L[1], z / R.g.L[2], q);
+      a.sid[k] = id;
+    }
+    grid_barrier(a.bar, a.err);
+    return;
   }
-  grid_barrier(a.bar, a.err);
 
-  // ---- P3: cell starts -------------------------------------------------------
-  for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-    const int64_t base = (int64_t)t * kScanTileB + (int64_t)tid * 8;
-    int v[8];
-    int s = 0;
-    for (int k = 0; k < 8; ++k) {
-      v[k] = base + k < a.nkeys ? a.count[base + k] : 0;
-      s += v[k];
-    }
-    int tot;
-    int run = a.tile_sum[t] + block_scan_excl(s, lds, &tot);
-    for (int k = 0; k < 8; ++k) {
-      if (base + k < a.nkeys) a.cell_start[base + k] = run;
-      run += v[k];
-    }
-  }
-  grid_barrier(a.bar, a.err);
 
-  // ---- P4: provisional scatter -----------------------------------------------
-  for (int64_t i = gtid; i < a.ntot; i += gstride) a.tmp[a.cell_start[a.key[i]] + a.slot[i]] = (int32_t)i;
-  grid_barrier(a.bar, a.err);
-
-  // ---- P5: stable placement; clear the histogram for the next step -----------
-  for (int64_t k = gtid; k < a.nkeys; k += gstride) place_bucket(a.cell_start[k], a.cell_start[k + 1], a.tmp, a.perm);
-  for (int64_t k = gtid; k < a.nkeys; k += gstride) a.count[k] = 0;
-  grid_barrier(a.bar, a.err);
-
-  // ---- P6: reorder + pack ------------------------------------------------------
-  for (int64_t k = gtid; k < a.ntot; k += gstride) {
-    const int j = a.perm[k];
-    const RepDesc &R = a.reps[a.rep_of[k]];
-    const double x = wrap_coord(a.ix[j], R.g.L[0]), y = wrap_coord(a.iy[j], R.g.L[1]),
-                 z = wrap_coord(a.iz[j], R.g.L[2]), q = a.iq[j];
-    const int32_t id = a.iid[j];
-    a.ox[k] = x;
-    a.oy[k] = y;
-    a.oz[k] = z;
-    a.oq[k] = q;
-    a.oid[k] = id;
-    if (a.mode == 0) {
-      a.ovx[k] = a.ivx[j];
-      a.ovy[k] = a.ivy[j];
-      a.ovz[k] = a.ivz[j];
-    }
-    a.xq[k] = make_double4(x, y, z, q);
-    if (q != 0.0) a.sq[k] = make_double4(x / R.g.L[0], y / R.g.L[1], z / R.g.L[2], q);
-    a.sid[k] = id;
-  }
-  grid_barrier(a.bar, a.err);
-
-  // ---- P7: near field; structure-factor partials ---------------------------------
-  for (int64_t i = gtid; i < a.ntot; i += gstride) {
-    if (do_near) {
-      batch_pair<F32>(a, a.reps[a.rep_of[i]], i);
-    } else {
-      a.ofx[i] = 0.0;
-      a.ofy[i] = 0.0;
-      a.ofz[i] = 0.0;
-    }
-  }
+  // ---- P7: structure-factor partials (the near field ran in k_batch_near) --------
   if (P > 0 && do_far) {
     const int groups = (P + 63) / 64;
     const int64_t rho_items = *a.rho_items;
@@ -420,6 +417,25 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch_step(BatchArgs a) {
   if (a.mode == 0 && gtid == 0) *((volatile uint64_t *)a.eval) = eval + 1;
 }
 
+// The near field of every particle of the batch, between the two launches of
+// the step kernel: a plain launch, so that its occupancy is not bound to the
+// persistent kernel's registers. Four waves per SIMD in FP32C (no spills;
+// five, with 13 VGPRs spilled, ran no faster), three in FP64 (16 VGPRs
+// spilled, 11.0 against 12.1 ms per 256-replica step at two).
+template <bool F32>
+__global__ void __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(F32 ? 4 : 3)))
+k_batch_near(BatchArgs a) {
+  const int64_t i = blockIdx.x * (int64_t)kBatchThreads + threadIdx.x;
+  if (i >= a.ntot) return;
+  if (a.pp.do_coul || a.pp.do_lj) {
+    batch_pair<F32>(a, a.reps[a.rep_of[i]], i);
+  } else {
+    a.ofx[i] = 0.0;
+    a.ofy[i] = 0.0;
+    a.ofz[i] = 0.0;
+  }
+}
+
 int batch_grid_blocks(int prec, int device) {
   int per_cu = 0, cus = 0;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
@@ -435,26 +451,52 @@ int batch_grid_blocks(int prec, int device) {
 }
 
 void launch_batch_step(int prec, int blocks, const BatchArgs &a, hipStream_t st) {
-  if (prec == RBE_FP32C)
-    k_batch_step<true><<<blocks, kBatchThreads, 0, st>>>(a);
-  else
-    k_batch_step<false><<<blocks, kBatchThreads, 0, st>>>(a);
+  BatchArgs a1 = a, a2 = a;
+  a1.launch_part = 1;
+  a2.launch_part = 2;
+  const unsigned near_blocks = (unsigned)((a.ntot + kBatchThreads - 1) / kBatchThreads);
+  if (prec == RBE_FP32C) {
+    k_batch_step<true><<<blocks, kBatchThreads, 0, st>>>(a1);
+    k_batch_near<true><<<near_blocks, kBatchThreads, 0, st>>>(a);
+    k_batch_step<true><<<blocks, kBatchThreads, 0, st>>>(a2);
+  } else {
+    k_batch_step<false><<<blocks, kBatchThreads, 0, st>>>(a1);
+    k_batch_near<false><<<near_blocks, kBatchThreads, 0, st>>>(a);
+    k_batch_step<false><<<blocks, kBatchThreads, 0, st>>>(a2);
+  }
 }
 
 int batch_scan_tiles(int64_t nkeys) { return (int)((nkeys + kScanTileB - 1) / kScanTileB); }
 
 hipError_t add_batch_node(hipGraph_t graph, hipGraphNode_t *node, const hipGraphNode_t *deps, int ndeps, int prec,
                           int blocks, BatchArgs *a) {
-  hipKernelNodeParams kp{};
-  kp.func = prec == RBE_FP32C ? reinterpret_cast<void *>(k_batch_step<true>)
-                              : reinterpret_cast<void *>(k_batch_step<false>);
-  kp.gridDim = dim3((unsigned)blocks);
-  kp.blockDim = dim3(kBatchThreads);
-  kp.sharedMemBytes = 0;
-  void *args[] = {a};
-  kp.kernelParams = args;
-  kp.extra = nullptr;
-  return hipGraphAddKernelNode(node, graph, deps, (size_t)ndeps, &kp);
+  const bool f32 = prec == RBE_FP32C;
+  BatchArgs parts[3] = {*a, *a, *a};
+  parts[0].launch_part = 1;
+  parts[2].launch_part = 2;
+  void *funcs[3] = {f32 ? reinterpret_cast<void *>(k_batch_step<true>) : reinterpret_cast<void *>(k_batch_step<false>),
+                    f32 ? reinterpret_cast<void *>(k_batch_near<true>) : reinterpret_cast<void *>(k_batch_near<false>),
+                    f32 ? reinterpret_cast<void *>(k_batch_step<true>) : reinterpret_cast<void *>(k_batch_step<false>)};
+  const unsigned grids[3] = {(unsigned)blocks, (unsigned)((a->ntot + kBatchThreads - 1) / kBatchThreads),
+                             (unsigned)blocks};
+  hipGraphNode_t prev = nullptr;
+  for (int k = 0; k < 3; ++k) {
+    hipKernelNodeParams kp{};
+    kp.func = funcs[k];
+    kp.gridDim = dim3(grids[k]);
+    kp.blockDim = dim3(kBatchThreads);
+    kp.sharedMemBytes = 0;
+    void *args[] = {&parts[k]};
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    // the node copies the arguments
+    const hipGraphNode_t dep = prev;
+    const hipError_t e = k == 0 ? hipGraphAddKernelNode(&prev, graph, deps, (size_t)ndeps, &kp)
+                                : hipGraphAddKernelNode(&prev, graph, &dep, 1, &kp);
+    if (e != hipSuccess) return e;
+  }
+  *node = prev;
+  return hipSuccess;
 }
 
 __global__ void __launch_bounds__(256) k_qstats_rep(const int64_t *__restrict__ off, const double *__restrict__ q,

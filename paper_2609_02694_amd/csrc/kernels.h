@@ -299,6 +299,7 @@ struct BatchArgs {
   int ntiles;
   int P;
   int mode;               // 0: step, 1: force evaluation only
+  int launch_part;        // launch of the step: 1 phases P0-P6, 2 phases P7-P9 (set by the launchers)
   const int *rho_items;   // total structure-factor items (chunk x 64-mode group), on the device
   int do_far;             // Fourier part on
   PairParams pp;          // physics shared by all replicas (grid fields unused)
@@ -326,7 +327,8 @@ struct BatchArgs {
 int batch_grid_blocks(int prec, int device);
 void launch_batch_step(int prec, int blocks, const BatchArgs &a, hipStream_t st);
 int batch_scan_tiles(int64_t nkeys);
-// Adds one step launch to `graph` (the node copies *a).
+// Adds one step to `graph`: the first part of the step kernel, the near-field
+// kernel and the second part, chained; *node is the last (the nodes copy *a).
 hipError_t add_batch_node(hipGraph_t graph, hipGraphNode_t *node, const hipGraphNode_t *deps, int ndeps, int prec,
                           int blocks, BatchArgs *a);
 // Per-replica charge statistics: nq[r] charged count, qs[2r] = sum q, qs[2r+1] = sum |q|.
