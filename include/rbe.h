@@ -151,8 +151,10 @@ int rbe_create(rbe_ctx **out, const rbe_params *p /* host */, int64_t n_max, int
    mode sample of Eq. 9 (drawn from its own seed for the common eval) and its
    own structure factors. rbe_forces and rbe_step then take the concatenated
    state (n = offset[n_sys]); rbe_forces requires m, w and rho_out to be NULL.
-   rbe_step runs every velocity-Verlet step of all replicas as ONE persistent
-   launch (captured two steps at a time in a HIP graph) and returns each
+   rbe_step runs every velocity-Verlet step of all replicas in three launches
+   (a persistent kernel for binning and reorder, a near-field kernel, the
+   persistent kernel again for the Fourier part and the second half-kick;
+   captured two steps at a time in a HIP graph) and returns each
    replica's particles in cell order inside its own range. rbe_build_cells is
    not available on a batched context. With n_sys == 1 this is rbe_create
    with n_max = offset[1] - offset[0]. */
@@ -346,8 +348,8 @@ enum {
   RBE_TK_PAIR_SHELL = 11, /* reserved: the shell of Eq. 11 is timed with
                              RBE_TK_PAIR_CHARGED (one fused launch)          */
   RBE_TK_GHOST = 12,      /* ghost shell build and sort                     */
-  RBE_TK_BATCH = 13,      /* persistent step of a batched context (one entry
-                             per step; the phases are not timed apart)      */
+  RBE_TK_BATCH = 13,      /* step of a batched context (one entry per step,
+                             its three launches together)                   */
   RBE_TIMING_KINDS = 14
 };
 int rbe_set_timing(rbe_ctx *ctx, int enable);

@@ -1,5 +1,5 @@
-"""GPU parity of the batched form: many replicas of uneven size in one
-persistent launch per step, through the C ABI, against the FP64 oracle run
+"""GPU parity of the batched form: many replicas of uneven size advanced
+together (three launches per step), through the C ABI, against the FP64 oracle run
 on every replica separately (each replica is its own periodic system with
 its own mode sample). FP64 <= 1e-12, FP32C <= 1e-5 (RMS relative, per
 replica)."""
