@@ -690,7 +690,7 @@ __global__ void __launch_bounds__(256) k_qstats(int64_t n, const double *__restr
 
 // Eq. 1 asks for a neutral system: |sum q| above 1e-10 sum |q| (and above
 // 1e-12) raises kErrNonNeutral.
-__global__ void k_qverdict(const double *__restrict__ stats, int *err) {
+__global__ void k_qstatus(const double *__restrict__ stats, int *err) {
   const double s = stats[0], a = stats[1];
   if (isfinite(s) && isfinite(a) && fabs(s) > 1e-10 * fmax(a, 1e-300) && fabs(s) > 1e-12)
     atomicOr(err, kErrNonNeutral);
@@ -705,7 +705,7 @@ static void launch_charge_check(rbe_ctx *c, int64_t n, const double *q, hipStrea
   if (blocks > 1024) blocks = 1024;
   if (blocks < 1) blocks = 1;
   k_qstats<<<(unsigned)blocks, 256, 0, st>>>(n, q, c->qstats, c->err);
-  k_qverdict<<<1, 1, 0, st>>>(c->qstats, c->err);
+  k_qstatus<<<1, 1, 0, st>>>(c->qstats, c->err);
 }
 
 // ---------------------------------------------------------------------------
