@@ -40,10 +40,17 @@ constexpr uint64_t kBarrierTimeoutTicks = 200000000ull;  // 2 s at the 100 MHz w
 // Grid-wide barrier. A wait longer than the time limit flags kErrBarrier;
 // once that flag is up no block waits again, so a launch whose blocks were
 // not all resident still ends (with its result reported as failed).
+// Every wave waits until its own stores have reached the L2 (s_waitcnt 0)
+// before the block barrier; one wave per block then releases the block's
+// stores at agent scope (the L2 write-back covers them all) and, after the
+// wait, acquires the other blocks' (invalidating the caches every wave of the
+// block reads through). Fences in every wave would repeat the write-back and
+// the invalidation per wave.
 __device__ inline void grid_barrier(unsigned *bar, int *err) {
-  __threadfence();
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
+    __threadfence();
     const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
     if (arrived == gridDim.x) {
@@ -60,9 +67,9 @@ __device__ inline void grid_barrier(unsigned *bar, int *err) {
         }
       }
     }
+    __threadfence();
   }
   __syncthreads();
-  __threadfence();
 }
 
 __device__ inline int block_scan_excl(int v, int *lds, int *total) {
