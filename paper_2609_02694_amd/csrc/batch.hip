@@ -58,7 +58,9 @@ __device__ inline void grid_barrier(unsigned *bar, int *err) {
       __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       const uint64_t t0 = wall_clock64();
-      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+      // relaxed polls (an acquire would invalidate the caches on every poll);
+      // the fence after the wait acquires
+      while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
         if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrBarrier) break;
         __builtin_amdgcn_s_sleep(4);
         if (wall_clock64() - t0 > kBarrierTimeoutTicks) {
