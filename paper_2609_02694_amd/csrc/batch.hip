@@ -42,16 +42,18 @@ constexpr uint64_t kBarrierTimeoutTicks = 200000000ull;  // 2 s at the 100 MHz w
 // not all resident still ends (with its result reported as failed).
 // Every wave waits until its own stores have reached the L2 (s_waitcnt 0)
 // before the block barrier; one wave per block then releases the block's
-// stores at agent scope (the L2 write-back covers them all) and, after the
-// wait, acquires the other blocks' (invalidating the caches every wave of the
-// block reads through). Fences in every wave would repeat the write-back and
-// the invalidation per wave.
+// stores at agent scope with its arrival (the L2 write-back covers them all)
+// and, after the wait, acquires the other blocks' (invalidating the caches
+// every wave of the block reads through). Fences in every wave would repeat
+// the write-back and the invalidation per wave.
 __device__ inline void grid_barrier(unsigned *bar, int *err) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    // the arrival releases the block's stores (and acquires the earlier
+    // arrivals' for the last one); the generation read before it needs no
+    // ordering of its own
+    const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1;
     if (arrived == gridDim.x) {
       __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
